@@ -147,9 +147,12 @@ class Run:
         self._lists = None
 
     def __del__(self):
-        if getattr(self, "ptr", None):
-            lib().or_run_free(self.ptr)
-            self.ptr = None
+        try:
+            if getattr(self, "ptr", None):
+                lib().or_run_free(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
 
     def tree(self, which: int) -> dict:
         return _export_tree(lib().or_run_tree(self.ptr, which), self.N if which else self.M)

@@ -1,0 +1,196 @@
+"""Thin Python binding of the BLDTT C ABI: argument marshalling only.
+
+Every step of the compute phase runs in libbldtt.so (HIP kernels and the C++
+host engine).  torch supplies device memory and the stream; nothing here
+computes potentials.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import KERNELS, DEFAULT_PARAM, TYPES, check, lib
+
+
+def _f64_cuda(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 torch.cuda tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream_ptr(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _kernel(kernel: str, param):
+    if kernel not in KERNELS:
+        raise ValueError(f"unknown kernel {kernel!r}")
+    return KERNELS[kernel], DEFAULT_PARAM[kernel] if param is None else float(param)
+
+
+def _tree_dict(view: _lib.TreeView) -> dict:
+    nc, npart = view.n_clusters, view.n_particles
+
+    def arr(p, n, dt):
+        return np.ctypeslib.as_array(p, shape=(n,)).astype(dt, copy=True)
+
+    return dict(lo=arr(view.lo, 3 * nc, np.float64).reshape(nc, 3), hi=arr(view.hi, 3 * nc, np.float64).reshape(nc, 3),
+                center=arr(view.center, 3 * nc, np.float64).reshape(nc, 3), radius=arr(view.radius, nc, np.float64),
+                begin=arr(view.begin, nc, np.int64), count=arr(view.count, nc, np.int64),
+                parent=arr(view.parent, nc, np.int64), child=arr(view.child, 8 * nc, np.int64).reshape(nc, 8),
+                perm=arr(view.perm, npart, np.int64), level=arr(view.level, nc, np.int32),
+                nchild=arr(view.nchild, nc, np.int32), depth=int(view.depth))
+
+
+class _PlanBase:
+    _handle = None
+
+    def close(self):
+        if self._handle:
+            check(lib().bldtt_destroy(self._handle))
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def tree(self, which: int = 0) -> dict:
+        v = _lib.TreeView()
+        check(lib().bldtt_get_tree(self._handle, which, C.byref(v)))
+        return _tree_dict(v)
+
+    def lists(self) -> dict:
+        out = {}
+        for k, name in enumerate(TYPES):
+            tc, sc, n = _lib._I64(), _lib._I64(), C.c_int64()
+            check(lib().bldtt_get_lists(self._handle, k, C.byref(tc), C.byref(sc), C.byref(n)))
+            if n.value:
+                out[name] = (np.ctypeslib.as_array(tc, shape=(n.value,)).copy(),
+                             np.ctypeslib.as_array(sc, shape=(n.value,)).copy())
+            else:
+                out[name] = (np.empty(0, np.int64), np.empty(0, np.int64))
+        return out
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        check(lib().bldtt_get_stats(self._handle, C.byref(s)))
+        return dict(n_entries=dict(zip(TYPES, list(s.n_entries))),
+                    interactions=dict(zip(TYPES, list(s.interactions))),
+                    n_target_clusters=s.n_target_clusters, n_source_clusters=s.n_source_clusters,
+                    target_depth=s.target_depth, source_depth=s.source_depth, setup_ms=s.setup_ms,
+                    traverse_ms=s.traverse_ms, compute_host_ms=s.compute_host_ms,
+                    phase_ms=dict(zip(_lib.PHASES, list(s.phase_ms))), profiled_computes=s.profiled_computes)
+
+    def traverse_host(self):
+        check(lib().bldtt_traverse_host(self._handle))
+
+
+class Plan(_PlanBase):
+    """bldtt_setup on device tensors; compute() returns potentials in caller order.
+
+    targets: (x, y, z) float64 cuda tensors, or None when targets = sources.
+    sources: (x, y, z, q) float64 cuda tensors.
+    """
+
+    def __init__(self, targets, sources, kernel="coulomb", theta=0.7, degree=6, leaf=500, param=None, flags=0,
+                 stream=None):
+        sx, sy, sz, q = (_f64_cuda(t, n) for t, n in zip(sources, ("sx", "sy", "sz", "q")))
+        if targets is None:
+            tx, ty, tz = sx, sy, sz
+        else:
+            tx, ty, tz = (_f64_cuda(t, n) for t, n in zip(targets, ("tx", "ty", "tz")))
+        kind, kparam = _kernel(kernel, param)
+        self.M, self.N, self.degree = tx.numel(), sx.numel(), degree
+        self.P = (degree + 1) ** 3
+        self.device = sx.device
+        p = _lib.Particles(self.M, tx.data_ptr(), ty.data_ptr(), tz.data_ptr(), self.N, sx.data_ptr(),
+                           sy.data_ptr(), sz.data_ptr(), q.data_ptr())
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_setup(C.byref(h), C.byref(p), kind, kparam, float(theta), int(degree), int(leaf),
+                                    int(flags), _stream_ptr(stream)))
+        self._handle = h
+
+    def compute(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        _f64_cuda(out, "out")
+        if out.numel() != self.M:
+            raise ValueError("out must hold M values")
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_compute(self._handle, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def qhat(self) -> np.ndarray:
+        n = self.stats()["n_source_clusters"]
+        out = np.empty(n * self.P)
+        check(lib().bldtt_get_qhat(self._handle, out.ctypes.data_as(_lib._D)))
+        return out.reshape(n, self.P)
+
+    def phihat(self) -> np.ndarray:
+        n = self.stats()["n_target_clusters"]
+        out = np.empty(n * self.P)
+        check(lib().bldtt_get_phihat(self._handle, out.ctypes.data_as(_lib._D)))
+        return out.reshape(n, self.P)
+
+
+class HostPlan(_PlanBase):
+    """bldtt_setup_host on numpy arrays: trees and traversal only, no device."""
+
+    def __init__(self, targets, sources, kernel="coulomb", theta=0.7, degree=6, leaf=500, param=None, flags=0):
+        def f64(a):
+            return np.ascontiguousarray(a, dtype=np.float64)
+
+        self._keep = [f64(a) for a in sources]
+        sx, sy, sz, q = self._keep
+        if targets is None:
+            tx, ty, tz = sx, sy, sz
+        else:
+            self._keep += [f64(a) for a in targets]
+            tx, ty, tz = self._keep[4:7]
+        kind, kparam = _kernel(kernel, param)
+        p = _lib.Particles(tx.shape[0], tx.ctypes.data, ty.ctypes.data, tz.ctypes.data, sx.shape[0], sx.ctypes.data,
+                           sy.ctypes.data, sz.ctypes.data, q.ctypes.data)
+        h = C.c_void_p()
+        check(lib().bldtt_setup_host(C.byref(h), C.byref(p), kind, kparam, float(theta), int(degree), int(leaf),
+                                     int(flags)))
+        self._handle = h
+
+
+def direct_sum(targets, sources, kernel="coulomb", param=None, sel: torch.Tensor | None = None, stream=None):
+    """Compensated FP64 direct sum (Eq. 1) at all targets or at caller indices `sel` (int64 cuda tensor)."""
+    tx, ty, tz = (_f64_cuda(t, n) for t, n in zip(targets, ("tx", "ty", "tz")))
+    sx, sy, sz, q = (_f64_cuda(t, n) for t, n in zip(sources, ("sx", "sy", "sz", "q")))
+    kind, kparam = _kernel(kernel, param)
+    if sel is not None:
+        if sel.dtype != torch.int64 or sel.device.type != "cuda":
+            raise TypeError("sel must be an int64 cuda tensor")
+        n = sel.numel()
+        selp = sel.data_ptr()
+    else:
+        n = tx.numel()
+        selp = None
+    out = torch.empty(n, dtype=torch.float64, device=sx.device)
+    with torch.cuda.device(sx.device):
+        check(lib().bldtt_direct_sum(kind, kparam, tx.numel(), tx.data_ptr(), ty.data_ptr(), tz.data_ptr(),
+                                     sx.numel(), sx.data_ptr(), sy.data_ptr(), sz.data_ptr(), q.data_ptr(), n,
+                                     selp, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def version() -> str:
+    return lib().bldtt_version().decode()

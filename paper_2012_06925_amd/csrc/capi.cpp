@@ -1,0 +1,627 @@
+// capi.cpp -- the C ABI declared in include/bldtt.h: plan lifecycle, device
+// memory, and the order of the compute phase on the caller's stream.
+//
+// Compute phase (Algorithm 1 after the tree build):
+//   1. upward pass on the device: leaf proxy charges, then parents level by
+//      level from the deepest (Sec. 2.5);
+//   2. meanwhile on the host: dual tree traversal (Algorithm 2) and packing
+//      of the four lists into work items; then one upload;
+//   3. CP + CC sums into the target proxies, then the downward transfer from
+//      the root (Sec. 2.7);
+//   4. PP + PC sums into the target particles;
+//   5. leaf proxies to targets plus the PP/PC part, scattered to caller order.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bldtt.h"
+#include "engine.hpp"
+#include "kernels.hpp"
+
+using namespace bldtt;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    int code = e == hipErrorOutOfMemory ? BLDTT_ENOMEM : BLDTT_EDEVICE;
+    throw Error(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x)
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        return BLDTT_OK;
+    } catch (const Error& e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return BLDTT_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return BLDTT_EDEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return BLDTT_EDEVICE;
+    }
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocation owned by a plan.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) b = 8;
+        HIPCHK(hipMalloc(&p, b));
+        bytes = b;
+    }
+    void reserve(size_t b) {
+        if (b > bytes) alloc(b + b / 4);
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host staging buffer (allocated, never registered).
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void reserve(size_t b) {
+        if (b <= bytes) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        HIPCHK(hipHostMalloc(&p, b + b / 4, hipHostMallocDefault));
+        bytes = b + b / 4;
+    }
+};
+
+struct DevTreeBufs {
+    DevBuf box, begin, count, nchild, child, parent;
+    DevTree view() const {
+        return DevTree{box.as<double>(), begin.as<int32_t>(), count.as<int32_t>(), nchild.as<int32_t>(),
+                       child.as<int32_t>(), parent.as<int32_t>()};
+    }
+};
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v) {
+    b.alloc(sizeof(T) * v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+}
+
+void upload_tree(DevTreeBufs& d, const Tree& t) {
+    int64_t nc = t.size();
+    std::vector<double> box(6 * nc);
+    std::vector<int32_t> begin(nc), count(nc), nchild(nc), child(8 * nc), parent(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int k = 0; k < 3; ++k) {
+            box[6 * c + k] = t.lo[3 * c + k];
+            box[6 * c + 3 + k] = t.hi[3 * c + k];
+        }
+        begin[c] = (int32_t)t.begin[c];
+        count[c] = (int32_t)t.count[c];
+        nchild[c] = t.nchild[c];
+        parent[c] = (int32_t)t.parent[c];
+        for (int k = 0; k < 8; ++k) child[8 * c + k] = (int32_t)t.child[8 * c + k];
+    }
+    upload(d.box, box);
+    upload(d.begin, begin);
+    upload(d.count, count);
+    upload(d.nchild, nchild);
+    upload(d.child, child);
+    upload(d.parent, parent);
+}
+
+bool all_finite(const double* a, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct bldtt_plan {
+    int32_t kind = 0;
+    double param = 0.0, theta = 0.7;
+    int degree = 6;
+    int64_t leaf = 500;
+    uint32_t flags = 0;
+    bool host_only = false, aliased = false;
+    int64_t M = 0, N = 0;
+    Tree S, Tsep;
+    const Tree& T() const { return aliased ? S : Tsep; }
+    Lists lists;
+    bool have_lists = false;
+    Work work;
+    bldtt_stats stats{};
+
+    // device state
+    DevBuf tx, ty, tz, sx, sy, sz, sq, perm, tab, qhat, phihat, phi_tree;
+    DevTreeBufs dS, dTsep;
+    const DevTreeBufs& dT() const { return aliased ? dS : dTsep; }
+    DevBuf src_leaves, up_parents, down_kids;
+    int n_src_leaves = 0;
+    std::vector<int64_t> up_off, down_off;   // per level offsets into up_parents / down_kids
+    DevBuf pitems, pentries, qitems, qentries, has_far;
+    PinnedBuf staging;
+    hipEvent_t staging_free = nullptr;
+    hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
+    bool prof_pending = false;
+
+    int P() const { return (degree + 1) * (degree + 1) * (degree + 1); }
+    DevParticles dsrc() const { return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), sq.as<double>()}; }
+    DevParticles dtgt() const {
+        if (aliased) return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), nullptr};
+        return DevParticles{tx.as<double>(), ty.as<double>(), tz.as<double>(), nullptr};
+    }
+    ~bldtt_plan() {
+        if (staging_free) (void)hipEventDestroy(staging_free);
+        for (auto& e : prof_ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+void validate(const bldtt_particles* p, int32_t kernel, double theta, int32_t degree, int64_t leaf_size) {
+    if (!p) throw Error(BLDTT_EINVAL, "particles is NULL");
+    if (p->M < 1 || p->N < 1) throw Error(BLDTT_EINVAL, "M and N must be >= 1");
+    if (p->M > INT32_MAX || p->N > INT32_MAX) throw Error(BLDTT_EINVAL, "M and N must be < 2^31");
+    if (!p->tx || !p->ty || !p->tz || !p->sx || !p->sy || !p->sz || !p->q)
+        throw Error(BLDTT_EINVAL, "a particle array is NULL");
+    if (!(theta > 0.0 && theta < 1.0)) throw Error(BLDTT_EINVAL, "theta must lie in (0, 1)");
+    if (degree < 1 || degree > kMaxDegree) throw Error(BLDTT_EINVAL, "degree must lie in [1, 12]");
+    if (leaf_size < 1) throw Error(BLDTT_EINVAL, "leaf_size must be >= 1");
+    if (kernel != BLDTT_COULOMB && kernel != BLDTT_YUKAWA && kernel != BLDTT_OSCILLATORY &&
+        kernel != BLDTT_REGCOULOMB && kernel != BLDTT_POLY_TEST)
+        throw Error(BLDTT_EINVAL, "unknown kernel");
+}
+
+// Trees from host arrays; fills the plan's host side.
+void build_host(bldtt_plan* pl, const double* tx, const double* ty, const double* tz, const double* sx,
+                const double* sy, const double* sz, const double* q, std::vector<double>* sxs,
+                std::vector<double>* txs) {
+    if (!all_finite(sx, pl->N) || !all_finite(sy, pl->N) || !all_finite(sz, pl->N) || !all_finite(q, pl->N))
+        throw Error(BLDTT_EINVAL, "non-finite source coordinate or charge");
+    if (!pl->aliased && (!all_finite(tx, pl->M) || !all_finite(ty, pl->M) || !all_finite(tz, pl->M)))
+        throw Error(BLDTT_EINVAL, "non-finite target coordinate");
+    build_tree(pl->N, sx, sy, sz, pl->leaf, pl->S, sxs[0], sxs[1], sxs[2]);
+    if (!pl->aliased) build_tree(pl->M, tx, ty, tz, pl->leaf, pl->Tsep, txs[0], txs[1], txs[2]);
+}
+
+void fill_stats_tree(bldtt_plan* pl) {
+    pl->stats.n_target_clusters = pl->T().size();
+    pl->stats.n_source_clusters = pl->S.size();
+    pl->stats.target_depth = pl->T().depth;
+    pl->stats.source_depth = pl->S.depth;
+}
+
+void do_traverse(bldtt_plan* pl) {
+    double t0 = now_ms();
+    traverse(pl->T(), pl->S, pl->theta, pl->degree, (pl->flags & BLDTT_PP_CC_ONLY) != 0, pl->lists);
+    pl->have_lists = true;
+    for (int k = 0; k < 4; ++k) pl->stats.n_entries[k] = (int64_t)pl->lists.tc[k].size();
+    pl->stats.traverse_ms = now_ms() - t0;
+}
+
+// Level lists: source parents per level (for the upward pass) and target
+// non-root clusters per level (for the downward pass).
+void level_lists(const Tree& t, bool parents, std::vector<int32_t>& ids, std::vector<int64_t>& off) {
+    int32_t depth = t.depth;
+    std::vector<std::vector<int32_t>> by(depth + 1);
+    for (int64_t c = 0; c < t.size(); ++c) {
+        if (parents ? t.nchild[c] > 0 : t.level[c] > 0) by[t.level[c]].push_back((int32_t)c);
+    }
+    ids.clear();
+    off.assign(depth + 2, 0);
+    for (int32_t l = 0; l <= depth; ++l) {
+        off[l] = (int64_t)ids.size();
+        ids.insert(ids.end(), by[l].begin(), by[l].end());
+    }
+    off[depth + 1] = (int64_t)ids.size();
+}
+
+// Fold the events of the last profiled compute into the stats.
+void collect_profile(bldtt_plan* pl) {
+    if (!pl->prof_pending) return;
+    for (int ph = 0; ph < BLDTT_N_PHASES; ++ph) {
+        HIPCHK(hipEventSynchronize(pl->prof_ev[2 * ph + 1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pl->prof_ev[2 * ph], pl->prof_ev[2 * ph + 1]));
+        pl->stats.phase_ms[ph] += ms;
+    }
+    pl->stats.profiled_computes += 1;
+    pl->prof_pending = false;
+}
+
+struct PhaseMark {
+    bldtt_plan* pl;
+    int ph;
+    hipStream_t st;
+    PhaseMark(bldtt_plan* p, int phase, hipStream_t s) : pl(p), ph(phase), st(s) {
+        if (pl->flags & BLDTT_PROFILE) HIPCHK(hipEventRecord(pl->prof_ev[2 * ph], st));
+    }
+    ~PhaseMark() noexcept(false) {
+        if (pl->flags & BLDTT_PROFILE) HIPCHK(hipEventRecord(pl->prof_ev[2 * ph + 1], st));
+    }
+};
+
+constexpr int kTile = 256;    // targets per particle work item (= workgroup size)
+constexpr int kPTile = 256;   // proxies per proxy work item
+
+void compute(bldtt_plan* pl, double* out, hipStream_t st) {
+    double t0 = now_ms();
+    const Tree& T = pl->T();
+    const Tree& S = pl->S;
+    const int deg = pl->degree;
+    const DevTree dS = pl->dS.view(), dT = pl->dT().view();
+    const double* tab = pl->tab.as<double>();
+    KernelSpec ks{pl->kind, pl->param};
+
+    collect_profile(pl);
+    // 1. upward pass
+    {
+    PhaseMark mark(pl, BLDTT_PH_UP, st);
+    launch_up_leaf(deg, pl->src_leaves.as<int32_t>(), pl->n_src_leaves, dS, pl->dsrc(), tab, pl->qhat.as<double>(), st);
+    for (int l = S.depth; l >= 0; --l) {
+        int64_t b = pl->up_off[l], e = pl->up_off[l + 1];
+        launch_up_transfer(deg, pl->up_parents.as<int32_t>() + b, (int)(e - b), dS, tab, pl->qhat.as<double>(), st);
+    }
+    }
+
+    // 2. traversal and work packing on the host, overlapping the upward pass
+    do_traverse(pl);
+    double tp = now_ms();
+    pack_work(T, S, pl->lists, deg, kTile, kPTile, pl->work);
+    pl->stats.traverse_ms += now_ms() - tp;
+    for (int k = 0; k < 4; ++k) pl->stats.interactions[k] = pl->work.interactions[k];
+    Work& w = pl->work;
+    size_t bp = sizeof(PItem) * w.pitems.size(), be = sizeof(int32_t) * w.pentries.size();
+    size_t bq = sizeof(QItem) * w.qitems.size(), bqe = sizeof(int32_t) * w.qentries.size();
+    size_t bf = w.leaf_has_far.size();
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t total = al(bp) + al(be) + al(bq) + al(bqe) + al(bf);
+    HIPCHK(hipEventSynchronize(pl->staging_free));      // the previous upload has left the staging buffer
+    pl->staging.reserve(total);
+    char* h = static_cast<char*>(pl->staging.p);
+    size_t o = 0;
+    auto put = [&](DevBuf& d, const void* src, size_t n) {
+        d.reserve(n);
+        if (n) {
+            std::memcpy(h + o, src, n);
+            HIPCHK(hipMemcpyAsync(d.p, h + o, n, hipMemcpyHostToDevice, st));
+        }
+        o += al(n);
+    };
+    put(pl->pitems, w.pitems.data(), bp);
+    put(pl->pentries, w.pentries.data(), be);
+    put(pl->qitems, w.qitems.data(), bq);
+    put(pl->qentries, w.qentries.data(), bqe);
+    put(pl->has_far, w.leaf_has_far.data(), bf);
+    HIPCHK(hipEventRecord(pl->staging_free, st));
+
+    // 3. CP + CC, then downward transfer
+    const int P = pl->P();
+    {
+        PhaseMark mark(pl, BLDTT_PH_CPCC, st);
+        launch_fill(pl->phihat.as<double>(), (int64_t)T.size() * P, 0.0, st);
+        launch_cp_cc(ks, deg, pl->qitems.as<DevQItem>(), (int)w.qitems.size(), pl->qentries.as<int32_t>(), dT,
+                     pl->dsrc(), dS, tab, pl->qhat.as<double>(), pl->phihat.as<double>(), st);
+    }
+    {
+        PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
+        for (int l = 1; l <= T.depth; ++l) {
+            int64_t b = pl->down_off[l], e = pl->down_off[l + 1];
+            launch_down_transfer(deg, pl->down_kids.as<int32_t>() + b, (int)(e - b), dT, tab,
+                                 pl->phihat.as<double>(), st);
+        }
+    }
+    // 4. PP + PC
+    {
+        PhaseMark mark(pl, BLDTT_PH_PPPC, st);
+        launch_pp_pc(ks, deg, pl->pitems.as<DevPItem>(), (int)w.pitems.size(), pl->pentries.as<int32_t>(),
+                     pl->dtgt(), pl->dsrc(), dS, tab, pl->qhat.as<double>(), pl->phi_tree.as<double>(), st);
+    }
+    // 5. leaves to targets, caller order
+    {
+        PhaseMark mark(pl, BLDTT_PH_DOWN_LEAF, st);
+        launch_down_leaf(deg, pl->pitems.as<DevPItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
+                         pl->dtgt(), dT, tab, pl->phihat.as<double>(), pl->phi_tree.as<double>(),
+                         pl->perm.as<int32_t>(), out, st);
+    }
+    if (pl->flags & BLDTT_PROFILE) pl->prof_pending = true;
+    if (pl->flags & BLDTT_SYNC) HIPCHK(hipStreamSynchronize(st));
+    pl->stats.compute_host_ms = now_ms() - t0;
+}
+
+void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
+    double t0 = now_ms();
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t M = p->M, N = p->N;
+    std::vector<double> hs[4], ht[3];
+    for (int k = 0; k < 4; ++k) hs[k].resize(N);
+    HIPCHK(hipMemcpy(hs[0].data(), p->sx, 8 * N, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hs[1].data(), p->sy, 8 * N, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hs[2].data(), p->sz, 8 * N, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hs[3].data(), p->q, 8 * N, hipMemcpyDeviceToHost));
+    if (!pl->aliased) {
+        for (int k = 0; k < 3; ++k) ht[k].resize(M);
+        HIPCHK(hipMemcpy(ht[0].data(), p->tx, 8 * M, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(ht[1].data(), p->ty, 8 * M, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(ht[2].data(), p->tz, 8 * M, hipMemcpyDeviceToHost));
+    }
+    std::vector<double> sxs[3], txs[3];
+    build_host(pl, ht[0].data(), ht[1].data(), ht[2].data(), hs[0].data(), hs[1].data(), hs[2].data(), hs[3].data(),
+               sxs, txs);
+    // charges in tree order
+    std::vector<double> qs(N);
+    for (int64_t i = 0; i < N; ++i) qs[i] = hs[3][pl->S.perm[i]];
+    upload(pl->sx, sxs[0]);
+    upload(pl->sy, sxs[1]);
+    upload(pl->sz, sxs[2]);
+    upload(pl->sq, qs);
+    upload_tree(pl->dS, pl->S);
+    if (!pl->aliased) {
+        upload(pl->tx, txs[0]);
+        upload(pl->ty, txs[1]);
+        upload(pl->tz, txs[2]);
+        upload_tree(pl->dTsep, pl->Tsep);
+    }
+    const Tree& T = pl->T();
+    std::vector<int32_t> perm(M);
+    for (int64_t i = 0; i < M; ++i) perm[i] = (int32_t)T.perm[i];
+    upload(pl->perm, perm);
+    // Chebyshev points of the 2nd kind, xi_k = cos(pi k / n) evaluated as
+    // sin(pi (n - 2k) / (2n)) (exactly antisymmetric), and weights (-1)^k delta_k.
+    std::vector<double> tab(32, 0.0);
+    const int n = pl->degree;
+    for (int k = 0; k <= n; ++k) {
+        tab[k] = std::sin(M_PI * (double)(n - 2 * k) / (double)(2 * n));
+        tab[16 + k] = (k % 2 ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
+    }
+    upload(pl->tab, tab);
+    std::vector<int32_t> leaves;
+    for (int64_t c = 0; c < pl->S.size(); ++c)
+        if (pl->S.is_leaf(c)) leaves.push_back((int32_t)c);
+    upload(pl->src_leaves, leaves);
+    pl->n_src_leaves = (int)leaves.size();
+    std::vector<int32_t> ids;
+    level_lists(pl->S, true, ids, pl->up_off);
+    upload(pl->up_parents, ids);
+    level_lists(T, false, ids, pl->down_off);
+    upload(pl->down_kids, ids);
+    const int P = pl->P();
+    pl->qhat.alloc(sizeof(double) * pl->S.size() * P);
+    pl->phihat.alloc(sizeof(double) * T.size() * P);
+    pl->phi_tree.alloc(sizeof(double) * M);
+    HIPCHK(hipEventCreateWithFlags(&pl->staging_free, hipEventDisableTiming));
+    if (pl->flags & BLDTT_PROFILE)
+        for (auto& e : pl->prof_ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(pl->staging_free, st));
+    fill_stats_tree(pl);
+    pl->stats.setup_ms = now_ms() - t0;
+}
+
+bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_param, double theta, int32_t degree,
+                     int64_t leaf_size, uint32_t flags) {
+    validate(p, kernel, theta, degree, leaf_size);
+    if (flags & (BLDTT_FP32_EVAL | BLDTT_LEARNED_DEGREE))
+        throw Error(BLDTT_EUNSUPPORTED, "flag not implemented in this build");
+    auto pl = std::make_unique<bldtt_plan>();
+    pl->kind = kernel;
+    pl->param = kernel_param;
+    pl->theta = theta;
+    pl->degree = degree;
+    pl->leaf = leaf_size;
+    pl->flags = flags;
+    pl->M = p->M;
+    pl->N = p->N;
+    pl->aliased = p->M == p->N && p->tx == p->sx && p->ty == p->sy && p->tz == p->sz;
+    return pl.release();
+}
+
+}  // namespace
+
+extern "C" {
+
+int bldtt_setup(bldtt_plan** out, const bldtt_particles* p, int32_t kernel, double kernel_param, double theta,
+                int32_t degree, int64_t leaf_size, uint32_t flags, void* hip_stream) {
+    if (!out) {
+        set_error("out is NULL");
+        return BLDTT_EINVAL;
+    }
+    *out = nullptr;
+    return guarded([&] {
+        std::unique_ptr<bldtt_plan> pl(new_plan(p, kernel, kernel_param, theta, degree, leaf_size, flags));
+        setup_device(pl.get(), p, static_cast<hipStream_t>(hip_stream));
+        *out = pl.release();
+    });
+}
+
+int bldtt_setup_host(bldtt_plan** out, const bldtt_particles* p, int32_t kernel, double kernel_param,
+                     double theta, int32_t degree, int64_t leaf_size, uint32_t flags) {
+    if (!out) {
+        set_error("out is NULL");
+        return BLDTT_EINVAL;
+    }
+    *out = nullptr;
+    return guarded([&] {
+        std::unique_ptr<bldtt_plan> pl(new_plan(p, kernel, kernel_param, theta, degree, leaf_size, flags));
+        pl->host_only = true;
+        double t0 = now_ms();
+        std::vector<double> sxs[3], txs[3];
+        build_host(pl.get(), p->tx, p->ty, p->tz, p->sx, p->sy, p->sz, p->q, sxs, txs);
+        fill_stats_tree(pl.get());
+        pl->stats.setup_ms = now_ms() - t0;
+        *out = pl.release();
+    });
+}
+
+int bldtt_traverse_host(bldtt_plan* plan) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return BLDTT_EINVAL;
+    }
+    return guarded([&] {
+        do_traverse(plan);
+        pack_work(plan->T(), plan->S, plan->lists, plan->degree, kTile, kPTile, plan->work);
+        for (int k = 0; k < 4; ++k) plan->stats.interactions[k] = plan->work.interactions[k];
+    });
+}
+
+int bldtt_compute(bldtt_plan* plan, double* potentials, void* hip_stream) {
+    if (!plan || !potentials) {
+        set_error("plan or potentials is NULL");
+        return BLDTT_EINVAL;
+    }
+    if (plan->host_only) {
+        set_error("bldtt_compute on a host-only plan");
+        return BLDTT_ESTATE;
+    }
+    return guarded([&] { compute(plan, potentials, static_cast<hipStream_t>(hip_stream)); });
+}
+
+int bldtt_destroy(bldtt_plan* plan) {
+    if (!plan) return BLDTT_OK;
+    return guarded([&] {
+        if (!plan->host_only) (void)hipDeviceSynchronize();
+        delete plan;
+    });
+}
+
+const char* bldtt_last_error(void) { return g_last_error.c_str(); }
+
+int bldtt_get_tree(const bldtt_plan* plan, int which, bldtt_tree_view* out) {
+    if (!plan || !out || (which != 0 && which != 1)) {
+        set_error("bad argument to bldtt_get_tree");
+        return BLDTT_EINVAL;
+    }
+    const Tree& t = which ? plan->S : plan->T();
+    out->n_clusters = t.size();
+    out->n_particles = t.n_particles;
+    out->depth = t.depth;
+    out->lo = t.lo.data();
+    out->hi = t.hi.data();
+    out->center = t.center.data();
+    out->radius = t.radius.data();
+    out->begin = t.begin.data();
+    out->count = t.count.data();
+    out->parent = t.parent.data();
+    out->child = t.child.data();
+    out->perm = t.perm.data();
+    out->level = t.level.data();
+    out->nchild = t.nchild.data();
+    return BLDTT_OK;
+}
+
+int bldtt_get_lists(const bldtt_plan* plan, int type, const int64_t** tc, const int64_t** sc, int64_t* n) {
+    if (!plan || !tc || !sc || !n || type < 0 || type > 3) {
+        set_error("bad argument to bldtt_get_lists");
+        return BLDTT_EINVAL;
+    }
+    if (!plan->have_lists) {
+        set_error("no traversal has run on this plan");
+        return BLDTT_ESTATE;
+    }
+    *tc = plan->lists.tc[type].data();
+    *sc = plan->lists.sc[type].data();
+    *n = (int64_t)plan->lists.tc[type].size();
+    return BLDTT_OK;
+}
+
+int bldtt_get_qhat(const bldtt_plan* plan, double* host_out) {
+    if (!plan || !host_out) {
+        set_error("bad argument to bldtt_get_qhat");
+        return BLDTT_EINVAL;
+    }
+    if (plan->host_only) {
+        set_error("host-only plan has no device state");
+        return BLDTT_ESTATE;
+    }
+    return guarded([&] {
+        HIPCHK(hipMemcpy(host_out, plan->qhat.p, sizeof(double) * plan->S.size() * plan->P(), hipMemcpyDeviceToHost));
+    });
+}
+
+int bldtt_get_phihat(const bldtt_plan* plan, double* host_out) {
+    if (!plan || !host_out) {
+        set_error("bad argument to bldtt_get_phihat");
+        return BLDTT_EINVAL;
+    }
+    if (plan->host_only) {
+        set_error("host-only plan has no device state");
+        return BLDTT_ESTATE;
+    }
+    return guarded([&] {
+        HIPCHK(hipMemcpy(host_out, plan->phihat.p, sizeof(double) * plan->T().size() * plan->P(),
+                         hipMemcpyDeviceToHost));
+    });
+}
+
+int bldtt_get_stats(bldtt_plan* plan, bldtt_stats* out) {
+    if (!plan || !out) {
+        set_error("bad argument to bldtt_get_stats");
+        return BLDTT_EINVAL;
+    }
+    return guarded([&] {
+        if (!plan->host_only) collect_profile(plan);
+        *out = plan->stats;
+    });
+}
+
+int bldtt_direct_sum(int32_t kernel, double kernel_param, int64_t M, const double* tx, const double* ty,
+                     const double* tz, int64_t N, const double* sx, const double* sy, const double* sz,
+                     const double* q, int64_t nsel, const int64_t* sel, double* out, void* hip_stream) {
+    if (M < 1 || N < 1 || !tx || !ty || !tz || !sx || !sy || !sz || !q || !out || (sel && nsel < 0)) {
+        set_error("bad argument to bldtt_direct_sum");
+        return BLDTT_EINVAL;
+    }
+    if (kernel != BLDTT_COULOMB && kernel != BLDTT_YUKAWA && kernel != BLDTT_OSCILLATORY &&
+        kernel != BLDTT_REGCOULOMB && kernel != BLDTT_POLY_TEST) {
+        set_error("unknown kernel");
+        return BLDTT_EINVAL;
+    }
+    if (sel && nsel > INT32_MAX) {
+        set_error("too many selected targets");
+        return BLDTT_EINVAL;
+    }
+    return guarded([&] {
+        launch_direct(KernelSpec{kernel, kernel_param}, sel ? nsel : M, sel, tx, ty, tz, N, sx, sy, sz, q, out,
+                      static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+const char* bldtt_version(void) { return "bldtt-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

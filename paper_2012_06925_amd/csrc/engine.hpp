@@ -1,0 +1,86 @@
+// engine.hpp -- host side of the BLDTT library: trees, traversal, work packing.
+//
+// Everything here is plain C++17 on the host.  The files that include it are
+// compiled with -ffp-contract=off so every floating point expression of the
+// tree build and of the MAC rounds exactly as written (the trees and lists
+// are compared bit for bit against an independent implementation).
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace bldtt {
+
+constexpr int kMaxDegree = 12;
+
+// Error carrying a bldtt_status code across the C++ parts of the library.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// ---------------------------------------------------------------------------
+// Thread pool: run(n, f) calls f(0..n-1) across the workers and the caller.
+// ---------------------------------------------------------------------------
+int num_threads();
+void parallel_run(int64_t ntasks, const std::function<void(int64_t)>& fn);
+
+// ---------------------------------------------------------------------------
+// Tree of clusters (Sec. 2.3), numbered in depth-first preorder.
+// ---------------------------------------------------------------------------
+struct Tree {
+    int64_t n_particles = 0;
+    int32_t depth = 0;
+    std::vector<double> lo, hi, center;       // 3 per cluster (x, y, z)
+    std::vector<double> radius;               // half box diagonal
+    std::vector<int64_t> begin, count, parent;
+    std::vector<int64_t> child;               // 8 per cluster, -1 past nchild
+    std::vector<int32_t> level, nchild;
+    std::vector<int64_t> perm;                // perm[p] = caller index at tree position p
+    int64_t size() const { return (int64_t)radius.size(); }
+    bool is_leaf(int64_t c) const { return nchild[c] == 0; }
+};
+
+// Build the tree of n particles (caller order x, y, z) with at most `leaf`
+// particles per leaf.  On return xs, ys, zs hold the coordinates in tree order.
+void build_tree(int64_t n, const double* x, const double* y, const double* z, int64_t leaf, Tree& t,
+                std::vector<double>& xs, std::vector<double>& ys, std::vector<double>& zs);
+
+// ---------------------------------------------------------------------------
+// Dual tree traversal (Algorithm 2) into the four interaction lists.
+// ---------------------------------------------------------------------------
+enum { PP = 0, PC = 1, CP = 2, CC = 3 };
+
+struct Lists {
+    std::vector<int64_t> tc[4], sc[4];
+    void clear() { for (int k = 0; k < 4; ++k) { tc[k].clear(); sc[k].clear(); } }
+};
+
+void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out);
+
+// ---------------------------------------------------------------------------
+// Work items for the device (see kernels.hip for their consumers).
+// ---------------------------------------------------------------------------
+// Entry codes: (source cluster << 2) | kind.
+enum { E_PP = 0, E_PP_GUARD = 1, E_PC = 2 };   // particle-target entries
+enum { E_CP = 0, E_CC = 1 };                   // proxy-target entries
+
+struct PItem { int32_t tb, tn, eb, ee, leaf; }; // targets [tb, tb+tn) of target leaf `leaf`, entries [eb, ee)
+struct QItem { int32_t tc, lb, ln, eb, ee; };   // cluster tc, proxies [lb, lb+ln), entries
+
+struct Work {
+    std::vector<int32_t> pentries;              // particle-target entries, grouped per target leaf
+    std::vector<PItem> pitems;
+    std::vector<int32_t> qentries;              // proxy-target entries, grouped per target cluster
+    std::vector<QItem> qitems;
+    std::vector<uint8_t> leaf_has_far;          // per target cluster: chain has CP/CC entries
+    double interactions[4] = {0, 0, 0, 0};
+};
+
+// tile: targets per particle item; ptile: proxies per proxy item.
+void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w);
+
+}  // namespace bldtt

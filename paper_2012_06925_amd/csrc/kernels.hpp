@@ -1,0 +1,70 @@
+// kernels.hpp -- launch interface of the device kernels (kernels.hip).
+//
+// Device data layout (all in HBM, owned by a plan):
+//   particles in tree order, structure of arrays: x[], y[], z[] (and q[] for sources)
+//   cluster boxes: box[6*c + 0..2] = lo (x,y,z), box[6*c + 3..5] = hi
+//   cluster begin[], count[], nchild[], child[8*c + k] (int32)
+//   node table tab[0..15] = Chebyshev points xi_k, tab[16..31] = weights w_k
+//   proxy arrays qhat[c * P + k], phihat[c * P + k], P = (n+1)^3,
+//   flat proxy index k = k1 + (n+1) k2 + (n+1)^2 k3
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bldtt {
+
+struct DevTree {
+    const double* box;
+    const int32_t* begin;
+    const int32_t* count;
+    const int32_t* nchild;
+    const int32_t* child;
+    const int32_t* parent;
+};
+
+struct DevParticles {
+    const double* x;
+    const double* y;
+    const double* z;
+    const double* q;      // null for targets
+};
+
+// Item layouts shared with the host packer (engine.hpp): plain int32 records.
+struct DevPItem { int32_t tb, tn, eb, ee, leaf; };
+struct DevQItem { int32_t tc, lb, ln, eb, ee; };
+
+struct KernelSpec {
+    int kind;
+    double param;
+};
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+
+void launch_up_leaf(int degree, const int32_t* leaves, int n_leaves, DevTree S, DevParticles src,
+                    const double* tab, double* qhat, hipStream_t st);
+
+void launch_up_transfer(int degree, const int32_t* parents, int n_parents, DevTree S, const double* tab,
+                        double* qhat, hipStream_t st);
+
+void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T, const double* tab,
+                          double* phihat, hipStream_t st);
+
+void launch_pp_pc(KernelSpec k, int degree, const DevPItem* items, int n_items, const int32_t* entries,
+                  DevParticles tgt, DevParticles src, DevTree S, const double* tab, const double* qhat,
+                  double* phi_tree, hipStream_t st);
+
+void launch_cp_cc(KernelSpec k, int degree, const DevQItem* items, int n_items, const int32_t* entries,
+                  DevTree T, DevParticles src, DevTree S, const double* tab, const double* qhat,
+                  double* phihat, hipStream_t st);
+
+void launch_down_leaf(int degree, const DevPItem* items, int n_items, const uint8_t* has_far,
+                      DevParticles tgt, DevTree T, const double* tab, const double* phihat,
+                      const double* phi_tree, const int32_t* perm, double* out, hipStream_t st);
+
+void launch_direct(KernelSpec k, int64_t nsel, const int64_t* sel, const double* tx, const double* ty,
+                   const double* tz, int64_t N, const double* sx, const double* sy, const double* sz,
+                   const double* q, double* out, hipStream_t st);
+
+}  // namespace bldtt

@@ -1,0 +1,205 @@
+// traverse.cpp -- dual tree traversal (Algorithm 2) and packing of the four
+// interaction lists into device work items.
+//
+// MAC (Sec. 2.6): clusters are well separated when (r_t + r_s) / R < theta,
+// r = half the box diagonal, R = distance of the box midpoints; R == 0 never
+// separates.  Separated pairs interact by CC when both clusters hold more
+// than n_p = (n+1)^3 particles, by CP when only the target does, by PC when
+// only the source does, and by PP otherwise.  A pair that is not separated
+// interacts by PP when both are leaves; otherwise the traversal recurses into
+// the children of the target when the source is a leaf, of the source when
+// the target is a leaf, and else of the larger cluster by particle count,
+// descending into the source on a tie.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "engine.hpp"
+
+namespace bldtt {
+namespace {
+
+struct Ctx {
+    const Tree& T;
+    const Tree& S;
+    double theta;
+    int64_t np;
+    bool pp_cc_only;
+};
+
+// One step of Algorithm 2.  Returns the list type for a terminal pair, or -1
+// after appending the child pairs to `kids`.
+template <class Push>
+int step(const Ctx& x, int64_t t, int64_t s, Push&& push_pair) {
+    const Tree& T = x.T;
+    const Tree& S = x.S;
+    double dx = T.center[3 * t] - S.center[3 * s];
+    double dy = T.center[3 * t + 1] - S.center[3 * s + 1];
+    double dz = T.center[3 * t + 2] - S.center[3 * s + 2];
+    double R = std::sqrt((dx * dx + dy * dy) + dz * dz);
+    bool sep = R > 0.0 && (T.radius[t] + S.radius[s]) / R < x.theta;
+    int64_t ct = T.count[t], cs = S.count[s];
+    if (sep) {
+        if (ct > x.np && cs > x.np) return CC;
+        if (x.pp_cc_only) return PP;
+        if (ct > x.np) return CP;
+        if (cs > x.np) return PC;
+        return PP;
+    }
+    bool tl = T.is_leaf(t), sl = S.is_leaf(s);
+    if (tl && sl) return PP;
+    bool into_target = sl ? true : (tl ? false : (cs < ct));
+    if (into_target) {
+        for (int k = 0; k < T.nchild[t]; ++k) push_pair(T.child[8 * t + k], s);
+    } else {
+        for (int k = 0; k < S.nchild[s]; ++k) push_pair(t, S.child[8 * s + k]);
+    }
+    return -1;
+}
+
+void recurse(const Ctx& x, int64_t t, int64_t s, Lists& out) {
+    int ty = step(x, t, s, [&](int64_t a, int64_t b) { recurse(x, a, b, out); });
+    if (ty >= 0) {
+        out.tc[ty].push_back(t);
+        out.sc[ty].push_back(s);
+    }
+}
+
+}  // namespace
+
+void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out) {
+    Ctx x{T, S, theta, (int64_t)(degree + 1) * (degree + 1) * (degree + 1), pp_cc_only};
+    out.clear();
+    // Breadth-first expansion until there is enough independent work, then
+    // depth-first recursion per frontier pair on all threads.  Per-pair lists
+    // are concatenated in frontier order, so the output is deterministic.
+    std::vector<std::pair<int64_t, int64_t>> cur{{0, 0}}, nxt;
+    const size_t want = (size_t)64 * num_threads();
+    while (!cur.empty() && cur.size() < want) {
+        nxt.clear();
+        for (auto& pr : cur) {
+            int ty = step(x, pr.first, pr.second, [&](int64_t a, int64_t b) { nxt.emplace_back(a, b); });
+            if (ty >= 0) {
+                out.tc[ty].push_back(pr.first);
+                out.sc[ty].push_back(pr.second);
+            }
+        }
+        cur.swap(nxt);
+    }
+    std::vector<Lists> part(cur.size());
+    parallel_run((int64_t)cur.size(), [&](int64_t i) { recurse(x, cur[i].first, cur[i].second, part[i]); });
+    for (int k = 0; k < 4; ++k) {
+        size_t tot = out.tc[k].size();
+        for (auto& p : part) tot += p.tc[k].size();
+        out.tc[k].reserve(tot);
+        out.sc[k].reserve(tot);
+        for (auto& p : part) {
+            out.tc[k].insert(out.tc[k].end(), p.tc[k].begin(), p.tc[k].end());
+            out.sc[k].insert(out.sc[k].end(), p.sc[k].begin(), p.sc[k].end());
+        }
+    }
+}
+
+namespace {
+
+// CSR of the entries of some types, grouped by target cluster in list order.
+struct ByTarget {
+    std::vector<int64_t> off;      // n_clusters + 1
+    std::vector<int64_t> code;     // (source cluster << 2) | type
+};
+
+ByTarget group(const Tree& T, const Lists& L, int t0, int t1) {
+    ByTarget g;
+    int64_t nc = T.size();
+    g.off.assign(nc + 1, 0);
+    for (int ty = t0; ty <= t1; ++ty)
+        for (int64_t tc : L.tc[ty]) g.off[tc + 1]++;
+    for (int64_t c = 0; c < nc; ++c) g.off[c + 1] += g.off[c];
+    g.code.resize(g.off[nc]);
+    std::vector<int64_t> fill(g.off.begin(), g.off.end() - 1);
+    for (int ty = t0; ty <= t1; ++ty)
+        for (size_t e = 0; e < L.tc[ty].size(); ++e)
+            g.code[fill[L.tc[ty][e]]++] = (L.sc[ty][e] << 2) | ty;
+    return g;
+}
+
+bool boxes_touch(const Tree& T, int64_t t, const Tree& S, int64_t s) {
+    for (int d = 0; d < 3; ++d)
+        if (T.hi[3 * t + d] < S.lo[3 * s + d] || S.hi[3 * s + d] < T.lo[3 * t + d]) return false;
+    return true;
+}
+
+}  // namespace
+
+void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w) {
+    const int64_t np = (int64_t)(degree + 1) * (degree + 1) * (degree + 1);
+    w = Work();
+    for (int ty = 0; ty < 4; ++ty) {
+        double acc = 0.0;
+        for (size_t e = 0; e < L.tc[ty].size(); ++e) {
+            double ct = ty == PP || ty == PC ? (double)T.count[L.tc[ty][e]] : (double)np;
+            double cs = ty == PP || ty == CP ? (double)S.count[L.sc[ty][e]] : (double)np;
+            acc += ct * cs;
+        }
+        w.interactions[ty] = acc;
+    }
+
+    ByTarget part = group(T, L, PP, PC);
+    ByTarget prox = group(T, L, CP, CC);
+    const int64_t nc = T.size();
+
+    // Particle-target work: per target leaf, the PP/PC entries of the leaf and of
+    // every ancestor (each leaf owns its targets, so no two items share an output).
+    std::vector<std::pair<double, PItem>> items;
+    w.leaf_has_far.assign(nc, 0);
+    for (int64_t leaf = 0; leaf < nc; ++leaf) {
+        if (!T.is_leaf(leaf)) continue;
+        int64_t eb = (int64_t)w.pentries.size();
+        double src = 0.0;
+        bool far = false;
+        for (int64_t c = leaf; c >= 0; c = T.parent[c]) {
+            if (prox.off[c + 1] > prox.off[c]) far = true;
+            for (int64_t e = part.off[c]; e < part.off[c + 1]; ++e) {
+                int64_t sc = part.code[e] >> 2;
+                int ty = (int)(part.code[e] & 3);
+                int kind = ty == PC ? E_PC : (boxes_touch(T, leaf, S, sc) ? E_PP_GUARD : E_PP);
+                w.pentries.push_back((int32_t)((sc << 2) | kind));
+                src += ty == PC ? (double)np : (double)S.count[sc];
+            }
+        }
+        w.leaf_has_far[leaf] = far;
+        int64_t ee = (int64_t)w.pentries.size();
+        for (int64_t tb = T.begin[leaf]; tb < T.begin[leaf] + T.count[leaf]; tb += tile) {
+            int64_t tn = std::min<int64_t>(tile, T.begin[leaf] + T.count[leaf] - tb);
+            items.push_back({src * (double)tn, PItem{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee, (int32_t)leaf}});
+        }
+    }
+    // Longest items first: the tail of the grid is then made of short items.
+    std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    w.pitems.reserve(items.size());
+    for (auto& it : items) w.pitems.push_back(it.second);
+
+    // Proxy-target work: per target cluster with CP/CC entries, tiles of its proxies.
+    std::vector<std::pair<double, QItem>> qitems;
+    for (int64_t c = 0; c < nc; ++c) {
+        if (prox.off[c + 1] == prox.off[c]) continue;
+        int64_t eb = (int64_t)w.qentries.size();
+        double src = 0.0;
+        for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) {
+            int64_t sc = prox.code[e] >> 2;
+            int ty = (int)(prox.code[e] & 3);
+            w.qentries.push_back((int32_t)((sc << 2) | (ty == CC ? E_CC : E_CP)));
+            src += ty == CC ? (double)np : (double)S.count[sc];
+        }
+        int64_t ee = (int64_t)w.qentries.size();
+        for (int64_t lb = 0; lb < np; lb += ptile) {
+            int64_t ln = std::min<int64_t>(ptile, np - lb);
+            qitems.push_back({src * (double)ln, QItem{(int32_t)c, (int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee}});
+        }
+    }
+    std::stable_sort(qitems.begin(), qitems.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    w.qitems.reserve(qitems.size());
+    for (auto& it : qitems) w.qitems.push_back(it.second);
+}
+
+}  // namespace bldtt

@@ -1,0 +1,218 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: trees and lists bit-exact; proxy charges and proxy potentials per
+cluster within 1e-13 of the largest magnitude; plain-FP64 potentials within
+1e-12 relative l2 of the oracle's BLDTT.  The error against the direct sum is
+printed for every case.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import core  # noqa: E402
+from paper_2012_06925_amd import inputs  # noqa: E402
+
+PARITY = 1e-12
+PROXY = 1e-13
+
+
+def _api():
+    from paper_2012_06925_amd import api
+    return api
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_plan(tgt, src, same, **kw):
+    api = _api()
+    s = [dev(a) for a in (src.x, src.y, src.z, src.q)]
+    t = None if same else [dev(a) for a in (tgt.x, tgt.y, tgt.z)]
+    plan = api.Plan(t, s, **kw)
+    phi = plan.compute()
+    torch.cuda.synchronize()
+    return plan, phi.cpu().numpy(), (t, s)
+
+
+def _same_lists(la, lb):
+    for k in ("PP", "PC", "CP", "CC"):
+        assert sorted(zip(*la[k])) == sorted(zip(*lb[k])), k
+
+
+def _proxy_close(a, b, what):
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    assert err < PROXY, f"{what}: {err:.3e}"
+
+
+def full_parity(tgt, src, same, kernel="coulomb", theta=0.7, degree=6, leaf=500, check_proxies=True):
+    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf)
+    run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same)
+    ref = run.run_all()
+    for which in (0, 1):
+        a, b = plan.tree(which), run.tree(which)
+        for k in a:
+            assert np.array_equal(a[k], b[k]) if k != "depth" else a[k] == b[k], k
+    _same_lists(plan.lists(), run.lists())
+    if check_proxies:
+        _proxy_close(plan.qhat(), run.qhat(), "qhat")
+        _proxy_close(plan.phihat(), run.phihat(), "phihat")
+    err = core.rel_l2(phi, ref)
+    ds = core.direct_sum(tgt, src, kernel=kernel) if tgt.n * src.n <= 4e8 else None
+    e_ds = core.rel_l2(phi, ds) if ds is not None else float("nan")
+    print(f"\n  M={tgt.n} N={src.n} {kernel} theta={theta} n={degree} leaf={leaf} "
+          f"entries={plan.stats()['n_entries']} gpu-vs-oracle={err:.2e} err-vs-direct={e_ds:.2e}")
+    assert err < PARITY, err
+    plan.close()
+    return phi, ref, ds
+
+
+def test_direct_sum_kernel_vs_oracle():
+    api = _api()
+    t, s = inputs.unequal_sets(700, "sphere", 5000, "gaussian", seed=41)
+    tt = [dev(a) for a in (t.x, t.y, t.z)]
+    ss = [dev(a) for a in (s.x, s.y, s.z, s.q)]
+    for kernel in ("coulomb", "yukawa", "oscillatory", "regcoulomb", "poly"):
+        got = api.direct_sum(tt, ss, kernel=kernel).cpu().numpy()
+        ref = core.direct_sum(t, s, kernel=kernel)
+        assert core.rel_l2(got, ref) < 1e-14, kernel
+    sel = np.array([3, 0, 699, 42], dtype=np.int64)
+    got = api.direct_sum(tt, ss, sel=dev(sel)).cpu().numpy()
+    assert core.rel_l2(got, core.direct_sum(t, s, sel=sel)) < 1e-14
+    # self term skipped when targets = sources
+    p = inputs.particles(3000, seed=42)
+    pp = [dev(a) for a in (p.x, p.y, p.z, p.q)]
+    got = api.direct_sum(pp[:3], pp).cpu().numpy()
+    assert core.rel_l2(got, core.direct_sum(p, p)) < 1e-14
+
+
+def test_cube1e4_config_parity():
+    # 1E4 uniform, targets = sources, Coulomb, theta 0.7, n 6, leaf 500
+    p = inputs.particles(10_000, "uniform", seed=inputs.workload_seed("cube1e4"))
+    phi, ref, ds = full_parity(p, p, True, theta=0.7, degree=6, leaf=500)
+    assert core.rel_l2(phi, ds) < 1e-5
+
+
+@pytest.mark.parametrize("kernel", ["coulomb", "yukawa", "oscillatory", "regcoulomb"])
+def test_kernels_unequal_sets(kernel):
+    t, s = inputs.unequal_sets(6000, "sphere", 9000, "gaussian", seed=43)
+    full_parity(t, s, False, kernel=kernel, theta=0.8, degree=4, leaf=64)
+
+
+def test_polynomial_kernel_exact_on_gpu():
+    t, s = inputs.unequal_sets(4000, "uniform", 6000, "gaussian", seed=44)
+    phi, ref, ds = full_parity(t, s, False, kernel="poly", theta=0.9, degree=3, leaf=40)
+    assert core.rel_l2(phi, ds) < 1e-12
+
+
+@pytest.mark.parametrize("degree", [1, 2, 5, 9, 12])
+def test_every_degree_template(degree):
+    p = inputs.particles(12_000, "gaussian", seed=45 + degree)
+    full_parity(p, p, True, theta=0.8, degree=degree, leaf=100)
+
+
+def test_ragged_tiles_and_ablation():
+    # leaf 300: 256-target tiles plus ragged tails; PP/CC-only traversal variant
+    api = _api()
+    p = inputs.particles(9000, "uniform", seed=46)
+    full_parity(p, p, True, theta=0.75, degree=3, leaf=300)
+    s = [dev(a) for a in (p.x, p.y, p.z, p.q)]
+    plan = api.Plan(None, s, theta=0.75, degree=3, leaf=300, flags=16)
+    phi = plan.compute().cpu().numpy()
+    ref = core.bldtt(p, p, theta=0.75, degree=3, leaf=300, pp_cc_only=True)
+    assert core.rel_l2(phi, ref) < PARITY
+    L = plan.lists()
+    assert len(L["PC"][0]) == 0 and len(L["CP"][0]) == 0
+
+
+def test_far_target_blob_root_interactions():
+    # targets far from the sources: the target root takes CC entries, the
+    # downward pass carries them through every level
+    t, s = inputs.unequal_sets(5000, "sphere", 7000, "uniform", seed=47)
+    t = inputs.ParticleSet(0.5 * t.x + 4.0, 0.5 * t.y, 0.5 * t.z)
+    full_parity(t, s, False, theta=0.7, degree=4, leaf=60)
+
+
+def test_degenerate_inputs():
+    rng = np.random.default_rng(48)
+    n = 2500
+    cases = {
+        "identical": (np.full(n, 0.3), np.full(n, -0.2), np.full(n, 0.7)),
+        "collinear": (rng.uniform(-1, 1, n), np.full(n, 0.1), np.full(n, 0.1)),
+        "coplanar": (rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), np.zeros(n)),
+        "duplicates": tuple(np.repeat(rng.uniform(-1, 1, n // 5), 5) for _ in range(3)),
+    }
+    for name, (x, y, z) in cases.items():
+        q = rng.uniform(-1, 1, x.shape[0])
+        p = inputs.ParticleSet(x.copy(), y.copy(), z.copy(), q)
+        full_parity(p, p, True, theta=0.8, degree=2, leaf=20)
+
+
+def test_tiny_sets_and_single_leaf():
+    one = inputs.ParticleSet(np.array([0.1]), np.array([0.2]), np.array([0.3]), np.array([0.5]))
+    two = inputs.ParticleSet(np.array([1.0, 2.0]), np.array([0.0, 0.5]), np.array([0.0, 0.0]), np.array([1.0, -2.0]))
+    for t, s, same in ((one, one, True), (one, two, False), (two, one, False), (two, two, True)):
+        full_parity(t, s, same, theta=0.5, degree=2, leaf=1, check_proxies=False)
+    # leaf >= N: everything is one PP pair, equal to the direct sum
+    p = inputs.particles(3000, seed=49)
+    phi, ref, ds = full_parity(p, p, True, theta=0.7, degree=4, leaf=5000)
+    assert core.rel_l2(phi, ds) < 1e-14
+
+
+def test_determinism_and_recompute():
+    p = inputs.particles(30_000, "gaussian", seed=50)
+    plan, phi1, _ = gpu_plan(p, p, True, theta=0.7, degree=5, leaf=200)
+    phi2 = plan.compute().cpu().numpy()
+    phi3 = plan.compute().cpu().numpy()
+    assert np.array_equal(phi1, phi2) and np.array_equal(phi2, phi3)
+
+
+def test_caller_stream_is_used():
+    api = _api()
+    p = inputs.particles(20_000, seed=51)
+    s = [dev(a) for a in (p.x, p.y, p.z, p.q)]
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan = api.Plan(None, s, theta=0.7, degree=4, leaf=200, stream=st)
+        out = torch.empty(p.n, dtype=torch.float64, device="cuda")
+        plan.compute(out, stream=st)
+    st.synchronize()
+    ref = core.bldtt(p, p, theta=0.7, degree=4, leaf=200)
+    assert core.rel_l2(out.cpu().numpy(), ref) < PARITY
+
+
+def _sampled_parity(tgt, src, same, kernel, theta, degree, leaf, n_leaves=3, n_random=150, seed=0):
+    """Full-size parity on every target of a few leaves plus random targets."""
+    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf)
+    run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same)
+    run.traverse()
+    _same_lists(plan.lists(), run.lists())
+    run.upward()
+    tree = run.tree(0)
+    rng = np.random.default_rng(seed)
+    leaves = np.flatnonzero(tree["nchild"] == 0)
+    pick = rng.choice(leaves, size=min(n_leaves, leaves.size), replace=False)
+    sel = [tree["perm"][tree["begin"][c]:tree["begin"][c] + tree["count"][c]] for c in pick]
+    sel.append(rng.choice(tgt.n, size=n_random, replace=False))
+    sel = np.unique(np.concatenate(sel))
+    ref = run.eval_targets(sel)
+    err = core.rel_l2(phi[sel], ref)
+    print(f"\n  sampled parity M={tgt.n} N={src.n} {kernel} targets={sel.size} gpu-vs-oracle={err:.2e} "
+          f"stats={plan.stats()}")
+    assert err < PARITY, err
+    plan.close()
+
+
+def test_cube1e6_config_sampled():
+    # 1E6 uniform, theta 0.8, n 8, leaf 2000
+    p = inputs.particles(1_000_000, "uniform", seed=inputs.workload_seed("cube1e6"))
+    _sampled_parity(p, p, True, "coulomb", 0.8, 8, 2000, seed=1)
+
+
+def test_sphere_targets_gaussian_sources_yukawa_sampled():
+    # the unequal Yukawa workload's shape at 1/10 size: 2E5 sphere targets, 1E6 Gaussian sources
+    t, s = inputs.unequal_sets(200_000, "sphere", 1_000_000, "gaussian", seed=inputs.workload_seed("sphere2e6_gauss1e7"))
+    _sampled_parity(t, s, False, "yukawa", 0.7, 8, 2000, seed=2)
