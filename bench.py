@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particles/s (compute phase) at rel L2 err 1e-6, plain vs tuned BLDTT, N=1E7"
 FP64_VALU_PEAK = 78.6          # TFLOP/s, MI355X vector FP64
+FP32_VALU_PEAK = 157.3         # TFLOP/s, MI355X vector FP32 (packed); unpacked FP32 issues at the FP64 rate
 FLOPS_PER_EVAL = {"coulomb": 11, "yukawa": 15, "oscillatory": 15, "regcoulomb": 12, "poly": 8}
 
 
@@ -65,6 +66,38 @@ def cpu_baseline(args, wl) -> dict:
             "phase_s": {k: round(float(v), 4) for k, v in run.times().items()}}
 
 
+def sweep(args, wl, M, seed, src, p, dev) -> int:
+    """Time the plain FP64 method over a (theta, degree) grid at the workload's leaf size."""
+    import torch
+    from paper_2012_06925_amd import api, inputs
+    sel = inputs.error_sample(M, seed, fraction=1e-3, minimum=min(M, 1000))
+    ds = api.direct_sum(src[:3], src, kernel=wl["kernel"], sel=torch.from_numpy(sel).to(dev)).cpu().numpy()
+    out = torch.empty(M, dtype=torch.float64, device=dev)
+    rows = []
+    for th in [float(x) for x in args.sweep_thetas.split(",")]:
+        for n in [int(x) for x in args.sweep_degrees.split(",")]:
+            plan = api.Plan(None, src, kernel=wl["kernel"], theta=th, degree=n, leaf=args.leaf)
+            plan.compute(out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.compute(out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            phi = out.cpu().numpy()
+            err = float(np.sqrt(np.sum((phi[sel] - ds) ** 2) / np.sum(ds ** 2)))
+            row = {"theta": th, "degree": n, "ms": round(ms, 2), "err": err, "particles_per_s": M / (ms * 1e-3),
+                   "interactions": plan.stats()["interactions"]}
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            plan.close()
+    ok = [r for r in rows if r["err"] <= 1e-6]
+    best = min(ok, key=lambda r: r["ms"]) if ok else None
+    print(json.dumps({"sweep": args.workload, "M": M, "leaf": args.leaf, "mode": "plain-fp64", "best": best,
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +111,13 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--fp32", action="store_true", help="FP32 kernel evaluation with FP64 accumulation")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every (theta, degree) of the grid below and report the fastest with error <= 1e-6")
+    ap.add_argument("--sweep-thetas", default="0.5,0.6,0.7,0.8,0.9")
+    ap.add_argument("--sweep-degrees", default="4,5,6,7,8,9,10")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration under rocprofv3)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,15 +137,26 @@ def main() -> int:
     seed = inputs.workload_seed(args.workload)
     dev = torch.device("cuda:0")
 
+    if args.copy_calib_mib:
+        a = torch.empty(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.copy_calib_mib} MiB done", file=sys.stderr, flush=True)
+        del a, b
     print(f"[bench] generating {M} {wl['dist']} particles", file=sys.stderr, flush=True)
     p = inputs.particles(M, wl["dist"], seed=seed)
     src = [torch.from_numpy(a).to(dev) for a in (p.x, p.y, p.z, p.q)]
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    if args.sweep:
+        return sweep(args, wl, M, seed, src, p, dev)
     t0 = time.perf_counter()
+    flags = _lib.PROFILE | (_lib.FP32_EVAL if args.fp32 else 0)
     plan = api.Plan(None, src, kernel=wl["kernel"], theta=args.theta, degree=args.degree, leaf=args.leaf,
-                    flags=_lib.PROFILE)
+                    flags=flags)
     setup_ms = (time.perf_counter() - t0) * 1e3
     print(f"[bench] setup {setup_ms:.1f} ms", file=sys.stderr, flush=True)
     out = torch.empty(M, dtype=torch.float64, device=dev)
@@ -151,8 +202,9 @@ def main() -> int:
     dom = max(("pp_pc", "cp_cc"), key=lambda k: phase[k])
     achieved = phase_work[dom] / (phase[dom] * 1e-3) / 1e12
     traffic = traffic_for(dom, 1)
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP64_VALU_PEAK, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_VALU_PEAK, 4), "traffic": traffic,
+    peak = FP32_VALU_PEAK if args.fp32 else FP64_VALU_PEAK
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic,
             "flops_per_launch": phase_work[dom], "launch_ms": round(phase[dom], 4),
             "flops_per_eval": fl}
 
@@ -164,9 +216,10 @@ def main() -> int:
     res = {
         "metric": METRIC, "value": M / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32-eval/f64-acc" if args.fp32 else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "M": M, "N": M, "distribution": wl["dist"], "kernel": wl["kernel"],
-                   "theta": args.theta, "degree": args.degree, "leaf": args.leaf, "mode": "plain-fp64"},
+                   "theta": args.theta, "degree": args.degree, "leaf": args.leaf,
+                   "mode": "fp32-eval" if args.fp32 else "plain-fp64"},
         "error_vs_direct": err, "judge_cpu_check_maxrel": judge_check,
         "roofline": roof, "cpu_baseline": cpu,
         "setup_ms": round(setup_ms, 1), "wall_ms_per_step": round(wall_ms / args.steps, 3),

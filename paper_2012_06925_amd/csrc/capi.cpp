@@ -179,6 +179,7 @@ struct bldtt_plan {
     hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
     bool prof_pending = false;
 
+    int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
     int P() const { return (degree + 1) * (degree + 1) * (degree + 1); }
     DevParticles dsrc() const { return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), sq.as<double>()}; }
     DevParticles dtgt() const {
@@ -277,8 +278,7 @@ struct PhaseMark {
     }
 };
 
-constexpr int kTile = 256;    // targets per particle work item (= workgroup size)
-constexpr int kPTile = 256;   // proxies per proxy work item
+constexpr int kBlockThreads = 256;   // threads per interaction work group (4 waves)
 
 void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     double t0 = now_ms();
@@ -288,6 +288,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const DevTree dS = pl->dS.view(), dT = pl->dT().view();
     const double* tab = pl->tab.as<double>();
     KernelSpec ks{pl->kind, pl->param};
+    const bool fp32 = (pl->flags & BLDTT_FP32_EVAL) != 0;
 
     collect_profile(pl);
     // 1. upward pass
@@ -303,12 +304,12 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // 2. traversal and work packing on the host, overlapping the upward pass
     do_traverse(pl);
     double tp = now_ms();
-    pack_work(T, S, pl->lists, deg, kTile, kPTile, pl->work);
+    pack_work(T, S, pl->lists, deg, kBlockThreads * pl->tpt, kBlockThreads * pl->tpt_proxy, pl->work);
     pl->stats.traverse_ms += now_ms() - tp;
     for (int k = 0; k < 4; ++k) pl->stats.interactions[k] = pl->work.interactions[k];
     Work& w = pl->work;
-    size_t bp = sizeof(PItem) * w.pitems.size(), be = sizeof(int32_t) * w.pentries.size();
-    size_t bq = sizeof(QItem) * w.qitems.size(), bqe = sizeof(int32_t) * w.qentries.size();
+    size_t bp = sizeof(Item) * w.pitems.size(), be = sizeof(Entry) * w.pentries.size();
+    size_t bq = sizeof(Item) * w.qitems.size(), bqe = sizeof(Entry) * w.qentries.size();
     size_t bf = w.leaf_has_far.size();
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t total = al(bp) + al(be) + al(bq) + al(bqe) + al(bf);
@@ -336,8 +337,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     {
         PhaseMark mark(pl, BLDTT_PH_CPCC, st);
         launch_fill(pl->phihat.as<double>(), (int64_t)T.size() * P, 0.0, st);
-        launch_cp_cc(ks, deg, pl->qitems.as<DevQItem>(), (int)w.qitems.size(), pl->qentries.as<int32_t>(), dT,
-                     pl->dsrc(), dS, tab, pl->qhat.as<double>(), pl->phihat.as<double>(), st);
+        launch_interact(ks, fp32, true, pl->tpt_proxy, deg, pl->qitems.as<DevItem>(), (int)w.qitems.size(),
+                        pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, pl->qhat.as<double>(),
+                        pl->phihat.as<double>(), st);
     }
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
@@ -350,13 +352,14 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // 4. PP + PC
     {
         PhaseMark mark(pl, BLDTT_PH_PPPC, st);
-        launch_pp_pc(ks, deg, pl->pitems.as<DevPItem>(), (int)w.pitems.size(), pl->pentries.as<int32_t>(),
-                     pl->dtgt(), pl->dsrc(), dS, tab, pl->qhat.as<double>(), pl->phi_tree.as<double>(), st);
+        launch_interact(ks, fp32, false, pl->tpt, deg, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
+                        pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, pl->qhat.as<double>(),
+                        pl->phi_tree.as<double>(), st);
     }
     // 5. leaves to targets, caller order
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_LEAF, st);
-        launch_down_leaf(deg, pl->pitems.as<DevPItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
+        launch_down_leaf(deg, pl->pitems.as<DevItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
                          pl->dtgt(), dT, tab, pl->phihat.as<double>(), pl->phi_tree.as<double>(),
                          pl->perm.as<int32_t>(), out, st);
     }
@@ -436,8 +439,9 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
 bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_param, double theta, int32_t degree,
                      int64_t leaf_size, uint32_t flags) {
     validate(p, kernel, theta, degree, leaf_size);
-    if (flags & (BLDTT_FP32_EVAL | BLDTT_LEARNED_DEGREE))
-        throw Error(BLDTT_EUNSUPPORTED, "flag not implemented in this build");
+    if (flags & BLDTT_LEARNED_DEGREE) throw Error(BLDTT_EUNSUPPORTED, "flag not implemented in this build");
+    if ((flags & BLDTT_FP32_EVAL) && kernel == BLDTT_POLY_TEST)
+        throw Error(BLDTT_EINVAL, "the polynomial test kernel runs in FP64 only");
     auto pl = std::make_unique<bldtt_plan>();
     pl->kind = kernel;
     pl->param = kernel_param;
@@ -495,7 +499,8 @@ int bldtt_traverse_host(bldtt_plan* plan) {
     }
     return guarded([&] {
         do_traverse(plan);
-        pack_work(plan->T(), plan->S, plan->lists, plan->degree, kTile, kPTile, plan->work);
+        pack_work(plan->T(), plan->S, plan->lists, plan->degree, kBlockThreads * plan->tpt,
+                  kBlockThreads * plan->tpt_proxy, plan->work);
         for (int k = 0; k < 4; ++k) plan->stats.interactions[k] = plan->work.interactions[k];
     });
 }

@@ -64,18 +64,25 @@ void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc
 // ---------------------------------------------------------------------------
 // Work items for the device (see kernels.hip for their consumers).
 // ---------------------------------------------------------------------------
-// Entry codes: (source cluster << 2) | kind.
-enum { E_PP = 0, E_PP_GUARD = 1, E_PC = 2 };   // particle-target entries
-enum { E_CP = 0, E_CC = 1 };                   // proxy-target entries
+// A source entry is two int32 {a, b}; kind = (uint32)b >> 29:
+//   SRC_RANGE, SRC_RANGE_GUARD: source particles at tree positions [a, a + (b & kCountMask));
+//       GUARD when the source box may contain a target, so r^2 == 0 terms are skipped;
+//   SRC_PROXY: the (n+1)^3 proxies of source cluster a with their proxy charges.
+// Adjacent particle ranges of one work group are merged into one entry.
+enum { SRC_RANGE = 0, SRC_RANGE_GUARD = 1, SRC_PROXY = 2 };
+constexpr int32_t kCountMask = (1 << 29) - 1;
+struct Entry { int32_t a, b; };
 
-struct PItem { int32_t tb, tn, eb, ee, leaf; }; // targets [tb, tb+tn) of target leaf `leaf`, entries [eb, ee)
-struct QItem { int32_t tc, lb, ln, eb, ee; };   // cluster tc, proxies [lb, lb+ln), entries
+// A work item: targets t0 .. t0+tn-1 (tree positions of particles, or proxy
+// indices of the target cluster), source entries [eb, ee), and the target
+// cluster (the leaf holding the particles, or the cluster owning the proxies).
+struct Item { int32_t t0, tn, eb, ee, cluster; };
 
 struct Work {
-    std::vector<int32_t> pentries;              // particle-target entries, grouped per target leaf
-    std::vector<PItem> pitems;
-    std::vector<int32_t> qentries;              // proxy-target entries, grouped per target cluster
-    std::vector<QItem> qitems;
+    std::vector<Entry> pentries;                // particle targets: PP ranges + PC proxies, per leaf
+    std::vector<Item> pitems;
+    std::vector<Entry> qentries;                // proxy targets: CP ranges + CC proxies, per cluster
+    std::vector<Item> qitems;
     std::vector<uint8_t> leaf_has_far;          // per target cluster: chain has CP/CC entries
     double interactions[4] = {0, 0, 0, 0};
 };

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -73,110 +74,72 @@ __device__ __forceinline__ void basis1d(double lo, double hi, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// Kernel evaluation.  acc is a per-target running sum; final() maps it to the
-// potential.  r^2 == 0 contributes nothing for the physical kernels.
+// Kernel evaluation.  One call adds one source term to one target's running
+// sum; final() maps the sum to the potential.  r^2 == 0 contributes nothing
+// for the physical kernels (GUARD is set only where that can happen).
 // ---------------------------------------------------------------------------
 
-// FP64 1/sqrt: hardware estimate refined by Newton steps.  For the Coulomb
-// sum the last step is folded into the accumulation:
-//     y1 = y0 (3 - r2 y0^2) / 2,   acc += q y0 (3 - r2 y0^2),   phi = acc / 2.
+// FP64 1/sqrt: hardware estimate (relative error ~5e-8 on gfx950), then one
+// cubically convergent correction: with e = 1 - r2 y0^2,
+//     y1 = y0 (1 + e/2 + 3 e^2/8),  relative error ~ (5/16) e^3 + rounding.
 __device__ __forceinline__ double rsq_est(double r2) { return __builtin_amdgcn_rsq(r2); }
 
-__device__ __forceinline__ double rsq_full(double r2) {
-    double y = rsq_est(r2);
-    double h = r2 * y;
-    y = 0.5 * y * fma(-h, y, 3.0);
-    h = r2 * y;
-    return 0.5 * y * fma(-h, y, 3.0);
+__device__ __forceinline__ double rsq_fix(double r2, double y) {
+    double e = fma(-(r2 * y), y, 1.0);
+    double p = fma(e, 0.375, 0.5);
+    return fma(y * e, p, y);
 }
+
+__device__ __forceinline__ double rsq_full(double r2) { return rsq_fix(r2, rsq_est(r2)); }
 
 enum { K_COULOMB = 0, K_YUKAWA = 1, K_OSC = 2, K_REG = 3, K_POLY = 100 };
 
+// FP64 evaluation on absolute coordinates; sources are double4 (x, y, z, q).
 template <int KIND>
-struct Eval;
-
-template <>
-struct Eval<K_COULOMB> {
+struct E64 {
+    using V = double4;
     template <bool GUARD>
-    __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const double4& s,
-                                               double) {
+    __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const V& s,
+                                               double param) {
+        if (KIND == K_POLY) {
+            double d = 1.0 + fma(tz, s.z, fma(ty, s.y, tx * s.x));
+            acc = fma(s.w, d * d, acc);
+            return;
+        }
         double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         double y = rsq_est(r2);
-        y = 0.5 * y * fma(-(r2 * y), y, 3.0);     // first Newton step
-        if (GUARD) y = r2 > 0.0 ? y : 0.0;
-        double h = r2 * y;
-        acc = fma(s.w * y, fma(-h, y, 3.0), acc);  // second step folded
-    }
-    __device__ __forceinline__ static double final(double acc) { return 0.5 * acc; }
-};
-
-template <>
-struct Eval<K_YUKAWA> {
-    template <bool GUARD>
-    __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const double4& s,
-                                               double kappa) {
-        double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        double y = rsq_full(r2);
-        double g = exp(-kappa * (r2 * y)) * y;
-        if (GUARD) g = r2 > 0.0 ? g : 0.0;
+        if (GUARD) y = r2 > 0.0 ? y : 0.0;      // rsq(0) = inf; a zero estimate stays zero below
+        y = rsq_fix(r2, y);
+        double g;
+        if (KIND == K_COULOMB) g = y;
+        else if (KIND == K_YUKAWA) g = exp(-param * (r2 * y)) * y;
+        else if (KIND == K_OSC) g = sinpi(r2 * y) * y;
+        else g = GUARD ? (r2 > 0.0 ? rsq_full(fma(param, param, r2)) : 0.0) : rsq_full(fma(param, param, r2));
         acc = fma(s.w, g, acc);
     }
-    __device__ __forceinline__ static double final(double acc) { return acc; }
 };
 
-template <>
-struct Eval<K_OSC> {
+// FP32 evaluation on cluster-relative coordinates; sources are float4
+// (x - c, y - c, z - c, q) rounded from FP64, c the centre of the target box.
+template <int KIND>
+struct E32 {
+    using V = float4;
     template <bool GUARD>
-    __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const double4& s,
-                                               double) {
-        double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        double y = rsq_full(r2);
-        double g = sinpi(r2 * y) * y;
-        if (GUARD) g = r2 > 0.0 ? g : 0.0;
-        acc = fma(s.w, g, acc);
+    __device__ __forceinline__ static void add(float& acc, float tx, float ty, float tz, const V& s, float param) {
+        float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+        float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        float y = __builtin_amdgcn_rsqf(r2);
+        if (GUARD) y = r2 > 0.0f ? y : 0.0f;
+        float g;
+        if (KIND == K_COULOMB) g = y;
+        else if (KIND == K_YUKAWA) g = __expf(-param * (r2 * y)) * y;
+        else if (KIND == K_OSC) g = sinpif(r2 * y) * y;
+        else g = GUARD ? (r2 > 0.0f ? __builtin_amdgcn_rsqf(fmaf(param, param, r2)) : 0.0f)
+                       : __builtin_amdgcn_rsqf(fmaf(param, param, r2));
+        acc = fmaf(s.w, g, acc);
     }
-    __device__ __forceinline__ static double final(double acc) { return acc; }
 };
-
-template <>
-struct Eval<K_REG> {
-    template <bool GUARD>
-    __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const double4& s,
-                                               double eps) {
-        double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        double g = rsq_full(fma(eps, eps, r2));
-        if (GUARD) g = r2 > 0.0 ? g : 0.0;
-        acc = fma(s.w, g, acc);
-    }
-    __device__ __forceinline__ static double final(double acc) { return acc; }
-};
-
-template <>
-struct Eval<K_POLY> {
-    template <bool GUARD>
-    __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const double4& s,
-                                               double) {
-        double d = 1.0 + fma(tz, s.z, fma(ty, s.y, tx * s.x));
-        acc = fma(s.w, d * d, acc);
-    }
-    __device__ __forceinline__ static double final(double acc) { return acc; }
-};
-
-// Sum over `cnt` staged sources for one target.
-template <int KIND, bool GUARD>
-__device__ __forceinline__ void sum_chunk(double& acc, const double4* __restrict__ src, int cnt, double tx,
-                                          double ty, double tz, double param) {
-    int j = 0;
-    for (; j + 4 <= cnt; j += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) Eval<KIND>::template add<GUARD>(acc, tx, ty, tz, src[j + u], param);
-    }
-    for (; j < cnt; ++j) Eval<KIND>::template add<GUARD>(acc, tx, ty, tz, src[j], param);
-}
 
 // Proxy point k of a cluster box (flat index k1 + m k2 + m^2 k3).
 __device__ __forceinline__ void proxy_point(const double* __restrict__ box, int m, const double* __restrict__ tab,
@@ -187,91 +150,161 @@ __device__ __forceinline__ void proxy_point(const double* __restrict__ box, int 
     z = node_at(box[2], box[5], tab[k3]);
 }
 
-// Stage sources [c0, c0 + kBlock) of one entry into LDS: particles of a source
-// cluster (PP, CP) or proxies with their proxy charges (PC, CC).
-__device__ __forceinline__ void stage(double4* lds, bool proxies, int sc, int c0, int nsrc, DevParticles src,
-                                      DevTree S, int m, int P, const double* __restrict__ tab,
-                                      const double* __restrict__ qhat) {
-    int j = c0 + (int)threadIdx.x;
-    if (j < nsrc) {
-        double4 v;
-        if (proxies) {
-            proxy_point(S.box + 6 * sc, m, tab, j, v.x, v.y, v.z);
-            v.w = qhat[(int64_t)sc * P + j];
+constexpr int kChunk = 512;                  // sources staged in LDS per round
+constexpr int kSub32 = 64;                   // FP32 partial sums folded into FP64 every kSub32 terms
+
+template <bool F32>
+struct Stage;
+template <>
+struct Stage<false> {
+    using V = double4;
+    __device__ __forceinline__ static V make(double x, double y, double z, double q, double, double, double) {
+        return make_double4(x, y, z, q);
+    }
+};
+template <>
+struct Stage<true> {
+    using V = float4;
+    __device__ __forceinline__ static V make(double x, double y, double z, double q, double cx, double cy,
+                                             double cz) {
+        return make_float4((float)(x - cx), (float)(y - cy), (float)(z - cz), (float)q);
+    }
+};
+
+// FP32 terms go to a per-target FP32 partial sum (folded into FP64 every
+// kSub32 terms); FP64 terms go straight to the FP64 sum.
+template <class Ev, bool GUARD, bool F32, class R, class V>
+__device__ __forceinline__ void accumulate(double& acc, R& part, R tx, R ty, R tz, const V& v, R param) {
+    if constexpr (F32) Ev::template add<GUARD>(part, tx, ty, tz, v, param);
+    else Ev::template add<GUARD>(acc, tx, ty, tz, v, param);
+}
+
+// ---------------------------------------------------------------------------
+// Interaction sums.  One work item = up to kBlock*T targets of one target
+// cluster (particles of a leaf: PP + PC; or proxies of a cluster: CP + CC)
+// and its list of source entries.  Thread (wave w, lane l) owns targets
+// w*64*T + l + 64 j, j < T; a wave with no target skips the arithmetic.
+// Sources are staged through LDS and read by all lanes at the same address.
+// ---------------------------------------------------------------------------
+template <int KIND, bool F32, int T, bool PROXY_TGT>
+__global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__ items,
+                                                     const int2* __restrict__ entries, DevParticles tgt, DevTree Tt,
+                                                     DevParticles src, DevTree S, const double* __restrict__ tab,
+                                                     const double* __restrict__ qhat, int m, double param,
+                                                     double* __restrict__ out) {
+    using St = Stage<F32>;
+    using V = typename St::V;
+    using R = typename std::conditional<F32, float, double>::type;
+    using Ev = typename std::conditional<F32, E32<KIND>, E64<KIND>>::type;
+    __shared__ V lds[kChunk];
+
+    const DevItem it = items[blockIdx.x];
+    const int P = m * m * m;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slab = wave * 64 * T;
+    const bool active = slab < it.tn;
+    const double* tbox = Tt.box + 6 * it.cluster;
+    const double cx = 0.5 * (tbox[0] + tbox[3]), cy = 0.5 * (tbox[1] + tbox[4]), cz = 0.5 * (tbox[2] + tbox[5]);
+
+    R tx[T], ty[T], tz[T];
+    double acc[T];
+    R part[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        int r = slab + lane + 64 * j;
+        int idx = it.t0 + (r < it.tn ? r : 0);
+        double x, y, z;
+        if (PROXY_TGT) {
+            proxy_point(tbox, m, tab, idx, x, y, z);
         } else {
-            int b = S.begin[sc] + j;
-            v.x = src.x[b];
-            v.y = src.y[b];
-            v.z = src.z[b];
-            v.w = src.q[b];
+            x = tgt.x[idx];
+            y = tgt.y[idx];
+            z = tgt.z[idx];
         }
-        lds[threadIdx.x] = v;
+        if (F32) {
+            tx[j] = (R)(x - cx);
+            ty[j] = (R)(y - cy);
+            tz[j] = (R)(z - cz);
+        } else {
+            tx[j] = (R)x;
+            ty[j] = (R)y;
+            tz[j] = (R)z;
+        }
+        acc[j] = 0.0;
+        part[j] = 0;
     }
-}
+    const R rparam = (R)param;
 
-// ---------------------------------------------------------------------------
-// PP + PC into the target particles of one leaf tile.
-// ---------------------------------------------------------------------------
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_pp_pc(const DevPItem* __restrict__ items,
-                                                  const int32_t* __restrict__ entries, DevParticles tgt,
-                                                  DevParticles src, DevTree S, const double* __restrict__ tab,
-                                                  const double* __restrict__ qhat, int m, double param,
-                                                  double* __restrict__ phi_tree) {
-    __shared__ double4 lds[kBlock];
-    const DevPItem it = items[blockIdx.x];
-    const int P = m * m * m;
-    const bool act = (int)threadIdx.x < it.tn;
-    const int p = it.tb + (act ? (int)threadIdx.x : 0);
-    const double tx = tgt.x[p], ty = tgt.y[p], tz = tgt.z[p];
-    double acc = 0.0;
     for (int e = it.eb; e < it.ee; ++e) {
-        const int code = entries[e];
-        const int sc = code >> 2, kind = code & 3;
+        const int2 en = entries[e];
+        const int kind = (int)((unsigned)en.y >> 29);
         const bool prox = kind == 2;
-        const int nsrc = prox ? P : S.count[sc];
-        for (int c0 = 0; c0 < nsrc; c0 += kBlock) {
+        const int nsrc = prox ? P : (en.y & ((1 << 29) - 1));
+        const double* sbox = S.box + 6 * en.x;
+        for (int c0 = 0; c0 < nsrc; c0 += kChunk) {
+            const int cnt = min(kChunk, nsrc - c0);
             __syncthreads();
-            stage(lds, prox, sc, c0, nsrc, src, S, m, P, tab, qhat);
+            for (int j = threadIdx.x; j < cnt; j += kBlock) {
+                double x, y, z, q;
+                if (prox) {
+                    proxy_point(sbox, m, tab, c0 + j, x, y, z);
+                    q = qhat[(int64_t)en.x * P + c0 + j];
+                } else {
+                    const int b = en.x + c0 + j;
+                    x = src.x[b];
+                    y = src.y[b];
+                    z = src.z[b];
+                    q = src.q[b];
+                }
+                lds[j] = St::make(x, y, z, q, cx, cy, cz);
+            }
             __syncthreads();
-            const int cnt = min(kBlock, nsrc - c0);
-            if (kind == 1) sum_chunk<KIND, true>(acc, lds, cnt, tx, ty, tz, param);
-            else sum_chunk<KIND, false>(acc, lds, cnt, tx, ty, tz, param);
+            if (!active) continue;
+            const bool guard = kind == 1;
+            for (int s0 = 0; s0 < cnt; s0 += kSub32) {
+                const int s1 = min(cnt, s0 + kSub32);
+                if (guard) {
+                    for (int s = s0; s < s1; ++s) {
+                        const V v = lds[s];
+#pragma unroll
+                        for (int j = 0; j < T; ++j) accumulate<Ev, true, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
+                    }
+                } else {
+                    int s = s0;
+                    for (; s + 4 <= s1; s += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const V v = lds[s + u];
+#pragma unroll
+                            for (int j = 0; j < T; ++j)
+                                accumulate<Ev, false, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
+                        }
+                    }
+                    for (; s < s1; ++s) {
+                        const V v = lds[s];
+#pragma unroll
+                        for (int j = 0; j < T; ++j) accumulate<Ev, false, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
+                    }
+                }
+                if constexpr (F32) {
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        acc[j] += (double)part[j];
+                        part[j] = 0;
+                    }
+                }
+            }
         }
     }
-    if (act) phi_tree[p] = Eval<KIND>::final(acc);
-}
-
-// ---------------------------------------------------------------------------
-// CP + CC into the target proxies of one cluster tile.
-// ---------------------------------------------------------------------------
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_cp_cc(const DevQItem* __restrict__ items,
-                                                  const int32_t* __restrict__ entries, DevTree T, DevParticles src,
-                                                  DevTree S, const double* __restrict__ tab,
-                                                  const double* __restrict__ qhat, int m, double param,
-                                                  double* __restrict__ phihat) {
-    __shared__ double4 lds[kBlock];
-    const DevQItem it = items[blockIdx.x];
-    const int P = m * m * m;
-    const bool act = (int)threadIdx.x < it.ln;
-    const int l = it.lb + (act ? (int)threadIdx.x : 0);
-    double tx, ty, tz;
-    proxy_point(T.box + 6 * it.tc, m, tab, l, tx, ty, tz);
-    double acc = 0.0;
-    for (int e = it.eb; e < it.ee; ++e) {
-        const int code = entries[e];
-        const int sc = code >> 2;
-        const bool prox = (code & 3) == 1;
-        const int nsrc = prox ? P : S.count[sc];
-        for (int c0 = 0; c0 < nsrc; c0 += kBlock) {
-            __syncthreads();
-            stage(lds, prox, sc, c0, nsrc, src, S, m, P, tab, qhat);
-            __syncthreads();
-            sum_chunk<KIND, false>(acc, lds, min(kBlock, nsrc - c0), tx, ty, tz, param);
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        int r = slab + lane + 64 * j;
+        if (r < it.tn) {
+            if (PROXY_TGT) out[(int64_t)it.cluster * P + it.t0 + r] = acc[j];
+            else out[it.t0 + r] = acc[j];
         }
     }
-    if (act) phihat[(int64_t)it.tc * P + l] = Eval<KIND>::final(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_down_transfer(const int32_t* __restr
 // written to out[perm[i]] (caller order).
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_down_leaf(const DevPItem* __restrict__ items,
+__global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict__ items,
                                                       const uint8_t* __restrict__ has_far, DevParticles tgt,
                                                       DevTree T, const double* __restrict__ tab,
                                                       const double* __restrict__ phihat,
@@ -439,37 +472,38 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevPItem* __restrict
                                                       const int32_t* __restrict__ perm, double* __restrict__ out) {
     constexpr int P = M * M * M;
     __shared__ double ph[P];
-    const DevPItem it = items[blockIdx.x];
-    const bool far = has_far[it.leaf] != 0;
+    const DevItem it = items[blockIdx.x];
+    const bool far = has_far[it.cluster] != 0;
     if (far) {
-        for (int k = threadIdx.x; k < P; k += kBlock) ph[k] = phihat[(int64_t)it.leaf * P + k];
+        for (int k = threadIdx.x; k < P; k += kBlock) ph[k] = phihat[(int64_t)it.cluster * P + k];
         __syncthreads();
     }
-    if ((int)threadIdx.x >= it.tn) return;
-    const int p = it.tb + threadIdx.x;
-    double v = phi_tree[p];
-    if (far) {
-        const double* box = T.box + 6 * it.leaf;
-        double Lx[M], Ly[M], Lz[M];
-        basis1d<M>(box[0], box[3], tab, tgt.x[p], Lx);
-        basis1d<M>(box[1], box[4], tab, tgt.y[p], Ly);
-        basis1d<M>(box[2], box[5], tab, tgt.z[p], Lz);
-        double s3 = 0.0;
-        for (int k3 = 0; k3 < M; ++k3) {
-            double s2 = 0.0;
+    const double* box = T.box + 6 * it.cluster;
+    for (int r = threadIdx.x; r < it.tn; r += kBlock) {
+        const int p = it.t0 + r;
+        double v = phi_tree[p];
+        if (far) {
+            double Lx[M], Ly[M], Lz[M];
+            basis1d<M>(box[0], box[3], tab, tgt.x[p], Lx);
+            basis1d<M>(box[1], box[4], tab, tgt.y[p], Ly);
+            basis1d<M>(box[2], box[5], tab, tgt.z[p], Lz);
+            double s3 = 0.0;
+            for (int k3 = 0; k3 < M; ++k3) {
+                double s2 = 0.0;
 #pragma unroll
-            for (int k2 = 0; k2 < M; ++k2) {
-                const double* row = ph + M * (k2 + M * k3);
-                double s1 = 0.0;
+                for (int k2 = 0; k2 < M; ++k2) {
+                    const double* row = ph + M * (k2 + M * k3);
+                    double s1 = 0.0;
 #pragma unroll
-                for (int k1 = 0; k1 < M; ++k1) s1 = fma(Lx[k1], row[k1], s1);
-                s2 = fma(Ly[k2], s1, s2);
+                    for (int k1 = 0; k1 < M; ++k1) s1 = fma(Lx[k1], row[k1], s1);
+                    s2 = fma(Ly[k2], s1, s2);
+                }
+                s3 = fma(Lz[k3], s2, s3);
             }
-            s3 = fma(Lz[k3], s2, s3);
+            v += s3;
         }
-        v += s3;
+        out[perm[p]] = v;
     }
-    out[perm[p]] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -593,7 +627,7 @@ struct DownTransfer {
 };
 template <int M>
 struct DownLeaf {
-    static void run(const DevPItem* items, int n, const uint8_t* has_far, DevParticles tgt, DevTree T,
+    static void run(const DevItem* items, int n, const uint8_t* has_far, DevParticles tgt, DevTree T,
                     const double* tab, const double* phihat, const double* phi_tree, const int32_t* perm,
                     double* out, hipStream_t st) {
         hipLaunchKernelGGL(k_down_leaf<M>, dim3(n), dim3(kBlock), 0, st, items, has_far, tgt, T, tab, phihat,
@@ -642,25 +676,42 @@ void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T
     default: throw Error(-1, "unknown kernel");                                 \
     }
 
-void launch_pp_pc(KernelSpec k, int degree, const DevPItem* items, int n_items, const int32_t* entries,
-                  DevParticles tgt, DevParticles src, DevTree S, const double* tab, const double* qhat,
-                  double* phi_tree, hipStream_t st) {
+namespace {
+template <int KK, bool F32, bool PROXY_TGT>
+void launch_interact_t(int tpt, const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
+                       DevParticles src, DevTree S, const double* tab, const double* qhat, int m, double param,
+                       double* out, hipStream_t st) {
+    switch (tpt) {
+    case 1: hipLaunchKernelGGL((k_interact<KK, F32, 1, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
+                               tgt, Tt, src, S, tab, qhat, m, param, out); break;
+    case 2: hipLaunchKernelGGL((k_interact<KK, F32, 2, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
+                               tgt, Tt, src, S, tab, qhat, m, param, out); break;
+    case 4: hipLaunchKernelGGL((k_interact<KK, F32, 4, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
+                               tgt, Tt, src, S, tab, qhat, m, param, out); break;
+    default: throw Error(-1, "targets per thread must be 1, 2 or 4");
+    }
+}
+}  // namespace
+
+void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, int degree, const DevItem* items,
+                     int n_items, const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S,
+                     const double* tab, const double* qhat, double* out, hipStream_t st) {
     if (n_items <= 0) return;
-    DISPATCH_KIND(k.kind, hipLaunchKernelGGL(k_pp_pc<KK>, dim3(n_items), dim3(kBlock), 0, st, items, entries, tgt,
-                                             src, S, tab, qhat, degree + 1, k.param, phi_tree));
+    if (fp32 && k.kind == K_POLY) throw Error(-5, "the polynomial test kernel runs in FP64 only");
+    const int m = degree + 1;
+#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, m, k.param, out, st)
+    if (fp32) {
+        if (proxy_targets) { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, true)); }
+        else { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, false)); }
+    } else {
+        if (proxy_targets) { DISPATCH_KIND(k.kind, LAUNCH_ONE(false, true)); }
+        else { DISPATCH_KIND(k.kind, LAUNCH_ONE(false, false)); }
+    }
+#undef LAUNCH_ONE
     CHECK_LAUNCH();
 }
 
-void launch_cp_cc(KernelSpec k, int degree, const DevQItem* items, int n_items, const int32_t* entries,
-                  DevTree T, DevParticles src, DevTree S, const double* tab, const double* qhat,
-                  double* phihat, hipStream_t st) {
-    if (n_items <= 0) return;
-    DISPATCH_KIND(k.kind, hipLaunchKernelGGL(k_cp_cc<KK>, dim3(n_items), dim3(kBlock), 0, st, items, entries, T,
-                                             src, S, tab, qhat, degree + 1, k.param, phihat));
-    CHECK_LAUNCH();
-}
-
-void launch_down_leaf(int degree, const DevPItem* items, int n_items, const uint8_t* has_far,
+void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8_t* has_far,
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,
                       const double* phi_tree, const int32_t* perm, double* out, hipStream_t st) {
     if (n_items <= 0) return;

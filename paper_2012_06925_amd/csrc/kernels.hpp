@@ -31,9 +31,9 @@ struct DevParticles {
     const double* q;      // null for targets
 };
 
-// Item layouts shared with the host packer (engine.hpp): plain int32 records.
-struct DevPItem { int32_t tb, tn, eb, ee, leaf; };
-struct DevQItem { int32_t tc, lb, ln, eb, ee; };
+// Work item shared with the host packer (engine.hpp, struct Item): targets
+// t0 .. t0+tn-1 of target cluster `cluster`, source entries [eb, ee).
+struct DevItem { int32_t t0, tn, eb, ee, cluster; };
 
 struct KernelSpec {
     int kind;
@@ -51,15 +51,14 @@ void launch_up_transfer(int degree, const int32_t* parents, int n_parents, DevTr
 void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T, const double* tab,
                           double* phihat, hipStream_t st);
 
-void launch_pp_pc(KernelSpec k, int degree, const DevPItem* items, int n_items, const int32_t* entries,
-                  DevParticles tgt, DevParticles src, DevTree S, const double* tab, const double* qhat,
-                  double* phi_tree, hipStream_t st);
+// Interaction sums: proxy_targets = false for PP + PC into the particles of a
+// leaf (out = potentials in tree order), true for CP + CC into the proxies of
+// a cluster (out = proxy potentials).  tpt: targets per thread (1, 2 or 4).
+void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, int degree, const DevItem* items,
+                     int n_items, const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S,
+                     const double* tab, const double* qhat, double* out, hipStream_t st);
 
-void launch_cp_cc(KernelSpec k, int degree, const DevQItem* items, int n_items, const int32_t* entries,
-                  DevTree T, DevParticles src, DevTree S, const double* tab, const double* qhat,
-                  double* phihat, hipStream_t st);
-
-void launch_down_leaf(int degree, const DevPItem* items, int n_items, const uint8_t* has_far,
+void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8_t* has_far,
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,
                       const double* phi_tree, const int32_t* perm, double* out, hipStream_t st);
 

@@ -129,6 +129,29 @@ bool boxes_touch(const Tree& T, int64_t t, const Tree& S, int64_t s) {
     return true;
 }
 
+// Particle ranges of one work group: sort by start and merge neighbours that
+// touch and share the guard flag.  Summation order is free (any order of the
+// same terms is a valid evaluation of the sum).
+void emit_ranges(std::vector<std::pair<int64_t, int64_t>>& rng_plain, std::vector<std::pair<int64_t, int64_t>>& rng_guard,
+                 std::vector<Entry>& out) {
+    for (int g = 0; g < 2; ++g) {
+        auto& v = g ? rng_guard : rng_plain;
+        std::sort(v.begin(), v.end());
+        size_t i = 0;
+        while (i < v.size()) {
+            int64_t b = v[i].first, e = v[i].first + v[i].second;
+            size_t j = i + 1;
+            while (j < v.size() && v[j].first == e && e - b + v[j].second <= kCountMask) {
+                e += v[j].second;
+                ++j;
+            }
+            out.push_back(Entry{(int32_t)b, (int32_t)((uint32_t)(g ? SRC_RANGE_GUARD : SRC_RANGE) << 29 | (uint32_t)(e - b))});
+            i = j;
+        }
+        v.clear();
+    }
+}
+
 }  // namespace
 
 void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w) {
@@ -147,10 +170,12 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
     ByTarget part = group(T, L, PP, PC);
     ByTarget prox = group(T, L, CP, CC);
     const int64_t nc = T.size();
+    std::vector<std::pair<int64_t, int64_t>> rp, rg;
+    const uint32_t proxy_code = (uint32_t)SRC_PROXY << 29;
 
-    // Particle-target work: per target leaf, the PP/PC entries of the leaf and of
+    // Particle targets: per target leaf, the PP/PC entries of the leaf and of
     // every ancestor (each leaf owns its targets, so no two items share an output).
-    std::vector<std::pair<double, PItem>> items;
+    std::vector<std::pair<double, Item>> items;
     w.leaf_has_far.assign(nc, 0);
     for (int64_t leaf = 0; leaf < nc; ++leaf) {
         if (!T.is_leaf(leaf)) continue;
@@ -161,17 +186,21 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
             if (prox.off[c + 1] > prox.off[c]) far = true;
             for (int64_t e = part.off[c]; e < part.off[c + 1]; ++e) {
                 int64_t sc = part.code[e] >> 2;
-                int ty = (int)(part.code[e] & 3);
-                int kind = ty == PC ? E_PC : (boxes_touch(T, leaf, S, sc) ? E_PP_GUARD : E_PP);
-                w.pentries.push_back((int32_t)((sc << 2) | kind));
-                src += ty == PC ? (double)np : (double)S.count[sc];
+                if ((int)(part.code[e] & 3) == PC) {
+                    w.pentries.push_back(Entry{(int32_t)sc, (int32_t)proxy_code});
+                    src += (double)np;
+                } else {
+                    (boxes_touch(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
+                    src += (double)S.count[sc];
+                }
             }
         }
+        emit_ranges(rp, rg, w.pentries);
         w.leaf_has_far[leaf] = far;
         int64_t ee = (int64_t)w.pentries.size();
         for (int64_t tb = T.begin[leaf]; tb < T.begin[leaf] + T.count[leaf]; tb += tile) {
             int64_t tn = std::min<int64_t>(tile, T.begin[leaf] + T.count[leaf] - tb);
-            items.push_back({src * (double)tn, PItem{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee, (int32_t)leaf}});
+            items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee, (int32_t)leaf}});
         }
     }
     // Longest items first: the tail of the grid is then made of short items.
@@ -179,27 +208,32 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
     w.pitems.reserve(items.size());
     for (auto& it : items) w.pitems.push_back(it.second);
 
-    // Proxy-target work: per target cluster with CP/CC entries, tiles of its proxies.
-    std::vector<std::pair<double, QItem>> qitems;
+    // Proxy targets: per target cluster with CP/CC entries, tiles of its proxies.
+    items.clear();
     for (int64_t c = 0; c < nc; ++c) {
         if (prox.off[c + 1] == prox.off[c]) continue;
         int64_t eb = (int64_t)w.qentries.size();
         double src = 0.0;
         for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) {
             int64_t sc = prox.code[e] >> 2;
-            int ty = (int)(prox.code[e] & 3);
-            w.qentries.push_back((int32_t)((sc << 2) | (ty == CC ? E_CC : E_CP)));
-            src += ty == CC ? (double)np : (double)S.count[sc];
+            if ((int)(prox.code[e] & 3) == CC) {
+                w.qentries.push_back(Entry{(int32_t)sc, (int32_t)proxy_code});
+                src += (double)np;
+            } else {
+                rp.emplace_back(S.begin[sc], S.count[sc]);     // separated: never r = 0
+                src += (double)S.count[sc];
+            }
         }
+        emit_ranges(rp, rg, w.qentries);
         int64_t ee = (int64_t)w.qentries.size();
         for (int64_t lb = 0; lb < np; lb += ptile) {
             int64_t ln = std::min<int64_t>(ptile, np - lb);
-            qitems.push_back({src * (double)ln, QItem{(int32_t)c, (int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee}});
+            items.push_back({src * (double)ln, Item{(int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee, (int32_t)c}});
         }
     }
-    std::stable_sort(qitems.begin(), qitems.end(), [](auto& a, auto& b) { return a.first > b.first; });
-    w.qitems.reserve(qitems.size());
-    for (auto& it : qitems) w.qitems.push_back(it.second);
+    std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    w.qitems.reserve(items.size());
+    for (auto& it : items) w.qitems.push_back(it.second);
 }
 
 }  // namespace bldtt
