@@ -149,6 +149,11 @@ int bldtt_get_tree(const bldtt_plan *plan, int which, bldtt_tree_view *out);
  * by the plan.  ESTATE before any traversal. */
 int bldtt_get_lists(const bldtt_plan *plan, int type, const int64_t **tc, const int64_t **sc, int64_t *n);
 
+/* Interpolation degree of every entry of one list type from the last
+ * traversal, aligned with bldtt_get_lists (for PP entries the value is the
+ * plan's degree and has no meaning).  ESTATE before any traversal. */
+int bldtt_get_list_degrees(const bldtt_plan *plan, int type, const int8_t **deg, int64_t *n);
+
 /* Device intermediates after bldtt_compute (the stream must have been
  * synchronized), copied to host arrays of n_clusters * (n+1)^3 doubles:
  * proxy charges per source cluster, proxy potentials per target cluster
@@ -171,6 +176,12 @@ typedef struct {
     double phase_ms[BLDTT_N_PHASES];/* BLDTT_PROFILE: device time per phase, summed over
                                       every profiled compute so far (HIP events)         */
     int64_t profiled_computes;     /* number of computes summed in phase_ms              */
+    int32_t down_degree;           /* degree of the last downward pass                   */
+    uint32_t degree_mask;          /* bit d: some PC/CP/CC entry used degree d           */
+    int64_t sep_pairs;             /* BLDTT_LEARNED_DEGREE: separated pairs last compute */
+    int64_t sep_fallback;          /*   of which outside the model's range (fallback)    */
+    int64_t sep_direct;            /*   of which evaluated directly (PP chosen)          */
+    int64_t pairs_per_degree[13];  /*   approximated pairs per degree                     */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the
@@ -187,6 +198,77 @@ int bldtt_direct_sum(int32_t kernel, double kernel_param,
                      int64_t M, const double *tx, const double *ty, const double *tz,
                      int64_t N, const double *sx, const double *sy, const double *sz, const double *q,
                      int64_t nsel, const int64_t *sel, double *out, void *hip_stream);
+
+/* ---- Per-pair interpolation degree (BLDTT_LEARNED_DEGREE) --------------- */
+/*
+ * The paper uses one degree n for every approximated pair.  A plan set up
+ * with BLDTT_LEARNED_DEGREE instead chooses, for every separated pair of
+ * Algorithm 2 (the recursion itself is unchanged), the cheapest (type, degree)
+ * whose predicted error is at most tau: degree d in [2, 12] with the type given
+ * by the counts against (d+1)^3, or direct evaluation (PP).  Cost is the
+ * number of kernel evaluations.  The prediction comes from a small MLP
+ * (4 -> 64 -> 64 -> 11, FP32) mapping the pair features
+ *     ln(r_t / r_s), ln(R / (r_t + r_s)), ln |C_t|, ln |C_s|   (radii floored at 1e-6 R)
+ * to log10 of the pair's relative l2 error at each degree.  Pairs whose two
+ * geometric features lie outside the training range use fallback_degree.
+ * Lower-degree proxy potentials are lifted exactly to the largest degree in
+ * use before the downward pass (interpolation reproduces polynomials of lower
+ * degree, Appendix A).
+ *
+ * Model record: bldtt_mlp_model_size() floats = parameters (W1[64][4], b1[64],
+ * W2[64][64], b2[64], W3[11][64], b3[11]) then input mean[4], scale[4] and the
+ * training feature range lo[4], hi[4].
+ */
+
+/* Floats in a model record. */
+int bldtt_mlp_model_size(void);
+
+/* Degree policy of a BLDTT_LEARNED_DEGREE plan.  model: host array of
+ * n_floats = bldtt_mlp_model_size() floats, copied; or NULL (n_floats 0): every
+ * separated pair uses fallback_degree (the plain method through the
+ * per-pair path).  fallback_degree in [1, 12]; tau > 0.
+ * Errors: EINVAL; ESTATE when the plan lacks BLDTT_LEARNED_DEGREE; EDEVICE. */
+int bldtt_set_degree_model(bldtt_plan *plan, const float *model, size_t n_floats, int32_t fallback_degree,
+                           double tau);
+
+/* Test policy exercising every degree: separated pair (tc, sc) gets degree
+ * 2 + (7 tc + 13 sc) mod 11, typed by the counts.  For parity tests of the
+ * per-pair degree machinery only.  Errors: EINVAL, ESTATE as above. */
+int bldtt_set_degree_test_rule(bldtt_plan *plan);
+
+/* Training data measured by the method itself: traverse the plan's problem,
+ * and for every separated pair compute, on the GPU, the relative l2 error
+ * over the target cluster's particles of the pair's cluster-cluster
+ * approximation at each degree 2..12 against the pair's exact (PP) sum.
+ * Outputs (host arrays owned by the plan, valid until the next call or
+ * bldtt_destroy): n pairs, features[n][4] (as above), log10_errors[n][11]
+ * (clamped below at -14, the rounding level of the FP64 sums; NaN where the
+ * exact pair sum is zero), and when pairs is not NULL the
+ * cluster ids pairs[2p] (target) and pairs[2p+1] (source).  Synchronizes
+ * hip_stream.  Errors: EINVAL; ESTATE for a host-only plan; ENOMEM; EDEVICE. */
+int bldtt_pair_errors(bldtt_plan *plan, void *hip_stream, int64_t *n, const float **features,
+                      const float **log10_errors, const int64_t **pairs);
+
+/* Model forward pass on device arrays: out[n][11] = predicted log10 errors
+ * for features[n][4].  Errors: EINVAL, EDEVICE. */
+int bldtt_mlp_forward(const float *model, const float *features, int64_t n, float *out, void *hip_stream);
+
+/* Mean squared error of the predictions against targets[n][11] (NaN entries
+ * ignored) and its gradient with respect to the parameters (the first
+ * bldtt_mlp_model_size() - 16 floats of the model), all device arrays:
+ * grad receives that many floats, loss one float.  Errors: EINVAL, EDEVICE. */
+int bldtt_mlp_loss_grad(const float *model, const float *features, const float *targets, int64_t n, float *grad,
+                        float *loss, void *hip_stream);
+
+/* Train a model on the GPU from host arrays features[n][4], targets[n][11]
+ * (NaN entries ignored): input standardisation and feature range from the
+ * data, Glorot-uniform initial weights from `seed`, Adam (beta 0.9, 0.999) on
+ * shuffled mini-batches for `epochs` passes.  model_out: host array of
+ * bldtt_mlp_model_size() floats; loss_history: host array of `epochs` floats
+ * (mean batch loss per epoch), may be NULL.  Synchronizes hip_stream.
+ * Errors: EINVAL (n < 1, epochs < 1, batch < 1, lr <= 0), ENOMEM, EDEVICE. */
+int bldtt_mlp_train(const float *features, const float *targets, int64_t n, int32_t epochs, int32_t batch,
+                    float lr, uint64_t seed, float *model_out, float *loss_history, void *hip_stream);
 
 /* Library version string. */
 const char *bldtt_version(void);

@@ -859,3 +859,190 @@ void or_run_times(const or_run *r, double *out)
     out[0] = r->t_traverse; out[1] = r->t_up; out[2] = r->t_interact; out[3] = r->t_down;
 }
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------- */
+/* Per-pair degrees.  Given lists whose PC/CP/CC entries each carry their own */
+/* interpolation degree, the potential is the sum over entries of the         */
+/* approximated sums at each entry's degree: proxy charges of degree d from   */
+/* the upward pass run at degree d, proxy potentials of degree d formed per   */
+/* target cluster, and every cluster of a target's chain interpolating its    */
+/* own proxy potentials of every degree straight to the target (the direct    */
+/* form of the downward pass, Eq. 1d-direct-downpass).                        */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int n;
+    double xi[32], w[32];
+} or_deg;
+
+static void deg_init(or_deg *D, int n) { D->n = n; or_cheb(n, D->xi, D->w); }
+
+static void dbasis(const or_tree *t, int64_t c, int dim, const or_deg *D, double y, double *L)
+{
+    double s[32];
+    box_nodes(D->n, D->xi, t->lo[3 * c + dim], t->hi[3 * c + dim], s);
+    basis_nodes(D->n, s, D->w, y, L);
+}
+
+static void dgrid(const or_tree *t, int64_t c, const or_deg *D, double *px, double *py, double *pz)
+{
+    int m = D->n + 1;
+    double s[3][32];
+    for (int d = 0; d < 3; ++d) box_nodes(D->n, D->xi, t->lo[3 * c + d], t->hi[3 * c + d], s[d]);
+    for (int k3 = 0; k3 < m; ++k3)
+        for (int k2 = 0; k2 < m; ++k2)
+            for (int k1 = 0; k1 < m; ++k1) {
+                int64_t k = k1 + m * (k2 + (int64_t)m * k3);
+                px[k] = s[0][k1]; py[k] = s[1][k2]; pz[k] = s[2][k3];
+            }
+}
+
+/* Upward pass at degree D (same steps as or_run_upward, explicit degree). */
+static double *upward_deg(const or_run *r, const or_deg *D)
+{
+    const or_tree *S = r->S;
+    int m = D->n + 1;
+    int64_t P = (int64_t)m * m * m;
+    double *q = calloc((size_t)(S->n * P), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < S->n; ++c) {
+        if (S->nchild[c]) continue;
+        for (int64_t p = S->begin[c]; p < S->begin[c] + S->count[c]; ++p) {
+            int64_t j = S->perm[p];
+            double Lx[32], Ly[32], Lz[32];
+            dbasis(S, c, 0, D, r->sx[j], Lx);
+            dbasis(S, c, 1, D, r->sy[j], Ly);
+            dbasis(S, c, 2, D, r->sz[j], Lz);
+            for (int k3 = 0; k3 < m; ++k3)
+                for (int k2 = 0; k2 < m; ++k2)
+                    for (int k1 = 0; k1 < m; ++k1)
+                        q[c * P + k1 + m * (k2 + m * k3)] += Lx[k1] * Ly[k2] * Lz[k3] * r->q[j];
+        }
+    }
+    for (int lev = S->depth - 1; lev >= 0; --lev) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t c = 0; c < S->n; ++c) {
+            if (S->level[c] != lev || S->nchild[c] == 0) continue;
+            double *Tm = malloc(sizeof(double) * 3 * m * m);
+            for (int k = 0; k < S->nchild[c]; ++k) {
+                int64_t ch = S->child[8 * c + k];
+                for (int d = 0; d < 3; ++d) {
+                    double sb[32], L[32];
+                    box_nodes(D->n, D->xi, S->lo[3 * ch + d], S->hi[3 * ch + d], sb);
+                    for (int kp = 0; kp < m; ++kp) {
+                        dbasis(S, c, d, D, sb[kp], L);
+                        for (int kk = 0; kk < m; ++kk) Tm[d * m * m + kk * m + kp] = L[kk];
+                    }
+                }
+                apply_tensor(m, Tm, q + ch * P, q + c * P, 0);
+            }
+            free(Tm);
+        }
+    }
+    return q;
+}
+
+/* phi at caller-order targets (all M) for lists with per-entry degrees.
+ * types: arrays indexed OR_PP..OR_CC; deg[type][e] is ignored for PP. */
+void or_run_eval_degrees(or_run *r, const int64_t *n_entries, const int64_t *const *tc, const int64_t *const *sc,
+                         const int32_t *const *deg, double *out)
+{
+    const or_tree *T = r->T, *S = r->S;
+    or_deg D[13];
+    for (int d = 1; d <= 12; ++d) deg_init(&D[d], d);
+    int used_src[13] = {0}, used_tgt[13] = {0};
+    for (int ty = OR_PC; ty <= OR_CC; ++ty)
+        for (int64_t e = 0; e < n_entries[ty]; ++e) {
+            if (ty == OR_PC || ty == OR_CC) used_src[deg[ty][e]] = 1;
+            if (ty == OR_CP || ty == OR_CC) used_tgt[deg[ty][e]] = 1;
+        }
+    double *qd[13] = {0}, *own[13] = {0};
+    for (int d = 1; d <= 12; ++d) {
+        int64_t P = (int64_t)(d + 1) * (d + 1) * (d + 1);
+        if (used_src[d]) qd[d] = upward_deg(r, &D[d]);
+        if (used_tgt[d]) own[d] = calloc((size_t)(T->n * P), sizeof(double));
+    }
+    /* Proxy potentials of every target cluster and degree from its CP/CC entries. */
+    for (int ty = OR_CP; ty <= OR_CC; ++ty) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t c = 0; c < T->n; ++c) {
+            for (int64_t e = 0; e < n_entries[ty]; ++e) {
+                if (tc[ty][e] != c) continue;
+                const or_deg *Dd = &D[deg[ty][e]];
+                int m = Dd->n + 1;
+                int64_t P = (int64_t)m * m * m;
+                double *tg = malloc(sizeof(double) * 6 * P);
+                dgrid(T, c, Dd, tg, tg + P, tg + 2 * P);
+                if (ty == OR_CC) dgrid(S, sc[ty][e], Dd, tg + 3 * P, tg + 4 * P, tg + 5 * P);
+                for (int64_t l = 0; l < P; ++l) {
+                    double t3[3] = {tg[l], tg[P + l], tg[2 * P + l]}, y[3], acc = 0.0;
+                    if (ty == OR_CP) {
+                        for (int64_t b = S->begin[sc[ty][e]]; b < S->begin[sc[ty][e]] + S->count[sc[ty][e]]; ++b) {
+                            int64_t j = S->perm[b];
+                            y[0] = r->sx[j]; y[1] = r->sy[j]; y[2] = r->sz[j];
+                            acc += G(r, t3, y) * r->q[j];
+                        }
+                    } else {
+                        for (int64_t k = 0; k < P; ++k) {
+                            y[0] = tg[3 * P + k]; y[1] = tg[4 * P + k]; y[2] = tg[5 * P + k];
+                            acc += G(r, t3, y) * qd[Dd->n][sc[ty][e] * P + k];
+                        }
+                    }
+                    own[Dd->n][c * P + l] += acc;
+                }
+                free(tg);
+            }
+        }
+    }
+    /* Each target: PP and PC entries of its chain, plus every chain cluster's
+     * own proxy potentials of every degree interpolated to the target. */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < r->M; ++p) {
+        int64_t i = T->perm[p];
+        double x[3] = {r->tx[i], r->ty[i], r->tz[i]}, y[3], acc = 0.0;
+        int64_t leaf = 0;
+        while (T->nchild[leaf]) {
+            for (int k = 0; k < T->nchild[leaf]; ++k) {
+                int64_t ch = T->child[8 * leaf + k];
+                if (p >= T->begin[ch] && p < T->begin[ch] + T->count[ch]) { leaf = ch; break; }
+            }
+        }
+        for (int64_t c = leaf; c >= 0; c = T->parent[c]) {
+            for (int64_t e = 0; e < n_entries[OR_PP]; ++e) {
+                if (tc[OR_PP][e] != c) continue;
+                for (int64_t b = S->begin[sc[OR_PP][e]]; b < S->begin[sc[OR_PP][e]] + S->count[sc[OR_PP][e]]; ++b) {
+                    int64_t j = S->perm[b];
+                    y[0] = r->sx[j]; y[1] = r->sy[j]; y[2] = r->sz[j];
+                    acc += G(r, x, y) * r->q[j];
+                }
+            }
+            for (int64_t e = 0; e < n_entries[OR_PC]; ++e) {
+                if (tc[OR_PC][e] != c) continue;
+                const or_deg *Dd = &D[deg[OR_PC][e]];
+                int m = Dd->n + 1;
+                int64_t P = (int64_t)m * m * m;
+                double *g = malloc(sizeof(double) * 3 * P);
+                dgrid(S, sc[OR_PC][e], Dd, g, g + P, g + 2 * P);
+                for (int64_t k = 0; k < P; ++k) {
+                    y[0] = g[k]; y[1] = g[P + k]; y[2] = g[2 * P + k];
+                    acc += G(r, x, y) * qd[Dd->n][sc[OR_PC][e] * P + k];
+                }
+                free(g);
+            }
+            for (int d = 1; d <= 12; ++d) {
+                if (!own[d]) continue;
+                int m = d + 1;
+                double Lx[32], Ly[32], Lz[32];
+                dbasis(T, c, 0, &D[d], x[0], Lx);
+                dbasis(T, c, 1, &D[d], x[1], Ly);
+                dbasis(T, c, 2, &D[d], x[2], Lz);
+                const double *v = own[d] + c * (int64_t)m * m * m;
+                for (int k3 = 0; k3 < m; ++k3)
+                    for (int k2 = 0; k2 < m; ++k2)
+                        for (int k1 = 0; k1 < m; ++k1) acc += Lx[k1] * Ly[k2] * Lz[k3] * v[k1 + m * (k2 + m * k3)];
+            }
+        }
+        out[i] = acc;
+    }
+    for (int d = 1; d <= 12; ++d) { free(qd[d]); free(own[d]); }
+}

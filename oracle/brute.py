@@ -96,6 +96,9 @@ def direct_sum(tgt_xyz: np.ndarray, src_xyz: np.ndarray, q: np.ndarray, kernel="
 def explicit_bldtt(tgt_xyz, src_xyz, q, tree_t, tree_s, lists, n, kernel="coulomb", param=0.0):
     """sum over list entries of the approximated kernel matrix times the charges.
 
+    lists[name] = (tcs, scs) with every approximation at degree n, or
+    (tcs, scs, degs) with one degree per entry.
+
     PP: G(x_i, y_j); PC: sum_k G(x_i, s_k) L_k(y_j); CP: sum_l L_l(x_i) G(t_l, y_j);
     CC: sum_l sum_k L_l(x_i) G(t_l, s_k) L_k(y_j).  Trees give cluster membership
     (tree position ranges + permutation) and boxes; lists give (tc, sc) pairs.
@@ -106,8 +109,11 @@ def explicit_bldtt(tgt_xyz, src_xyz, q, tree_t, tree_s, lists, n, kernel="coulom
         b, cnt = tree["begin"][c], tree["count"][c]
         return tree["perm"][b:b + cnt]
 
-    for name, (tcs, scs) in lists.items():
-        for tc, sc in zip(tcs, scs):
+    for name, entry in lists.items():
+        tcs, scs = entry[0], entry[1]
+        degs = entry[2] if len(entry) > 2 else [n] * len(tcs)
+        for tc, sc, n in zip(tcs, scs, degs):
+            n = int(n)
             ti = members(tree_t, tc)
             sj = members(tree_s, sc)
             X, Y = tgt_xyz[ti], src_xyz[sj]

@@ -54,6 +54,7 @@ def lib():
                   "or_run_qhat", "or_run_phihat", "or_run_phihat_own", "or_run_times"):
             getattr(L, f).argtypes = [v, _D]
         L.or_run_eval_targets.argtypes = [v, C.c_int64, _I64, _D]
+        L.or_run_eval_degrees.argtypes = [v, _I64, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), _D]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -221,6 +222,26 @@ class Run:
 
     def times(self):
         return dict(zip(("traverse", "upward", "interact", "downward"), self._get("or_run_times", 4)))
+
+    def eval_degrees(self, lists: dict) -> np.ndarray:
+        """Potentials (caller order) for lists whose PC/CP/CC entries carry their own degree:
+        lists[name] = (tc, sc, deg) for name in PP, PC, CP, CC (deg ignored for PP)."""
+        keep = []
+        n = np.zeros(4, np.int64)
+        tcs, scs, degs = (_I64 * 4)(), (_I64 * 4)(), (_I32 * 4)()
+        for k, name in enumerate(TYPES):
+            tc, sc, dg = lists[name]
+            tc = np.ascontiguousarray(tc, np.int64)
+            sc = np.ascontiguousarray(sc, np.int64)
+            dg = np.ascontiguousarray(dg, np.int32)
+            keep += [tc, sc, dg]
+            n[k] = tc.shape[0]
+            tcs[k] = tc.ctypes.data_as(_I64)
+            scs[k] = sc.ctypes.data_as(_I64)
+            degs[k] = dg.ctypes.data_as(_I32)
+        out = np.empty(self.M)
+        lib().or_run_eval_degrees(self.ptr, n.ctypes.data_as(_I64), tcs, scs, degs, _d(out))
+        return out
 
     def eval_targets(self, sel) -> np.ndarray:
         """Potentials at caller-order targets `sel` (needs traverse + upward only)."""

@@ -45,7 +45,9 @@ class Stats(C.Structure):
                 ("n_target_clusters", C.c_int64), ("n_source_clusters", C.c_int64),
                 ("target_depth", C.c_int32), ("source_depth", C.c_int32),
                 ("setup_ms", C.c_double), ("traverse_ms", C.c_double), ("compute_host_ms", C.c_double),
-                ("phase_ms", C.c_double * 5), ("profiled_computes", C.c_int64)]
+                ("phase_ms", C.c_double * 5), ("profiled_computes", C.c_int64),
+                ("down_degree", C.c_int32), ("degree_mask", C.c_uint32), ("sep_pairs", C.c_int64),
+                ("sep_fallback", C.c_int64), ("sep_direct", C.c_int64), ("pairs_per_degree", C.c_int64 * 13)]
 
 
 # Every symbol the header declares, with its signature.
@@ -60,6 +62,7 @@ SIGNATURES = {
     "bldtt_last_error": (C.c_char_p, []),
     "bldtt_get_tree": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(TreeView)]),
     "bldtt_get_lists": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(C.c_int64)]),
+    "bldtt_get_list_degrees": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.POINTER(C.c_int8)), C.POINTER(C.c_int64)]),
     "bldtt_get_qhat": (C.c_int, [C.c_void_p, _D]),
     "bldtt_get_phihat": (C.c_int, [C.c_void_p, _D]),
     "bldtt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
@@ -67,6 +70,16 @@ SIGNATURES = {
                                    C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     "bldtt_version": (C.c_char_p, []),
+    "bldtt_mlp_model_size": (C.c_int, []),
+    "bldtt_set_degree_model": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_double]),
+    "bldtt_set_degree_test_rule": (C.c_int, [C.c_void_p]),
+    "bldtt_pair_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.POINTER(C.c_float)),
+                                    C.POINTER(C.POINTER(C.c_float)), C.POINTER(_I64)]),
+    "bldtt_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "bldtt_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+    "bldtt_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

@@ -85,6 +85,14 @@ class _PlanBase:
                 out[name] = (np.empty(0, np.int64), np.empty(0, np.int64))
         return out
 
+    def list_degrees(self) -> dict:
+        out = {}
+        for k, name in enumerate(TYPES):
+            d, n = C.POINTER(C.c_int8)(), C.c_int64()
+            check(lib().bldtt_get_list_degrees(self._handle, k, C.byref(d), C.byref(n)))
+            out[name] = np.ctypeslib.as_array(d, shape=(n.value,)).astype(np.int32) if n.value else np.empty(0, np.int32)
+        return out
+
     def stats(self) -> dict:
         s = _lib.Stats()
         check(lib().bldtt_get_stats(self._handle, C.byref(s)))
@@ -93,7 +101,10 @@ class _PlanBase:
                     n_target_clusters=s.n_target_clusters, n_source_clusters=s.n_source_clusters,
                     target_depth=s.target_depth, source_depth=s.source_depth, setup_ms=s.setup_ms,
                     traverse_ms=s.traverse_ms, compute_host_ms=s.compute_host_ms,
-                    phase_ms=dict(zip(_lib.PHASES, list(s.phase_ms))), profiled_computes=s.profiled_computes)
+                    phase_ms=dict(zip(_lib.PHASES, list(s.phase_ms))), profiled_computes=s.profiled_computes,
+                    down_degree=s.down_degree, degree_mask=s.degree_mask, sep_pairs=s.sep_pairs,
+                    sep_fallback=s.sep_fallback, sep_direct=s.sep_direct,
+                    pairs_per_degree={d: int(s.pairs_per_degree[d]) for d in range(13) if s.pairs_per_degree[d]})
 
     def traverse_host(self):
         check(lib().bldtt_traverse_host(self._handle))
@@ -140,6 +151,32 @@ class Plan(_PlanBase):
         out = np.empty(n * self.P)
         check(lib().bldtt_get_qhat(self._handle, out.ctypes.data_as(_lib._D)))
         return out.reshape(n, self.P)
+
+    def set_degree_model(self, model: np.ndarray | None, fallback: int = 8, tau: float = 1e-7):
+        """Per-pair degree policy of a plan set up with LEARNED_DEGREE (model None: fallback degree everywhere)."""
+        if model is None:
+            check(lib().bldtt_set_degree_model(self._handle, None, 0, int(fallback), float(tau)))
+            return
+        m = np.ascontiguousarray(model, dtype=np.float32)
+        check(lib().bldtt_set_degree_model(self._handle, m.ctypes.data, m.size, int(fallback), float(tau)))
+
+    def set_degree_test_rule(self):
+        check(lib().bldtt_set_degree_test_rule(self._handle))
+
+    def pair_errors(self, stream=None, with_pairs=False):
+        """(features[n, 4], log10 errors[n, 11][, pairs[n, 2]]) of every separated pair, measured on the GPU."""
+        n = C.c_int64()
+        f, e, pr = C.POINTER(C.c_float)(), C.POINTER(C.c_float)(), _lib._I64()
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_pair_errors(self._handle, _stream_ptr(stream), C.byref(n), C.byref(f), C.byref(e),
+                                          C.byref(pr)))
+        if n.value == 0:
+            out = (np.empty((0, 4), np.float32), np.empty((0, 11), np.float32), np.empty((0, 2), np.int64))
+        else:
+            out = (np.ctypeslib.as_array(f, shape=(n.value, 4)).copy(),
+                   np.ctypeslib.as_array(e, shape=(n.value, 11)).copy(),
+                   np.ctypeslib.as_array(pr, shape=(n.value, 2)).copy())
+        return out if with_pairs else out[:2]
 
     def phihat(self) -> np.ndarray:
         n = self.stats()["n_target_clusters"]
@@ -190,6 +227,52 @@ def direct_sum(targets, sources, kernel="coulomb", param=None, sel: torch.Tensor
                                      sx.numel(), sx.data_ptr(), sy.data_ptr(), sz.data_ptr(), q.data_ptr(), n,
                                      selp, out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def mlp_model_size() -> int:
+    return int(lib().bldtt_mlp_model_size())
+
+
+def _f32_cuda(t, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 cuda tensor")
+    return t
+
+
+def mlp_forward(model: torch.Tensor, features: torch.Tensor, stream=None) -> torch.Tensor:
+    """Predicted log10 pair errors [n, 11] for features [n, 4] (device tensors)."""
+    _f32_cuda(model, "model")
+    _f32_cuda(features, "features")
+    n = features.shape[0]
+    out = torch.empty((n, 11), dtype=torch.float32, device=features.device)
+    check(lib().bldtt_mlp_forward(model.data_ptr(), features.data_ptr(), n, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def mlp_loss_grad(model: torch.Tensor, features: torch.Tensor, targets: torch.Tensor, stream=None):
+    """(loss, gradient) of the mean squared error, computed by the GPU backward kernels."""
+    for t, nm in ((model, "model"), (features, "features"), (targets, "targets")):
+        _f32_cuda(t, nm)
+    n = features.shape[0]
+    grad = torch.empty(mlp_model_size() - 16, dtype=torch.float32, device=features.device)
+    loss = torch.empty(1, dtype=torch.float32, device=features.device)
+    check(lib().bldtt_mlp_loss_grad(model.data_ptr(), features.data_ptr(), targets.data_ptr(), n, grad.data_ptr(),
+                                    loss.data_ptr(), _stream_ptr(stream)))
+    return float(loss.item()), grad
+
+
+def mlp_train(features: np.ndarray, targets: np.ndarray, epochs: int = 200, batch: int = 1024, lr: float = 2e-3,
+              seed: int = 0, stream=None):
+    """Train the degree model on the GPU; returns (model record, loss per epoch)."""
+    f = np.ascontiguousarray(features, dtype=np.float32)
+    t = np.ascontiguousarray(targets, dtype=np.float32)
+    if f.ndim != 2 or f.shape[1] != 4 or t.shape != (f.shape[0], 11):
+        raise ValueError("features must be [n, 4] and targets [n, 11]")
+    model = np.empty(mlp_model_size(), dtype=np.float32)
+    hist = np.empty(epochs, dtype=np.float32)
+    check(lib().bldtt_mlp_train(f.ctypes.data, t.ctypes.data, f.shape[0], int(epochs), int(batch), float(lr),
+                                int(seed), model.ctypes.data, hist.ctypes.data, _stream_ptr(stream)))
+    return model, hist
 
 
 def version() -> str:

@@ -27,6 +27,8 @@ HOST_EXACT = ["-ffp-contract=off", "-fno-fast-math"]
 
 UNITS = [
     ("kernels.hip", DEVICE),
+    ("mlp.hip", DEVICE),
+    ("degree.cpp", HOST_EXACT + ["-D__HIP_PLATFORM_AMD__"]),
     ("tree.cpp", HOST_EXACT),
     ("traverse.cpp", HOST_EXACT),
     ("capi.cpp", HOST_EXACT + ["-D__HIP_PLATFORM_AMD__"]),

@@ -21,98 +21,12 @@
 #include <vector>
 
 #include "../../include/bldtt.h"
-#include "engine.hpp"
-#include "kernels.hpp"
-
-using namespace bldtt;
+#include "plan.hpp"
 
 namespace {
 
-thread_local std::string g_last_error = "no error";
 
-void set_error(const std::string& m) { g_last_error = m; }
 
-void hip_check(hipError_t e, const char* what) {
-    if (e == hipSuccess) return;
-    int code = e == hipErrorOutOfMemory ? BLDTT_ENOMEM : BLDTT_EDEVICE;
-    throw Error(code, std::string(what) + ": " + hipGetErrorString(e));
-}
-#define HIPCHK(x) hip_check((x), #x)
-
-template <class F>
-int guarded(F&& f) {
-    try {
-        f();
-        return BLDTT_OK;
-    } catch (const Error& e) {
-        set_error(e.what());
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        set_error("host allocation failed");
-        return BLDTT_ENOMEM;
-    } catch (const std::exception& e) {
-        set_error(e.what());
-        return BLDTT_EDEVICE;
-    } catch (...) {
-        set_error("unknown failure");
-        return BLDTT_EDEVICE;
-    }
-}
-
-double now_ms() {
-    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// Device allocation owned by a plan.
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    void alloc(size_t b) {
-        release();
-        if (b == 0) b = 8;
-        HIPCHK(hipMalloc(&p, b));
-        bytes = b;
-    }
-    void reserve(size_t b) {
-        if (b > bytes) alloc(b + b / 4);
-    }
-    template <class T>
-    T* as() const { return static_cast<T*>(p); }
-};
-
-// Pinned host staging buffer (allocated, never registered).
-struct PinnedBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    ~PinnedBuf() {
-        if (p) (void)hipHostFree(p);
-    }
-    void reserve(size_t b) {
-        if (b <= bytes) return;
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        bytes = 0;
-        HIPCHK(hipHostMalloc(&p, b + b / 4, hipHostMallocDefault));
-        bytes = b + b / 4;
-    }
-};
-
-struct DevTreeBufs {
-    DevBuf box, begin, count, nchild, child, parent;
-    DevTree view() const {
-        return DevTree{box.as<double>(), begin.as<int32_t>(), count.as<int32_t>(), nchild.as<int32_t>(),
-                       child.as<int32_t>(), parent.as<int32_t>()};
-    }
-};
 
 template <class T>
 void upload(DevBuf& b, const std::vector<T>& v) {
@@ -151,48 +65,6 @@ bool all_finite(const double* a, int64_t n) {
 
 }  // namespace
 
-struct bldtt_plan {
-    int32_t kind = 0;
-    double param = 0.0, theta = 0.7;
-    int degree = 6;
-    int64_t leaf = 500;
-    uint32_t flags = 0;
-    bool host_only = false, aliased = false;
-    int64_t M = 0, N = 0;
-    Tree S, Tsep;
-    const Tree& T() const { return aliased ? S : Tsep; }
-    Lists lists;
-    bool have_lists = false;
-    Work work;
-    bldtt_stats stats{};
-
-    // device state
-    DevBuf tx, ty, tz, sx, sy, sz, sq, perm, tab, qhat, phihat, phi_tree;
-    DevTreeBufs dS, dTsep;
-    const DevTreeBufs& dT() const { return aliased ? dS : dTsep; }
-    DevBuf src_leaves, up_parents, down_kids;
-    int n_src_leaves = 0;
-    std::vector<int64_t> up_off, down_off;   // per level offsets into up_parents / down_kids
-    DevBuf pitems, pentries, qitems, qentries, has_far;
-    PinnedBuf staging;
-    hipEvent_t staging_free = nullptr;
-    hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
-    bool prof_pending = false;
-
-    int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
-    int P() const { return (degree + 1) * (degree + 1) * (degree + 1); }
-    DevParticles dsrc() const { return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), sq.as<double>()}; }
-    DevParticles dtgt() const {
-        if (aliased) return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), nullptr};
-        return DevParticles{tx.as<double>(), ty.as<double>(), tz.as<double>(), nullptr};
-    }
-    ~bldtt_plan() {
-        if (staging_free) (void)hipEventDestroy(staging_free);
-        for (auto& e : prof_ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
-
 namespace {
 
 void validate(const bldtt_particles* p, int32_t kernel, double theta, int32_t degree, int64_t leaf_size) {
@@ -230,7 +102,8 @@ void fill_stats_tree(bldtt_plan* pl) {
 
 void do_traverse(bldtt_plan* pl) {
     double t0 = now_ms();
-    traverse(pl->T(), pl->S, pl->theta, pl->degree, (pl->flags & BLDTT_PP_CC_ONLY) != 0, pl->lists);
+    traverse(pl->T(), pl->S, pl->theta, pl->degree, (pl->flags & BLDTT_PP_CC_ONLY) != 0, pl->lists,
+             pl->varied_degree());
     pl->have_lists = true;
     for (int k = 0; k < 4; ++k) pl->stats.n_entries[k] = (int64_t)pl->lists.tc[k].size();
     pl->stats.traverse_ms = now_ms() - t0;
@@ -280,39 +153,41 @@ struct PhaseMark {
 
 constexpr int kBlockThreads = 256;   // threads per interaction work group (4 waves)
 
+inline int64_t cube(int d) { return (int64_t)(d + 1) * (d + 1) * (d + 1); }
+
 void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     double t0 = now_ms();
     const Tree& T = pl->T();
     const Tree& S = pl->S;
-    const int deg = pl->degree;
     const DevTree dS = pl->dS.view(), dT = pl->dT().view();
     const double* tab = pl->tab.as<double>();
     KernelSpec ks{pl->kind, pl->param};
     const bool fp32 = (pl->flags & BLDTT_FP32_EVAL) != 0;
+    const bool varied = pl->varied_degree();
 
     collect_profile(pl);
-    // 1. upward pass
-    {
-    PhaseMark mark(pl, BLDTT_PH_UP, st);
-    launch_up_leaf(deg, pl->src_leaves.as<int32_t>(), pl->n_src_leaves, dS, pl->dsrc(), tab, pl->qhat.as<double>(), st);
-    for (int l = S.depth; l >= 0; --l) {
-        int64_t b = pl->up_off[l], e = pl->up_off[l + 1];
-        launch_up_transfer(deg, pl->up_parents.as<int32_t>() + b, (int)(e - b), dS, tab, pl->qhat.as<double>(), st);
-    }
+    // 1. upward pass at the base degree, overlapping the host traversal (a
+    //    per-pair degree plan runs it after the degrees are chosen)
+    if (!varied) {
+        PhaseMark mark(pl, BLDTT_PH_UP, st);
+        upward(pl, pl->degree, st);
     }
 
-    // 2. traversal and work packing on the host, overlapping the upward pass
+    // 2. traversal, per-pair degrees, work packing
     do_traverse(pl);
     double tp = now_ms();
-    pack_work(T, S, pl->lists, deg, kBlockThreads * pl->tpt, kBlockThreads * pl->tpt_proxy, pl->work);
+    if (varied) select_degrees(pl, st);
+    pack_work(T, S, pl->lists, pl->degree, kBlockThreads * pl->tpt, kBlockThreads * pl->tpt_proxy, pl->work);
     pl->stats.traverse_ms += now_ms() - tp;
-    for (int k = 0; k < 4; ++k) pl->stats.interactions[k] = pl->work.interactions[k];
     Work& w = pl->work;
+    for (int k = 0; k < 4; ++k) pl->stats.interactions[k] = w.interactions[k];
+    pl->stats.down_degree = w.down_degree;
+    pl->stats.degree_mask = w.src_degrees | w.tgt_degrees;
     size_t bp = sizeof(Item) * w.pitems.size(), be = sizeof(Entry) * w.pentries.size();
     size_t bq = sizeof(Item) * w.qitems.size(), bqe = sizeof(Entry) * w.qentries.size();
-    size_t bf = w.leaf_has_far.size();
+    size_t bf = w.leaf_has_far.size(), bl = sizeof(Item) * w.prolong.size();
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t total = al(bp) + al(be) + al(bq) + al(bqe) + al(bf);
+    size_t total = al(bp) + al(be) + al(bq) + al(bqe) + al(bf) + al(bl);
     HIPCHK(hipEventSynchronize(pl->staging_free));      // the previous upload has left the staging buffer
     pl->staging.reserve(total);
     char* h = static_cast<char*>(pl->staging.p);
@@ -330,37 +205,52 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     put(pl->qitems, w.qitems.data(), bq);
     put(pl->qentries, w.qentries.data(), bqe);
     put(pl->has_far, w.leaf_has_far.data(), bf);
+    put(pl->prolong, w.prolong.data(), bl);
     HIPCHK(hipEventRecord(pl->staging_free, st));
 
-    // 3. CP + CC, then downward transfer
-    const int P = pl->P();
+    if (varied) {
+        PhaseMark mark(pl, BLDTT_PH_UP, st);
+        for (int d = 0; d <= kMaxDegree; ++d)
+            if (w.src_degrees >> d & 1) upward(pl, d, st);
+    }
+
+    // 3. CP + CC into proxy potentials per degree, lift to the downward degree,
+    //    downward transfer from the root
+    const int D = w.down_degree;
     {
         PhaseMark mark(pl, BLDTT_PH_CPCC, st);
-        launch_fill(pl->phihat.as<double>(), (int64_t)T.size() * P, 0.0, st);
-        launch_interact(ks, fp32, true, pl->tpt_proxy, deg, pl->qitems.as<DevItem>(), (int)w.qitems.size(),
-                        pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, pl->qhat.as<double>(),
-                        pl->phihat.as<double>(), st);
+        for (int d = 0; d <= kMaxDegree; ++d) {
+            if (!((w.tgt_degrees | (1u << D)) >> d & 1)) continue;
+            DevBuf& f = pl->phihat_deg[d];
+            f.reserve(sizeof(double) * T.size() * cube(d));
+            launch_fill(f.as<double>(), (int64_t)T.size() * cube(d), 0.0, st);
+        }
+        launch_interact(ks, fp32, true, pl->tpt_proxy, pl->qitems.as<DevItem>(), (int)w.qitems.size(),
+                        pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                        nullptr, deg_out(pl->phihat_deg), st);
     }
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
+        launch_prolong(pl->prolong.as<DevItem>(), (int)w.prolong.size(), dT, tab, deg_ptrs(pl->phihat_deg),
+                       pl->phihat_deg[D].as<double>(), D, st);
         for (int l = 1; l <= T.depth; ++l) {
             int64_t b = pl->down_off[l], e = pl->down_off[l + 1];
-            launch_down_transfer(deg, pl->down_kids.as<int32_t>() + b, (int)(e - b), dT, tab,
-                                 pl->phihat.as<double>(), st);
+            launch_down_transfer(D, pl->down_kids.as<int32_t>() + b, (int)(e - b), dT, tab,
+                                 pl->phihat_deg[D].as<double>(), st);
         }
     }
     // 4. PP + PC
     {
         PhaseMark mark(pl, BLDTT_PH_PPPC, st);
-        launch_interact(ks, fp32, false, pl->tpt, deg, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
-                        pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, pl->qhat.as<double>(),
-                        pl->phi_tree.as<double>(), st);
+        launch_interact(ks, fp32, false, pl->tpt, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
+                        pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                        pl->phi_tree.as<double>(), DegOut{}, st);
     }
     // 5. leaves to targets, caller order
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_LEAF, st);
-        launch_down_leaf(deg, pl->pitems.as<DevItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
-                         pl->dtgt(), dT, tab, pl->phihat.as<double>(), pl->phi_tree.as<double>(),
+        launch_down_leaf(D, pl->pitems.as<DevItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
+                         pl->dtgt(), dT, tab, pl->phihat_deg[D].as<double>(), pl->phi_tree.as<double>(),
                          pl->perm.as<int32_t>(), out, st);
     }
     if (pl->flags & BLDTT_PROFILE) pl->prof_pending = true;
@@ -405,14 +295,15 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     std::vector<int32_t> perm(M);
     for (int64_t i = 0; i < M; ++i) perm[i] = (int32_t)T.perm[i];
     upload(pl->perm, perm);
-    // Chebyshev points of the 2nd kind, xi_k = cos(pi k / n) evaluated as
-    // sin(pi (n - 2k) / (2n)) (exactly antisymmetric), and weights (-1)^k delta_k.
-    std::vector<double> tab(32, 0.0);
-    const int n = pl->degree;
-    for (int k = 0; k <= n; ++k) {
-        tab[k] = std::sin(M_PI * (double)(n - 2 * k) / (double)(2 * n));
-        tab[16 + k] = (k % 2 ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
-    }
+    // Chebyshev points of the 2nd kind for every degree d = 1..12, xi_k = cos(pi k / d)
+    // evaluated as sin(pi (d - 2k) / (2d)) (exactly antisymmetric), and weights
+    // (-1)^k delta_k; 32 doubles per degree.
+    std::vector<double> tab(32 * (kMaxDegree + 1), 0.0);
+    for (int d = 1; d <= kMaxDegree; ++d)
+        for (int k = 0; k <= d; ++k) {
+            tab[32 * d + k] = std::sin(M_PI * (double)(d - 2 * k) / (double)(2 * d));
+            tab[32 * d + 16 + k] = (k % 2 ? -1.0 : 1.0) * ((k == 0 || k == d) ? 0.5 : 1.0);
+        }
     upload(pl->tab, tab);
     std::vector<int32_t> leaves;
     for (int64_t c = 0; c < pl->S.size(); ++c)
@@ -424,9 +315,6 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     upload(pl->up_parents, ids);
     level_lists(T, false, ids, pl->down_off);
     upload(pl->down_kids, ids);
-    const int P = pl->P();
-    pl->qhat.alloc(sizeof(double) * pl->S.size() * P);
-    pl->phihat.alloc(sizeof(double) * T.size() * P);
     pl->phi_tree.alloc(sizeof(double) * M);
     HIPCHK(hipEventCreateWithFlags(&pl->staging_free, hipEventDisableTiming));
     if (pl->flags & BLDTT_PROFILE)
@@ -439,7 +327,6 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
 bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_param, double theta, int32_t degree,
                      int64_t leaf_size, uint32_t flags) {
     validate(p, kernel, theta, degree, leaf_size);
-    if (flags & BLDTT_LEARNED_DEGREE) throw Error(BLDTT_EUNSUPPORTED, "flag not implemented in this build");
     if ((flags & BLDTT_FP32_EVAL) && kernel == BLDTT_POLY_TEST)
         throw Error(BLDTT_EINVAL, "the polynomial test kernel runs in FP64 only");
     auto pl = std::make_unique<bldtt_plan>();
@@ -452,10 +339,44 @@ bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_par
     pl->M = p->M;
     pl->N = p->N;
     pl->aliased = p->M == p->N && p->tx == p->sx && p->ty == p->sy && p->tz == p->sz;
+    pl->policy.fallback = degree;
     return pl.release();
 }
 
 }  // namespace
+
+namespace bldtt {
+
+thread_local std::string g_last_error = "no error";
+void set_error(const std::string& m) { g_last_error = m; }
+
+// Proxy charges of every source cluster at degree d (Sec. 2.5): leaves from
+// their particles, then parents level by level from the deepest.
+void upward(bldtt_plan* pl, int d, hipStream_t st) {
+    const DevTree dS = pl->dS.view();
+    const double* tab = pl->tab.as<double>();
+    DevBuf& q = pl->qhat_deg[d];
+    q.reserve(sizeof(double) * pl->S.size() * cube(d));
+    launch_up_leaf(d, pl->src_leaves.as<int32_t>(), pl->n_src_leaves, dS, pl->dsrc(), tab, q.as<double>(), st);
+    for (int l = pl->S.depth; l >= 0; --l) {
+        int64_t b = pl->up_off[l], e = pl->up_off[l + 1];
+        launch_up_transfer(d, pl->up_parents.as<int32_t>() + b, (int)(e - b), dS, tab, q.as<double>(), st);
+    }
+}
+
+DegPtrs deg_ptrs(const DevBuf* bufs) {
+    DegPtrs p{};
+    for (int d = 0; d <= kMaxDegree; ++d) p.p[d] = bufs[d].as<double>();
+    return p;
+}
+
+DegOut deg_out(DevBuf* bufs) {
+    DegOut p{};
+    for (int d = 0; d <= kMaxDegree; ++d) p.p[d] = bufs[d].as<double>();
+    return p;
+}
+
+}  // namespace bldtt
 
 extern "C" {
 
@@ -565,6 +486,20 @@ int bldtt_get_lists(const bldtt_plan* plan, int type, const int64_t** tc, const 
     return BLDTT_OK;
 }
 
+int bldtt_get_list_degrees(const bldtt_plan* plan, int type, const int8_t** deg, int64_t* n) {
+    if (!plan || !deg || !n || type < 0 || type > 3) {
+        set_error("bad argument to bldtt_get_list_degrees");
+        return BLDTT_EINVAL;
+    }
+    if (!plan->have_lists) {
+        set_error("no traversal has run on this plan");
+        return BLDTT_ESTATE;
+    }
+    *deg = plan->lists.deg[type].data();
+    *n = (int64_t)plan->lists.deg[type].size();
+    return BLDTT_OK;
+}
+
 int bldtt_get_qhat(const bldtt_plan* plan, double* host_out) {
     if (!plan || !host_out) {
         set_error("bad argument to bldtt_get_qhat");
@@ -575,7 +510,9 @@ int bldtt_get_qhat(const bldtt_plan* plan, double* host_out) {
         return BLDTT_ESTATE;
     }
     return guarded([&] {
-        HIPCHK(hipMemcpy(host_out, plan->qhat.p, sizeof(double) * plan->S.size() * plan->P(), hipMemcpyDeviceToHost));
+        const DevBuf& q = plan->qhat_deg[plan->degree];
+        if (!q.p) throw Error(BLDTT_ESTATE, "no proxy charges at the plan's degree");
+        HIPCHK(hipMemcpy(host_out, q.p, sizeof(double) * plan->S.size() * plan->P(), hipMemcpyDeviceToHost));
     });
 }
 
@@ -589,8 +526,10 @@ int bldtt_get_phihat(const bldtt_plan* plan, double* host_out) {
         return BLDTT_ESTATE;
     }
     return guarded([&] {
-        HIPCHK(hipMemcpy(host_out, plan->phihat.p, sizeof(double) * plan->T().size() * plan->P(),
-                         hipMemcpyDeviceToHost));
+        const DevBuf& f = plan->phihat_deg[plan->degree];
+        if (!f.p || plan->work.down_degree != plan->degree)
+            throw Error(BLDTT_ESTATE, "no proxy potentials at the plan's degree");
+        HIPCHK(hipMemcpy(host_out, f.p, sizeof(double) * plan->T().size() * plan->P(), hipMemcpyDeviceToHost));
     });
 }
 

@@ -56,10 +56,28 @@ enum { PP = 0, PC = 1, CP = 2, CC = 3 };
 
 struct Lists {
     std::vector<int64_t> tc[4], sc[4];
-    void clear() { for (int k = 0; k < 4; ++k) { tc[k].clear(); sc[k].clear(); } }
+    std::vector<int8_t> deg[4];               // interpolation degree of each PC/CP/CC entry
+    std::vector<int64_t> sep_tc, sep_sc;      // separated pairs awaiting a (type, degree) choice
+    void clear() {
+        for (int k = 0; k < 4; ++k) { tc[k].clear(); sc[k].clear(); deg[k].clear(); }
+        sep_tc.clear();
+        sep_sc.clear();
+    }
+    void push(int type, int64_t t, int64_t s, int d) {
+        tc[type].push_back(t);
+        sc[type].push_back(s);
+        deg[type].push_back((int8_t)d);
+    }
 };
 
-void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out);
+// Algorithm 2.  With defer_separated, separated pairs are recorded in
+// sep_tc/sep_sc instead of being typed by the counts (their type then depends
+// on a per-pair degree chosen later); the recursion itself is unchanged.
+void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out,
+              bool defer_separated = false);
+
+// Type of a separated pair for degree d (Algorithm 2, separated branch).
+int separated_type(int64_t ct, int64_t cs, int d, bool pp_cc_only);
 
 // ---------------------------------------------------------------------------
 // Work items for the device (see kernels.hip for their consumers).
@@ -67,16 +85,19 @@ void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc
 // A source entry is two int32 {a, b}; kind = (uint32)b >> 29:
 //   SRC_RANGE, SRC_RANGE_GUARD: source particles at tree positions [a, a + (b & kCountMask));
 //       GUARD when the source box may contain a target, so r^2 == 0 terms are skipped;
-//   SRC_PROXY: the (n+1)^3 proxies of source cluster a with their proxy charges.
+//   SRC_PROXY: the (d+1)^3 proxies of source cluster a with their proxy charges,
+//       d = b & kCountMask the interpolation degree.
 // Adjacent particle ranges of one work group are merged into one entry.
 enum { SRC_RANGE = 0, SRC_RANGE_GUARD = 1, SRC_PROXY = 2 };
 constexpr int32_t kCountMask = (1 << 29) - 1;
 struct Entry { int32_t a, b; };
 
 // A work item: targets t0 .. t0+tn-1 (tree positions of particles, or proxy
-// indices of the target cluster), source entries [eb, ee), and the target
-// cluster (the leaf holding the particles, or the cluster owning the proxies).
-struct Item { int32_t t0, tn, eb, ee, cluster; };
+// indices of the target cluster), source entries [eb, ee), the target cluster
+// (the leaf holding the particles, or the cluster owning the proxies), the
+// degree of the target proxies, and the output slot (particle targets write
+// out[slot + r], proxy targets out_degree[slot * (degree+1)^3 + t0 + r]).
+struct Item { int32_t t0, tn, eb, ee, cluster, degree, slot; };
 
 struct Work {
     std::vector<Entry> pentries;                // particle targets: PP ranges + PC proxies, per leaf
@@ -84,10 +105,16 @@ struct Work {
     std::vector<Entry> qentries;                // proxy targets: CP ranges + CC proxies, per cluster
     std::vector<Item> qitems;
     std::vector<uint8_t> leaf_has_far;          // per target cluster: chain has CP/CC entries
+    std::vector<Item> prolong;                  // per cluster: bit mask (in .degree) of the degrees
+                                                // whose proxy potentials are lifted to the downward degree
+    uint32_t src_degrees = 0, tgt_degrees = 0;  // bit d set: proxy charges / potentials of degree d used
+    int down_degree = 0;                        // degree of the downward pass
     double interactions[4] = {0, 0, 0, 0};
 };
 
-// tile: targets per particle item; ptile: proxies per proxy item.
+// tile: targets per particle item; ptile: proxies per proxy item.  Degrees come
+// from the lists (L.deg); `degree` is the plan's base degree (the downward
+// degree when no proxy potentials are produced).
 void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w);
 
 }  // namespace bldtt

@@ -190,8 +190,8 @@ template <int KIND, bool F32, int T, bool PROXY_TGT>
 __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles tgt, DevTree Tt,
                                                      DevParticles src, DevTree S, const double* __restrict__ tab,
-                                                     const double* __restrict__ qhat, int m, double param,
-                                                     double* __restrict__ out) {
+                                                     DegPtrs qhat, double param, double* __restrict__ out,
+                                                     DegOut pout) {
     using St = Stage<F32>;
     using V = typename St::V;
     using R = typename std::conditional<F32, float, double>::type;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
     __shared__ V lds[kChunk];
 
     const DevItem it = items[blockIdx.x];
-    const int P = m * m * m;
+    const int mt = it.degree + 1, Pt = mt * mt * mt;      // target proxies (PROXY_TGT)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slab = wave * 64 * T;
     const bool active = slab < it.tn;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
         int idx = it.t0 + (r < it.tn ? r : 0);
         double x, y, z;
         if (PROXY_TGT) {
-            proxy_point(tbox, m, tab, idx, x, y, z);
+            proxy_point(tbox, mt, tab + 32 * it.degree, idx, x, y, z);
         } else {
             x = tgt.x[idx];
             y = tgt.y[idx];
@@ -239,16 +239,20 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
         const int2 en = entries[e];
         const int kind = (int)((unsigned)en.y >> 29);
         const bool prox = kind == 2;
-        const int nsrc = prox ? P : (en.y & ((1 << 29) - 1));
+        const int low = en.y & ((1 << 29) - 1);               // count, or degree of proxy sources
+        const int ms = low + 1, P = ms * ms * ms;
+        const int nsrc = prox ? P : low;
         const double* sbox = S.box + 6 * en.x;
+        const double* stab = tab + 32 * (prox ? low : 0);
+        const double* sq = qhat.p[prox ? low : 0];
         for (int c0 = 0; c0 < nsrc; c0 += kChunk) {
             const int cnt = min(kChunk, nsrc - c0);
             __syncthreads();
             for (int j = threadIdx.x; j < cnt; j += kBlock) {
                 double x, y, z, q;
                 if (prox) {
-                    proxy_point(sbox, m, tab, c0 + j, x, y, z);
-                    q = qhat[(int64_t)en.x * P + c0 + j];
+                    proxy_point(sbox, ms, stab, c0 + j, x, y, z);
+                    q = sq[(int64_t)en.x * P + c0 + j];
                 } else {
                     const int b = en.x + c0 + j;
                     x = src.x[b];
@@ -301,8 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
     for (int j = 0; j < T; ++j) {
         int r = slab + lane + 64 * j;
         if (r < it.tn) {
-            if (PROXY_TGT) out[(int64_t)it.cluster * P + it.t0 + r] = acc[j];
-            else out[it.t0 + r] = acc[j];
+            if (PROXY_TGT) pout.p[it.degree][(int64_t)it.slot * Pt + it.t0 + r] = acc[j];
+            else out[it.slot + r] = acc[j];
         }
     }
 }
@@ -459,6 +463,82 @@ __global__ __launch_bounds__(kBlock) void k_down_transfer(const int32_t* __restr
     for (int k = threadIdx.x; k < P; k += kBlock) phihat[(int64_t)c * P + k] += b[k];
 }
 
+// Runtime-degree basis (m <= 13 nodes) for the degree-lifting kernel.
+__device__ __forceinline__ void basis1d_rt(int m, double lo, double hi, const double* __restrict__ tab, double y,
+                                           double* L) {
+    int hit = -1;
+    for (int k = 0; k < m; ++k)
+        if (y - node_at(lo, hi, tab[k]) == 0.0 && hit < 0) hit = k;
+    if (hit >= 0) {
+        for (int k = 0; k < m; ++k) L[k] = k == hit ? 1.0 : 0.0;
+        return;
+    }
+    double den = 0.0;
+    for (int k = 0; k < m; ++k) {
+        L[k] = tab[16 + k] / (y - node_at(lo, hi, tab[k]));
+        den += L[k];
+    }
+    for (int k = 0; k < m; ++k) L[k] = L[k] / den;
+}
+
+// ---------------------------------------------------------------------------
+// Degree lifting of proxy potentials: the degree-d interpolant of a cluster,
+// evaluated at the cluster's degree-D grid, is added to its degree-D proxy
+// potentials.  Exact for d <= D (a degree-d polynomial is reproduced), so
+// one downward pass at degree D carries every degree.  One work group per
+// cluster (item.degree holds the bit mask of the degrees to lift), so the
+// additions into one cluster never race.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_prolong(const DevItem* __restrict__ items, DevTree T,
+                                                    const double* __restrict__ tab, DegPtrs from, double* __restrict__ to,
+                                                    int D) {
+    constexpr int MX = 13;
+    __shared__ double mat[3][MX][MX];              // mat[dim][k (degree d)][kb (degree D)]
+    __shared__ double a[MX * MX * MX], b[MX * MX * MX];
+    const DevItem it = items[blockIdx.x];
+    const int c = it.cluster;
+    const int mD = D + 1, PD = mD * mD * mD;
+    const double* box = T.box + 6 * c;
+    const double* tabD = tab + 32 * D;
+    for (int d = 0; d < MX; ++d) {
+        if (!((unsigned)it.degree >> d & 1u)) continue;
+        const int md = d + 1, Pd = md * md * md;
+        const double* tabd = tab + 32 * d;
+        __syncthreads();
+        if ((int)threadIdx.x < 3 * mD) {
+            int dim = threadIdx.x / mD, kb = threadIdx.x % mD;
+            double L[MX];
+            basis1d_rt(md, box[dim], box[3 + dim], tabd, node_at(box[dim], box[3 + dim], tabD[kb]), L);
+            for (int k = 0; k < md; ++k) mat[dim][k][kb] = L[k];
+        }
+        for (int k = threadIdx.x; k < Pd; k += kBlock) a[k] = from.p[d][(int64_t)c * Pd + k];
+        __syncthreads();
+        // x: (md, md, md) -> (mD, md, md)
+        for (int idx = threadIdx.x; idx < mD * md * md; idx += kBlock) {
+            int kb = idx % mD, rest = idx / mD;
+            double s = 0.0;
+            for (int k = 0; k < md; ++k) s = fma(mat[0][k][kb], a[k + md * rest], s);
+            b[idx] = s;
+        }
+        __syncthreads();
+        // y: (mD, md, md) -> (mD, mD, md)
+        for (int idx = threadIdx.x; idx < mD * mD * md; idx += kBlock) {
+            int i1 = idx % mD, kb = (idx / mD) % mD, i3 = idx / (mD * mD);
+            double s = 0.0;
+            for (int k = 0; k < md; ++k) s = fma(mat[1][k][kb], b[i1 + mD * (k + md * i3)], s);
+            a[idx] = s;
+        }
+        __syncthreads();
+        // z: (mD, mD, md) -> (mD, mD, mD), added to the degree-D proxy potentials
+        for (int idx = threadIdx.x; idx < PD; idx += kBlock) {
+            int i12 = idx % (mD * mD), kb = idx / (mD * mD);
+            double s = 0.0;
+            for (int k = 0; k < md; ++k) s = fma(mat[2][k][kb], a[i12 + mD * mD * k], s);
+            to[(int64_t)c * PD + idx] += s;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Downward pass, leaves: phi(x_i) = phi_PP+PC(x_i) + sum_k L_k(x_i) phihat_leaf[k],
 // written to out[perm[i]] (caller order).
@@ -504,6 +584,65 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
         }
         out[perm[p]] = v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair error of the degree-d cluster-cluster approximation (training data
+// for the degree model): for separated pair p = (tc, sc), the pair's proxy
+// potentials phip[p] (target grid of tc, degree d) are interpolated to the
+// particles of tc and compared with the pair's exact sum exact[off[p] + r]:
+//     err[p] = ||approx - exact|| / ||exact||   (NaN when ||exact|| = 0).
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_pair_error(const int32_t* __restrict__ pair_tc,
+                                                       const int64_t* __restrict__ exact_off,
+                                                       const double* __restrict__ exact, const double* __restrict__ phip,
+                                                       DevParticles tgt, DevTree T, const double* __restrict__ tab,
+                                                       double* __restrict__ err) {
+    constexpr int P = M * M * M;
+    __shared__ double ph[P];
+    __shared__ double r_e[kBlock], r_x[kBlock];
+    const int pr = blockIdx.x;
+    const int tc = pair_tc[pr];
+    for (int k = threadIdx.x; k < P; k += kBlock) ph[k] = phip[(int64_t)pr * P + k];
+    __syncthreads();
+    const double* box = T.box + 6 * tc;
+    const int b = T.begin[tc], n = T.count[tc];
+    double se = 0.0, sx = 0.0;
+    for (int r = threadIdx.x; r < n; r += kBlock) {
+        const int p = b + r;
+        double Lx[M], Ly[M], Lz[M];
+        basis1d<M>(box[0], box[3], tab, tgt.x[p], Lx);
+        basis1d<M>(box[1], box[4], tab, tgt.y[p], Ly);
+        basis1d<M>(box[2], box[5], tab, tgt.z[p], Lz);
+        double s3 = 0.0;
+        for (int k3 = 0; k3 < M; ++k3) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int k2 = 0; k2 < M; ++k2) {
+                const double* row = ph + M * (k2 + M * k3);
+                double s1 = 0.0;
+#pragma unroll
+                for (int k1 = 0; k1 < M; ++k1) s1 = fma(Lx[k1], row[k1], s1);
+                s2 = fma(Ly[k2], s1, s2);
+            }
+            s3 = fma(Lz[k3], s2, s3);
+        }
+        const double ex = exact[exact_off[pr] + r];
+        se = fma(s3 - ex, s3 - ex, se);
+        sx = fma(ex, ex, sx);
+    }
+    r_e[threadIdx.x] = se;
+    r_x[threadIdx.x] = sx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            r_e[threadIdx.x] += r_e[threadIdx.x + w];
+            r_x[threadIdx.x] += r_x[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) err[pr] = r_x[0] > 0.0 ? sqrt(r_e[0] / r_x[0]) : (double)NAN;
 }
 
 // ---------------------------------------------------------------------------
@@ -626,6 +765,13 @@ struct DownTransfer {
     }
 };
 template <int M>
+struct PairError {
+    static void run(const int32_t* pair_tc, int n, const int64_t* off, const double* exact, const double* phip,
+                    DevParticles tgt, DevTree T, const double* tab, double* err, hipStream_t st) {
+        hipLaunchKernelGGL(k_pair_error<M>, dim3(n), dim3(kBlock), 0, st, pair_tc, off, exact, phip, tgt, T, tab, err);
+    }
+};
+template <int M>
 struct DownLeaf {
     static void run(const DevItem* items, int n, const uint8_t* has_far, DevParticles tgt, DevTree T,
                     const double* tab, const double* phihat, const double* phi_tree, const int32_t* perm,
@@ -648,21 +794,21 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
 void launch_up_leaf(int degree, const int32_t* leaves, int n_leaves, DevTree S, DevParticles src,
                     const double* tab, double* qhat, hipStream_t st) {
     if (n_leaves <= 0) return;
-    by_degree<UpLeaf>(degree, leaves, n_leaves, S, src, tab, qhat, st);
+    by_degree<UpLeaf>(degree, leaves, n_leaves, S, src, tab + 32 * degree, qhat, st);
     CHECK_LAUNCH();
 }
 
 void launch_up_transfer(int degree, const int32_t* parents, int n_parents, DevTree S, const double* tab,
                         double* qhat, hipStream_t st) {
     if (n_parents <= 0) return;
-    by_degree<UpTransfer>(degree, parents, n_parents, S, tab, qhat, st);
+    by_degree<UpTransfer>(degree, parents, n_parents, S, tab + 32 * degree, qhat, st);
     CHECK_LAUNCH();
 }
 
 void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T, const double* tab,
                           double* phihat, hipStream_t st) {
     if (n_kids <= 0) return;
-    by_degree<DownTransfer>(degree, kids, n_kids, T, tab, phihat, st);
+    by_degree<DownTransfer>(degree, kids, n_kids, T, tab + 32 * degree, phihat, st);
     CHECK_LAUNCH();
 }
 
@@ -679,27 +825,26 @@ void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T
 namespace {
 template <int KK, bool F32, bool PROXY_TGT>
 void launch_interact_t(int tpt, const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
-                       DevParticles src, DevTree S, const double* tab, const double* qhat, int m, double param,
-                       double* out, hipStream_t st) {
+                       DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double param, double* out,
+                       DegOut pout, hipStream_t st) {
     switch (tpt) {
     case 1: hipLaunchKernelGGL((k_interact<KK, F32, 1, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, m, param, out); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout); break;
     case 2: hipLaunchKernelGGL((k_interact<KK, F32, 2, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, m, param, out); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout); break;
     case 4: hipLaunchKernelGGL((k_interact<KK, F32, 4, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, m, param, out); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout); break;
     default: throw Error(-1, "targets per thread must be 1, 2 or 4");
     }
 }
 }  // namespace
 
-void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, int degree, const DevItem* items,
-                     int n_items, const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S,
-                     const double* tab, const double* qhat, double* out, hipStream_t st) {
+void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const DevItem* items, int n_items,
+                     const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
+                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st) {
     if (n_items <= 0) return;
     if (fp32 && k.kind == K_POLY) throw Error(-5, "the polynomial test kernel runs in FP64 only");
-    const int m = degree + 1;
-#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, m, k.param, out, st)
+#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, st)
     if (fp32) {
         if (proxy_targets) { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, true)); }
         else { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, false)); }
@@ -715,7 +860,22 @@ void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,
                       const double* phi_tree, const int32_t* perm, double* out, hipStream_t st) {
     if (n_items <= 0) return;
-    by_degree<DownLeaf>(degree, items, n_items, has_far, tgt, T, tab, phihat, phi_tree, perm, out, st);
+    by_degree<DownLeaf>(degree, items, n_items, has_far, tgt, T, tab + 32 * degree, phihat, phi_tree, perm, out, st);
+    CHECK_LAUNCH();
+}
+
+void launch_pair_error(int degree, const int32_t* pair_tc, int n_pairs, const int64_t* exact_off,
+                       const double* exact, const double* phip, DevParticles tgt, DevTree T, const double* tab,
+                       double* err, hipStream_t st) {
+    if (n_pairs <= 0) return;
+    by_degree<PairError>(degree, pair_tc, n_pairs, exact_off, exact, phip, tgt, T, tab + 32 * degree, err, st);
+    CHECK_LAUNCH();
+}
+
+void launch_prolong(const DevItem* items, int n_items, DevTree T, const double* tab, DegPtrs from, double* to,
+                    int down_degree, hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(k_prolong, dim3(n_items), dim3(kBlock), 0, st, items, T, tab, from, to, down_degree);
     CHECK_LAUNCH();
 }
 

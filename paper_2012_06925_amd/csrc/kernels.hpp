@@ -32,8 +32,14 @@ struct DevParticles {
 };
 
 // Work item shared with the host packer (engine.hpp, struct Item): targets
-// t0 .. t0+tn-1 of target cluster `cluster`, source entries [eb, ee).
-struct DevItem { int32_t t0, tn, eb, ee, cluster; };
+// t0 .. t0+tn-1 of target cluster `cluster` (proxies of degree `degree`),
+// source entries [eb, ee), output slot.  The node table holds 32 doubles per
+// degree: tab[32 d + k] = xi_k, tab[32 d + 16 + k] = w_k of degree d.
+struct DevItem { int32_t t0, tn, eb, ee, cluster, degree, slot; };
+
+// Per-degree arrays (index = interpolation degree 0..12; unused degrees null).
+struct DegPtrs { const double* p[13]; };
+struct DegOut { double* p[13]; };
 
 struct KernelSpec {
     int kind;
@@ -54,9 +60,19 @@ void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T
 // Interaction sums: proxy_targets = false for PP + PC into the particles of a
 // leaf (out = potentials in tree order), true for CP + CC into the proxies of
 // a cluster (out = proxy potentials).  tpt: targets per thread (1, 2 or 4).
-void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, int degree, const DevItem* items,
-                     int n_items, const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S,
-                     const double* tab, const double* qhat, double* out, hipStream_t st);
+void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const DevItem* items, int n_items,
+                     const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
+                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st);
+
+// Per-pair relative error of degree-d proxy potentials phip[p] interpolated to
+// the particles of pair_tc[p], against exact[exact_off[p] + r].
+void launch_pair_error(int degree, const int32_t* pair_tc, int n_pairs, const int64_t* exact_off,
+                       const double* exact, const double* phip, DevParticles tgt, DevTree T, const double* tab,
+                       double* err, hipStream_t st);
+
+// Lift the proxy potentials of (cluster, degree) items to the downward degree.
+void launch_prolong(const DevItem* items, int n_items, DevTree T, const double* tab, DegPtrs from, double* to,
+                    int down_degree, hipStream_t st);
 
 void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8_t* has_far,
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,

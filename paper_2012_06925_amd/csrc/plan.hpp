@@ -1,0 +1,169 @@
+// plan.hpp -- the opaque bldtt_plan behind the C ABI, and the small RAII
+// helpers for device and pinned host memory it owns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bldtt.h"
+#include "degree.hpp"
+#include "engine.hpp"
+#include "kernels.hpp"
+
+namespace bldtt {
+
+inline void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    int code = e == hipErrorOutOfMemory ? BLDTT_ENOMEM : BLDTT_EDEVICE;
+    throw Error(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x)
+
+inline double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocation owned by a plan.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) b = 8;
+        HIPCHK(hipMalloc(&p, b));
+        bytes = b;
+    }
+    void reserve(size_t b) {
+        if (b > bytes) alloc(b + b / 4);
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host staging buffer (allocated, never registered).
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void reserve(size_t b) {
+        if (b <= bytes) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        HIPCHK(hipHostMalloc(&p, b + b / 4, hipHostMallocDefault));
+        bytes = b + b / 4;
+    }
+};
+
+struct DevTreeBufs {
+    DevBuf box, begin, count, nchild, child, parent;
+    DevTree view() const {
+        return DevTree{box.as<double>(), begin.as<int32_t>(), count.as<int32_t>(), nchild.as<int32_t>(),
+                       child.as<int32_t>(), parent.as<int32_t>()};
+    }
+};
+
+// Last failure message of the calling thread (capi.cpp).
+void set_error(const std::string& m);
+extern thread_local std::string g_last_error;
+
+// Run f, mapping every exception to a bldtt_status and the thread's message.
+template <class F>
+inline int guarded(F&& f) {
+    try {
+        f();
+        return BLDTT_OK;
+    } catch (const Error& e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return BLDTT_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return BLDTT_EDEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return BLDTT_EDEVICE;
+    }
+}
+
+}  // namespace bldtt
+
+using namespace bldtt;
+
+struct bldtt_plan {
+    int32_t kind = 0;
+    double param = 0.0, theta = 0.7;
+    int degree = 6;
+    int64_t leaf = 500;
+    uint32_t flags = 0;
+    bool host_only = false, aliased = false;
+    int64_t M = 0, N = 0;
+    Tree S, Tsep;
+    const Tree& T() const { return aliased ? S : Tsep; }
+    Lists lists;
+    bool have_lists = false;
+    Work work;
+    bldtt_stats stats{};
+
+    // device state
+    DevBuf tx, ty, tz, sx, sy, sz, sq, perm, tab, phi_tree;
+    DevBuf qhat_deg[kMaxDegree + 1], phihat_deg[kMaxDegree + 1];   // proxy charges / potentials per degree
+    DevTreeBufs dS, dTsep;
+    const DevTreeBufs& dT() const { return aliased ? dS : dTsep; }
+    DevBuf src_leaves, up_parents, down_kids;
+    int n_src_leaves = 0;
+    std::vector<int64_t> up_off, down_off;   // per level offsets into up_parents / down_kids
+    DevBuf pitems, pentries, qitems, qentries, has_far, prolong;
+    DegreePolicy policy;                     // per-pair degree choice (BLDTT_LEARNED_DEGREE)
+    DevBuf sel_feats, sel_counts, sel_choice;// per-pair choice inputs / output on the device
+    PinnedBuf sel_in, sel_out;
+    std::vector<float> pe_feats, pe_errs;    // last bldtt_pair_errors result
+    std::vector<int64_t> pe_pairs;
+    bool varied_degree() const { return (flags & BLDTT_LEARNED_DEGREE) != 0; }
+    PinnedBuf staging;
+    hipEvent_t staging_free = nullptr;
+    hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
+    bool prof_pending = false;
+
+    int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
+    int P() const { return (degree + 1) * (degree + 1) * (degree + 1); }
+    DevParticles dsrc() const { return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), sq.as<double>()}; }
+    DevParticles dtgt() const {
+        if (aliased) return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), nullptr};
+        return DevParticles{tx.as<double>(), ty.as<double>(), tz.as<double>(), nullptr};
+    }
+    ~bldtt_plan() {
+        if (policy.dev_model) (void)hipFree(policy.dev_model);
+        if (staging_free) (void)hipEventDestroy(staging_free);
+        for (auto& e : prof_ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+
+namespace bldtt {
+// Per-pair (type, degree) choice for the separated pairs of the last traversal
+// (BLDTT_LEARNED_DEGREE): moves plan->lists.sep_* into the typed lists.
+void select_degrees(bldtt_plan* pl, hipStream_t st);
+// Proxy charges of every source cluster at degree d into plan->qhat_deg[d].
+void upward(bldtt_plan* pl, int d, hipStream_t st);
+DegPtrs deg_ptrs(const DevBuf* bufs);
+DegOut deg_out(DevBuf* bufs);
+}  // namespace bldtt

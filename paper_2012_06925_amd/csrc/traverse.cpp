@@ -17,18 +17,32 @@
 #include "engine.hpp"
 
 namespace bldtt {
+
+int separated_type(int64_t ct, int64_t cs, int d, bool pp_cc_only) {
+    const int64_t np = (int64_t)(d + 1) * (d + 1) * (d + 1);
+    if (ct > np && cs > np) return CC;
+    if (pp_cc_only) return PP;
+    if (ct > np) return CP;
+    if (cs > np) return PC;
+    return PP;
+}
+
 namespace {
+
+constexpr int kSeparated = 4;   // step() result: separated pair, type deferred
 
 struct Ctx {
     const Tree& T;
     const Tree& S;
     double theta;
-    int64_t np;
+    int degree;
     bool pp_cc_only;
+    bool defer;
 };
 
-// One step of Algorithm 2.  Returns the list type for a terminal pair, or -1
-// after appending the child pairs to `kids`.
+// One step of Algorithm 2.  Returns the list type for a terminal pair
+// (kSeparated when the choice is deferred), or -1 after passing the child
+// pairs to push_pair.
 template <class Push>
 int step(const Ctx& x, int64_t t, int64_t s, Push&& push_pair) {
     const Tree& T = x.T;
@@ -39,13 +53,7 @@ int step(const Ctx& x, int64_t t, int64_t s, Push&& push_pair) {
     double R = std::sqrt((dx * dx + dy * dy) + dz * dz);
     bool sep = R > 0.0 && (T.radius[t] + S.radius[s]) / R < x.theta;
     int64_t ct = T.count[t], cs = S.count[s];
-    if (sep) {
-        if (ct > x.np && cs > x.np) return CC;
-        if (x.pp_cc_only) return PP;
-        if (ct > x.np) return CP;
-        if (cs > x.np) return PC;
-        return PP;
-    }
+    if (sep) return x.defer ? kSeparated : separated_type(ct, cs, x.degree, x.pp_cc_only);
     bool tl = T.is_leaf(t), sl = S.is_leaf(s);
     if (tl && sl) return PP;
     bool into_target = sl ? true : (tl ? false : (cs < ct));
@@ -57,18 +65,25 @@ int step(const Ctx& x, int64_t t, int64_t s, Push&& push_pair) {
     return -1;
 }
 
+void record(Lists& out, int ty, int64_t t, int64_t s, int degree) {
+    if (ty == kSeparated) {
+        out.sep_tc.push_back(t);
+        out.sep_sc.push_back(s);
+    } else {
+        out.push(ty, t, s, degree);
+    }
+}
+
 void recurse(const Ctx& x, int64_t t, int64_t s, Lists& out) {
     int ty = step(x, t, s, [&](int64_t a, int64_t b) { recurse(x, a, b, out); });
-    if (ty >= 0) {
-        out.tc[ty].push_back(t);
-        out.sc[ty].push_back(s);
-    }
+    if (ty >= 0) record(out, ty, t, s, x.degree);
 }
 
 }  // namespace
 
-void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out) {
-    Ctx x{T, S, theta, (int64_t)(degree + 1) * (degree + 1) * (degree + 1), pp_cc_only};
+void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out,
+              bool defer_separated) {
+    Ctx x{T, S, theta, degree, pp_cc_only, defer_separated};
     out.clear();
     // Breadth-first expansion until there is enough independent work, then
     // depth-first recursion per frontier pair on all threads.  Per-pair lists
@@ -79,24 +94,22 @@ void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc
         nxt.clear();
         for (auto& pr : cur) {
             int ty = step(x, pr.first, pr.second, [&](int64_t a, int64_t b) { nxt.emplace_back(a, b); });
-            if (ty >= 0) {
-                out.tc[ty].push_back(pr.first);
-                out.sc[ty].push_back(pr.second);
-            }
+            if (ty >= 0) record(out, ty, pr.first, pr.second, degree);
         }
         cur.swap(nxt);
     }
     std::vector<Lists> part(cur.size());
     parallel_run((int64_t)cur.size(), [&](int64_t i) { recurse(x, cur[i].first, cur[i].second, part[i]); });
     for (int k = 0; k < 4; ++k) {
-        size_t tot = out.tc[k].size();
-        for (auto& p : part) tot += p.tc[k].size();
-        out.tc[k].reserve(tot);
-        out.sc[k].reserve(tot);
         for (auto& p : part) {
             out.tc[k].insert(out.tc[k].end(), p.tc[k].begin(), p.tc[k].end());
             out.sc[k].insert(out.sc[k].end(), p.sc[k].begin(), p.sc[k].end());
+            out.deg[k].insert(out.deg[k].end(), p.deg[k].begin(), p.deg[k].end());
         }
+    }
+    for (auto& p : part) {
+        out.sep_tc.insert(out.sep_tc.end(), p.sep_tc.begin(), p.sep_tc.end());
+        out.sep_sc.insert(out.sep_sc.end(), p.sep_sc.begin(), p.sep_sc.end());
     }
 }
 
@@ -105,21 +118,28 @@ namespace {
 // CSR of the entries of some types, grouped by target cluster in list order.
 struct ByTarget {
     std::vector<int64_t> off;      // n_clusters + 1
-    std::vector<int64_t> code;     // (source cluster << 2) | type
+    std::vector<int64_t> sc;       // source cluster
+    std::vector<int8_t> type, deg;
 };
 
-ByTarget group(const Tree& T, const Lists& L, int t0, int t1) {
+ByTarget group(const Tree& T, const Lists& L, int t0, int t1, int degree) {
     ByTarget g;
     int64_t nc = T.size();
     g.off.assign(nc + 1, 0);
     for (int ty = t0; ty <= t1; ++ty)
         for (int64_t tc : L.tc[ty]) g.off[tc + 1]++;
     for (int64_t c = 0; c < nc; ++c) g.off[c + 1] += g.off[c];
-    g.code.resize(g.off[nc]);
+    g.sc.resize(g.off[nc]);
+    g.type.resize(g.off[nc]);
+    g.deg.resize(g.off[nc]);
     std::vector<int64_t> fill(g.off.begin(), g.off.end() - 1);
     for (int ty = t0; ty <= t1; ++ty)
-        for (size_t e = 0; e < L.tc[ty].size(); ++e)
-            g.code[fill[L.tc[ty][e]]++] = (L.sc[ty][e] << 2) | ty;
+        for (size_t e = 0; e < L.tc[ty].size(); ++e) {
+            int64_t at = fill[L.tc[ty][e]]++;
+            g.sc[at] = L.sc[ty][e];
+            g.type[at] = (int8_t)ty;
+            g.deg[at] = L.deg[ty].empty() ? (int8_t)degree : L.deg[ty][e];
+        }
     return g;
 }
 
@@ -152,26 +172,42 @@ void emit_ranges(std::vector<std::pair<int64_t, int64_t>>& rng_plain, std::vecto
     }
 }
 
+inline int64_t cube(int d) { return (int64_t)(d + 1) * (d + 1) * (d + 1); }
+
+inline Entry proxy_entry(int64_t sc, int d) {
+    return Entry{(int32_t)sc, (int32_t)((uint32_t)SRC_PROXY << 29 | (uint32_t)d)};
+}
+
 }  // namespace
 
 void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w) {
-    const int64_t np = (int64_t)(degree + 1) * (degree + 1) * (degree + 1);
     w = Work();
+    auto deg_of = [&](int ty, size_t e) { return L.deg[ty].empty() ? degree : (int)L.deg[ty][e]; };
     for (int ty = 0; ty < 4; ++ty) {
         double acc = 0.0;
         for (size_t e = 0; e < L.tc[ty].size(); ++e) {
-            double ct = ty == PP || ty == PC ? (double)T.count[L.tc[ty][e]] : (double)np;
-            double cs = ty == PP || ty == CP ? (double)S.count[L.sc[ty][e]] : (double)np;
+            double np = (double)cube(deg_of(ty, e));
+            double ct = ty == PP || ty == PC ? (double)T.count[L.tc[ty][e]] : np;
+            double cs = ty == PP || ty == CP ? (double)S.count[L.sc[ty][e]] : np;
             acc += ct * cs;
+            if (ty == PC || ty == CC) w.src_degrees |= 1u << deg_of(ty, e);
+            if (ty == CP || ty == CC) w.tgt_degrees |= 1u << deg_of(ty, e);
         }
         w.interactions[ty] = acc;
     }
+    // Downward degree: the largest degree of any proxy potential (lower degrees
+    // are lifted to it exactly), or the base degree when there are none.
+    w.down_degree = degree;
+    for (int d = kMaxDegree; d >= 0; --d)
+        if (w.tgt_degrees >> d & 1) {
+            w.down_degree = d;
+            break;
+        }
 
-    ByTarget part = group(T, L, PP, PC);
-    ByTarget prox = group(T, L, CP, CC);
+    ByTarget part = group(T, L, PP, PC, degree);
+    ByTarget prox = group(T, L, CP, CC, degree);
     const int64_t nc = T.size();
     std::vector<std::pair<int64_t, int64_t>> rp, rg;
-    const uint32_t proxy_code = (uint32_t)SRC_PROXY << 29;
 
     // Particle targets: per target leaf, the PP/PC entries of the leaf and of
     // every ancestor (each leaf owns its targets, so no two items share an output).
@@ -185,10 +221,10 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
         for (int64_t c = leaf; c >= 0; c = T.parent[c]) {
             if (prox.off[c + 1] > prox.off[c]) far = true;
             for (int64_t e = part.off[c]; e < part.off[c + 1]; ++e) {
-                int64_t sc = part.code[e] >> 2;
-                if ((int)(part.code[e] & 3) == PC) {
-                    w.pentries.push_back(Entry{(int32_t)sc, (int32_t)proxy_code});
-                    src += (double)np;
+                int64_t sc = part.sc[e];
+                if (part.type[e] == PC) {
+                    w.pentries.push_back(proxy_entry(sc, part.deg[e]));
+                    src += (double)cube(part.deg[e]);
                 } else {
                     (boxes_touch(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
                     src += (double)S.count[sc];
@@ -200,7 +236,8 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
         int64_t ee = (int64_t)w.pentries.size();
         for (int64_t tb = T.begin[leaf]; tb < T.begin[leaf] + T.count[leaf]; tb += tile) {
             int64_t tn = std::min<int64_t>(tile, T.begin[leaf] + T.count[leaf] - tb);
-            items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee, (int32_t)leaf}});
+            items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee, (int32_t)leaf,
+                                                     (int32_t)w.down_degree, (int32_t)tb}});
         }
     }
     // Longest items first: the tail of the grid is then made of short items.
@@ -208,28 +245,39 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
     w.pitems.reserve(items.size());
     for (auto& it : items) w.pitems.push_back(it.second);
 
-    // Proxy targets: per target cluster with CP/CC entries, tiles of its proxies.
+    // Proxy targets: per (target cluster, degree) with CP/CC entries, tiles of its proxies.
     items.clear();
     for (int64_t c = 0; c < nc; ++c) {
         if (prox.off[c + 1] == prox.off[c]) continue;
-        int64_t eb = (int64_t)w.qentries.size();
-        double src = 0.0;
-        for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) {
-            int64_t sc = prox.code[e] >> 2;
-            if ((int)(prox.code[e] & 3) == CC) {
-                w.qentries.push_back(Entry{(int32_t)sc, (int32_t)proxy_code});
-                src += (double)np;
-            } else {
-                rp.emplace_back(S.begin[sc], S.count[sc]);     // separated: never r = 0
-                src += (double)S.count[sc];
+        uint32_t used = 0;
+        for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) used |= 1u << prox.deg[e];
+        for (int d = 0; d <= kMaxDegree; ++d) {
+            if (!(used >> d & 1)) continue;
+            int64_t eb = (int64_t)w.qentries.size();
+            double src = 0.0;
+            for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) {
+                if (prox.deg[e] != d) continue;
+                int64_t sc = prox.sc[e];
+                if (prox.type[e] == CC) {
+                    w.qentries.push_back(proxy_entry(sc, d));
+                    src += (double)cube(d);
+                } else {
+                    rp.emplace_back(S.begin[sc], S.count[sc]);     // separated: never r = 0
+                    src += (double)S.count[sc];
+                }
+            }
+            emit_ranges(rp, rg, w.qentries);
+            int64_t ee = (int64_t)w.qentries.size();
+            const int64_t np = cube(d);
+            for (int64_t lb = 0; lb < np; lb += ptile) {
+                int64_t ln = std::min<int64_t>(ptile, np - lb);
+                items.push_back({src * (double)ln, Item{(int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee, (int32_t)c,
+                                                         (int32_t)d, (int32_t)c}});
             }
         }
-        emit_ranges(rp, rg, w.qentries);
-        int64_t ee = (int64_t)w.qentries.size();
-        for (int64_t lb = 0; lb < np; lb += ptile) {
-            int64_t ln = std::min<int64_t>(ptile, np - lb);
-            items.push_back({src * (double)ln, Item{(int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee, (int32_t)c}});
-        }
+        // degrees of this cluster's proxy potentials that are lifted to the downward degree
+        uint32_t lift = used & ~(1u << w.down_degree);
+        if (lift) w.prolong.push_back(Item{0, 0, 0, 0, (int32_t)c, (int32_t)lift, (int32_t)c});
     }
     std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
     w.qitems.reserve(items.size());

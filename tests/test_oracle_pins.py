@@ -483,3 +483,75 @@ def test_eval_targets_equals_full_run():
     sel = np.array([0, 7, 3999, 1234, 2500])
     got = run.eval_targets(sel)
     assert core.rel_l2(got, phi[sel]) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Per-pair degrees: lists whose approximated entries carry their own degree
+# --------------------------------------------------------------------------
+
+def test_per_entry_degree_evaluator_equals_standard_run_at_one_degree():
+    # every entry at the run's degree: the direct chain form must equal the recursive run
+    t, s = inputs.unequal_sets(3000, "sphere", 4000, "gaussian", seed=23)
+    run = core.Run(t, s, theta=0.8, degree=4, leaf=40)
+    phi = run.run_all()
+    L = {k: (tc, sc, np.full(tc.shape[0], 4, np.int32)) for k, (tc, sc) in run.lists().items()}
+    got = run.eval_degrees(L)
+    assert core.rel_l2(got, phi) < 1e-13
+
+
+def test_per_entry_degree_evaluator_vs_explicit_matrices():
+    # mixed degrees per entry (2..7): the oracle's evaluator against the explicit approximated matrices
+    t, s = inputs.unequal_sets(900, "sphere", 1300, "gaussian", seed=24)
+    run = core.Run(t, s, theta=0.9, degree=2, leaf=20)
+    run.traverse()
+    rng = np.random.default_rng(24)
+    L = {k: (tc, sc, rng.integers(2, 8, size=tc.shape[0]).astype(np.int32)) for k, (tc, sc) in run.lists().items()}
+    assert min(len(v[0]) for v in L.values()) > 0
+    got = run.eval_degrees(L)
+    ref = brute.explicit_bldtt(t.xyz(), s.xyz(), s.q, run.tree(0), run.tree(1), L, 2)
+    assert core.rel_l2(got, ref) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# The FP64 reference of the degree model: backpropagation against central
+# finite differences, and the network's closed forms.
+# --------------------------------------------------------------------------
+
+def _random_model(seed, scale=0.3):
+    from oracle import mlp
+    rng = np.random.default_rng(seed)
+    m = rng.normal(0, scale, mlp.N_MODEL)
+    m[mlp.N_PARAMS:mlp.N_PARAMS + 4] = rng.normal(0, 1, 4)        # mean
+    m[mlp.N_PARAMS + 4:mlp.N_PARAMS + 8] = rng.uniform(0.5, 2, 4)  # scale
+    return m
+
+
+def test_mlp_reference_gradient_matches_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(30)
+    model = _random_model(30)
+    f = rng.normal(0, 1, (17, 4))
+    t = rng.normal(-6, 2, (17, 11))
+    t[3, 5] = np.nan                      # missing targets are ignored
+    g = mlp.grad(model, f, t)
+    h = 1e-6
+    for q in rng.choice(mlp.N_PARAMS, size=60, replace=False):
+        mp, mm = model.copy(), model.copy()
+        mp[q] += h
+        mm[q] -= h
+        fd = (mlp.loss(mp, f, t) - mlp.loss(mm, f, t)) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-7 + 1e-6 * abs(fd), (q, fd, g[q])
+
+
+def test_mlp_reference_closed_forms():
+    from oracle import mlp
+    model = np.zeros(mlp.N_MODEL)
+    model[mlp.N_PARAMS + 4:mlp.N_PARAMS + 8] = 1.0
+    p = mlp.unpack(model)
+    p["b3"][:] = np.arange(11)           # views into model
+    y, _ = mlp.forward(model, np.ones((3, 4)))
+    assert np.array_equal(y, np.tile(np.arange(11.0), (3, 1)))
+    # a single path: y_0 = W3[0,0] tanh(W2[0,0] tanh(W1[0,0] x0))
+    p["W1"][0, 0], p["W2"][0, 0], p["W3"][0, 0] = 0.5, -1.5, 2.0
+    y, _ = mlp.forward(model, np.array([[0.8, 0.0, 0.0, 0.0]]))
+    assert y[0, 0] == pytest.approx(2.0 * np.tanh(-1.5 * np.tanh(0.5 * 0.8)), rel=1e-15)
