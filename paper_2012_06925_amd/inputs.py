@@ -79,7 +79,9 @@ WORKLOADS = {
                                kernel="yukawa", theta=0.7, degree=8, leaf=2000),
     # targets = sources, uniform cube 1E7, Coulomb (the throughput workload).  theta and degree are
     # the fastest plain-FP64 pair with relative l2 error <= 1e-6 in a theta x degree sweep at leaf 2000.
-    "cube1e7": dict(id=0, M=10_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=7, leaf=2000),
+    # tuned_theta / tau: the fastest FP32-evaluation + per-pair-degree point with error <= 1e-6.
+    "cube1e7": dict(id=0, M=10_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=7, leaf=2000,
+                    tuned_theta=0.8, tau=1e-6, tuned_fallback=8),
     "cube1e8": dict(id=5, M=100_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=8, leaf=2000),
 }
 
