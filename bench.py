@@ -38,17 +38,22 @@ FP32_VALU_PEAK = 157.3         # TFLOP/s, MI355X vector FP32 (packed)
 FLOPS_PER_EVAL = {"coulomb": 11, "yukawa": 15, "oscillatory": 15, "regcoulomb": 12, "poly": 8}
 
 
+KERNEL_SOURCES = ("kernels.hip", "device.hpp")
+
+
 def kernel_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the interaction kernel's sources."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2012_06925_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2012_06925_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def traffic_for(kernel_name: str, mode: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_name}_{mode}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_name}_{mode}.txt")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))

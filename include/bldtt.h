@@ -270,6 +270,124 @@ int bldtt_mlp_loss_grad(const float *model, const float *features, const float *
 int bldtt_mlp_train(const float *features, const float *targets, int64_t n, int32_t epochs, int32_t batch,
                     float lr, uint64_t seed, float *model_out, float *loss_history, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Tile autotuning (extension, no counterpart in the paper).
+ *
+ * A tuning choice is stored under a key made of the kernel, precision,
+ * degree, leaf size and the problem size rounded to a power of two.  The
+ * cache lives in memory and, when a path is set, in a text file (one
+ * "key<TAB>tpt tpt_proxy groups_per_cu ms" line per key) that is read on
+ * first use and rewritten after every store.  Path: the last
+ * bldtt_set_tune_cache call, else the BLDTT_TUNE_CACHE environment variable,
+ * else none.  bldtt_setup looks its key up and takes the stored targets per
+ * thread; a miss keeps the defaults.
+ * ------------------------------------------------------------------------ */
+
+/* Set (path != NULL) or clear (NULL) the cache file; drops the in-memory
+ * entries read from a previous file.  Errors: none (returns OK). */
+int bldtt_set_tune_cache(const char *path);
+
+/* Time bldtt_compute for every targets-per-thread pair (1, 2, 4) x (1, 2, 4)
+ * of the particle and proxy work items, `reps` timed calls each after one
+ * warm-up, writing into `scratch` (device, M doubles); keep the fastest on
+ * the plan and store it in the cache.  Synchronizes hip_stream.
+ * Errors: EINVAL (NULL arguments, reps < 1); ESTATE for a host-only plan. */
+int bldtt_autotune(bldtt_plan *plan, double *scratch, int32_t reps, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched persistent launch (extension).  `count` independent problems,
+ * each as in bldtt_setup (Algorithm 1 for every problem, same kernel, theta,
+ * degree and leaf size), are joined into one forest: the trees of every
+ * problem are built once at setup (Sec. 2.3), the traversal of Algorithm 2
+ * runs from every problem's pair of roots, and the whole compute phase --
+ * upward pass (Sec. 2.5), PP/PC/CP/CC sums (Sec. 2.4), downward pass
+ * (Sec. 2.7) and the scatter to caller order -- runs as ONE persistent
+ * kernel (work groups take tasks from a counter; dependencies are device
+ * counters with bounded waits) captured once in a hipGraph.  The per-problem
+ * results equal those of bldtt_setup + bldtt_compute with the same arguments
+ * (the same sums in the same order).  Supported: Coulomb and Yukawa (FP64 or
+ * BLDTT_FP32_EVAL), POLY_TEST (FP64); degree 1..10; a fixed degree (no
+ * BLDTT_LEARNED_DEGREE).
+ * ------------------------------------------------------------------------ */
+typedef struct bldtt_batch bldtt_batch;
+
+enum {
+    BLDTT_AUTOTUNE = 1u << 5       /* batch setup: take the tile choice from the tune
+                                      cache, or measure every candidate and store it */
+};
+
+typedef struct {
+    int32_t n_problems;
+    int64_t n_targets, n_sources;                   /* totals over the problems          */
+    int64_t n_target_clusters, n_source_clusters;   /* forest sizes                      */
+    int64_t n_entries[4];                           /* PP, PC, CP, CC list entries        */
+    double interactions[4];                         /* kernel evaluations per type        */
+    int64_t n_tasks;                                /* tasks of one launch                */
+    int32_t tpt;                                    /* targets per thread (1, 2, 4)       */
+    int32_t groups_per_cu, grid;                    /* resident groups per CU used, grid  */
+    int32_t tuned;                                  /* 0 default, 1 from the cache, 2 measured */
+    double setup_ms, tree_ms, traverse_ms, tune_ms; /* host wall times of setup            */
+    double tune_best_ms;                            /* device ms of the chosen tile (tuning) */
+} bldtt_batch_stats;
+
+/* Build the forest, the task lists and the graph.  problems[i] as for
+ * bldtt_setup (device pointers; read only during this call).  flags:
+ * BLDTT_FP32_EVAL, BLDTT_SYNC, BLDTT_PP_CC_ONLY, BLDTT_AUTOTUNE.
+ * Synchronizes hip_stream.  Errors: EINVAL (count < 1, a bad problem, the
+ * sums of M or N reach 2^31); EUNSUPPORTED (kernel, degree or flags outside
+ * the supported set); ENOMEM; EDEVICE. */
+int bldtt_batch_setup(bldtt_batch **out, int32_t count, const bldtt_particles *problems, int32_t kernel,
+                      double kernel_param, double theta, int32_t degree, int64_t leaf_size, uint32_t flags,
+                      void *hip_stream);
+
+/* Host-only batch (host pointers, no device use): the forest, the traversal
+ * from every problem's pair of roots and the work items for tile tpt (1, 2
+ * or 4), for inspection and tests.  Device calls on it return ESTATE.
+ * Errors: as bldtt_batch_setup. */
+int bldtt_batch_setup_host(bldtt_batch **out, int32_t count, const bldtt_particles *problems, int32_t kernel,
+                           double kernel_param, double theta, int32_t degree, int64_t leaf_size, uint32_t flags,
+                           int32_t tpt);
+
+/* The forest (which = 0 targets, 1 sources) in the layout of
+ * bldtt_get_tree: problem i's clusters follow problem i-1's, its particle
+ * positions likewise, and perm maps to the index in the concatenation of
+ * the problems' caller orders.  Valid until bldtt_batch_destroy. */
+int bldtt_batch_get_tree(const bldtt_batch *b, int which, bldtt_tree_view *out);
+
+/* The interaction lists of the forest traversal, as bldtt_get_lists (forest
+ * cluster ids).  Errors: EINVAL. */
+int bldtt_batch_get_lists(const bldtt_batch *b, int type, const int64_t **tc, const int64_t **sc, int64_t *n);
+
+/* Run the compute phase of every problem: potentials[i] is a device array of
+ * problems[i].M doubles, written in that problem's caller order.  One small
+ * copy of the pointer table and one graph launch, enqueued on hip_stream.
+ * With BLDTT_SYNC, waits and reports a failed dependency wait as EDEVICE.
+ * Errors: EINVAL (NULL pointers). */
+int bldtt_batch_compute(bldtt_batch *b, double *const *potentials, void *hip_stream);
+
+/* Wait for hip_stream and report whether the last launch completed every
+ * dependency wait (OK) or gave one up (EDEVICE: results are invalid). */
+int bldtt_batch_check(bldtt_batch *b, void *hip_stream);
+
+/* Measure every tile candidate (targets per thread 1, 2, 4 x resident
+ * groups per CU), `reps` timed launches each after one warm-up, keep the
+ * fastest and store it in the tune cache.  Synchronizes hip_stream.
+ * Errors: EINVAL; EDEVICE. */
+int bldtt_batch_tune(bldtt_batch *b, int32_t reps, void *hip_stream);
+
+/* Set the tile by hand (tpt 1, 2 or 4; groups_per_cu 0 = as many as fit)
+ * and rebuild the graph.  Errors: EINVAL. */
+int bldtt_batch_set_tile(bldtt_batch *b, int32_t tpt, int32_t groups_per_cu);
+
+/* Bound of each dependency wait, in polls (default 2^22), for tests of the
+ * failure path; rebuilds the graph.  Errors: EINVAL (limit < 0). */
+int bldtt_batch_set_spin_limit(bldtt_batch *b, int32_t limit);
+
+int bldtt_batch_get_stats(const bldtt_batch *b, bldtt_batch_stats *out);
+
+/* Waits for the device, frees everything.  NULL is a no-op. */
+int bldtt_batch_destroy(bldtt_batch *b);
+
 /* Library version string. */
 const char *bldtt_version(void);
 

@@ -19,7 +19,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 
 KERNELS = {"coulomb": 0, "yukawa": 1, "oscillatory": 2, "regcoulomb": 3, "poly": 100}
 DEFAULT_PARAM = {"coulomb": 0.0, "yukawa": 0.5, "oscillatory": 0.0, "regcoulomb": 0.005, "poly": 0.0}
-FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY = 1, 2, 4, 8, 16
+FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE = 1, 2, 4, 8, 16, 32
 PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf")
 TYPES = ("PP", "PC", "CP", "CC")
 
@@ -50,6 +50,15 @@ class Stats(C.Structure):
                 ("sep_fallback", C.c_int64), ("sep_direct", C.c_int64), ("pairs_per_degree", C.c_int64 * 13)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("n_problems", C.c_int32), ("n_targets", C.c_int64), ("n_sources", C.c_int64),
+                ("n_target_clusters", C.c_int64), ("n_source_clusters", C.c_int64),
+                ("n_entries", C.c_int64 * 4), ("interactions", C.c_double * 4), ("n_tasks", C.c_int64),
+                ("tpt", C.c_int32), ("groups_per_cu", C.c_int32), ("grid", C.c_int32), ("tuned", C.c_int32),
+                ("setup_ms", C.c_double), ("tree_ms", C.c_double), ("traverse_ms", C.c_double),
+                ("tune_ms", C.c_double), ("tune_best_ms", C.c_double)]
+
+
 # Every symbol the header declares, with its signature.
 SIGNATURES = {
     "bldtt_setup": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(Particles), C.c_int32, C.c_double, C.c_double,
@@ -78,6 +87,21 @@ SIGNATURES = {
     "bldtt_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "bldtt_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "bldtt_set_tune_cache": (C.c_int, [C.c_char_p]),
+    "bldtt_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "bldtt_batch_setup": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Particles), C.c_int32, C.c_double,
+                                    C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_void_p]),
+    "bldtt_batch_setup_host": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Particles), C.c_int32,
+                                         C.c_double, C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_int32]),
+    "bldtt_batch_get_tree": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(TreeView)]),
+    "bldtt_batch_get_lists": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(C.c_int64)]),
+    "bldtt_batch_compute": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p]),
+    "bldtt_batch_check": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "bldtt_batch_tune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "bldtt_batch_set_tile": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "bldtt_batch_set_spin_limit": (C.c_int, [C.c_void_p, C.c_int32]),
+    "bldtt_batch_get_stats": (C.c_int, [C.c_void_p, C.POINTER(BatchStats)]),
+    "bldtt_batch_destroy": (C.c_int, [C.c_void_p]),
     "bldtt_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
 }

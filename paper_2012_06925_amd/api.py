@@ -229,6 +229,162 @@ def direct_sum(targets, sources, kernel="coulomb", param=None, sel: torch.Tensor
     return out
 
 
+def set_tune_cache(path: str | None) -> None:
+    """File that holds the autotuner's choices (None: memory only)."""
+    check(lib().bldtt_set_tune_cache(None if path is None else str(path).encode()))
+
+
+def autotune(plan: Plan, reps: int = 2, stream=None) -> None:
+    """Time every tile pair on `plan`, keep the fastest, store it in the tune cache."""
+    scratch = torch.empty(plan.M, dtype=torch.float64, device=plan.device)
+    with torch.cuda.device(plan.device):
+        check(lib().bldtt_autotune(plan._handle, scratch.data_ptr(), int(reps), _stream_ptr(stream)))
+
+
+class Batch:
+    """bldtt_batch_setup: many independent targets = sources (or separate)
+    problems in one persistent, graph-captured launch.
+
+    problems: list of (targets, sources) pairs as for Plan (targets None when
+    targets = sources).  compute() returns one potentials tensor per problem.
+    """
+
+    _handle = None
+
+    def __init__(self, problems, kernel="coulomb", theta=0.7, degree=6, leaf=500, param=None, flags=0, stream=None):
+        kind, kparam = _kernel(kernel, param)
+        arr = (_lib.Particles * len(problems))()
+        self.M = []
+        self._keep = []
+        for i, (targets, sources) in enumerate(problems):
+            sx, sy, sz, q = (_f64_cuda(t, n) for t, n in zip(sources, ("sx", "sy", "sz", "q")))
+            if targets is None:
+                tx, ty, tz = sx, sy, sz
+            else:
+                tx, ty, tz = (_f64_cuda(t, n) for t, n in zip(targets, ("tx", "ty", "tz")))
+            arr[i] = _lib.Particles(tx.numel(), tx.data_ptr(), ty.data_ptr(), tz.data_ptr(), sx.numel(),
+                                    sx.data_ptr(), sy.data_ptr(), sz.data_ptr(), q.data_ptr())
+            self.M.append(tx.numel())
+            self.device = sx.device
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_batch_setup(C.byref(h), len(problems), arr, kind, kparam, float(theta), int(degree),
+                                          int(leaf), int(flags), _stream_ptr(stream)))
+        self._handle = h
+
+    def compute(self, outs=None, stream=None):
+        if outs is None:
+            outs = [torch.empty(m, dtype=torch.float64, device=self.device) for m in self.M]
+        if len(outs) != len(self.M):
+            raise ValueError("one output tensor per problem")
+        ptrs = (C.c_void_p * len(outs))()
+        for i, (o, m) in enumerate(zip(outs, self.M)):
+            _f64_cuda(o, "out")
+            if o.numel() != m:
+                raise ValueError(f"output {i} must hold {m} values")
+            ptrs[i] = o.data_ptr()
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_batch_compute(self._handle, ptrs, _stream_ptr(stream)))
+        return outs
+
+    def check(self, stream=None):
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_batch_check(self._handle, _stream_ptr(stream)))
+
+    def tune(self, reps: int = 3, stream=None):
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_batch_tune(self._handle, int(reps), _stream_ptr(stream)))
+
+    def set_tile(self, tpt: int, groups_per_cu: int = 0):
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_batch_set_tile(self._handle, int(tpt), int(groups_per_cu)))
+
+    def set_spin_limit(self, limit: int):
+        with torch.cuda.device(self.device):
+            check(lib().bldtt_batch_set_spin_limit(self._handle, int(limit)))
+
+    def stats(self) -> dict:
+        s = _lib.BatchStats()
+        check(lib().bldtt_batch_get_stats(self._handle, C.byref(s)))
+        out = {name: getattr(s, name) for name, _ in s._fields_ if name not in ("n_entries", "interactions")}
+        out["n_entries"] = dict(zip(TYPES, list(s.n_entries)))
+        out["interactions"] = dict(zip(TYPES, list(s.interactions)))
+        return out
+
+    def close(self):
+        if self._handle:
+            check(lib().bldtt_batch_destroy(self._handle))
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class HostBatch:
+    """bldtt_batch_setup_host on host (numpy) arrays: the forest, its traversal
+    and work items, with no device use.  problems: list of (targets, sources)
+    with targets (x, y, z) or None, sources (x, y, z, q) float64 arrays."""
+
+    _handle = None
+
+    def __init__(self, problems, kernel="coulomb", theta=0.7, degree=6, leaf=500, param=None, flags=0, tpt=2):
+        kind, kparam = _kernel(kernel, param)
+        arr = (_lib.Particles * len(problems))()
+        self._keep = []
+        for i, (targets, sources) in enumerate(problems):
+            sx, sy, sz, q = (np.ascontiguousarray(a, dtype=np.float64) for a in sources)
+            if targets is None:
+                tx, ty, tz = sx, sy, sz
+            else:
+                tx, ty, tz = (np.ascontiguousarray(a, dtype=np.float64) for a in targets)
+            self._keep += [sx, sy, sz, q, tx, ty, tz]
+            ptr = lambda a: a.ctypes.data
+            arr[i] = _lib.Particles(tx.size, ptr(tx), ptr(ty), ptr(tz), sx.size, ptr(sx), ptr(sy), ptr(sz), ptr(q))
+        h = C.c_void_p()
+        check(lib().bldtt_batch_setup_host(C.byref(h), len(problems), arr, kind, kparam, float(theta), int(degree),
+                                           int(leaf), int(flags), int(tpt)))
+        self._handle = h
+        self._keep = []
+
+    def tree(self, which: int = 0) -> dict:
+        v = _lib.TreeView()
+        check(lib().bldtt_batch_get_tree(self._handle, int(which), C.byref(v)))
+        return _tree_dict(v)
+
+    def lists(self) -> dict:
+        out = {}
+        for k, name in enumerate(TYPES):
+            tc, sc, n = _lib._I64(), _lib._I64(), C.c_int64()
+            check(lib().bldtt_batch_get_lists(self._handle, k, C.byref(tc), C.byref(sc), C.byref(n)))
+            m = n.value
+            a = np.ctypeslib.as_array(tc, shape=(m,)).copy() if m else np.zeros(0, np.int64)
+            b = np.ctypeslib.as_array(sc, shape=(m,)).copy() if m else np.zeros(0, np.int64)
+            out[name] = (a, b)
+        return out
+
+    def stats(self) -> dict:
+        return Batch.stats(self)
+
+    def compute_raw(self):
+        """bldtt_batch_compute on this handle (returns the status; host-only batches refuse)."""
+        ptrs = (C.c_void_p * 1)()
+        return lib().bldtt_batch_compute(self._handle, ptrs, None)
+
+    close = Batch.close
+    __del__ = Batch.__del__
+    __enter__ = Batch.__enter__
+    __exit__ = Batch.__exit__
+
+
 def mlp_model_size() -> int:
     return int(lib().bldtt_mlp_model_size())
 

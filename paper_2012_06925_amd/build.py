@@ -25,13 +25,20 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "
           "-munsafe-fp-atomics"]
 HOST_EXACT = ["-ffp-contract=off", "-fno-fast-math"]
 
+HIP_HOST = ["-D__HIP_PLATFORM_AMD__"]
+
+# (source, flags, object name); the batch kernel's instantiations are split
+# over six objects so they compile in parallel.
 UNITS = [
-    ("kernels.hip", DEVICE),
-    ("mlp.hip", DEVICE),
-    ("degree.cpp", HOST_EXACT + ["-D__HIP_PLATFORM_AMD__"]),
-    ("tree.cpp", HOST_EXACT),
-    ("traverse.cpp", HOST_EXACT),
-    ("capi.cpp", HOST_EXACT + ["-D__HIP_PLATFORM_AMD__"]),
+    ("kernels.hip", DEVICE, "kernels"),
+    ("mlp.hip", DEVICE, "mlp"),
+] + [("batch.hip", DEVICE + [f"-DBATCH_PART={k}"], f"batch{k}") for k in range(6)] + [
+    ("degree.cpp", HOST_EXACT + HIP_HOST, "degree"),
+    ("tree.cpp", HOST_EXACT, "tree"),
+    ("traverse.cpp", HOST_EXACT, "traverse"),
+    ("capi.cpp", HOST_EXACT + HIP_HOST, "capi"),
+    ("batch_host.cpp", HOST_EXACT + HIP_HOST, "batch_host"),
+    ("tune.cpp", [], "tune"),
 ]
 
 
@@ -39,8 +46,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     procs = []
     objs = []
-    for src, extra in UNITS:
-        obj = os.path.join(OBJ, src.replace(".", "_") + ".o")
+    for src, extra, name in UNITS:
+        obj = os.path.join(OBJ, name + ".o")
         objs.append(obj)
         cmd = [HIPCC, "-c"] + COMMON + extra + ["-o", obj, os.path.join(CSRC, src)]
         if verbose:

@@ -1,0 +1,255 @@
+// batch.hip -- one persistent launch that runs the whole compute phase of many
+// independent problems (the trees of all problems form one forest).
+//
+// Tasks are numbered in an order in which every task depends only on tasks
+// with smaller numbers:
+//
+//   [up_leaf]  proxy charges of each source leaf (Sec. 2.5)
+//   [up_xfer]  proxy charges of each source parent, deepest level first
+//   [q item]   CP + CC sums into target proxies (needs the upward pass)
+//   [p item]   PP + PC sums into target particles (PC needs the upward pass)
+//   [dn_xfer]  parent-to-child proxy potentials, shallowest level first (Sec. 2.7)
+//   [final]    leaf interpolation plus the PP/PC part, to the caller's buffers
+//
+// Work groups take task numbers from a ticket counter, so a task starts only
+// after every smaller number has been taken by a running work group: waits
+// always end.  Each dependency is a counter in device memory that the
+// producer increments after a release fence and the consumer polls with
+// relaxed loads, followed by an acquire fence (the L2 of each XCD is
+// private, so both fences are at agent scope).  Every wait is bounded: past
+// `spin_limit` polls the kernel records an error and stops waiting, so the
+// grid always drains.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#ifndef BATCH_PART
+#error "compile with -DBATCH_PART=0..5"
+#endif
+
+#include "device.hpp"
+#include "engine.hpp"
+#include "kernels.hpp"
+
+namespace bldtt {
+namespace {
+
+using namespace dev;
+
+enum { C_TICKET = 0, C_UP_DONE = 1, C_ERROR = 2 };
+
+__device__ __forceinline__ int poll(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until p0 >= need0 and (p1 == null or p1 >= need1); the group
+// then acquires.  A wait that gives up sets the error flag, which also ends
+// every later wait at once.
+__device__ __forceinline__ void wait2(const BatchDev& a, const int32_t* p0, int need0, const int32_t* p1, int need1) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        bool ok = true;
+        while (poll(p0) < need0 || (p1 && poll(p1) < need1)) {
+            if (poll(a.ctr + C_ERROR) != 0 || ++spins > a.spin_limit) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ok) __hip_atomic_store(a.ctr + C_ERROR, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Publish this group's stores, then count the task as done in *p.
+__device__ __forceinline__ void signal(int32_t* p) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int A, int B>
+constexpr int cmax() { return A > B ? A : B; }
+
+template <int KIND, bool F32, int T, int M>
+__global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
+    constexpr int kLds = cmax<cmax<interact_lds_bytes<F32>(), up_leaf_lds_bytes<M>()>(),
+                              cmax<cmax<up_transfer_lds_bytes<M>(), down_transfer_lds_bytes<M>()>(),
+                                   down_leaf_lds_bytes<M>()>()>();
+    __shared__ double4 pool[(kLds + 31) / 32];
+    __shared__ int s_task;
+    double* dl = reinterpret_cast<double*>(pool);
+    using V = typename Stage<F32>::V;
+    V* vl = reinterpret_cast<V*>(pool);
+
+    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, e2 = e1 + a.n_q, e3 = e2 + a.n_p, e4 = e3 + a.n_kids;
+    const int n_up = e1;
+    bool up_seen = false;                     // this group has already acquired the finished upward pass
+    for (;;) {
+        if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(a.ctr + C_TICKET, 1, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();                      // everyone has read s_task before it is rewritten
+        if (t >= a.n_tasks) break;
+
+        if (t < e0) {
+            const int c = a.leaves[t];
+            up_leaf_body<M>(c, a.S, a.src, a.tab, a.qhat, dl);
+            const int par = a.S.parent[c];
+            signal(par >= 0 ? a.up_cnt + par : a.ctr + C_UP_DONE);
+            if (par >= 0 && threadIdx.x == 0)
+                __hip_atomic_fetch_add(a.ctr + C_UP_DONE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (t < e1) {
+            const int c = a.parents[t - e0];
+            wait2(a, a.up_cnt + c, a.S.nchild[c], nullptr, 0);
+            up_transfer_body<M>(c, a.S, a.tab, a.qhat, dl);
+            const int par = a.S.parent[c];
+            signal(par >= 0 ? a.up_cnt + par : a.ctr + C_UP_DONE);
+            if (par >= 0 && threadIdx.x == 0)
+                __hip_atomic_fetch_add(a.ctr + C_UP_DONE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (t < e2) {
+            const int i = t - e1;
+            const DevItem it = a.qitems[i];
+            if (a.qneeds[i] && !up_seen) {
+                wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
+                up_seen = true;
+            }
+            interact_body<KIND, F32, T, true>(it, a.qentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
+                                              nullptr, a.po, vl);
+            signal(a.dn + it.cluster);
+        } else if (t < e3) {
+            const int i = t - e2;
+            const DevItem it = a.pitems[i];
+            if (a.pneeds[i] && !up_seen) {
+                wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
+                up_seen = true;
+            }
+            interact_body<KIND, F32, T, false>(it, a.pentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
+                                               a.phi_tree, a.po, vl);
+            signal(a.pdone + i);
+        } else if (t < e4) {
+            const int c = a.kids[t - e3];
+            const int par = a.T.parent[c];
+            wait2(a, a.dn + par, a.nq[par] + (a.T.parent[par] >= 0 ? 1 : 0), a.dn + c, a.nq[c]);
+            down_transfer_body<M>(c, a.T, a.tab, a.phihat, dl);
+            signal(a.dn + c);
+        } else {
+            const int i = t - e4;
+            const DevItem it = a.pitems[i];
+            const int c = it.cluster;
+            wait2(a, a.pdone + i, 1, a.dn + c, a.nq[c] + (a.T.parent[c] >= 0 ? 1 : 0));
+            const int prob = a.prob[c];
+            down_leaf_body<M>(it, a.has_far[c] != 0, a.tgt, a.T, a.tab, a.phihat, a.phi_tree, a.perm,
+                              a.outs[prob], a.caller0[prob], dl);
+            __syncthreads();                  // LDS is reused by the next task
+        }
+    }
+}
+
+[[noreturn]] void fail(hipError_t e, const char* where) {
+    throw Error(-3, std::string("HIP launch failed in ") + where + ": " + hipGetErrorString(e));
+}
+
+// Kernel pointer for (tpt, degree) of one (kind, precision); the switches
+// cover every supported combination.
+template <int KK, bool F32, int T>
+const void* pick_m(int degree) {
+    switch (degree + 1) {
+    case 2: return (const void*)k_batch<KK, F32, T, 2>;
+    case 3: return (const void*)k_batch<KK, F32, T, 3>;
+    case 4: return (const void*)k_batch<KK, F32, T, 4>;
+    case 5: return (const void*)k_batch<KK, F32, T, 5>;
+    case 6: return (const void*)k_batch<KK, F32, T, 6>;
+    case 7: return (const void*)k_batch<KK, F32, T, 7>;
+    case 8: return (const void*)k_batch<KK, F32, T, 8>;
+    case 9: return (const void*)k_batch<KK, F32, T, 9>;
+    case 10: return (const void*)k_batch<KK, F32, T, 10>;
+    case 11: return (const void*)k_batch<KK, F32, T, 11>;
+    default: return nullptr;
+    }
+}
+
+template <int KK, bool F32>
+const void* pick_t(int tpt, int degree) {
+    switch (tpt) {
+    case 1: return pick_m<KK, F32, 1>(degree);
+    case 2: return pick_m<KK, F32, 2>(degree);
+    case 4: return pick_m<KK, F32, 4>(degree);
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+// The instantiations are split over several objects (this file compiled with
+// BATCH_PART = 1..5) so they build in parallel; part 0 holds the launchers.
+const void* batch_pick_c64(int tpt, int degree);
+const void* batch_pick_c32(int tpt, int degree);
+const void* batch_pick_y64(int tpt, int degree);
+const void* batch_pick_y32(int tpt, int degree);
+const void* batch_pick_p64(int tpt, int degree);
+
+#if BATCH_PART == 1
+const void* batch_pick_c64(int tpt, int degree) { return pick_t<K_COULOMB, false>(tpt, degree); }
+#elif BATCH_PART == 2
+const void* batch_pick_c32(int tpt, int degree) { return pick_t<K_COULOMB, true>(tpt, degree); }
+#elif BATCH_PART == 3
+const void* batch_pick_y64(int tpt, int degree) { return pick_t<K_YUKAWA, false>(tpt, degree); }
+#elif BATCH_PART == 4
+const void* batch_pick_y32(int tpt, int degree) { return pick_t<K_YUKAWA, true>(tpt, degree); }
+#elif BATCH_PART == 5
+const void* batch_pick_p64(int tpt, int degree) { return pick_t<K_POLY, false>(tpt, degree); }
+#elif BATCH_PART == 0
+namespace {
+const void* pick(KernelSpec k, bool fp32, int tpt, int degree) {
+    if (tpt != 1 && tpt != 2 && tpt != 4) throw Error(-1, "targets per thread must be 1, 2 or 4");
+    if (degree < 1 || degree > 10) throw Error(-5, "the batch kernel supports degrees 1..10");
+    const void* f = nullptr;
+    if (k.kind == K_COULOMB) f = fp32 ? batch_pick_c32(tpt, degree) : batch_pick_c64(tpt, degree);
+    else if (k.kind == K_YUKAWA) f = fp32 ? batch_pick_y32(tpt, degree) : batch_pick_y64(tpt, degree);
+    else if (k.kind == K_POLY && !fp32) f = batch_pick_p64(tpt, degree);
+    if (!f)
+        throw Error(-5, "the batch kernel supports the Coulomb and Yukawa kernels (FP64 or FP32 evaluation) and "
+                        "the polynomial test kernel (FP64)");
+    return f;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace
+
+int batch_groups_per_cu(KernelSpec k, bool fp32, int tpt, int degree) {
+    const void* f = pick(k, fp32, tpt, degree);
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, 0);
+    if (e != hipSuccess) fail(e, __func__);
+    return n;
+}
+
+void launch_batch(KernelSpec k, bool fp32, int tpt, int degree, int grid, const BatchDev& a, hipStream_t st) {
+    const void* f = pick(k, fp32, tpt, degree);
+    if (grid < 1) throw Error(-1, "batch grid must be >= 1");
+    BatchDev arg = a;
+    void* args[] = {&arg};
+    hipError_t e = hipLaunchKernel(f, dim3(grid), dim3(kBlock), args, 0, st);
+    if (e != hipSuccess) fail(e, __func__);
+}
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n, v);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(e, __func__);
+}
+#endif  // BATCH_PART
+
+}  // namespace bldtt

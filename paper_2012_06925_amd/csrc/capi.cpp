@@ -12,6 +12,7 @@
 //   5. leaf proxies to targets plus the PP/PC part, scattered to caller order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -22,16 +23,13 @@
 
 #include "../../include/bldtt.h"
 #include "plan.hpp"
+#include "tune.hpp"
 
-namespace {
+namespace bldtt {
 
-
-
-
-template <class T>
-void upload(DevBuf& b, const std::vector<T>& v) {
-    b.alloc(sizeof(T) * v.size());
-    if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+void upload_bytes(DevBuf& b, const void* src, size_t n) {
+    b.alloc(n);
+    if (n) HIPCHK(hipMemcpy(b.p, src, n, hipMemcpyHostToDevice));
 }
 
 void upload_tree(DevTreeBufs& d, const Tree& t) {
@@ -63,10 +61,6 @@ bool all_finite(const double* a, int64_t n) {
     return true;
 }
 
-}  // namespace
-
-namespace {
-
 void validate(const bldtt_particles* p, int32_t kernel, double theta, int32_t degree, int64_t leaf_size) {
     if (!p) throw Error(BLDTT_EINVAL, "particles is NULL");
     if (p->M < 1 || p->N < 1) throw Error(BLDTT_EINVAL, "M and N must be >= 1");
@@ -80,6 +74,41 @@ void validate(const bldtt_particles* p, int32_t kernel, double theta, int32_t de
         kernel != BLDTT_REGCOULOMB && kernel != BLDTT_POLY_TEST)
         throw Error(BLDTT_EINVAL, "unknown kernel");
 }
+
+// Level lists: source parents per level (for the upward pass) and target
+// non-root clusters per level (for the downward pass).
+void level_lists(const Tree& t, bool parents, std::vector<int32_t>& ids, std::vector<int64_t>& off) {
+    int32_t depth = t.depth;
+    std::vector<std::vector<int32_t>> by(depth + 1);
+    for (int64_t c = 0; c < t.size(); ++c) {
+        if (parents ? t.nchild[c] > 0 : t.level[c] > 0) by[t.level[c]].push_back((int32_t)c);
+    }
+    ids.clear();
+    off.assign(depth + 2, 0);
+    for (int32_t l = 0; l <= depth; ++l) {
+        off[l] = (int64_t)ids.size();
+        ids.insert(ids.end(), by[l].begin(), by[l].end());
+    }
+    off[depth + 1] = (int64_t)ids.size();
+}
+
+// Chebyshev points of the 2nd kind for every degree d = 1..12, xi_k = cos(pi k / d)
+// evaluated as sin(pi (d - 2k) / (2d)) (exactly antisymmetric), and weights
+// (-1)^k delta_k (Sec. 2.1); 32 doubles per degree.
+std::vector<double> node_table() {
+    std::vector<double> tab(32 * (kMaxDegree + 1), 0.0);
+    for (int d = 1; d <= kMaxDegree; ++d)
+        for (int k = 0; k <= d; ++k) {
+            tab[32 * d + k] = std::sin(M_PI * (double)(d - 2 * k) / (double)(2 * d));
+            tab[32 * d + 16 + k] = (k % 2 ? -1.0 : 1.0) * ((k == 0 || k == d) ? 0.5 : 1.0);
+        }
+    return tab;
+}
+
+}  // namespace bldtt
+
+namespace {
+
 
 // Trees from host arrays; fills the plan's host side.
 void build_host(bldtt_plan* pl, const double* tx, const double* ty, const double* tz, const double* sx,
@@ -109,22 +138,6 @@ void do_traverse(bldtt_plan* pl) {
     pl->stats.traverse_ms = now_ms() - t0;
 }
 
-// Level lists: source parents per level (for the upward pass) and target
-// non-root clusters per level (for the downward pass).
-void level_lists(const Tree& t, bool parents, std::vector<int32_t>& ids, std::vector<int64_t>& off) {
-    int32_t depth = t.depth;
-    std::vector<std::vector<int32_t>> by(depth + 1);
-    for (int64_t c = 0; c < t.size(); ++c) {
-        if (parents ? t.nchild[c] > 0 : t.level[c] > 0) by[t.level[c]].push_back((int32_t)c);
-    }
-    ids.clear();
-    off.assign(depth + 2, 0);
-    for (int32_t l = 0; l <= depth; ++l) {
-        off[l] = (int64_t)ids.size();
-        ids.insert(ids.end(), by[l].begin(), by[l].end());
-    }
-    off[depth + 1] = (int64_t)ids.size();
-}
 
 // Fold the events of the last profiled compute into the stats.
 void collect_profile(bldtt_plan* pl) {
@@ -295,16 +308,7 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     std::vector<int32_t> perm(M);
     for (int64_t i = 0; i < M; ++i) perm[i] = (int32_t)T.perm[i];
     upload(pl->perm, perm);
-    // Chebyshev points of the 2nd kind for every degree d = 1..12, xi_k = cos(pi k / d)
-    // evaluated as sin(pi (d - 2k) / (2d)) (exactly antisymmetric), and weights
-    // (-1)^k delta_k; 32 doubles per degree.
-    std::vector<double> tab(32 * (kMaxDegree + 1), 0.0);
-    for (int d = 1; d <= kMaxDegree; ++d)
-        for (int k = 0; k <= d; ++k) {
-            tab[32 * d + k] = std::sin(M_PI * (double)(d - 2 * k) / (double)(2 * d));
-            tab[32 * d + 16 + k] = (k % 2 ? -1.0 : 1.0) * ((k == 0 || k == d) ? 0.5 : 1.0);
-        }
-    upload(pl->tab, tab);
+    upload(pl->tab, node_table());
     std::vector<int32_t> leaves;
     for (int64_t c = 0; c < pl->S.size(); ++c)
         if (pl->S.is_leaf(c)) leaves.push_back((int32_t)c);
@@ -324,6 +328,13 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     pl->stats.setup_ms = now_ms() - t0;
 }
 
+std::string plan_tune_key(const bldtt_plan* pl) {
+    return tune_key("single", pl->kind, (pl->flags & BLDTT_FP32_EVAL) != 0, pl->varied_degree(), pl->degree, pl->leaf,
+                    std::max(pl->M, pl->N), 1);
+}
+
+bool valid_tpt(int t) { return t == 1 || t == 2 || t == 4; }
+
 bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_param, double theta, int32_t degree,
                      int64_t leaf_size, uint32_t flags) {
     validate(p, kernel, theta, degree, leaf_size);
@@ -340,6 +351,11 @@ bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_par
     pl->N = p->N;
     pl->aliased = p->M == p->N && p->tx == p->sx && p->ty == p->sy && p->tz == p->sz;
     pl->policy.fallback = degree;
+    TuneChoice tc;
+    if (tune_lookup(plan_tune_key(pl.get()), tc) && valid_tpt(tc.tpt) && valid_tpt(tc.tpt_proxy)) {
+        pl->tpt = tc.tpt;
+        pl->tpt_proxy = tc.tpt_proxy;
+    }
     return pl.release();
 }
 
@@ -563,6 +579,59 @@ int bldtt_direct_sum(int32_t kernel, double kernel_param, int64_t M, const doubl
     return guarded([&] {
         launch_direct(KernelSpec{kernel, kernel_param}, sel ? nsel : M, sel, tx, ty, tz, N, sx, sy, sz, q, out,
                       static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+int bldtt_set_tune_cache(const char* path) {
+    tune_set_path(path);
+    return BLDTT_OK;
+}
+
+int bldtt_autotune(bldtt_plan* plan, double* scratch, int32_t reps, void* hip_stream) {
+    if (!plan || !scratch || reps < 1) {
+        set_error("bad argument to bldtt_autotune");
+        return BLDTT_EINVAL;
+    }
+    if (plan->host_only) {
+        set_error("bldtt_autotune on a host-only plan");
+        return BLDTT_ESTATE;
+    }
+    return guarded([&] {
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        TuneChoice best;
+        best.ms = -1.0;
+        try {
+            for (int a : {1, 2, 4})
+                for (int b : {1, 2, 4}) {
+                    plan->tpt = a;
+                    plan->tpt_proxy = b;
+                    compute(plan, scratch, st);
+                    HIPCHK(hipEventRecord(e0, st));
+                    for (int r = 0; r < reps; ++r) compute(plan, scratch, st);
+                    HIPCHK(hipEventRecord(e1, st));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    double per = ms / reps;
+                    if (best.ms < 0.0 || per < best.ms) {
+                        best.tpt = a;
+                        best.tpt_proxy = b;
+                        best.ms = per;
+                    }
+                }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        plan->tpt = best.tpt;
+        plan->tpt_proxy = best.tpt_proxy;
+        tune_store(plan_tune_key(plan), best);
     });
 }
 

@@ -76,6 +76,16 @@ struct Lists {
 void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out,
               bool defer_separated = false);
 
+// Same, starting from every (target root, source root) pair of a forest of
+// independent problems (global cluster ids).
+void traverse_roots(const Tree& T, const Tree& S, const std::vector<std::pair<int64_t, int64_t>>& roots,
+                    double theta, int degree, bool pp_cc_only, Lists& out, bool defer_separated);
+
+// Append tree `t` (ids local to one problem) to forest `f` with cluster ids
+// shifted by f.size(), particle positions by `pos0` and caller indices by
+// `caller0`.  Returns the global id of t's root.
+int64_t append_tree(Tree& f, const Tree& t, int64_t pos0, int64_t caller0);
+
 // Type of a separated pair for degree d (Algorithm 2, separated branch).
 int separated_type(int64_t ct, int64_t cs, int d, bool pp_cc_only);
 

@@ -78,6 +78,52 @@ void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,
                       const double* phi_tree, const int32_t* perm, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Persistent batch kernel (batch.hip): every phase of a forest of independent
+// problems in one launch.  Task ranges, in ticket order: source leaves,
+// source parents (deepest level first), proxy items, particle items, target
+// non-root clusters (shallowest level first), particle items again (final
+// interpolation to the caller's buffers).
+// ---------------------------------------------------------------------------
+struct BatchDev {
+    DevTree S, T;
+    DevParticles src, tgt;
+    const double* tab;          // node table of the batch degree
+    const double* tab_all;      // node tables of every degree (source entries index it)
+    DegPtrs qp;                 // proxy charges (entry of the batch degree set)
+    DegOut po;                  // proxy potentials (entry of the batch degree set)
+    double* qhat;
+    double* phihat;
+    double* phi_tree;           // PP/PC sums, tree order
+    const int32_t* leaves;      // source leaves
+    const int32_t* parents;     // source parents, deepest level first
+    const int32_t* kids;        // target non-root clusters, shallowest level first
+    const DevItem* qitems;
+    const int2* qentries;
+    const uint8_t* qneeds;      // item reads proxy charges
+    const DevItem* pitems;
+    const int2* pentries;
+    const uint8_t* pneeds;
+    const uint8_t* has_far;     // per target cluster
+    const int32_t* nq;          // proxy items per target cluster
+    const int32_t* perm;        // tree position -> global caller index
+    const int32_t* prob;        // target cluster -> problem
+    const int64_t* caller0;     // first global caller index of each problem
+    double* const* outs;        // caller buffer of each problem
+    int32_t* ctr;               // ticket, finished upward tasks, error flag
+    int32_t* up_cnt;            // per source cluster: finished children
+    int32_t* dn;                // per target cluster: finished proxy items (+1 when its transfer is done)
+    int32_t* pdone;             // per particle item
+    int n_leaves, n_parents, n_q, n_p, n_kids, n_tasks;
+    int spin_limit;
+    double param;
+};
+
+// Work groups per CU the batch kernel can keep resident.
+int batch_groups_per_cu(KernelSpec k, bool fp32, int tpt, int degree);
+void launch_batch(KernelSpec k, bool fp32, int tpt, int degree, int grid, const BatchDev& a, hipStream_t st);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+
 void launch_direct(KernelSpec k, int64_t nsel, const int64_t* sel, const double* tx, const double* ty,
                    const double* tz, int64_t N, const double* sx, const double* sy, const double* sz,
                    const double* q, double* out, hipStream_t st);

@@ -78,6 +78,16 @@ struct DevTreeBufs {
     }
 };
 
+// Host helpers shared by the plan and the batch (capi.cpp).
+void upload_bytes(DevBuf& b, const void* src, size_t n);
+template <class T>
+inline void upload(DevBuf& b, const std::vector<T>& v) { upload_bytes(b, v.data(), sizeof(T) * v.size()); }
+void upload_tree(DevTreeBufs& d, const Tree& t);
+bool all_finite(const double* a, int64_t n);
+void validate(const bldtt_particles* p, int32_t kernel, double theta, int32_t degree, int64_t leaf_size);
+void level_lists(const Tree& t, bool parents, std::vector<int32_t>& ids, std::vector<int64_t>& off);
+std::vector<double> node_table();
+
 // Last failure message of the calling thread (capi.cpp).
 void set_error(const std::string& m);
 extern thread_local std::string g_last_error;

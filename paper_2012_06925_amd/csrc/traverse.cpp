@@ -83,12 +83,37 @@ void recurse(const Ctx& x, int64_t t, int64_t s, Lists& out) {
 
 void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out,
               bool defer_separated) {
+    traverse_roots(T, S, {{0, 0}}, theta, degree, pp_cc_only, out, defer_separated);
+}
+
+int64_t append_tree(Tree& f, const Tree& t, int64_t pos0, int64_t caller0) {
+    const int64_t c0 = f.size(), n = t.size();
+    f.lo.insert(f.lo.end(), t.lo.begin(), t.lo.end());
+    f.hi.insert(f.hi.end(), t.hi.begin(), t.hi.end());
+    f.center.insert(f.center.end(), t.center.begin(), t.center.end());
+    f.radius.insert(f.radius.end(), t.radius.begin(), t.radius.end());
+    f.level.insert(f.level.end(), t.level.begin(), t.level.end());
+    f.nchild.insert(f.nchild.end(), t.nchild.begin(), t.nchild.end());
+    for (int64_t c = 0; c < n; ++c) {
+        f.begin.push_back(t.begin[c] + pos0);
+        f.count.push_back(t.count[c]);
+        f.parent.push_back(t.parent[c] < 0 ? -1 : t.parent[c] + c0);
+        for (int k = 0; k < 8; ++k) f.child.push_back(t.child[8 * c + k] < 0 ? -1 : t.child[8 * c + k] + c0);
+    }
+    for (int64_t p = 0; p < t.n_particles; ++p) f.perm.push_back(t.perm[p] + caller0);
+    f.n_particles += t.n_particles;
+    f.depth = std::max(f.depth, t.depth);
+    return c0;
+}
+
+void traverse_roots(const Tree& T, const Tree& S, const std::vector<std::pair<int64_t, int64_t>>& roots,
+                    double theta, int degree, bool pp_cc_only, Lists& out, bool defer_separated) {
     Ctx x{T, S, theta, degree, pp_cc_only, defer_separated};
     out.clear();
     // Breadth-first expansion until there is enough independent work, then
     // depth-first recursion per frontier pair on all threads.  Per-pair lists
     // are concatenated in frontier order, so the output is deterministic.
-    std::vector<std::pair<int64_t, int64_t>> cur{{0, 0}}, nxt;
+    std::vector<std::pair<int64_t, int64_t>> cur(roots), nxt;
     const size_t want = (size_t)64 * num_threads();
     while (!cur.empty() && cur.size() < want) {
         nxt.clear();

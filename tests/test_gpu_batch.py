@@ -1,0 +1,207 @@
+"""Batched persistent launch on the GPU: every problem of a batch against the
+same problem run alone (bldtt_setup + bldtt_compute) and against the CPU
+oracle; graph replays; tile choices; the autotuner's cache; the bounded-wait
+failure path (forced from the host with a zero spin limit)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_2012_06925_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+api = pytest.importorskip("paper_2012_06925_amd.api")
+from paper_2012_06925_amd import _lib  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _problems(count, seed, lo=2.5, hi=4.0):
+    return [p for _, p in inputs.batch_problems(count=count, seed=seed, lo_exp=lo, hi_exp=hi)]
+
+
+def _dev_problem(p, targets=None):
+    src = tuple(_dev(a) for a in (p.x, p.y, p.z, p.q))
+    tgt = None if targets is None else tuple(_dev(a) for a in targets)
+    return tgt, src
+
+
+def _alone(problem, **kw):
+    tgt, src = problem
+    plan = api.Plan(tgt, src, **kw)
+    out = plan.compute()
+    torch.cuda.synchronize()
+    plan.close()
+    return out.cpu().numpy()
+
+
+def _rel(a, b):
+    d = np.abs(a - b).max()
+    s = np.abs(b).max()
+    return d / s if s > 0 else d
+
+
+@pytest.mark.parametrize("kernel,flags,theta,degree,leaf", [
+    ("coulomb", 0, 0.7, 6, 100),
+    ("coulomb", _lib.FP32_EVAL, 0.8, 5, 150),
+    ("yukawa", 0, 0.7, 4, 80),
+    ("yukawa", _lib.FP32_EVAL, 0.7, 6, 120),
+])
+def test_batch_equals_standalone_runs(kernel, flags, theta, degree, leaf):
+    probs = [_dev_problem(p) for p in _problems(10, inputs.BASE_SEED + 50)]
+    kw = dict(kernel=kernel, theta=theta, degree=degree, leaf=leaf, flags=flags)
+    b = api.Batch(probs, **kw)
+    outs = b.compute()
+    b.check()
+    worst = 0.0
+    for pr, o in zip(probs, outs):
+        ref = _alone(pr, **kw)
+        worst = max(worst, _rel(o.cpu().numpy(), ref))
+    print(f"max relative difference batch vs standalone: {worst:.3e}")
+    assert worst <= 1e-13
+    b.close()
+
+
+def test_batch_matches_oracle():
+    ps = _problems(4, inputs.BASE_SEED + 51, lo=2.7, hi=3.5)
+    probs = [_dev_problem(p) for p in ps]
+    b = api.Batch(probs, theta=0.7, degree=6, leaf=60)
+    outs = b.compute()
+    b.check()
+    for p, o in zip(ps, outs):
+        ref = core.Run(p, p, theta=0.7, degree=6, leaf=60).run_all()
+        got = o.cpu().numpy()
+        err = np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2))
+        assert err <= 1e-12, err
+    b.close()
+
+
+def test_batch_poly_kernel_reproduced_exactly():
+    # (1 + x.y)^2 has degree 2 per coordinate: every approximation type is exact
+    ps = _problems(5, inputs.BASE_SEED + 52, lo=2.5, hi=3.3)
+    probs = [_dev_problem(p) for p in ps]
+    b = api.Batch(probs, kernel="poly", theta=0.9, degree=2, leaf=30)
+    outs = b.compute()
+    b.check()
+    for p, o in zip(ps, outs):
+        ref = core.direct_sum(p, p, kernel="poly")
+        assert _rel(o.cpu().numpy(), ref) <= 1e-12
+    b.close()
+
+
+def test_batch_unequal_sets_equal_standalone():
+    rng = np.random.default_rng(9)
+    probs = []
+    for i, p in enumerate(_problems(6, inputs.BASE_SEED + 53, lo=2.8, hi=3.8)):
+        if i % 2:
+            t = rng.normal(0.0, 0.3, size=(3, 700 + 150 * i))
+            probs.append(_dev_problem(p, targets=(t[0], t[1], t[2])))
+        else:
+            probs.append(_dev_problem(p))
+    kw = dict(theta=0.75, degree=5, leaf=70)
+    b = api.Batch(probs, **kw)
+    outs = b.compute()
+    b.check()
+    for pr, o in zip(probs, outs):
+        assert _rel(o.cpu().numpy(), _alone(pr, **kw)) <= 1e-13
+    b.close()
+
+
+def test_graph_replays_and_tiles_give_identical_results():
+    probs = [_dev_problem(p) for p in _problems(8, inputs.BASE_SEED + 54)]
+    b = api.Batch(probs, theta=0.7, degree=6, leaf=100)
+    first = [o.cpu().numpy() for o in b.compute()]
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=DEV).sum()      # unrelated eager work between replays
+        outs = b.compute()
+        b.check()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for f, o in zip(first, outs):
+            assert np.array_equal(f, o.cpu().numpy()), rep
+    for tpt, g in ((1, 0), (4, 1), (2, 2)):
+        b.set_tile(tpt, g)
+        outs = b.compute()
+        b.check()
+        st = b.stats()
+        assert st["tpt"] == tpt and st["grid"] >= 1
+        for f, o in zip(first, outs):
+            assert _rel(o.cpu().numpy(), f) <= 1e-13, (tpt, g)
+    b.close()
+
+
+def test_autotuner_measures_then_reads_its_cache(tmp_path):
+    cache = tmp_path / "tune.txt"
+    api.set_tune_cache(str(cache))
+    try:
+        probs = [_dev_problem(p) for p in _problems(6, inputs.BASE_SEED + 55)]
+        plain = api.Batch(probs, theta=0.7, degree=6, leaf=100)
+        ref = [o.cpu().numpy() for o in plain.compute()]
+        plain.close()
+        b = api.Batch(probs, theta=0.7, degree=6, leaf=100, flags=_lib.AUTOTUNE)
+        st = b.stats()
+        assert st["tuned"] == 2 and st["tune_best_ms"] > 0
+        text = cache.read_text()
+        assert text.startswith("batch:") and "\t" in text
+        outs = b.compute()
+        b.check()
+        for r, o in zip(ref, outs):
+            assert _rel(o.cpu().numpy(), r) <= 1e-13
+        b.close()
+        api.set_tune_cache(str(cache))                     # re-read the file
+        b2 = api.Batch(probs, theta=0.7, degree=6, leaf=100, flags=_lib.AUTOTUNE)
+        st2 = b2.stats()
+        assert st2["tuned"] == 1 and st2["tpt"] == st["tpt"] and st2["groups_per_cu"] == st["groups_per_cu"]
+        b2.close()
+        # the single-problem path reads the same cache
+        tgt, src = probs[0]
+        plan = api.Plan(tgt, src, theta=0.7, degree=6, leaf=100)
+        api.autotune(plan, reps=1)
+        out = plan.compute()
+        torch.cuda.synchronize()
+        assert _rel(out.cpu().numpy(), ref[0]) <= 1e-13
+        plan.close()
+        assert "single:" in cache.read_text()
+    finally:
+        api.set_tune_cache(None)
+
+
+def test_bounded_wait_failure_is_reported_then_recovers():
+    probs = [_dev_problem(p) for p in _problems(8, inputs.BASE_SEED + 56)]
+    b = api.Batch(probs, theta=0.7, degree=6, leaf=100)
+    ref = [o.cpu().numpy() for o in b.compute()]
+    b.check()
+    b.set_spin_limit(0)                                     # every unmet dependency gives up at once
+    b.compute()
+    with pytest.raises(_lib.BldttError) as e:
+        b.check()
+    assert e.value.code == _lib.EDEVICE
+    b.set_spin_limit(1 << 22)
+    outs = b.compute()
+    b.check()
+    for r, o in zip(ref, outs):
+        assert np.array_equal(r, o.cpu().numpy())
+    b.close()
+
+
+def test_batch_sync_flag_and_errors():
+    probs = [_dev_problem(p) for p in _problems(3, inputs.BASE_SEED + 57)]
+    b = api.Batch(probs, theta=0.7, degree=6, leaf=100, flags=_lib.SYNC)
+    outs = b.compute()
+    assert all(o.numel() == p[1][0].numel() for o, p in zip(outs, probs))
+    with pytest.raises(ValueError):
+        b.compute(outs[:1])
+    b.close()
+    with pytest.raises(_lib.BldttError) as e:
+        api.Batch(probs, kernel="oscillatory", theta=0.7, degree=6, leaf=100)
+    assert e.value.code == _lib.EUNSUPPORTED
+    with pytest.raises(_lib.BldttError) as e:
+        api.Batch(probs, theta=0.7, degree=11, leaf=100)
+    assert e.value.code == _lib.EUNSUPPORTED
