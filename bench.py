@@ -2,6 +2,7 @@
 
     python bench.py [--steps K] [--warmup W] [--workload cube1e7] [--mode both|plain|tuned]
     python bench.py --sweep plain|tuned        # choose the operating points
+    python bench.py --workload batch256        # 256 problems in one persistent graph launch
 
 One step is one bldtt_compute: host traversal and list packing, upward pass,
 PP/PC/CP/CC sums, downward pass and the scatter to caller order, with the
@@ -187,6 +188,120 @@ class Bench:
         return {"sweep": mode, "workload": self.args.workload, "M": self.M, "best": best, "rows": rows}
 
 
+BATCH_METRIC = "particles/s (compute phase), 256 uneven problems in one persistent graph launch"
+
+
+def batch_bench(args, wl, name) -> dict:
+    """One graph launch of the batched persistent kernel per step, against the
+    same problems run one after another (bldtt_compute each)."""
+    import tempfile
+
+    import torch
+    from paper_2012_06925_amd import _lib, api, inputs
+    dev = torch.device("cuda:0")
+    probs = inputs.batch_problems(count=wl["count"], seed=inputs.workload_seed(name), lo_exp=wl["lo_exp"],
+                                  hi_exp=wl["hi_exp"])
+    sets = [p for _, p in probs]
+    total = sum(p.n for p in sets)
+    print(f"[bench] {len(sets)} problems, {total} particles", file=sys.stderr, flush=True)
+    dsets = [(None, tuple(torch.from_numpy(a).to(dev) for a in (p.x, p.y, p.z, p.q))) for p in sets]
+    kw = dict(kernel=wl["kernel"], theta=args.theta, degree=args.degree, leaf=args.leaf)
+    outs = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in sets]
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # the same problems one after another (plans built outside the timed region)
+    plans = [api.Plan(t, s, **kw) for t, s in dsets]
+    for pl, o in zip(plans, outs):
+        pl.compute(o)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for pl, o in zip(plans, outs):
+        pl.compute(o)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    seq_wall = (time.perf_counter() - w0) * 1e3
+    seq_ms = ev0.elapsed_time(ev1)
+    seq_traverse = sum(pl.stats()["traverse_ms"] for pl in plans)
+    seq_phi = [o.clone() for o in outs]
+    for pl in plans:
+        pl.close()
+    print(f"[bench] sequential: {seq_ms:.2f} ms (wall {seq_wall:.2f}, host traversal {seq_traverse:.2f})",
+          file=sys.stderr, flush=True)
+
+    # the batch: autotuned tile, one graph launch per step
+    cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "bldtt_tune_cache.txt")
+    api.set_tune_cache(cache)
+    t0 = time.perf_counter()
+    b = api.Batch(dsets, flags=_lib.AUTOTUNE, **kw)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    st = b.stats()
+    print(f"[bench] batch setup {setup_ms:.0f} ms, tile tpt={st['tpt']} groups/CU={st['groups_per_cu']} "
+          f"(tuned={st['tuned']}), {st['n_tasks']} tasks", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        b.compute(outs)
+    b.check()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        b.compute(outs)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) * 1e3 / args.steps
+    ms = ev0.elapsed_time(ev1) / args.steps
+    b.check()
+    parity = max(float((o - r).abs().max() / r.abs().max()) for o, r in zip(outs, seq_phi))
+    # accuracy against the direct sum on 0.1% of each problem's targets (at least 8)
+    num = den = 0.0
+    worst = 0.0
+    for i, (p, o) in enumerate(zip(sets, outs)):
+        sel = inputs.error_sample(p.n, inputs.workload_seed(name) + 7 * i, fraction=1e-3, minimum=min(p.n, 8))
+        src = dsets[i][1]
+        ds = api.direct_sum(src[:3], src, kernel=wl["kernel"], sel=torch.from_numpy(sel).to(dev)).cpu().numpy()
+        got = o.cpu().numpy()[sel]
+        e2, d2 = float(np.sum((got - ds) ** 2)), float(np.sum(ds ** 2))
+        num, den = num + e2, den + d2
+        worst = max(worst, np.sqrt(e2 / d2))
+    err = float(np.sqrt(num / den))
+    inter = st["interactions"]
+    fl = FLOPS_PER_EVAL[wl["kernel"]]
+    work = sum(inter.values()) * fl
+    achieved = work / (ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "k_batch (every phase, one launch)", "achieved": round(achieved, 3),
+            "peak": FP64_VALU_PEAK, "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK, 4),
+            "traffic": None, "flops_per_launch": work, "launch_ms": round(ms, 4), "flops_per_eval": fl}
+    b.close()
+    cpu = None
+    if not args.no_cpu:
+        k = args.cpu_problems
+        from oracle import core
+        t0 = time.perf_counter()
+        for p in sets[:k]:
+            core.Run(p, p, kernel=wl["kernel"], theta=args.theta, degree=args.degree, leaf=args.leaf).run_all()
+        wall_cpu = time.perf_counter() - t0
+        n_cpu = sum(p.n for p in sets[:k])
+        cpu = {"value": n_cpu / wall_cpu, "unit": "particles/s", "cores": core.num_threads(), "kind": "oracle",
+               "sample": f"the first {k} of the {len(sets)} problems ({n_cpu} particles), one after another, "
+                         f"FP64 ({wall_cpu:.2f} s)"}
+    return {
+        "metric": BATCH_METRIC, "value": total / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": name, "problems": len(sets), "particles": total, "kernel": wl["kernel"],
+                   "theta": args.theta, "degree": args.degree, "leaf": args.leaf},
+        "error_vs_direct": err, "worst_problem_error": worst, "batch_vs_sequential_maxrel": parity,
+        "wall_ms_per_step": round(wall, 3), "setup_ms": round(setup_ms, 1),
+        "tile": {"tpt": st["tpt"], "groups_per_cu": st["groups_per_cu"], "grid": st["grid"], "tuned": st["tuned"],
+                 "tune_ms": round(st["tune_ms"], 1)},
+        "n_tasks": st["n_tasks"], "interactions": inter,
+        "sequential": {"ms": round(seq_ms, 3), "wall_ms": round(seq_wall, 3), "host_traversal_ms": round(seq_traverse, 3),
+                       "particles_per_s": total / (seq_ms * 1e-3)},
+        "batch_over_sequential": seq_ms / ms,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +324,8 @@ def main() -> int:
     ap.add_argument("--sweep-degrees", default="4,5,6,7,8,9,10")
     ap.add_argument("--sweep-taus", default="3e-8,1e-7,3e-7,1e-6,3e-6")
     ap.add_argument("--sweep-leaves", default=None, help="comma list; default: the workload's leaf size")
+    ap.add_argument("--cpu-problems", type=int, default=16, help="batch workloads: problems in the CPU sample")
+    ap.add_argument("--tune-cache", default=None, help="batch workloads: autotune cache file")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -226,6 +343,12 @@ def main() -> int:
     from paper_2012_06925_amd.train_degree_model import DEFAULT_MODEL
 
     wl = dict(inputs.WORKLOADS[args.workload])
+    if "count" in wl:
+        args.theta = args.theta if args.theta is not None else wl["theta"]
+        args.degree = args.degree if args.degree is not None else wl["degree"]
+        args.leaf = args.leaf if args.leaf is not None else wl["leaf"]
+        print(json.dumps(batch_bench(args, wl, args.workload)), flush=True)
+        return 0
     if "dist" not in wl:
         raise SystemExit("bench.py times targets = sources workloads")
     M = args.n or wl["M"]
