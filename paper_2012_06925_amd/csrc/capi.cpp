@@ -179,11 +179,15 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const bool varied = pl->varied_degree();
 
     collect_profile(pl);
-    // 1. upward pass at the base degree, overlapping the host traversal (a
-    //    per-pair degree plan runs it after the degrees are chosen)
-    if (!varied) {
+    // 1. upward pass, overlapping the host traversal: at the base degree, or
+    //    for a per-pair degree plan at the source degrees its last compute used
+    //    (the same particles give the same choice); degrees missing from that
+    //    set follow once the degrees are chosen
+    const uint32_t pre = varied ? pl->up_degrees_last : (1u << pl->degree);
+    if (pre) {
         PhaseMark mark(pl, BLDTT_PH_UP, st);
-        upward(pl, pl->degree, st);
+        for (int d = 0; d <= kMaxDegree; ++d)
+            if (pre >> d & 1) upward(pl, d, st);
     }
 
     // 2. traversal, per-pair degrees, work packing
@@ -222,9 +226,13 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     HIPCHK(hipEventRecord(pl->staging_free, st));
 
     if (varied) {
-        PhaseMark mark(pl, BLDTT_PH_UP, st);
-        for (int d = 0; d <= kMaxDegree; ++d)
-            if (w.src_degrees >> d & 1) upward(pl, d, st);
+        const uint32_t rest = w.src_degrees & ~pre;
+        if (rest) {
+            PhaseMark mark(pl, BLDTT_PH_UP, st);
+            for (int d = 0; d <= kMaxDegree; ++d)
+                if (rest >> d & 1) upward(pl, d, st);
+        }
+        pl->up_degrees_last = w.src_degrees;
     }
 
     // 3. CP + CC into proxy potentials per degree, lift to the downward degree,

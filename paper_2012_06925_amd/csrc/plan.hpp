@@ -153,6 +153,7 @@ struct bldtt_plan {
     bool prof_pending = false;
 
     int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
+    uint32_t up_degrees_last = 0;            // source degrees of the last per-pair degree compute
     int P() const { return (degree + 1) * (degree + 1) * (degree + 1); }
     DevParticles dsrc() const { return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), sq.as<double>()}; }
     DevParticles dtgt() const {

@@ -147,24 +147,57 @@ struct ByTarget {
     std::vector<int8_t> type, deg;
 };
 
+// Parallel counting sort over the concatenated lists t0..t1: chunk k counts
+// its entries per cluster, and its entries land after those of chunks < k, so
+// the order within a cluster is the list order.
 ByTarget group(const Tree& T, const Lists& L, int t0, int t1, int degree) {
     ByTarget g;
-    int64_t nc = T.size();
-    g.off.assign(nc + 1, 0);
-    for (int ty = t0; ty <= t1; ++ty)
-        for (int64_t tc : L.tc[ty]) g.off[tc + 1]++;
-    for (int64_t c = 0; c < nc; ++c) g.off[c + 1] += g.off[c];
-    g.sc.resize(g.off[nc]);
-    g.type.resize(g.off[nc]);
-    g.deg.resize(g.off[nc]);
-    std::vector<int64_t> fill(g.off.begin(), g.off.end() - 1);
-    for (int ty = t0; ty <= t1; ++ty)
-        for (size_t e = 0; e < L.tc[ty].size(); ++e) {
-            int64_t at = fill[L.tc[ty][e]]++;
-            g.sc[at] = L.sc[ty][e];
-            g.type[at] = (int8_t)ty;
-            g.deg[at] = L.deg[ty].empty() ? (int8_t)degree : L.deg[ty][e];
+    const int64_t nc = T.size();
+    std::vector<int64_t> base{0};
+    for (int ty = t0; ty <= t1; ++ty) base.push_back(base.back() + (int64_t)L.tc[ty].size());
+    const int64_t E = base.back();
+    auto at = [&](int64_t i, int& ty, int64_t& e) {
+        ty = t0;
+        while (i >= base[ty - t0 + 1]) ++ty;
+        e = i - base[ty - t0];
+    };
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), E / 16384 + 1));
+    const int64_t per = (E + nch - 1) / nch;
+    std::vector<int64_t> cnt(nch * nc, 0);
+    parallel_run(nch, [&](int64_t k) {
+        int64_t* c = cnt.data() + k * nc;
+        for (int64_t i = k * per; i < std::min(E, (k + 1) * per); ++i) {
+            int ty;
+            int64_t e;
+            at(i, ty, e);
+            c[L.tc[ty][e]]++;
         }
+    });
+    g.off.assign(nc + 1, 0);
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t run = g.off[c];
+        for (int64_t k = 0; k < nch; ++k) {
+            int64_t n = cnt[k * nc + c];
+            cnt[k * nc + c] = run;             // start of chunk k's entries of cluster c
+            run += n;
+        }
+        g.off[c + 1] = run;
+    }
+    g.sc.resize(E);
+    g.type.resize(E);
+    g.deg.resize(E);
+    parallel_run(nch, [&](int64_t k) {
+        int64_t* fill = cnt.data() + k * nc;
+        for (int64_t i = k * per; i < std::min(E, (k + 1) * per); ++i) {
+            int ty;
+            int64_t e;
+            at(i, ty, e);
+            int64_t to = fill[L.tc[ty][e]]++;
+            g.sc[to] = L.sc[ty][e];
+            g.type[to] = (int8_t)ty;
+            g.deg[to] = L.deg[ty].empty() ? (int8_t)degree : L.deg[ty][e];
+        }
+    });
     return g;
 }
 
@@ -203,22 +236,74 @@ inline Entry proxy_entry(int64_t sc, int d) {
     return Entry{(int32_t)sc, (int32_t)((uint32_t)SRC_PROXY << 29 | (uint32_t)d)};
 }
 
+// Output of one block of target clusters, concatenated in block order.
+struct Block {
+    std::vector<Entry> entries;
+    std::vector<std::pair<double, Item>> items;      // eb, ee relative to this block's entries
+    std::vector<Item> prolong;
+};
+
+void append_blocks(std::vector<Block>& blocks, std::vector<Entry>& entries, std::vector<std::pair<double, Item>>& items,
+                   std::vector<Item>* prolong) {
+    size_t ne = 0, ni = 0;
+    for (auto& b : blocks) {
+        ne += b.entries.size();
+        ni += b.items.size();
+    }
+    entries.reserve(ne);
+    items.reserve(ni);
+    for (auto& b : blocks) {
+        const int32_t shift = (int32_t)entries.size();
+        entries.insert(entries.end(), b.entries.begin(), b.entries.end());
+        for (auto& it : b.items) {
+            it.second.eb += shift;
+            it.second.ee += shift;
+            items.push_back(it);
+        }
+        if (prolong) prolong->insert(prolong->end(), b.prolong.begin(), b.prolong.end());
+        b = Block();
+    }
+}
+
+void sort_items(std::vector<std::pair<double, Item>>& items, std::vector<Item>& out) {
+    // Longest items first: the tail of the grid is then made of short items.
+    std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    out.reserve(items.size());
+    for (auto& it : items) out.push_back(it.second);
+}
+
 }  // namespace
 
 void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w) {
     w = Work();
     auto deg_of = [&](int ty, size_t e) { return L.deg[ty].empty() ? degree : (int)L.deg[ty][e]; };
     for (int ty = 0; ty < 4; ++ty) {
-        double acc = 0.0;
-        for (size_t e = 0; e < L.tc[ty].size(); ++e) {
-            double np = (double)cube(deg_of(ty, e));
-            double ct = ty == PP || ty == PC ? (double)T.count[L.tc[ty][e]] : np;
-            double cs = ty == PP || ty == CP ? (double)S.count[L.sc[ty][e]] : np;
-            acc += ct * cs;
-            if (ty == PC || ty == CC) w.src_degrees |= 1u << deg_of(ty, e);
-            if (ty == CP || ty == CC) w.tgt_degrees |= 1u << deg_of(ty, e);
+        const int64_t n = (int64_t)L.tc[ty].size();
+        const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), n / 16384 + 1));
+        const int64_t per = (n + nch - 1) / nch;
+        std::vector<double> acc(nch, 0.0);
+        std::vector<uint32_t> sd(nch, 0), td(nch, 0);
+        parallel_run(nch, [&](int64_t k) {
+            double a = 0.0;
+            uint32_t s = 0, t = 0;
+            for (int64_t e = k * per; e < std::min(n, (k + 1) * per); ++e) {
+                const int d = deg_of(ty, e);
+                double np = (double)cube(d);
+                double ct = ty == PP || ty == PC ? (double)T.count[L.tc[ty][e]] : np;
+                double cs = ty == PP || ty == CP ? (double)S.count[L.sc[ty][e]] : np;
+                a += ct * cs;                        // integers below 2^53: exact in any order
+                if (ty == PC || ty == CC) s |= 1u << d;
+                if (ty == CP || ty == CC) t |= 1u << d;
+            }
+            acc[k] = a;
+            sd[k] = s;
+            td[k] = t;
+        });
+        for (int64_t k = 0; k < nch; ++k) {
+            w.interactions[ty] += acc[k];
+            w.src_degrees |= sd[k];
+            w.tgt_degrees |= td[k];
         }
-        w.interactions[ty] = acc;
     }
     // Downward degree: the largest degree of any proxy potential (lower degrees
     // are lifted to it exactly), or the base degree when there are none.
@@ -232,81 +317,90 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
     ByTarget part = group(T, L, PP, PC, degree);
     ByTarget prox = group(T, L, CP, CC, degree);
     const int64_t nc = T.size();
-    std::vector<std::pair<int64_t, int64_t>> rp, rg;
+    constexpr int64_t kBlockClusters = 64;
+    const int64_t nblk = (nc + kBlockClusters - 1) / kBlockClusters;
 
     // Particle targets: per target leaf, the PP/PC entries of the leaf and of
     // every ancestor (each leaf owns its targets, so no two items share an output).
-    std::vector<std::pair<double, Item>> items;
     w.leaf_has_far.assign(nc, 0);
-    for (int64_t leaf = 0; leaf < nc; ++leaf) {
-        if (!T.is_leaf(leaf)) continue;
-        int64_t eb = (int64_t)w.pentries.size();
-        double src = 0.0;
-        bool far = false;
-        for (int64_t c = leaf; c >= 0; c = T.parent[c]) {
-            if (prox.off[c + 1] > prox.off[c]) far = true;
-            for (int64_t e = part.off[c]; e < part.off[c + 1]; ++e) {
-                int64_t sc = part.sc[e];
-                if (part.type[e] == PC) {
-                    w.pentries.push_back(proxy_entry(sc, part.deg[e]));
-                    src += (double)cube(part.deg[e]);
-                } else {
-                    (boxes_touch(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
-                    src += (double)S.count[sc];
+    std::vector<Block> blocks(nblk);
+    parallel_run(nblk, [&](int64_t bi) {
+        Block& B = blocks[bi];
+        std::vector<std::pair<int64_t, int64_t>> rp, rg;
+        for (int64_t leaf = bi * kBlockClusters; leaf < std::min(nc, (bi + 1) * kBlockClusters); ++leaf) {
+            if (!T.is_leaf(leaf)) continue;
+            int64_t eb = (int64_t)B.entries.size();
+            double src = 0.0;
+            bool far = false;
+            for (int64_t c = leaf; c >= 0; c = T.parent[c]) {
+                if (prox.off[c + 1] > prox.off[c]) far = true;
+                for (int64_t e = part.off[c]; e < part.off[c + 1]; ++e) {
+                    int64_t sc = part.sc[e];
+                    if (part.type[e] == PC) {
+                        B.entries.push_back(proxy_entry(sc, part.deg[e]));
+                        src += (double)cube(part.deg[e]);
+                    } else {
+                        (boxes_touch(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
+                        src += (double)S.count[sc];
+                    }
                 }
             }
+            emit_ranges(rp, rg, B.entries);
+            w.leaf_has_far[leaf] = far;
+            int64_t ee = (int64_t)B.entries.size();
+            for (int64_t tb = T.begin[leaf]; tb < T.begin[leaf] + T.count[leaf]; tb += tile) {
+                int64_t tn = std::min<int64_t>(tile, T.begin[leaf] + T.count[leaf] - tb);
+                B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
+                                                          (int32_t)leaf, (int32_t)w.down_degree, (int32_t)tb}});
+            }
         }
-        emit_ranges(rp, rg, w.pentries);
-        w.leaf_has_far[leaf] = far;
-        int64_t ee = (int64_t)w.pentries.size();
-        for (int64_t tb = T.begin[leaf]; tb < T.begin[leaf] + T.count[leaf]; tb += tile) {
-            int64_t tn = std::min<int64_t>(tile, T.begin[leaf] + T.count[leaf] - tb);
-            items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee, (int32_t)leaf,
-                                                     (int32_t)w.down_degree, (int32_t)tb}});
-        }
-    }
-    // Longest items first: the tail of the grid is then made of short items.
-    std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
-    w.pitems.reserve(items.size());
-    for (auto& it : items) w.pitems.push_back(it.second);
+    });
+    std::vector<std::pair<double, Item>> items;
+    append_blocks(blocks, w.pentries, items, nullptr);
+    sort_items(items, w.pitems);
 
     // Proxy targets: per (target cluster, degree) with CP/CC entries, tiles of its proxies.
     items.clear();
-    for (int64_t c = 0; c < nc; ++c) {
-        if (prox.off[c + 1] == prox.off[c]) continue;
-        uint32_t used = 0;
-        for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) used |= 1u << prox.deg[e];
-        for (int d = 0; d <= kMaxDegree; ++d) {
-            if (!(used >> d & 1)) continue;
-            int64_t eb = (int64_t)w.qentries.size();
-            double src = 0.0;
-            for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) {
-                if (prox.deg[e] != d) continue;
-                int64_t sc = prox.sc[e];
-                if (prox.type[e] == CC) {
-                    w.qentries.push_back(proxy_entry(sc, d));
-                    src += (double)cube(d);
-                } else {
-                    rp.emplace_back(S.begin[sc], S.count[sc]);     // separated: never r = 0
-                    src += (double)S.count[sc];
+    blocks.assign(nblk, Block());
+    const int down = w.down_degree;
+    parallel_run(nblk, [&](int64_t bi) {
+        Block& B = blocks[bi];
+        std::vector<std::pair<int64_t, int64_t>> rp, rg;
+        for (int64_t c = bi * kBlockClusters; c < std::min(nc, (bi + 1) * kBlockClusters); ++c) {
+            if (prox.off[c + 1] == prox.off[c]) continue;
+            uint32_t used = 0;
+            for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) used |= 1u << prox.deg[e];
+            for (int d = 0; d <= kMaxDegree; ++d) {
+                if (!(used >> d & 1)) continue;
+                int64_t eb = (int64_t)B.entries.size();
+                double src = 0.0;
+                for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) {
+                    if (prox.deg[e] != d) continue;
+                    int64_t sc = prox.sc[e];
+                    if (prox.type[e] == CC) {
+                        B.entries.push_back(proxy_entry(sc, d));
+                        src += (double)cube(d);
+                    } else {
+                        rp.emplace_back(S.begin[sc], S.count[sc]);     // separated: never r = 0
+                        src += (double)S.count[sc];
+                    }
+                }
+                emit_ranges(rp, rg, B.entries);
+                int64_t ee = (int64_t)B.entries.size();
+                const int64_t np = cube(d);
+                for (int64_t lb = 0; lb < np; lb += ptile) {
+                    int64_t ln = std::min<int64_t>(ptile, np - lb);
+                    B.items.push_back({src * (double)ln, Item{(int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee,
+                                                              (int32_t)c, (int32_t)d, (int32_t)c}});
                 }
             }
-            emit_ranges(rp, rg, w.qentries);
-            int64_t ee = (int64_t)w.qentries.size();
-            const int64_t np = cube(d);
-            for (int64_t lb = 0; lb < np; lb += ptile) {
-                int64_t ln = std::min<int64_t>(ptile, np - lb);
-                items.push_back({src * (double)ln, Item{(int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee, (int32_t)c,
-                                                         (int32_t)d, (int32_t)c}});
-            }
+            // degrees of this cluster's proxy potentials that are lifted to the downward degree
+            uint32_t lift = used & ~(1u << down);
+            if (lift) B.prolong.push_back(Item{0, 0, 0, 0, (int32_t)c, (int32_t)lift, (int32_t)c});
         }
-        // degrees of this cluster's proxy potentials that are lifted to the downward degree
-        uint32_t lift = used & ~(1u << w.down_degree);
-        if (lift) w.prolong.push_back(Item{0, 0, 0, 0, (int32_t)c, (int32_t)lift, (int32_t)c});
-    }
-    std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
-    w.qitems.reserve(items.size());
-    for (auto& it : items) w.qitems.push_back(it.second);
+    });
+    append_blocks(blocks, w.qentries, items, &w.prolong);
+    sort_items(items, w.qitems);
 }
 
 }  // namespace bldtt
