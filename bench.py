@@ -93,6 +93,10 @@ class Bench:
     def plan(self, mode, theta, degree, tau=None, profile=False):
         from paper_2012_06925_amd import _lib
         flags = _lib.PROFILE if profile else 0
+        if self.args.valu_passes:
+            flags |= _lib.VALU_PASSES
+        if self.args.mfma_leaf:
+            flags |= _lib.MFMA_LEAF
         if mode in ("fp32", "tuned"):
             flags |= _lib.FP32_EVAL
         if mode == "tuned":
@@ -324,6 +328,10 @@ def main() -> int:
     ap.add_argument("--sweep-degrees", default="4,5,6,7,8,9,10")
     ap.add_argument("--sweep-taus", default="3e-8,1e-7,3e-7,1e-6,3e-6")
     ap.add_argument("--sweep-leaves", default=None, help="comma list; default: the workload's leaf size")
+    ap.add_argument("--valu-passes", action="store_true",
+                    help="run the up/down transfers on the vector ALUs instead of the matrix cores")
+    ap.add_argument("--mfma-leaf", action="store_true",
+                    help="run the leaf contractions on the matrix cores instead of the vector ALUs")
     ap.add_argument("--cpu-problems", type=int, default=16, help="batch workloads: problems in the CPU sample")
     ap.add_argument("--tune-cache", default=None, help="batch workloads: autotune cache file")
     ap.add_argument("--copy-calib-mib", type=int, default=0,

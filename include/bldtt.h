@@ -65,9 +65,17 @@ enum {
     BLDTT_SYNC = 1u << 2,          /* bldtt_compute waits for its stream before returning */
     BLDTT_PROFILE = 1u << 3,       /* record HIP events around every kernel phase on the
                                       compute stream; durations appear in bldtt_stats      */
-    BLDTT_PP_CC_ONLY = 1u << 4     /* ablation of Sec. 4.3: separated pairs use CC when
+    BLDTT_PP_CC_ONLY = 1u << 4,    /* ablation of Sec. 4.3: separated pairs use CC when
                                       both clusters hold more than (n+1)^3 particles,
                                       PP otherwise                                       */
+    BLDTT_VALU_PASSES = 1u << 6,   /* run the child-to-parent and parent-to-child
+                                      transfers on the vector ALUs instead of the FP64
+                                      matrix cores (the default)                         */
+    BLDTT_MFMA_LEAF = 1u << 7      /* run the leaf contractions (proxy charges from the
+                                      particles, interpolation to the targets) on the
+                                      FP64 matrix cores instead of the vector ALUs (the
+                                      default, faster on gfx950: FP64 matrix and vector
+                                      peaks are equal and 16x16 tiles pad n+1 rows)     */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host

@@ -19,7 +19,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 
 KERNELS = {"coulomb": 0, "yukawa": 1, "oscillatory": 2, "regcoulomb": 3, "poly": 100}
 DEFAULT_PARAM = {"coulomb": 0.0, "yukawa": 0.5, "oscillatory": 0.0, "regcoulomb": 0.005, "poly": 0.0}
-FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE = 1, 2, 4, 8, 16, 32
+FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE, VALU_PASSES, MFMA_LEAF = 1, 2, 4, 8, 16, 32, 64, 128
 PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf")
 TYPES = ("PP", "PC", "CP", "CC")
 

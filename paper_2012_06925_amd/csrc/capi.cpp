@@ -256,7 +256,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                        pl->phihat_deg[D].as<double>(), D, st);
         for (int l = 1; l <= T.depth; ++l) {
             int64_t b = pl->down_off[l], e = pl->down_off[l + 1];
-            launch_down_transfer(D, pl->down_kids.as<int32_t>() + b, (int)(e - b), dT, tab,
+            launch_down_transfer(D, pl->mfma_transfer(), pl->down_kids.as<int32_t>() + b, (int)(e - b), dT, tab,
                                  pl->phihat_deg[D].as<double>(), st);
         }
     }
@@ -270,7 +270,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // 5. leaves to targets, caller order
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_LEAF, st);
-        launch_down_leaf(D, pl->pitems.as<DevItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
+        launch_down_leaf(D, pl->mfma_leaf(), pl->pitems.as<DevItem>(), (int)w.pitems.size(), pl->has_far.as<uint8_t>(),
                          pl->dtgt(), dT, tab, pl->phihat_deg[D].as<double>(), pl->phi_tree.as<double>(),
                          pl->perm.as<int32_t>(), out, st);
     }
@@ -381,10 +381,10 @@ void upward(bldtt_plan* pl, int d, hipStream_t st) {
     const double* tab = pl->tab.as<double>();
     DevBuf& q = pl->qhat_deg[d];
     q.reserve(sizeof(double) * pl->S.size() * cube(d));
-    launch_up_leaf(d, pl->src_leaves.as<int32_t>(), pl->n_src_leaves, dS, pl->dsrc(), tab, q.as<double>(), st);
+    launch_up_leaf(d, pl->mfma_leaf(), pl->src_leaves.as<int32_t>(), pl->n_src_leaves, dS, pl->dsrc(), tab, q.as<double>(), st);
     for (int l = pl->S.depth; l >= 0; --l) {
         int64_t b = pl->up_off[l], e = pl->up_off[l + 1];
-        launch_up_transfer(d, pl->up_parents.as<int32_t>() + b, (int)(e - b), dS, tab, q.as<double>(), st);
+        launch_up_transfer(d, pl->mfma_transfer(), pl->up_parents.as<int32_t>() + b, (int)(e - b), dS, tab, q.as<double>(), st);
     }
 }
 

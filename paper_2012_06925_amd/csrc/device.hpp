@@ -512,5 +512,253 @@ __device__ __forceinline__ void down_leaf_body(const DevItem& it, bool far, DevP
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 matrix-core forms of the up/down contractions.
+//
+// v_mfma_f64_16x16x4f64 on one wave: D(16x16) += A(16x4) B(4x16).  Lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[l / 16 + 4 r][l % 16] in element r (measured on gfx950 with an in-bounds
+// probe).  Rows and columns past the problem size carry zeros.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Leaf proxy charges as a matrix product over the leaf's particles j:
+//   qhat[k1 + M c] = sum_j Lx_k1(x_j) * (q_j Ly_k2(y_j) Lz_k3(z_j)),  c = k2 + M k3,
+// rows k1 (one 16-row tile), columns c (ceil(M^2/16) tiles spread over the
+// four waves), K = particles in chunks of kUpChunk staged in LDS.
+template <int M>
+constexpr int up_leaf_mfma_lds_bytes() { return (int)sizeof(double) * kUpChunk * (16 + 2 * M); }
+
+template <int M>
+__device__ __forceinline__ void up_leaf_mfma_body(int c, DevTree S, DevParticles src, const double* __restrict__ tab,
+                                                  double* __restrict__ qhat, double* lds) {
+    constexpr int CH = kUpChunk, P2 = M * M, NCT = (P2 + 15) / 16, NT = (NCT + 3) / 4;
+    double (*wx)[16] = reinterpret_cast<double (*)[16]>(lds);
+    double (*wy)[M] = reinterpret_cast<double (*)[M]>(lds + CH * 16);
+    double (*wz)[M] = reinterpret_cast<double (*)[M]>(lds + CH * (16 + M));
+    const double* box = S.box + 6 * c;
+    const int b = S.begin[c], n = S.count[c];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    int k2[NT], k3[NT];
+    bool ok[NT];
+    v4d acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = (wave + 4 * t) * 16 + li;
+        ok[t] = col < P2;
+        k2[t] = ok[t] ? col % M : 0;
+        k3[t] = ok[t] ? col / M : 0;
+        acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int c0 = 0; c0 < n; c0 += CH) {
+        __syncthreads();
+        if (tid < 3 * CH) {
+            const int j = tid % CH, d = tid / CH;
+            double L[M];
+            if (c0 + j < n) {
+                const int pidx = b + c0 + j;
+                const double y = d == 0 ? src.x[pidx] : (d == 1 ? src.y[pidx] : src.z[pidx]);
+                basis1d<M>(box[d], box[3 + d], tab, y, L);
+                if (d == 2) {
+                    const double q = src.q[pidx];
+#pragma unroll
+                    for (int k = 0; k < M; ++k) L[k] *= q;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < M; ++k) L[k] = 0.0;
+            }
+            if (d == 0) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) wx[j][k] = k < M ? L[k < M ? k : 0] : 0.0;
+            } else if (d == 1) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) wy[j][k] = L[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < M; ++k) wz[j][k] = L[k];
+            }
+        }
+        __syncthreads();
+        const int steps = (min(CH, n - c0) + 3) / 4;
+        for (int s = 0; s < steps; ++s) {
+            const int j = 4 * s + lk;
+            const double a = wx[j][li];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (wave + 4 * t < NCT) {               // the same for the whole wave
+                    const double bv = ok[t] ? wy[j][k2[t]] * wz[j][k3[t]] : 0.0;
+                    acc[t] = mfma_f64(a, bv, acc[t]);
+                }
+            }
+        }
+    }
+    double* out = qhat + (int64_t)c * M * P2;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (wave + 4 * t >= NCT) continue;
+        const int col = (wave + 4 * t) * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k1 = lk + 4 * r;
+            if (k1 < M && col < P2) out[k1 + M * col] = acc[t][r];
+        }
+    }
+}
+
+// One axis of (A_x (x) A_y (x) A_z) as a matrix product: rows k_d, K = j_d,
+// columns = the other two indices; same axis order and buffers as apply3.
+template <int M>
+__device__ __forceinline__ int axis_pos(int d, int x, int col) {
+    return d == 0 ? x + M * col : (d == 1 ? col % M + M * x + M * M * (col / M) : col + M * M * x);
+}
+
+template <int M, bool TRANS>
+__device__ __forceinline__ void apply3_mfma(const double (*mat)[M][M], double* a, double* b) {
+    constexpr int P2 = M * M, NCT = (P2 + 15) / 16, KS = (M + 3) / 4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double* in = d == 1 ? b : a;
+        double* out = d == 1 ? a : b;
+        for (int t = wave; t < NCT; t += 4) {
+            v4d acc{0.0, 0.0, 0.0, 0.0};
+            const int colb = 16 * t + li;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + lk;
+                const double av = (li < M && k < M) ? (TRANS ? mat[d][k][li] : mat[d][li][k]) : 0.0;
+                const double bv = (k < M && colb < P2) ? in[axis_pos<M>(d, k, colb)] : 0.0;
+                acc = mfma_f64(av, bv, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = lk + 4 * r;
+                if (i < M && colb < P2) out[axis_pos<M>(d, i, colb)] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void up_transfer_mfma_body(int c, DevTree S, const double* __restrict__ tab,
+                                                      double* __restrict__ qhat, double* lds) {
+    constexpr int P = M * M * M;
+    double (*mat)[M][M] = reinterpret_cast<double (*)[M][M]>(lds);
+    double* a = lds + 3 * M * M;
+    double* b = a + P;
+    double* acc = b + P;
+    for (int k = threadIdx.x; k < P; k += kBlock) acc[k] = 0.0;
+    const int nk = S.nchild[c];
+    for (int i = 0; i < nk; ++i) {
+        const int ch = S.child[8 * c + i];
+        __syncthreads();
+        build_mats<M>(mat, S.box + 6 * c, S.box + 6 * ch, tab);
+        for (int k = threadIdx.x; k < P; k += kBlock) a[k] = qhat[(int64_t)ch * P + k];
+        __syncthreads();
+        apply3_mfma<M, false>(mat, a, b);
+        for (int k = threadIdx.x; k < P; k += kBlock) acc[k] += b[k];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < P; k += kBlock) qhat[(int64_t)c * P + k] = acc[k];
+}
+
+template <int M>
+__device__ __forceinline__ void down_transfer_mfma_body(int c, DevTree T, const double* __restrict__ tab,
+                                                        double* __restrict__ phihat, double* lds) {
+    constexpr int P = M * M * M;
+    double (*mat)[M][M] = reinterpret_cast<double (*)[M][M]>(lds);
+    double* a = lds + 3 * M * M;
+    double* b = a + P;
+    const int par = T.parent[c];
+    build_mats<M>(mat, T.box + 6 * par, T.box + 6 * c, tab);
+    for (int k = threadIdx.x; k < P; k += kBlock) a[k] = phihat[(int64_t)par * P + k];
+    __syncthreads();
+    apply3_mfma<M, true>(mat, a, b);
+    for (int k = threadIdx.x; k < P; k += kBlock) phihat[(int64_t)c * P + k] += b[k];
+}
+
+// Leaf interpolation per group of 16 targets (one wave): the 1D bases go to
+// the wave's LDS slice, then T1[i, c] = sum_k1 Lx_k1(x_i) phihat[k1 + M c] on
+// the matrix core (rows i, K = k1, columns c = k2 + M k3), and
+// phi_i = sum_c T1[i, c] Ly_k2(y_i) Lz_k3(z_i) on the VALU, reduced over the
+// 16 lanes that hold one row's columns.
+template <int M>
+constexpr int down_leaf_mfma_lds_bytes() { return (int)sizeof(double) * (M * M * M + 4 * 3 * 16 * 16); }
+
+template <int M>
+__device__ __forceinline__ void down_leaf_mfma_body(const DevItem& it, bool far, DevParticles tgt, DevTree T,
+                                                    const double* __restrict__ tab, const double* __restrict__ phihat,
+                                                    const double* __restrict__ phi_tree,
+                                                    const int32_t* __restrict__ perm, double* __restrict__ out,
+                                                    int64_t obase, double* lds) {
+    constexpr int P = M * M * M, P2 = M * M, NCT = (P2 + 15) / 16, KS = (M + 3) / 4;
+    if (!far) {
+        for (int r = threadIdx.x; r < it.tn; r += kBlock) {
+            const int p = it.t0 + r;
+            out[perm[p] - obase] = phi_tree[p];
+        }
+        return;
+    }
+    double* ph = lds;
+    for (int k = threadIdx.x; k < P; k += kBlock) ph[k] = phihat[(int64_t)it.cluster * P + k];
+    __syncthreads();
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    double (*wl)[16][16] = reinterpret_cast<double (*)[16][16]>(lds + P + wave * 3 * 256);   // [dim][target][k]
+    const double* box = T.box + 6 * it.cluster;
+    const int ngroups = (it.tn + 15) / 16;
+    for (int g = wave; g < ngroups; g += 4) {
+        const int base = it.t0 + 16 * g;
+        const int cnt = min(16, it.tn - 16 * g);
+        if (lk < 3) {
+            const int p = base + min(li, cnt - 1);
+            const double y = lk == 0 ? tgt.x[p] : (lk == 1 ? tgt.y[p] : tgt.z[p]);
+            double L[M];
+            basis1d<M>(box[lk], box[3 + lk], tab, y, L);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) wl[lk][li][k] = k < M ? L[k < M ? k : 0] : 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");     // the wave's LDS writes before its reads
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < NCT; ++t) {
+            v4d acc{0.0, 0.0, 0.0, 0.0};
+            const int col = 16 * t + li;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + lk;
+                const double av = wl[0][li][k];
+                const double bv = (k < M && col < P2) ? ph[k + M * col] : 0.0;
+                acc = mfma_f64(av, bv, acc);
+            }
+            if (col < P2) {
+                const int c2 = col % M, c3 = col / M;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = lk + 4 * r;
+                    s[r] = fma(acc[r], wl[1][i][c2] * wl[2][i][c3], s[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s[r] += __shfl_xor(s[r], m, 16);
+        if (li < 4) {
+            const int i = lk + 4 * li;
+            if (i < cnt) {
+                const int p = base + i;
+                const double v = li == 0 ? s[0] : (li == 1 ? s[1] : (li == 2 ? s[2] : s[3]));
+                out[perm[p] - obase] = phi_tree[p] + v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");     // reads done before the next group's writes
+    }
+}
+
 }  // namespace dev
 }  // namespace bldtt

@@ -46,40 +46,49 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
                                            lds);
 }
 
-template <int M>
+// MF selects the matrix-core form of the contraction (device.hpp).
+template <int M, bool MF>
 __global__ __launch_bounds__(kBlock) void k_up_leaf(const int32_t* __restrict__ leaves, DevTree S,
                                                     DevParticles src, const double* __restrict__ tab,
                                                     double* __restrict__ qhat) {
-    __shared__ double lds[up_leaf_lds_bytes<M>() / sizeof(double)];
-    up_leaf_body<M>(leaves[blockIdx.x], S, src, tab, qhat, lds);
+    constexpr int B = MF ? up_leaf_mfma_lds_bytes<M>() : up_leaf_lds_bytes<M>();
+    __shared__ double lds[B / sizeof(double)];
+    if constexpr (MF) up_leaf_mfma_body<M>(leaves[blockIdx.x], S, src, tab, qhat, lds);
+    else up_leaf_body<M>(leaves[blockIdx.x], S, src, tab, qhat, lds);
 }
 
-template <int M>
+template <int M, bool MF>
 __global__ __launch_bounds__(kBlock) void k_up_transfer(const int32_t* __restrict__ parents, DevTree S,
                                                         const double* __restrict__ tab,
                                                         double* __restrict__ qhat) {
     __shared__ double lds[up_transfer_lds_bytes<M>() / sizeof(double)];
-    up_transfer_body<M>(parents[blockIdx.x], S, tab, qhat, lds);
+    if constexpr (MF) up_transfer_mfma_body<M>(parents[blockIdx.x], S, tab, qhat, lds);
+    else up_transfer_body<M>(parents[blockIdx.x], S, tab, qhat, lds);
 }
 
-template <int M>
+template <int M, bool MF>
 __global__ __launch_bounds__(kBlock) void k_down_transfer(const int32_t* __restrict__ kids, DevTree T,
                                                           const double* __restrict__ tab,
                                                           double* __restrict__ phihat) {
     __shared__ double lds[down_transfer_lds_bytes<M>() / sizeof(double)];
-    down_transfer_body<M>(kids[blockIdx.x], T, tab, phihat, lds);
+    if constexpr (MF) down_transfer_mfma_body<M>(kids[blockIdx.x], T, tab, phihat, lds);
+    else down_transfer_body<M>(kids[blockIdx.x], T, tab, phihat, lds);
 }
 
-template <int M>
+template <int M, bool MF>
 __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict__ items,
                                                       const uint8_t* __restrict__ has_far, DevParticles tgt,
                                                       DevTree T, const double* __restrict__ tab,
                                                       const double* __restrict__ phihat,
                                                       const double* __restrict__ phi_tree,
                                                       const int32_t* __restrict__ perm, double* __restrict__ out) {
-    __shared__ double lds[down_leaf_lds_bytes<M>() / sizeof(double)];
+    constexpr int B = MF ? down_leaf_mfma_lds_bytes<M>() : down_leaf_lds_bytes<M>();
+    __shared__ double lds[B / sizeof(double)];
     const DevItem it = items[blockIdx.x];
-    down_leaf_body<M>(it, has_far[it.cluster] != 0, tgt, T, tab, phihat, phi_tree, perm, out, 0, lds);
+    if constexpr (MF)
+        down_leaf_mfma_body<M>(it, has_far[it.cluster] != 0, tgt, T, tab, phihat, phi_tree, perm, out, 0, lds);
+    else
+        down_leaf_body<M>(it, has_far[it.cluster] != 0, tgt, T, tab, phihat, phi_tree, perm, out, 0, lds);
 }
 
 // Runtime-degree basis (m <= 13 nodes) for the degree-lifting kernel.
@@ -321,21 +330,26 @@ void by_degree(int degree, A&&... a) {
 
 template <int M>
 struct UpLeaf {
-    static void run(const int32_t* leaves, int n, DevTree S, DevParticles src, const double* tab, double* qhat,
-                    hipStream_t st) {
-        hipLaunchKernelGGL(k_up_leaf<M>, dim3(n), dim3(kBlock), 0, st, leaves, S, src, tab, qhat);
+    static void run(bool mf, const int32_t* leaves, int n, DevTree S, DevParticles src, const double* tab,
+                    double* qhat, hipStream_t st) {
+        if (mf) hipLaunchKernelGGL((k_up_leaf<M, true>), dim3(n), dim3(kBlock), 0, st, leaves, S, src, tab, qhat);
+        else hipLaunchKernelGGL((k_up_leaf<M, false>), dim3(n), dim3(kBlock), 0, st, leaves, S, src, tab, qhat);
     }
 };
 template <int M>
 struct UpTransfer {
-    static void run(const int32_t* parents, int n, DevTree S, const double* tab, double* qhat, hipStream_t st) {
-        hipLaunchKernelGGL(k_up_transfer<M>, dim3(n), dim3(kBlock), 0, st, parents, S, tab, qhat);
+    static void run(bool mf, const int32_t* parents, int n, DevTree S, const double* tab, double* qhat,
+                    hipStream_t st) {
+        if (mf) hipLaunchKernelGGL((k_up_transfer<M, true>), dim3(n), dim3(kBlock), 0, st, parents, S, tab, qhat);
+        else hipLaunchKernelGGL((k_up_transfer<M, false>), dim3(n), dim3(kBlock), 0, st, parents, S, tab, qhat);
     }
 };
 template <int M>
 struct DownTransfer {
-    static void run(const int32_t* kids, int n, DevTree T, const double* tab, double* phihat, hipStream_t st) {
-        hipLaunchKernelGGL(k_down_transfer<M>, dim3(n), dim3(kBlock), 0, st, kids, T, tab, phihat);
+    static void run(bool mf, const int32_t* kids, int n, DevTree T, const double* tab, double* phihat,
+                    hipStream_t st) {
+        if (mf) hipLaunchKernelGGL((k_down_transfer<M, true>), dim3(n), dim3(kBlock), 0, st, kids, T, tab, phihat);
+        else hipLaunchKernelGGL((k_down_transfer<M, false>), dim3(n), dim3(kBlock), 0, st, kids, T, tab, phihat);
     }
 };
 template <int M>
@@ -347,11 +361,15 @@ struct PairError {
 };
 template <int M>
 struct DownLeaf {
-    static void run(const DevItem* items, int n, const uint8_t* has_far, DevParticles tgt, DevTree T,
+    static void run(bool mf, const DevItem* items, int n, const uint8_t* has_far, DevParticles tgt, DevTree T,
                     const double* tab, const double* phihat, const double* phi_tree, const int32_t* perm,
                     double* out, hipStream_t st) {
-        hipLaunchKernelGGL(k_down_leaf<M>, dim3(n), dim3(kBlock), 0, st, items, has_far, tgt, T, tab, phihat,
-                           phi_tree, perm, out);
+        if (mf)
+            hipLaunchKernelGGL((k_down_leaf<M, true>), dim3(n), dim3(kBlock), 0, st, items, has_far, tgt, T, tab,
+                               phihat, phi_tree, perm, out);
+        else
+            hipLaunchKernelGGL((k_down_leaf<M, false>), dim3(n), dim3(kBlock), 0, st, items, has_far, tgt, T, tab,
+                               phihat, phi_tree, perm, out);
     }
 };
 
@@ -365,24 +383,24 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
     CHECK_LAUNCH();
 }
 
-void launch_up_leaf(int degree, const int32_t* leaves, int n_leaves, DevTree S, DevParticles src,
+void launch_up_leaf(int degree, bool mfma, const int32_t* leaves, int n_leaves, DevTree S, DevParticles src,
                     const double* tab, double* qhat, hipStream_t st) {
     if (n_leaves <= 0) return;
-    by_degree<UpLeaf>(degree, leaves, n_leaves, S, src, tab + 32 * degree, qhat, st);
+    by_degree<UpLeaf>(degree, mfma, leaves, n_leaves, S, src, tab + 32 * degree, qhat, st);
     CHECK_LAUNCH();
 }
 
-void launch_up_transfer(int degree, const int32_t* parents, int n_parents, DevTree S, const double* tab,
+void launch_up_transfer(int degree, bool mfma, const int32_t* parents, int n_parents, DevTree S, const double* tab,
                         double* qhat, hipStream_t st) {
     if (n_parents <= 0) return;
-    by_degree<UpTransfer>(degree, parents, n_parents, S, tab + 32 * degree, qhat, st);
+    by_degree<UpTransfer>(degree, mfma, parents, n_parents, S, tab + 32 * degree, qhat, st);
     CHECK_LAUNCH();
 }
 
-void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T, const double* tab,
+void launch_down_transfer(int degree, bool mfma, const int32_t* kids, int n_kids, DevTree T, const double* tab,
                           double* phihat, hipStream_t st) {
     if (n_kids <= 0) return;
-    by_degree<DownTransfer>(degree, kids, n_kids, T, tab + 32 * degree, phihat, st);
+    by_degree<DownTransfer>(degree, mfma, kids, n_kids, T, tab + 32 * degree, phihat, st);
     CHECK_LAUNCH();
 }
 
@@ -430,11 +448,12 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
     CHECK_LAUNCH();
 }
 
-void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8_t* has_far,
+void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, const uint8_t* has_far,
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,
                       const double* phi_tree, const int32_t* perm, double* out, hipStream_t st) {
     if (n_items <= 0) return;
-    by_degree<DownLeaf>(degree, items, n_items, has_far, tgt, T, tab + 32 * degree, phihat, phi_tree, perm, out, st);
+    by_degree<DownLeaf>(degree, mfma, items, n_items, has_far, tgt, T, tab + 32 * degree, phihat, phi_tree, perm,
+                        out, st);
     CHECK_LAUNCH();
 }
 

@@ -48,13 +48,19 @@ struct KernelSpec {
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 
-void launch_up_leaf(int degree, const int32_t* leaves, int n_leaves, DevTree S, DevParticles src,
+// The up/down contractions below run on the FP64 matrix cores when mfma is
+// set (device.hpp, *_mfma_body), else on the vector ALUs.  Measured on gfx950
+// at 1E7: the transfers are slightly faster on the matrix cores, the leaf
+// contractions faster on the vector ALUs (equal FP64 peaks; 16-row tiles pad
+// the n+1 interpolation rows).
+
+void launch_up_leaf(int degree, bool mfma, const int32_t* leaves, int n_leaves, DevTree S, DevParticles src,
                     const double* tab, double* qhat, hipStream_t st);
 
-void launch_up_transfer(int degree, const int32_t* parents, int n_parents, DevTree S, const double* tab,
+void launch_up_transfer(int degree, bool mfma, const int32_t* parents, int n_parents, DevTree S, const double* tab,
                         double* qhat, hipStream_t st);
 
-void launch_down_transfer(int degree, const int32_t* kids, int n_kids, DevTree T, const double* tab,
+void launch_down_transfer(int degree, bool mfma, const int32_t* kids, int n_kids, DevTree T, const double* tab,
                           double* phihat, hipStream_t st);
 
 // Interaction sums: proxy_targets = false for PP + PC into the particles of a
@@ -74,7 +80,7 @@ void launch_pair_error(int degree, const int32_t* pair_tc, int n_pairs, const in
 void launch_prolong(const DevItem* items, int n_items, DevTree T, const double* tab, DegPtrs from, double* to,
                     int down_degree, hipStream_t st);
 
-void launch_down_leaf(int degree, const DevItem* items, int n_items, const uint8_t* has_far,
+void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, const uint8_t* has_far,
                       DevParticles tgt, DevTree T, const double* tab, const double* phihat,
                       const double* phi_tree, const int32_t* perm, double* out, hipStream_t st);
 

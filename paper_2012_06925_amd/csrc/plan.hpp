@@ -147,6 +147,8 @@ struct bldtt_plan {
     std::vector<float> pe_feats, pe_errs;    // last bldtt_pair_errors result
     std::vector<int64_t> pe_pairs;
     bool varied_degree() const { return (flags & BLDTT_LEARNED_DEGREE) != 0; }
+    bool mfma_transfer() const { return (flags & BLDTT_VALU_PASSES) == 0; }
+    bool mfma_leaf() const { return (flags & BLDTT_MFMA_LEAF) != 0; }
     PinnedBuf staging;
     hipEvent_t staging_free = nullptr;
     hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};

@@ -205,3 +205,25 @@ def test_batch_sync_flag_and_errors():
     with pytest.raises(_lib.BldttError) as e:
         api.Batch(probs, theta=0.7, degree=11, leaf=100)
     assert e.value.code == _lib.EUNSUPPORTED
+
+
+def test_batch256_config_equals_standalone_runs():
+    # the timed batch workload: 256 problems, sizes log-uniform in [1E3, 1E5],
+    # theta 0.7, n 6, leaf 500, tile from the autotuner, each problem against its
+    # standalone run
+    wl = inputs.WORKLOADS["batch256"]
+    sets = [p for _, p in inputs.batch_problems(count=wl["count"], seed=inputs.workload_seed("batch256"),
+                                                lo_exp=wl["lo_exp"], hi_exp=wl["hi_exp"])]
+    probs = [_dev_problem(p) for p in sets]
+    kw = dict(theta=wl["theta"], degree=wl["degree"], leaf=wl["leaf"])
+    api.set_tune_cache(None)
+    b = api.Batch(probs, flags=_lib.AUTOTUNE, **kw)
+    outs = b.compute()
+    b.check()
+    worst = 0.0
+    for pr, o in zip(probs, outs):
+        worst = max(worst, _rel(o.cpu().numpy(), _alone(pr, **kw)))
+    st = b.stats()
+    print(f"\n  batch256: {st['n_tasks']} tasks, tile {st['tpt']}/{st['groups_per_cu']}; max rel diff {worst:.2e}")
+    assert worst <= 1e-13
+    b.close()

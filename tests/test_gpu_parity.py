@@ -48,8 +48,8 @@ def _proxy_close(a, b, what):
     assert err < PROXY, f"{what}: {err:.3e}"
 
 
-def full_parity(tgt, src, same, kernel="coulomb", theta=0.7, degree=6, leaf=500, check_proxies=True):
-    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf)
+def full_parity(tgt, src, same, kernel="coulomb", theta=0.7, degree=6, leaf=500, check_proxies=True, flags=0):
+    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf, flags=flags)
     run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same)
     ref = run.run_all()
     for which in (0, 1):
@@ -109,10 +109,16 @@ def test_polynomial_kernel_exact_on_gpu():
     assert core.rel_l2(phi, ds) < 1e-12
 
 
+# contraction forms of the up/down passes: default (matrix-core transfers,
+# vector-ALU leaves), every contraction on the matrix cores, every one on the VALU
+CONTRACTIONS = {"default": 0, "mfma": 128, "valu": 64}
+
+
+@pytest.mark.parametrize("form", sorted(CONTRACTIONS))
 @pytest.mark.parametrize("degree", [1, 2, 5, 9, 12])
-def test_every_degree_template(degree):
+def test_every_degree_template(degree, form):
     p = inputs.particles(12_000, "gaussian", seed=45 + degree)
-    full_parity(p, p, True, theta=0.8, degree=degree, leaf=100)
+    full_parity(p, p, True, theta=0.8, degree=degree, leaf=100, flags=CONTRACTIONS[form])
 
 
 def test_ragged_tiles_and_ablation():
@@ -211,6 +217,35 @@ def test_cube1e6_config_sampled():
     # 1E6 uniform, theta 0.8, n 8, leaf 2000
     p = inputs.particles(1_000_000, "uniform", seed=inputs.workload_seed("cube1e6"))
     _sampled_parity(p, p, True, "coulomb", 0.8, 8, 2000, seed=1)
+
+
+def test_cube1e7_bench_config_sampled():
+    # the timed plain form: 1E7 uniform, theta 0.8, n 7, leaf 2000; lists bit-exact,
+    # every target of three leaves plus 150 random targets against the oracle
+    p = inputs.particles(10_000_000, "uniform", seed=inputs.workload_seed("cube1e7"))
+    _sampled_parity(p, p, True, "coulomb", 0.8, 7, 2000, seed=3)
+
+
+def test_cube1e7_tuned_form_meets_error_target():
+    # the timed tuned form (FP32 evaluation, learned degree, theta 0.8, tau 1e-6,
+    # fallback 8) on the same particles: relative l2 error against the direct sum
+    # on 0.1 % of the targets (the property bench.py reports) below 1e-6
+    from paper_2012_06925_amd.train_degree_model import load_model
+    api = _api()
+    seed = inputs.workload_seed("cube1e7")
+    p = inputs.particles(10_000_000, "uniform", seed=seed)
+    s = [dev(a) for a in (p.x, p.y, p.z, p.q)]
+    plan = api.Plan(None, s, theta=0.8, degree=8, leaf=2000, flags=1 | 2)
+    plan.set_degree_model(load_model(), fallback=8, tau=1e-6)
+    phi = plan.compute().cpu().numpy()
+    st = plan.stats()
+    plan.close()
+    sel = inputs.error_sample(p.n, seed, fraction=1e-3)
+    ds = api.direct_sum(s[:3], s, sel=dev(sel)).cpu().numpy()
+    err = core.rel_l2(phi[sel], ds)
+    print(f"\n  tuned 1E7: error vs direct {err:.3e}; degrees {st['pairs_per_degree']}")
+    assert err < 1e-6
+    assert st["sep_fallback"] < 0.01 * st["sep_pairs"]
 
 
 def test_sphere_targets_gaussian_sources_yukawa_sampled():
