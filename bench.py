@@ -145,8 +145,11 @@ class Bench:
         plan.close()
         inter = st["interactions"]
         fl = FLOPS_PER_EVAL[self.wl["kernel"]]
-        work = {"pp_pc": (inter["PP"] + inter["PC"]) * fl, "cp_cc": (inter["CP"] + inter["CC"]) * fl}
-        dom = max(("pp_pc", "cp_cc"), key=lambda k: phase[k])
+        # the particle pass (near-field PP in the per-pair degree form), its
+        # second pass (separated pairs' PP/PC), and the proxy pass
+        work = {"pp_pc": st["pass_interactions"][0] * fl, "pp_pc_sep": st["pass_interactions"][1] * fl,
+                "cp_cc": (inter["CP"] + inter["CC"]) * fl}
+        dom = max(work, key=lambda k: phase[k])
         achieved = work[dom] / (phase[dom] * 1e-3) / 1e12
         fp32 = mode != "plain"
         peak = FP32_VALU_PEAK if fp32 else FP64_VALU_PEAK

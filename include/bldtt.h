@@ -169,9 +169,13 @@ int bldtt_get_list_degrees(const bldtt_plan *plan, int type, const int8_t **deg,
 int bldtt_get_qhat(const bldtt_plan *plan, double *host_out);
 int bldtt_get_phihat(const bldtt_plan *plan, double *host_out);
 
-/* Kernel phases timed under BLDTT_PROFILE. */
+/* Kernel phases timed under BLDTT_PROFILE.  PPPC is the particle pass over
+ * the lists of the traversal; with BLDTT_LEARNED_DEGREE that pass holds the
+ * near-field PP entries only, it runs on a second stream while the host
+ * chooses the per-pair degrees, and PPPC_SEP is the second particle pass that
+ * adds the separated pairs' PP/PC terms. */
 enum { BLDTT_PH_UP = 0, BLDTT_PH_CPCC = 1, BLDTT_PH_DOWN_TRANSFER = 2, BLDTT_PH_PPPC = 3, BLDTT_PH_DOWN_LEAF = 4,
-       BLDTT_N_PHASES = 5 };
+       BLDTT_PH_PPPC_SEP = 5, BLDTT_N_PHASES = 6 };
 
 typedef struct {
     int64_t n_entries[4];          /* list lengths PP, PC, CP, CC                        */
@@ -190,6 +194,7 @@ typedef struct {
     int64_t sep_fallback;          /*   of which outside the model's range (fallback)    */
     int64_t sep_direct;            /*   of which evaluated directly (PP chosen)          */
     int64_t pairs_per_degree[13];  /*   approximated pairs per degree                     */
+    double pass_interactions[2];   /* kernel evaluations of the PPPC and PPPC_SEP passes */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the

@@ -143,6 +143,7 @@ void do_traverse(bldtt_plan* pl) {
 void collect_profile(bldtt_plan* pl) {
     if (!pl->prof_pending) return;
     for (int ph = 0; ph < BLDTT_N_PHASES; ++ph) {
+        if (!(pl->prof_mask >> ph & 1)) continue;
         HIPCHK(hipEventSynchronize(pl->prof_ev[2 * ph + 1]));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, pl->prof_ev[2 * ph], pl->prof_ev[2 * ph + 1]));
@@ -150,6 +151,7 @@ void collect_profile(bldtt_plan* pl) {
     }
     pl->stats.profiled_computes += 1;
     pl->prof_pending = false;
+    pl->prof_mask = 0;
 }
 
 struct PhaseMark {
@@ -157,7 +159,10 @@ struct PhaseMark {
     int ph;
     hipStream_t st;
     PhaseMark(bldtt_plan* p, int phase, hipStream_t s) : pl(p), ph(phase), st(s) {
-        if (pl->flags & BLDTT_PROFILE) HIPCHK(hipEventRecord(pl->prof_ev[2 * ph], st));
+        if (pl->flags & BLDTT_PROFILE) {
+            HIPCHK(hipEventRecord(pl->prof_ev[2 * ph], st));
+            pl->prof_mask |= 1u << ph;
+        }
     }
     ~PhaseMark() noexcept(false) {
         if (pl->flags & BLDTT_PROFILE) HIPCHK(hipEventRecord(pl->prof_ev[2 * ph + 1], st));
@@ -168,6 +173,40 @@ constexpr int kBlockThreads = 256;   // threads per interaction work group (4 wa
 
 inline int64_t cube(int d) { return (int64_t)(d + 1) * (d + 1) * (d + 1); }
 
+// Host arrays -> device buffers through one pinned staging buffer, on stream
+// st; `freed` marks when the copies have left the staging buffer.
+struct Upload {
+    struct Part {
+        DevBuf* dst;
+        const void* src;
+        size_t n;
+    };
+    std::vector<Part> parts;
+    template <class T>
+    Upload& add(DevBuf& d, const std::vector<T>& v) {
+        parts.push_back(Part{&d, v.data(), sizeof(T) * v.size()});
+        return *this;
+    }
+    void run(PinnedBuf& staging, hipEvent_t freed, hipStream_t st) {
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t total = 0;
+        for (auto& p : parts) total += al(p.n);
+        HIPCHK(hipEventSynchronize(freed));      // the previous upload has left the staging buffer
+        staging.reserve(total);
+        char* h = static_cast<char*>(staging.p);
+        size_t o = 0;
+        for (auto& p : parts) {
+            p.dst->reserve(p.n);
+            if (p.n) {
+                std::memcpy(h + o, p.src, p.n);
+                HIPCHK(hipMemcpyAsync(p.dst->p, h + o, p.n, hipMemcpyHostToDevice, st));
+            }
+            o += al(p.n);
+        }
+        HIPCHK(hipEventRecord(freed, st));
+    }
+};
+
 void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     double t0 = now_ms();
     const Tree& T = pl->T();
@@ -177,6 +216,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     KernelSpec ks{pl->kind, pl->param};
     const bool fp32 = (pl->flags & BLDTT_FP32_EVAL) != 0;
     const bool varied = pl->varied_degree();
+    const int tile = kBlockThreads * pl->tpt, ptile = kBlockThreads * pl->tpt_proxy;
 
     collect_profile(pl);
     // 1. upward pass, overlapping the host traversal: at the base degree, or
@@ -190,40 +230,60 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             if (pre >> d & 1) upward(pl, d, st);
     }
 
-    // 2. traversal, per-pair degrees, work packing
+    // 2. traversal (Algorithm 2)
     do_traverse(pl);
     double tp = now_ms();
-    if (varied) select_degrees(pl, st);
-    pack_work(T, S, pl->lists, pl->degree, kBlockThreads * pl->tpt, kBlockThreads * pl->tpt_proxy, pl->work);
-    pl->stats.traverse_ms += now_ms() - tp;
+    Lists sep;                          // per-pair degree form: the typed separated pairs
+    if (varied) {
+        // 2a. The traversal deferred every separated pair, so the lists hold the
+        //     near-field PP entries only.  Their particle pass starts now on the
+        //     second stream and overlaps the degree choice and the packing of
+        //     the rest.  It first waits for the work already on st (the
+        //     previous compute still reads phi_tree).
+        pack_work(T, S, pl->lists, pl->degree, tile, ptile, pl->work_near);
+        const Work& wn = pl->work_near;
+        HIPCHK(hipEventRecord(pl->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
+        Upload().add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries)
+            .run(pl->staging_near, pl->staging_near_free, pl->side);
+        {
+            PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
+            launch_interact(ks, fp32, false, pl->tpt, pl->near_items.as<DevItem>(), (int)wn.pitems.size(),
+                            pl->near_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                            pl->phi_tree.as<double>(), DegOut{}, pl->side);
+        }
+        HIPCHK(hipEventRecord(pl->ev_near_done, pl->side));
+        // 2b. per-pair (type, degree); select_degrees appends the typed pairs to
+        //     the lists, the second pass packs those alone
+        size_t n0[4];
+        for (int k = 0; k < 4; ++k) n0[k] = pl->lists.tc[k].size();
+        select_degrees(pl, st);
+        for (int k = 0; k < 4; ++k) {
+            const Lists& L = pl->lists;
+            sep.tc[k].assign(L.tc[k].begin() + n0[k], L.tc[k].end());
+            sep.sc[k].assign(L.sc[k].begin() + n0[k], L.sc[k].end());
+            sep.deg[k].assign(L.deg[k].begin() + n0[k], L.deg[k].end());
+        }
+    }
+    pack_work(T, S, varied ? sep : pl->lists, pl->degree, tile, ptile, pl->work);
     Work& w = pl->work;
-    for (int k = 0; k < 4; ++k) pl->stats.interactions[k] = w.interactions[k];
+    std::vector<Item> sep_items;        // second particle pass: leaves with separated-pair entries
+    if (varied)
+        for (const Item& it : w.pitems)
+            if (it.ee > it.eb) sep_items.push_back(it);
+    pl->stats.traverse_ms += now_ms() - tp;
+    for (int k = 0; k < 4; ++k)
+        pl->stats.interactions[k] = w.interactions[k] + (varied ? pl->work_near.interactions[k] : 0.0);
+    const double pass_w = w.interactions[PP] + w.interactions[PC];
+    pl->stats.pass_interactions[0] = varied ? pl->work_near.interactions[PP] : pass_w;
+    pl->stats.pass_interactions[1] = varied ? pass_w : 0.0;
     pl->stats.down_degree = w.down_degree;
     pl->stats.degree_mask = w.src_degrees | w.tgt_degrees;
-    size_t bp = sizeof(Item) * w.pitems.size(), be = sizeof(Entry) * w.pentries.size();
-    size_t bq = sizeof(Item) * w.qitems.size(), bqe = sizeof(Entry) * w.qentries.size();
-    size_t bf = w.leaf_has_far.size(), bl = sizeof(Item) * w.prolong.size();
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t total = al(bp) + al(be) + al(bq) + al(bqe) + al(bf) + al(bl);
-    HIPCHK(hipEventSynchronize(pl->staging_free));      // the previous upload has left the staging buffer
-    pl->staging.reserve(total);
-    char* h = static_cast<char*>(pl->staging.p);
-    size_t o = 0;
-    auto put = [&](DevBuf& d, const void* src, size_t n) {
-        d.reserve(n);
-        if (n) {
-            std::memcpy(h + o, src, n);
-            HIPCHK(hipMemcpyAsync(d.p, h + o, n, hipMemcpyHostToDevice, st));
-        }
-        o += al(n);
-    };
-    put(pl->pitems, w.pitems.data(), bp);
-    put(pl->pentries, w.pentries.data(), be);
-    put(pl->qitems, w.qitems.data(), bq);
-    put(pl->qentries, w.qentries.data(), bqe);
-    put(pl->has_far, w.leaf_has_far.data(), bf);
-    put(pl->prolong, w.prolong.data(), bl);
-    HIPCHK(hipEventRecord(pl->staging_free, st));
+    Upload up;
+    up.add(pl->pitems, w.pitems).add(pl->pentries, w.pentries).add(pl->qitems, w.qitems)
+        .add(pl->qentries, w.qentries).add(pl->has_far, w.leaf_has_far).add(pl->prolong, w.prolong);
+    if (varied) up.add(pl->sep_items, sep_items);
+    up.run(pl->staging, pl->staging_free, st);
 
     if (varied) {
         const uint32_t rest = w.src_degrees & ~pre;
@@ -260,12 +320,19 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                                  pl->phihat_deg[D].as<double>(), st);
         }
     }
-    // 4. PP + PC
-    {
+    // 4. PP + PC: one pass, or the second pass of the per-pair degree form
+    //    added to the near-field pass
+    if (!varied) {
         PhaseMark mark(pl, BLDTT_PH_PPPC, st);
         launch_interact(ks, fp32, false, pl->tpt, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
                         pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         pl->phi_tree.as<double>(), DegOut{}, st);
+    } else {
+        HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));
+        PhaseMark mark(pl, BLDTT_PH_PPPC_SEP, st);
+        launch_interact(ks, fp32, false, pl->tpt, pl->sep_items.as<DevItem>(), (int)sep_items.size(),
+                        pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                        pl->phi_tree.as<double>(), DegOut{}, st, true);
     }
     // 5. leaves to targets, caller order
     {
@@ -329,6 +396,11 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     upload(pl->down_kids, ids);
     pl->phi_tree.alloc(sizeof(double) * M);
     HIPCHK(hipEventCreateWithFlags(&pl->staging_free, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->staging_near_free, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->ev_near_done, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
+    HIPCHK(hipEventRecord(pl->staging_near_free, st));
     if (pl->flags & BLDTT_PROFILE)
         for (auto& e : pl->prof_ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(pl->staging_free, st));

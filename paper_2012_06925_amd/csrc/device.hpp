@@ -178,12 +178,14 @@ constexpr int interact_lds_bytes() { return kChunk * (int)sizeof(typename Stage<
 // and its list of source entries.  Thread (wave w, lane l) owns targets
 // w*64*T + l + 64 j, j < T; a wave with no target skips the arithmetic.
 // Sources are staged through LDS and read by all lanes at the same address.
+// Particle targets are written (out = sum) or, with `add`, accumulated
+// (out += sum) for a second pass over other entries of the same targets.
 // ---------------------------------------------------------------------------
 template <int KIND, bool F32, int T, bool PROXY_TGT>
 __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __restrict__ entries, DevParticles tgt,
                                               DevTree Tt, DevParticles src, DevTree S, const double* __restrict__ tab,
                                               const DegPtrs& qhat, double param, double* __restrict__ out,
-                                              const DegOut& pout, typename Stage<F32>::V* lds) {
+                                              const DegOut& pout, typename Stage<F32>::V* lds, bool add = false) {
     using St = Stage<F32>;
     using V = typename St::V;
     using R = typename std::conditional<F32, float, double>::type;
@@ -296,7 +298,7 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
         int r = slab + lane + 64 * j;
         if (r < it.tn) {
             if (PROXY_TGT) pout.p[it.degree][(int64_t)it.slot * Pt + it.t0 + r] = acc[j];
-            else out[it.slot + r] = acc[j];
+            else out[it.slot + r] = add ? out[it.slot + r] + acc[j] : acc[j];
         }
     }
 }

@@ -40,10 +40,10 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
                                                      const int2* __restrict__ entries, DevParticles tgt, DevTree Tt,
                                                      DevParticles src, DevTree S, const double* __restrict__ tab,
                                                      DegPtrs qhat, double param, double* __restrict__ out,
-                                                     DegOut pout) {
+                                                     DegOut pout, int add) {
     __shared__ typename Stage<F32>::V lds[kChunk];
     interact_body<KIND, F32, T, PROXY_TGT>(items[blockIdx.x], entries, tgt, Tt, src, S, tab, qhat, param, out, pout,
-                                           lds);
+                                           lds, add != 0);
 }
 
 // MF selects the matrix-core form of the contraction (device.hpp).
@@ -418,14 +418,14 @@ namespace {
 template <int KK, bool F32, bool PROXY_TGT>
 void launch_interact_t(int tpt, const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
                        DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double param, double* out,
-                       DegOut pout, hipStream_t st) {
+                       DegOut pout, int add, hipStream_t st) {
     switch (tpt) {
     case 1: hipLaunchKernelGGL((k_interact<KK, F32, 1, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, param, out, pout); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout, add); break;
     case 2: hipLaunchKernelGGL((k_interact<KK, F32, 2, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, param, out, pout); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout, add); break;
     case 4: hipLaunchKernelGGL((k_interact<KK, F32, 4, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, param, out, pout); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout, add); break;
     default: throw Error(-1, "targets per thread must be 1, 2 or 4");
     }
 }
@@ -433,10 +433,11 @@ void launch_interact_t(int tpt, const DevItem* items, int n_items, const int2* e
 
 void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const DevItem* items, int n_items,
                      const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
-                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st) {
+                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add) {
     if (n_items <= 0) return;
+    if (add && proxy_targets) throw Error(-1, "accumulating mode is for particle targets");
     if (fp32 && k.kind == K_POLY) throw Error(-5, "the polynomial test kernel runs in FP64 only");
-#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, st)
+#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, add ? 1 : 0, st)
     if (fp32) {
         if (proxy_targets) { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, true)); }
         else { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, false)); }

@@ -64,11 +64,12 @@ void launch_down_transfer(int degree, bool mfma, const int32_t* kids, int n_kids
                           double* phihat, hipStream_t st);
 
 // Interaction sums: proxy_targets = false for PP + PC into the particles of a
-// leaf (out = potentials in tree order), true for CP + CC into the proxies of
-// a cluster (out = proxy potentials).  tpt: targets per thread (1, 2 or 4).
+// leaf (out = potentials in tree order; with add, out += the sums), true for
+// CP + CC into the proxies of a cluster (pout = proxy potentials).  tpt:
+// targets per thread (1, 2 or 4).
 void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const DevItem* items, int n_items,
                      const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
-                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st);
+                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add = false);
 
 // Per-pair relative error of degree-d proxy potentials phip[p] interpolated to
 // the particles of pair_tc[p], against exact[exact_off[p] + r].

@@ -152,7 +152,15 @@ struct bldtt_plan {
     PinnedBuf staging;
     hipEvent_t staging_free = nullptr;
     hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
+    uint32_t prof_mask = 0;                  // phases recorded by the last profiled compute
     bool prof_pending = false;
+    // Per-pair degree form: the near-field PP pass runs on a second stream
+    // while the host chooses the degrees (capi.cpp, compute).
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_near_done = nullptr, staging_near_free = nullptr;
+    PinnedBuf staging_near;
+    Work work_near;
+    DevBuf near_items, near_entries, sep_items;
 
     int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
     uint32_t up_degrees_last = 0;            // source degrees of the last per-pair degree compute
@@ -165,6 +173,9 @@ struct bldtt_plan {
     ~bldtt_plan() {
         if (policy.dev_model) (void)hipFree(policy.dev_model);
         if (staging_free) (void)hipEventDestroy(staging_free);
+        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free})
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
         for (auto& e : prof_ev)
             if (e) (void)hipEventDestroy(e);
     }

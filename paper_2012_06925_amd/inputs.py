@@ -82,7 +82,9 @@ WORKLOADS = {
     # tuned_theta / tau: the fastest FP32-evaluation + per-pair-degree point with error <= 1e-6.
     "cube1e7": dict(id=0, M=10_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=7, leaf=2000,
                     tuned_theta=0.8, tau=1e-6, tuned_fallback=8),
-    "cube1e8": dict(id=5, M=100_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=8, leaf=2000),
+    # 1E8: the learned-degree form at the 1E7 operating point (theta 0.8, tau 1e-6, fallback 8)
+    "cube1e8": dict(id=5, M=100_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=8, leaf=2000,
+                    tuned_theta=0.8, tau=1e-6, tuned_fallback=8),
     # 256 independent targets = sources problems, sizes log-uniform in [1E3, 1E5], distribution per
     # problem from {uniform cube, Gaussian, sphere surface}; Coulomb, theta 0.7, n 6, leaf 500
     "batch256": dict(id=4, count=256, lo_exp=3.0, hi_exp=5.0, kernel="coulomb", theta=0.7, degree=6, leaf=500),
