@@ -86,10 +86,14 @@ __device__ __forceinline__ double rsq_fix(double r2, double y) {
 
 __device__ __forceinline__ double rsq_full(double r2) { return rsq_fix(r2, rsq_est(r2)); }
 
-// FP64 evaluation on absolute coordinates; sources are double4 (x, y, z, q).
+// FP64 evaluation on absolute coordinates; sources are double4 (x, y, z, w)
+// with w = q, or w = q/2 for Coulomb (charge_scale).  Coulomb folds one
+// Newton step into the sum: q/r ~= (q/2) y0 (3 - r^2 y0^2), relative error
+// ~1.5 e0^2 + rounding for an estimate y0 = (1 + e0)/r (|e0| ~ 5e-8).
 template <int KIND>
 struct E64 {
     using V = double4;
+    static constexpr double charge_scale = KIND == K_COULOMB ? 0.5 : 1.0;
     template <bool GUARD>
     __device__ __forceinline__ static void add(double& acc, double tx, double ty, double tz, const V& s,
                                                double param) {
@@ -102,6 +106,11 @@ struct E64 {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         double y = rsq_est(r2);
         if (GUARD) y = r2 > 0.0 ? y : 0.0;      // rsq(0) = inf; a zero estimate stays zero below
+        if (KIND == K_COULOMB) {
+            const double u = fma(-(r2 * y), y, 3.0);
+            acc = fma(s.w * y, u, acc);
+            return;
+        }
         y = rsq_fix(r2, y);
         double g;
         if (KIND == K_COULOMB) g = y;
@@ -117,6 +126,7 @@ struct E64 {
 template <int KIND>
 struct E32 {
     using V = float4;
+    static constexpr double charge_scale = 1.0;
     template <bool GUARD>
     __device__ __forceinline__ static void add(float& acc, float tx, float ty, float tz, const V& s, float param) {
         float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
@@ -252,7 +262,7 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
                     z = src.z[b];
                     q = src.q[b];
                 }
-                lds[j] = St::make(x, y, z, q, cx, cy, cz);
+                lds[j] = St::make(x, y, z, Ev::charge_scale * q, cx, cy, cz);   // scaling by 1/2 is exact
             }
             __syncthreads();
             if (!active) continue;
