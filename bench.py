@@ -146,9 +146,11 @@ class Bench:
         inter = st["interactions"]
         fl = FLOPS_PER_EVAL[self.wl["kernel"]]
         # the particle pass (near-field PP in the per-pair degree form), its
-        # second pass (separated pairs' PP/PC), and the proxy pass
+        # second pass (separated pairs' PP/PC), the symmetric PP pass (both
+        # directions counted: the algorithmic count; it evaluates G once per
+        # pair of particles), and the proxy pass
         work = {"pp_pc": st["pass_interactions"][0] * fl, "pp_pc_sep": st["pass_interactions"][1] * fl,
-                "cp_cc": (inter["CP"] + inter["CC"]) * fl}
+                "pp_sym": st["pass_interactions"][2] * fl, "cp_cc": (inter["CP"] + inter["CC"]) * fl}
         dom = max(work, key=lambda k: phase[k])
         achieved = work[dom] / (phase[dom] * 1e-3) / 1e12
         fp32 = mode != "plain"
@@ -156,7 +158,8 @@ class Bench:
         roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic_for(dom, "fp32" if fp32 else "fp64"),
                 "flops_per_launch": work[dom], "launch_ms": round(phase[dom], 4), "flops_per_eval": fl,
-                "evals_per_s": round(work[dom] / fl / (phase[dom] * 1e-3), 1)}
+                "evals_per_s": round(work[dom] / fl / (phase[dom] * 1e-3), 1),
+                "kernel_values_per_s": round(work[dom] / fl / (2.0 if dom == "pp_sym" else 1.0) / (phase[dom] * 1e-3), 1)}
         rec = {"mode": mode, "theta": theta, "degree": degree, "particles_per_s": self.M / (ms * 1e-3),
                "ms_per_step": round(ms, 3), "wall_ms_per_step": round(wall_ms, 3), "error_vs_direct": err,
                "setup_ms": round(setup_ms, 1), "phase_ms": {k: round(v, 4) for k, v in phase.items()},

@@ -71,11 +71,17 @@ enum {
     BLDTT_VALU_PASSES = 1u << 6,   /* run the child-to-parent and parent-to-child
                                       transfers on the vector ALUs instead of the FP64
                                       matrix cores (the default)                         */
-    BLDTT_MFMA_LEAF = 1u << 7      /* run the leaf contractions (proxy charges from the
+    BLDTT_MFMA_LEAF = 1u << 7,     /* run the leaf contractions (proxy charges from the
                                       particles, interpolation to the targets) on the
                                       FP64 matrix cores instead of the vector ALUs (the
                                       default, faster on gfx950: FP64 matrix and vector
                                       peaks are equal and 16x16 tiles pad n+1 rows)     */
+    BLDTT_ONE_SIDED_PP = 1u << 8   /* evaluate every PP pair one-sided.  By default, for
+                                      targets = sources with the Coulomb kernel, a pair
+                                      of distinct leaves listed as PP in both directions
+                                      is evaluated once for both (G is symmetric), with
+                                      FP64 atomic adds into the potentials: the result
+                                      then varies run to run at the rounding level     */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host
@@ -173,9 +179,10 @@ int bldtt_get_phihat(const bldtt_plan *plan, double *host_out);
  * the lists of the traversal; with BLDTT_LEARNED_DEGREE that pass holds the
  * near-field PP entries only, it runs on a second stream while the host
  * chooses the per-pair degrees, and PPPC_SEP is the second particle pass that
- * adds the separated pairs' PP/PC terms. */
+ * adds the separated pairs' PP/PC terms.  PP_SYM is the pass over the PP pairs
+ * evaluated once for both directions (see BLDTT_ONE_SIDED_PP). */
 enum { BLDTT_PH_UP = 0, BLDTT_PH_CPCC = 1, BLDTT_PH_DOWN_TRANSFER = 2, BLDTT_PH_PPPC = 3, BLDTT_PH_DOWN_LEAF = 4,
-       BLDTT_PH_PPPC_SEP = 5, BLDTT_N_PHASES = 6 };
+       BLDTT_PH_PPPC_SEP = 5, BLDTT_PH_PP_SYM = 6, BLDTT_N_PHASES = 7 };
 
 typedef struct {
     int64_t n_entries[4];          /* list lengths PP, PC, CP, CC                        */
@@ -194,7 +201,8 @@ typedef struct {
     int64_t sep_fallback;          /*   of which outside the model's range (fallback)    */
     int64_t sep_direct;            /*   of which evaluated directly (PP chosen)          */
     int64_t pairs_per_degree[13];  /*   approximated pairs per degree                     */
-    double pass_interactions[2];   /* kernel evaluations of the PPPC and PPPC_SEP passes */
+    double pass_interactions[3];   /* kernel terms of the PPPC, PPPC_SEP and PP_SYM passes
+                                      (PP_SYM: both directions counted)                  */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the

@@ -19,8 +19,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 
 KERNELS = {"coulomb": 0, "yukawa": 1, "oscillatory": 2, "regcoulomb": 3, "poly": 100}
 DEFAULT_PARAM = {"coulomb": 0.0, "yukawa": 0.5, "oscillatory": 0.0, "regcoulomb": 0.005, "poly": 0.0}
-FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE, VALU_PASSES, MFMA_LEAF = 1, 2, 4, 8, 16, 32, 64, 128
-PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf", "pp_pc_sep")
+FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE, VALU_PASSES, MFMA_LEAF, ONE_SIDED_PP = (
+    1, 2, 4, 8, 16, 32, 64, 128, 256)
+PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf", "pp_pc_sep", "pp_sym")
 TYPES = ("PP", "PC", "CP", "CC")
 
 _D = C.POINTER(C.c_double)
@@ -45,10 +46,10 @@ class Stats(C.Structure):
                 ("n_target_clusters", C.c_int64), ("n_source_clusters", C.c_int64),
                 ("target_depth", C.c_int32), ("source_depth", C.c_int32),
                 ("setup_ms", C.c_double), ("traverse_ms", C.c_double), ("compute_host_ms", C.c_double),
-                ("phase_ms", C.c_double * 6), ("profiled_computes", C.c_int64),
+                ("phase_ms", C.c_double * 7), ("profiled_computes", C.c_int64),
                 ("down_degree", C.c_int32), ("degree_mask", C.c_uint32), ("sep_pairs", C.c_int64),
                 ("sep_fallback", C.c_int64), ("sep_direct", C.c_int64), ("pairs_per_degree", C.c_int64 * 13),
-                ("pass_interactions", C.c_double * 2)]
+                ("pass_interactions", C.c_double * 3)]
 
 
 class BatchStats(C.Structure):

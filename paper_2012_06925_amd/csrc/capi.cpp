@@ -216,6 +216,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     KernelSpec ks{pl->kind, pl->param};
     const bool fp32 = (pl->flags & BLDTT_FP32_EVAL) != 0;
     const bool varied = pl->varied_degree();
+    const bool symm = pl->symmetric_pp();
     const int tile = kBlockThreads * pl->tpt, ptile = kBlockThreads * pl->tpt_proxy;
 
     collect_profile(pl);
@@ -240,17 +241,27 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     second stream and overlaps the degree choice and the packing of
         //     the rest.  It first waits for the work already on st (the
         //     previous compute still reads phi_tree).
-        pack_work(T, S, pl->lists, pl->degree, tile, ptile, pl->work_near);
+        //     Symmetric pairs go to their own pass after it (atomic adds).
+        Lists near_rest;
+        if (symm) split_symmetric(T, pl->lists, near_rest, pl->sym);
+        pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
         const Work& wn = pl->work_near;
         HIPCHK(hipEventRecord(pl->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
-        Upload().add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries)
-            .run(pl->staging_near, pl->staging_near_free, pl->side);
+        Upload un;
+        un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
+        if (symm) un.add(pl->sym_items, pl->sym.items).add(pl->sym_entries, pl->sym.entries);
+        un.run(pl->staging_near, pl->staging_near_free, pl->side);
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
             launch_interact(ks, fp32, false, pl->tpt, pl->near_items.as<DevItem>(), (int)wn.pitems.size(),
                             pl->near_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                             pl->phi_tree.as<double>(), DegOut{}, pl->side);
+        }
+        if (symm) {
+            PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
+            launch_sym_pp(fp32, pl->sym_items.as<DevItem>(), (int)pl->sym.items.size(), pl->sym_entries.as<int2>(),
+                          pl->dsrc(), dS, pl->phi_tree.as<double>(), pl->side);
         }
         HIPCHK(hipEventRecord(pl->ev_near_done, pl->side));
         // 2b. per-pair (type, degree); select_degrees appends the typed pairs to
@@ -265,24 +276,30 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             sep.deg[k].assign(L.deg[k].begin() + n0[k], L.deg[k].end());
         }
     }
-    pack_work(T, S, varied ? sep : pl->lists, pl->degree, tile, ptile, pl->work);
+    Lists rest;                         // fixed degree, symmetric pairs split off
+    if (!varied && symm) split_symmetric(T, pl->lists, rest, pl->sym);
+    pack_work(T, S, varied ? sep : (symm ? rest : pl->lists), pl->degree, tile, ptile, pl->work);
     Work& w = pl->work;
     std::vector<Item> sep_items;        // second particle pass: leaves with separated-pair entries
     if (varied)
         for (const Item& it : w.pitems)
             if (it.ee > it.eb) sep_items.push_back(it);
     pl->stats.traverse_ms += now_ms() - tp;
+    const double sym_w = symm ? pl->sym.evaluations : 0.0;
     for (int k = 0; k < 4; ++k)
         pl->stats.interactions[k] = w.interactions[k] + (varied ? pl->work_near.interactions[k] : 0.0);
+    pl->stats.interactions[PP] += sym_w;
     const double pass_w = w.interactions[PP] + w.interactions[PC];
     pl->stats.pass_interactions[0] = varied ? pl->work_near.interactions[PP] : pass_w;
     pl->stats.pass_interactions[1] = varied ? pass_w : 0.0;
+    pl->stats.pass_interactions[2] = sym_w;
     pl->stats.down_degree = w.down_degree;
     pl->stats.degree_mask = w.src_degrees | w.tgt_degrees;
     Upload up;
     up.add(pl->pitems, w.pitems).add(pl->pentries, w.pentries).add(pl->qitems, w.qitems)
         .add(pl->qentries, w.qentries).add(pl->has_far, w.leaf_has_far).add(pl->prolong, w.prolong);
     if (varied) up.add(pl->sep_items, sep_items);
+    if (!varied && symm) up.add(pl->sym_items, pl->sym.items).add(pl->sym_entries, pl->sym.entries);
     up.run(pl->staging, pl->staging_free, st);
 
     if (varied) {
@@ -323,10 +340,17 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // 4. PP + PC: one pass, or the second pass of the per-pair degree form
     //    added to the near-field pass
     if (!varied) {
-        PhaseMark mark(pl, BLDTT_PH_PPPC, st);
-        launch_interact(ks, fp32, false, pl->tpt, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
-                        pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                        pl->phi_tree.as<double>(), DegOut{}, st);
+        {
+            PhaseMark mark(pl, BLDTT_PH_PPPC, st);
+            launch_interact(ks, fp32, false, pl->tpt, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
+                            pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                            pl->phi_tree.as<double>(), DegOut{}, st);
+        }
+        if (symm) {
+            PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
+            launch_sym_pp(fp32, pl->sym_items.as<DevItem>(), (int)pl->sym.items.size(), pl->sym_entries.as<int2>(),
+                          pl->dsrc(), dS, pl->phi_tree.as<double>(), st);
+        }
     } else {
         HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));
         PhaseMark mark(pl, BLDTT_PH_PPPC_SEP, st);

@@ -127,4 +127,17 @@ struct Work {
 // degree when no proxy potentials are produced).
 void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w);
 
+// Symmetric PP pairs of a targets = sources plan: leaf pairs (A, B), A != B,
+// listed as PP in both directions.  `rest` receives a copy of L without both
+// directions of those pairs; the pairs with A < B are packed into items over
+// A's particles in tiles of 256 (cluster = A) whose entries are the merged
+// particle ranges of A's partners, longest first.  `evaluations` is the
+// number of kernel terms the items produce (both directions).
+struct SymWork {
+    std::vector<Entry> entries;
+    std::vector<Item> items;
+    double evaluations = 0.0;
+};
+void split_symmetric(const Tree& T, const Lists& L, Lists& rest, SymWork& sw);
+
 }  // namespace bldtt

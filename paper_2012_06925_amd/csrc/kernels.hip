@@ -91,6 +91,106 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
         down_leaf_body<M>(it, has_far[it.cluster] != 0, tgt, T, tab, phihat, phi_tree, perm, out, 0, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric PP pass for targets = sources (Coulomb): for a pair of distinct
+// leaves {A, B} each kernel value G(x_i, x_j) = G(x_j, x_i) serves both
+// phi_i += q_j G (i in A) and phi_j += q_i G (j in B).  One work item = a tile
+// of up to 256 targets of A (64 per wave) and the source ranges of its
+// partners B.  Sources are staged 64 at a time in LDS; at step s lane l pairs
+// its target with source (l + s) mod 64 and adds q_i G to a running source
+// partial that moves one lane down per step (DPP wave_rol:1: lane l receives
+// lane l+1), so after 64 steps lane l holds the partial of source (l - 1) mod
+// 64 over all 64 targets of its wave.  The wave partials are summed in LDS and
+// added to phi_j with one FP64 atomic per source; the targets' sums are added
+// with one atomic per target at the end.  (Distinct leaves never hold
+// coincident points; r^2 == 0 is still guarded because FP32 relative
+// coordinates of distinct points may round together.)  Results are
+// reproducible to rounding: the atomics' order varies.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rol1(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ double rol1(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x134, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x134, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+
+constexpr float kFar = 1e18f;            // padding lanes sit here with charge 0
+
+template <bool F32>
+__global__ __launch_bounds__(kBlock) void k_sym_pp(const DevItem* __restrict__ items, const int2* __restrict__ entries,
+                                                   DevParticles p, DevTree T, double* __restrict__ phi) {
+    using R = typename std::conditional<F32, float, double>::type;
+    using V = typename std::conditional<F32, float4, double4>::type;
+    // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
+    constexpr R qs = F32 ? (R)1 : (R)0.5;
+    __shared__ V src[128];                 // each block of 64 sources twice: step s reads src[lane + s]
+    __shared__ R part_red[4][64];
+    const DevItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool active = 64 * wave < it.tn;
+    const double* box = T.box + 6 * it.cluster;
+    const double cx = F32 ? 0.5 * (box[0] + box[3]) : 0.0, cy = F32 ? 0.5 * (box[1] + box[4]) : 0.0,
+                 cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
+    const int r = 64 * wave + lane;
+    const bool mine = r < it.tn;
+    const int ti = it.t0 + (mine ? r : 0);
+    const R tx = mine ? (R)(p.x[ti] - cx) : (R)kFar, ty = mine ? (R)(p.y[ti] - cy) : (R)kFar,
+            tz = mine ? (R)(p.z[ti] - cz) : (R)kFar;
+    const R qi = mine ? (R)(qs * p.q[ti]) : (R)0;
+    double acc = 0.0;
+    for (int e = it.eb; e < it.ee; ++e) {
+        const int2 en = entries[e];
+        const int b0 = en.x, bn = en.y & ((1 << 29) - 1);
+        for (int c0 = 0; c0 < bn; c0 += 64) {
+            __syncthreads();
+            if (tid < 64) {
+                const int j = b0 + c0 + tid;
+                V v{(R)kFar, (R)kFar, (R)kFar, (R)0};
+                if (c0 + tid < bn) v = V{(R)(p.x[j] - cx), (R)(p.y[j] - cy), (R)(p.z[j] - cz), (R)(qs * p.q[j])};
+                src[tid] = v;
+                src[tid + 64] = v;
+            }
+            __syncthreads();
+            R psi = 0;
+            if (active) {
+                R sum = 0;
+#pragma unroll
+                for (int s = 0; s < 64; ++s) {
+                    const V v = src[lane + s];
+                    const R dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
+                    R r2 = dz * dz;
+                    r2 = dy * dy + r2;
+                    r2 = dx * dx + r2;
+                    R y;
+                    if constexpr (F32) {
+                        y = __builtin_amdgcn_rsqf(r2);
+                        y = r2 > 0.0f ? y : 0.0f;
+                    } else {
+                        const double y0 = r2 > 0.0 ? rsq_est(r2) : 0.0;
+                        y = y0 * fma(-(r2 * y0), y0, 3.0);            // 2 y0 (3 - r^2 y0^2)/2; q staged /2
+                    }
+                    sum = fma(v.w, y, sum);
+                    psi = rol1(psi) + qi * y;
+                }
+                acc += (double)sum;
+                part_red[wave][(lane + 63) & 63] = psi;
+            }
+            __syncthreads();
+            if (tid < 64 && c0 + tid < bn) {
+                double t = 0.0;
+                for (int w = 0; w < 4; ++w)
+                    if (64 * w < it.tn) t += (double)part_red[w][tid];
+                atomicAdd(phi + b0 + c0 + tid, t);
+            }
+        }
+    }
+    if (mine) atomicAdd(phi + ti, acc);
+}
+
 // Runtime-degree basis (m <= 13 nodes) for the degree-lifting kernel.
 __device__ __forceinline__ void basis1d_rt(int m, double lo, double hi, const double* __restrict__ tab, double y,
                                            double* L) {
@@ -455,6 +555,14 @@ void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, 
     if (n_items <= 0) return;
     by_degree<DownLeaf>(degree, mfma, items, n_items, has_far, tgt, T, tab + 32 * degree, phihat, phi_tree, perm,
                         out, st);
+    CHECK_LAUNCH();
+}
+
+void launch_sym_pp(bool fp32, const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
+                   double* phi, hipStream_t st) {
+    if (n_items <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_sym_pp<true>, dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi);
+    else hipLaunchKernelGGL(k_sym_pp<false>, dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi);
     CHECK_LAUNCH();
 }
 

@@ -161,6 +161,12 @@ struct bldtt_plan {
     PinnedBuf staging_near;
     Work work_near;
     DevBuf near_items, near_entries, sep_items;
+    // symmetric PP pairs (targets = sources, Coulomb): one evaluation for both directions
+    SymWork sym;
+    DevBuf sym_items, sym_entries;
+    bool symmetric_pp() const {
+        return aliased && kind == BLDTT_COULOMB && (flags & BLDTT_ONE_SIDED_PP) == 0;
+    }
 
     int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
     uint32_t up_degrees_last = 0;            // source degrees of the last per-pair degree compute

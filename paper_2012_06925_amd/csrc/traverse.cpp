@@ -403,4 +403,108 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
     sort_items(items, w.qitems);
 }
 
+void split_symmetric(const Tree& T, const Lists& L, Lists& rest, SymWork& sw) {
+    sw = SymWork();
+    const int64_t nc = T.size();
+    const std::vector<int64_t>& ptc = L.tc[PP];
+    const std::vector<int64_t>& psc = L.sc[PP];
+    const int64_t n = (int64_t)ptc.size();
+    // leaf-leaf PP partners of every cluster, sorted (CSR by target)
+    std::vector<int64_t> off(nc + 1, 0), part;
+    for (int64_t e = 0; e < n; ++e)
+        if (T.is_leaf(ptc[e]) && T.is_leaf(psc[e]) && ptc[e] != psc[e]) off[ptc[e] + 1]++;
+    for (int64_t c = 0; c < nc; ++c) off[c + 1] += off[c];
+    part.resize(off[nc]);
+    {
+        std::vector<int64_t> fill(off.begin(), off.end() - 1);
+        for (int64_t e = 0; e < n; ++e)
+            if (T.is_leaf(ptc[e]) && T.is_leaf(psc[e]) && ptc[e] != psc[e]) part[fill[ptc[e]]++] = psc[e];
+    }
+    constexpr int64_t kBlk = 256;
+    const int64_t nblk = (nc + kBlk - 1) / kBlk;
+    parallel_run(nblk, [&](int64_t b) {
+        for (int64_t c = b * kBlk; c < std::min(nc, (b + 1) * kBlk); ++c)
+            std::sort(part.begin() + off[c], part.begin() + off[c + 1]);
+    });
+    auto listed = [&](int64_t a, int64_t b) {
+        return std::binary_search(part.begin() + off[a], part.begin() + off[a + 1], b);
+    };
+    auto is_sym = [&](int64_t a, int64_t b) {
+        return a != b && T.is_leaf(a) && T.is_leaf(b) && listed(a, b) && listed(b, a);
+    };
+    // the rest: every list except the symmetric PP pairs (both directions)
+    for (int k = 0; k < 4; ++k) {
+        if (k == PP) continue;
+        rest.tc[k] = L.tc[k];
+        rest.sc[k] = L.sc[k];
+        rest.deg[k] = L.deg[k];
+    }
+    rest.tc[PP].clear();
+    rest.sc[PP].clear();
+    rest.deg[PP].clear();
+    for (int64_t e = 0; e < n; ++e) {
+        if (is_sym(ptc[e], psc[e])) continue;
+        rest.tc[PP].push_back(ptc[e]);
+        rest.sc[PP].push_back(psc[e]);
+        if (!L.deg[PP].empty()) rest.deg[PP].push_back(L.deg[PP][e]);
+    }
+    rest.sep_tc = L.sep_tc;
+    rest.sep_sc = L.sep_sc;
+    // items: per leaf A, the partners B > A as merged particle ranges
+    struct Blk {
+        std::vector<Entry> entries;
+        std::vector<std::pair<double, Item>> items;
+        double evals = 0.0;
+    };
+    std::vector<Blk> blks(nblk);
+    parallel_run(nblk, [&](int64_t bi) {
+        Blk& B = blks[bi];
+        std::vector<std::pair<int64_t, int64_t>> rng;
+        for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
+            if (!T.is_leaf(a)) continue;
+            rng.clear();
+            double src = 0.0;
+            for (int64_t k = off[a]; k < off[a + 1]; ++k) {
+                const int64_t b = part[k];
+                if (b > a && listed(b, a)) {
+                    rng.emplace_back(T.begin[b], T.count[b]);
+                    src += (double)T.count[b];
+                }
+            }
+            if (rng.empty()) continue;
+            std::sort(rng.begin(), rng.end());
+            const int64_t eb = (int64_t)B.entries.size();
+            size_t i = 0;
+            while (i < rng.size()) {
+                int64_t s0 = rng[i].first, s1 = rng[i].first + rng[i].second;
+                size_t j = i + 1;
+                while (j < rng.size() && rng[j].first == s1 && s1 - s0 + rng[j].second <= kCountMask) s1 += rng[j++].second;
+                B.entries.push_back(Entry{(int32_t)s0, (int32_t)(s1 - s0)});
+                i = j;
+            }
+            const int64_t ee = (int64_t)B.entries.size();
+            B.evals += 2.0 * (double)T.count[a] * src;
+            for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += 256) {
+                const int64_t tn = std::min<int64_t>(256, T.begin[a] + T.count[a] - tb);
+                B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
+                                                          (int32_t)a, 0, (int32_t)tb}});
+            }
+        }
+    });
+    std::vector<std::pair<double, Item>> items;
+    for (auto& B : blks) {
+        const int32_t shift = (int32_t)sw.entries.size();
+        sw.entries.insert(sw.entries.end(), B.entries.begin(), B.entries.end());
+        for (auto& it : B.items) {
+            it.second.eb += shift;
+            it.second.ee += shift;
+            items.push_back(it);
+        }
+        sw.evaluations += B.evals;
+    }
+    std::stable_sort(items.begin(), items.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    sw.items.reserve(items.size());
+    for (auto& it : items) sw.items.push_back(it.second);
+}
+
 }  // namespace bldtt

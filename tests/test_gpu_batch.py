@@ -34,7 +34,9 @@ def _dev_problem(p, targets=None):
 
 
 def _alone(problem, **kw):
+    # the batch evaluates every PP pair one-sided: compare with the same arithmetic
     tgt, src = problem
+    kw = dict(kw, flags=kw.get("flags", 0) | _lib.ONE_SIDED_PP)
     plan = api.Plan(tgt, src, **kw)
     out = plan.compute()
     torch.cuda.synchronize()
@@ -162,7 +164,7 @@ def test_autotuner_measures_then_reads_its_cache(tmp_path):
         b2.close()
         # the single-problem path reads the same cache
         tgt, src = probs[0]
-        plan = api.Plan(tgt, src, theta=0.7, degree=6, leaf=100)
+        plan = api.Plan(tgt, src, theta=0.7, degree=6, leaf=100, flags=_lib.ONE_SIDED_PP)
         api.autotune(plan, reps=1)
         out = plan.compute()
         torch.cuda.synchronize()

@@ -169,12 +169,45 @@ def test_tiny_sets_and_single_leaf():
     assert core.rel_l2(phi, ds) < 1e-14
 
 
+ONE_SIDED_PP = 256
+
+
 def test_determinism_and_recompute():
+    # one-sided PP: every recompute is bit-identical
     p = inputs.particles(30_000, "gaussian", seed=50)
-    plan, phi1, _ = gpu_plan(p, p, True, theta=0.7, degree=5, leaf=200)
+    plan, phi1, _ = gpu_plan(p, p, True, theta=0.7, degree=5, leaf=200, flags=ONE_SIDED_PP)
     phi2 = plan.compute().cpu().numpy()
     phi3 = plan.compute().cpu().numpy()
     assert np.array_equal(phi1, phi2) and np.array_equal(phi2, phi3)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_symmetric_pp_equals_one_sided(fp32):
+    # targets = sources, Coulomb: pairs of leaves listed in both directions are
+    # evaluated once for both (atomic adds); the result equals the one-sided
+    # form to rounding, recomputes agree to rounding, and FP64 matches the oracle
+    p = inputs.particles(40_000, "uniform", seed=52)
+    flags = 1 if fp32 else 0
+    plan, sym1, _ = gpu_plan(p, p, True, theta=0.8, degree=6, leaf=150, flags=flags)
+    st = plan.stats()
+    sym2 = plan.compute().cpu().numpy()
+    plan.close()
+    one, ph1, _ = gpu_plan(p, p, True, theta=0.8, degree=6, leaf=150, flags=flags | ONE_SIDED_PP)
+    st1 = one.stats()
+    one.close()
+    assert st["pass_interactions"][2] > 0.5 * st["interactions"]["PP"]
+    assert st["interactions"] == st1["interactions"]
+    ref = core.bldtt(p, p, theta=0.8, degree=6, leaf=150)
+    if not fp32:
+        assert core.rel_l2(sym1, ph1) < 1e-14 and core.rel_l2(sym2, sym1) < 1e-14
+        assert core.rel_l2(sym1, ref) < PARITY
+    else:
+        # two FP32 evaluations with different partial sums: each within the
+        # FP32 bound of the FP64 oracle; recomputes differ by FP64 atomic order only
+        e_sym, e_one = core.rel_l2(sym1, ref), core.rel_l2(ph1, ref)
+        print(f"\n  FP32 vs FP64 oracle: symmetric {e_sym:.2e}, one-sided {e_one:.2e}")
+        assert e_sym < FP32_BOUND_CUBE and e_one < FP32_BOUND_CUBE
+        assert core.rel_l2(sym2, sym1) < 1e-12
 
 
 def test_caller_stream_is_used():
