@@ -76,12 +76,15 @@ enum {
                                       FP64 matrix cores instead of the vector ALUs (the
                                       default, faster on gfx950: FP64 matrix and vector
                                       peaks are equal and 16x16 tiles pad n+1 rows)     */
-    BLDTT_ONE_SIDED_PP = 1u << 8   /* evaluate every PP pair one-sided.  By default, for
-                                      targets = sources with the Coulomb kernel, a pair
-                                      of distinct leaves listed as PP in both directions
-                                      is evaluated once for both (G is symmetric), with
-                                      FP64 atomic adds into the potentials: the result
-                                      then varies run to run at the rounding level     */
+    BLDTT_ONE_SIDED_PP = 1u << 8   /* evaluate every PP and CC pair one-sided.  By
+                                      default, for targets = sources with the Coulomb
+                                      kernel, a pair of distinct leaves listed as PP in
+                                      both directions, or of clusters listed as CC in
+                                      both directions at one degree, is evaluated once
+                                      for both (G is symmetric; a cluster's proxy grid
+                                      is the same as target and as source), with FP64
+                                      atomic adds: the result then varies run to run
+                                      at the rounding level                              */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host
@@ -201,8 +204,9 @@ typedef struct {
     int64_t sep_fallback;          /*   of which outside the model's range (fallback)    */
     int64_t sep_direct;            /*   of which evaluated directly (PP chosen)          */
     int64_t pairs_per_degree[13];  /*   approximated pairs per degree                     */
-    double pass_interactions[3];   /* kernel terms of the PPPC, PPPC_SEP and PP_SYM passes
-                                      (PP_SYM: both directions counted)                  */
+    double pass_interactions[4];   /* kernel terms of the PPPC, PPPC_SEP and PP_SYM passes
+                                      and of the symmetric CC pairs (symmetric: both
+                                      directions counted)                                */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the

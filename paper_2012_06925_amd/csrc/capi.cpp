@@ -243,14 +243,14 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     previous compute still reads phi_tree).
         //     Symmetric pairs go to their own pass after it (atomic adds).
         Lists near_rest;
-        if (symm) split_symmetric(T, pl->lists, near_rest, pl->sym);
+        if (symm) split_symmetric(T, pl->lists, pl->degree, true, false, near_rest, pl->sym);
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
         const Work& wn = pl->work_near;
         HIPCHK(hipEventRecord(pl->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
         Upload un;
         un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
-        if (symm) un.add(pl->sym_items, pl->sym.items).add(pl->sym_entries, pl->sym.entries);
+        if (symm) un.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
         un.run(pl->staging_near, pl->staging_near_free, pl->side);
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
@@ -260,8 +260,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
-            launch_sym_pp(fp32, pl->sym_items.as<DevItem>(), (int)pl->sym.items.size(), pl->sym_entries.as<int2>(),
-                          pl->dsrc(), dS, pl->phi_tree.as<double>(), pl->side);
+            launch_sym(fp32, false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
+                       pl->sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
+                       deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), pl->side);
         }
         HIPCHK(hipEventRecord(pl->ev_near_done, pl->side));
         // 2b. per-pair (type, degree); select_degrees appends the typed pairs to
@@ -276,30 +277,38 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             sep.deg[k].assign(L.deg[k].begin() + n0[k], L.deg[k].end());
         }
     }
-    Lists rest;                         // fixed degree, symmetric pairs split off
-    if (!varied && symm) split_symmetric(T, pl->lists, rest, pl->sym);
-    pack_work(T, S, varied ? sep : (symm ? rest : pl->lists), pl->degree, tile, ptile, pl->work);
+    Lists rest;                         // the lists without their symmetric pairs
+    if (symm && !varied) split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym);
+    if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep);
+    const SymWork& scc = varied ? pl->sym_sep : pl->sym;          // symmetric CC pairs
+    std::vector<uint32_t> scc_deg;
+    if (symm) scc_deg = sym_cc_degrees(T, scc);
+    pack_work(T, S, symm ? rest : (varied ? sep : pl->lists), pl->degree, tile, ptile, pl->work,
+              symm ? &scc_deg : nullptr);
     Work& w = pl->work;
     std::vector<Item> sep_items;        // second particle pass: leaves with separated-pair entries
     if (varied)
         for (const Item& it : w.pitems)
             if (it.ee > it.eb) sep_items.push_back(it);
     pl->stats.traverse_ms += now_ms() - tp;
-    const double sym_w = symm ? pl->sym.evaluations : 0.0;
+    const double sym_w = symm ? pl->sym.pp_evaluations : 0.0, sym_c = symm ? scc.cc_evaluations : 0.0;
     for (int k = 0; k < 4; ++k)
         pl->stats.interactions[k] = w.interactions[k] + (varied ? pl->work_near.interactions[k] : 0.0);
     pl->stats.interactions[PP] += sym_w;
+    pl->stats.interactions[CC] += sym_c;
     const double pass_w = w.interactions[PP] + w.interactions[PC];
     pl->stats.pass_interactions[0] = varied ? pl->work_near.interactions[PP] : pass_w;
     pl->stats.pass_interactions[1] = varied ? pass_w : 0.0;
     pl->stats.pass_interactions[2] = sym_w;
+    pl->stats.pass_interactions[3] = sym_c;
     pl->stats.down_degree = w.down_degree;
     pl->stats.degree_mask = w.src_degrees | w.tgt_degrees;
     Upload up;
     up.add(pl->pitems, w.pitems).add(pl->pentries, w.pentries).add(pl->qitems, w.qitems)
         .add(pl->qentries, w.qentries).add(pl->has_far, w.leaf_has_far).add(pl->prolong, w.prolong);
     if (varied) up.add(pl->sep_items, sep_items);
-    if (!varied && symm) up.add(pl->sym_items, pl->sym.items).add(pl->sym_entries, pl->sym.entries);
+    if (!varied && symm) up.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
+    if (symm) up.add(pl->sym_cc_items, scc.cc_items).add(pl->sym_cc_entries, scc.cc_entries);
     up.run(pl->staging, pl->staging_free, st);
 
     if (varied) {
@@ -326,6 +335,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         launch_interact(ks, fp32, true, pl->tpt_proxy, pl->qitems.as<DevItem>(), (int)w.qitems.size(),
                         pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         nullptr, deg_out(pl->phihat_deg), st);
+        if (symm)               // symmetric CC pairs add to the proxy potentials the pass above wrote
+            launch_sym(fp32, true, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
+                       pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, nullptr, tab, deg_ptrs(pl->qhat_deg),
+                       deg_out(pl->phihat_deg), st);
     }
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
@@ -348,8 +361,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
-            launch_sym_pp(fp32, pl->sym_items.as<DevItem>(), (int)pl->sym.items.size(), pl->sym_entries.as<int2>(),
-                          pl->dsrc(), dS, pl->phi_tree.as<double>(), st);
+            launch_sym(fp32, false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
+                       pl->sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
+                       deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);
         }
     } else {
         HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));

@@ -125,19 +125,30 @@ struct Work {
 // tile: targets per particle item; ptile: proxies per proxy item.  Degrees come
 // from the lists (L.deg); `degree` is the plan's base degree (the downward
 // degree when no proxy potentials are produced).
-void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w);
+// extra (optional, one mask per target cluster): degrees of proxy potentials
+// the cluster receives from elsewhere (the symmetric CC pairs); they count for
+// the far-field flags, the degree masks and the lifting items like entries.
+void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w,
+               const std::vector<uint32_t>* extra = nullptr);
 
-// Symmetric PP pairs of a targets = sources plan: leaf pairs (A, B), A != B,
-// listed as PP in both directions.  `rest` receives a copy of L without both
-// directions of those pairs; the pairs with A < B are packed into items over
-// A's particles in tiles of 256 (cluster = A) whose entries are the merged
-// particle ranges of A's partners, longest first.  `evaluations` is the
-// number of kernel terms the items produce (both directions).
+
+// Symmetric pairs of a targets = sources plan (one tree): with `pp`, leaf
+// pairs (A, B), A != B, listed as PP in both directions; with `cc`, cluster
+// pairs listed as CC in both directions at one degree.  `rest` receives a copy
+// of L without both directions of those pairs.  The pairs with A < B are
+// packed into items over A's points in tiles of 256 (cluster = A): PP items
+// over A's particles with the merged particle ranges of A's partners, CC items
+// per (A, degree) over A's proxies with proxy entries of the partners; longest
+// first.  The evaluation counts are the kernel terms the items produce (both
+// directions).
 struct SymWork {
-    std::vector<Entry> entries;
-    std::vector<Item> items;
-    double evaluations = 0.0;
+    std::vector<Entry> pp_entries, cc_entries;
+    std::vector<Item> pp_items, cc_items;
+    double pp_evaluations = 0.0, cc_evaluations = 0.0;
 };
-void split_symmetric(const Tree& T, const Lists& L, Lists& rest, SymWork& sw);
+void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw);
+
+// Per-cluster degree masks of the symmetric CC pairs (both clusters of each pair).
+std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw);
 
 }  // namespace bldtt

@@ -92,20 +92,24 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric PP pass for targets = sources (Coulomb): for a pair of distinct
-// leaves {A, B} each kernel value G(x_i, x_j) = G(x_j, x_i) serves both
-// phi_i += q_j G (i in A) and phi_j += q_i G (j in B).  One work item = a tile
-// of up to 256 targets of A (64 per wave) and the source ranges of its
-// partners B.  Sources are staged 64 at a time in LDS; at step s lane l pairs
-// its target with source (l + s) mod 64 and adds q_i G to a running source
-// partial that moves one lane down per step (DPP wave_rol:1: lane l receives
-// lane l+1), so after 64 steps lane l holds the partial of source (l - 1) mod
-// 64 over all 64 targets of its wave.  The wave partials are summed in LDS and
-// added to phi_j with one FP64 atomic per source; the targets' sums are added
-// with one atomic per target at the end.  (Distinct leaves never hold
-// coincident points; r^2 == 0 is still guarded because FP32 relative
-// coordinates of distinct points may round together.)  Results are
-// reproducible to rounding: the atomics' order varies.
+// Symmetric passes for targets = sources (Coulomb).  G(x, y) = G(y, x), so one
+// kernel value serves two terms:
+//   PP (pairs of distinct leaves {A, B}): phi_i += q_j G, phi_j += q_i G;
+//   CC (pairs of clusters {A, B} at one degree): phihat_A[l] += G qhat_B[k] and
+//      phihat_B[k] += G qhat_A[l] -- the proxy grids of a cluster are the same
+//      points whether it is the target or the source.
+// One work item = a tile of up to 256 target points of A (64 per wave) and the
+// entries of its partners B.  Sources are staged 64 at a time in LDS (twice,
+// so step s reads src[lane + s]); at step s lane l pairs its target with
+// source (l + s) mod 64 and adds q_i G to a running source partial that moves
+// one lane down per step (DPP wave_rol:1: lane l receives lane l + 1), so
+// after 64 steps lane l holds the partial of source (l - 1) mod 64 over the 64
+// targets of its wave.  The wave partials are summed in LDS and added to the
+// source's output with one FP64 atomic per source; each target's sum is added
+// with one atomic at the end.  Results are reproducible to rounding only: the
+// order of the atomics varies.  PP guards r^2 == 0 (distinct leaves never
+// share a point, but FP32 relative coordinates of two close points may round
+// together); CC pairs are separated, so their proxies never meet.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float rol1(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf, 0xf, true));
@@ -120,14 +124,15 @@ __device__ __forceinline__ double rol1(double v) {
 
 constexpr float kFar = 1e18f;            // padding lanes sit here with charge 0
 
-template <bool F32>
-__global__ __launch_bounds__(kBlock) void k_sym_pp(const DevItem* __restrict__ items, const int2* __restrict__ entries,
-                                                   DevParticles p, DevTree T, double* __restrict__ phi) {
+template <bool F32, bool PROXY>
+__global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ items, const int2* __restrict__ entries,
+                                                DevParticles p, DevTree T, double* __restrict__ phi,
+                                                const double* __restrict__ tab, DegPtrs qhat, DegOut phihat) {
     using R = typename std::conditional<F32, float, double>::type;
     using V = typename std::conditional<F32, float4, double4>::type;
     // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
     constexpr R qs = F32 ? (R)1 : (R)0.5;
-    __shared__ V src[128];                 // each block of 64 sources twice: step s reads src[lane + s]
+    __shared__ V src[128];
     __shared__ R part_red[4][64];
     const DevItem it = items[blockIdx.x];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -135,22 +140,54 @@ __global__ __launch_bounds__(kBlock) void k_sym_pp(const DevItem* __restrict__ i
     const double* box = T.box + 6 * it.cluster;
     const double cx = F32 ? 0.5 * (box[0] + box[3]) : 0.0, cy = F32 ? 0.5 * (box[1] + box[4]) : 0.0,
                  cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
+    // proxies: degree of the item, grid size, per-degree tables and arrays
+    const int m = it.degree + 1, P = m * m * m;
+    const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
+    double* od = PROXY ? phihat.p[it.degree] : nullptr;
     const int r = 64 * wave + lane;
     const bool mine = r < it.tn;
     const int ti = it.t0 + (mine ? r : 0);
-    const R tx = mine ? (R)(p.x[ti] - cx) : (R)kFar, ty = mine ? (R)(p.y[ti] - cy) : (R)kFar,
-            tz = mine ? (R)(p.z[ti] - cz) : (R)kFar;
-    const R qi = mine ? (R)(qs * p.q[ti]) : (R)0;
+    R tx = (R)kFar, ty = (R)kFar, tz = (R)kFar, qi = 0;
+    if (mine) {
+        double x, y, z, q;
+        if constexpr (PROXY) {
+            proxy_point(box, m, tab + 32 * it.degree, ti, x, y, z);
+            q = qd[(int64_t)it.cluster * P + ti];
+        } else {
+            x = p.x[ti];
+            y = p.y[ti];
+            z = p.z[ti];
+            q = p.q[ti];
+        }
+        tx = (R)(x - cx);
+        ty = (R)(y - cy);
+        tz = (R)(z - cz);
+        qi = (R)(qs * q);
+    }
     double acc = 0.0;
     for (int e = it.eb; e < it.ee; ++e) {
         const int2 en = entries[e];
-        const int b0 = en.x, bn = en.y & ((1 << 29) - 1);
+        const int low = en.y & ((1 << 29) - 1);
+        const int bn = PROXY ? P : low;                    // proxy entries: en.x = cluster B
+        const double* sbox = T.box + 6 * en.x;
         for (int c0 = 0; c0 < bn; c0 += 64) {
             __syncthreads();
             if (tid < 64) {
-                const int j = b0 + c0 + tid;
                 V v{(R)kFar, (R)kFar, (R)kFar, (R)0};
-                if (c0 + tid < bn) v = V{(R)(p.x[j] - cx), (R)(p.y[j] - cy), (R)(p.z[j] - cz), (R)(qs * p.q[j])};
+                if (c0 + tid < bn) {
+                    double x, y, z, q;
+                    if constexpr (PROXY) {
+                        proxy_point(sbox, m, tab + 32 * it.degree, c0 + tid, x, y, z);
+                        q = qd[(int64_t)en.x * P + c0 + tid];
+                    } else {
+                        const int j = en.x + c0 + tid;
+                        x = p.x[j];
+                        y = p.y[j];
+                        z = p.z[j];
+                        q = p.q[j];
+                    }
+                    v = V{(R)(x - cx), (R)(y - cy), (R)(z - cz), (R)(qs * q)};
+                }
                 src[tid] = v;
                 src[tid + 64] = v;
             }
@@ -168,9 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_sym_pp(const DevItem* __restrict__ i
                     R y;
                     if constexpr (F32) {
                         y = __builtin_amdgcn_rsqf(r2);
-                        y = r2 > 0.0f ? y : 0.0f;
+                        if constexpr (!PROXY) y = r2 > 0.0f ? y : 0.0f;
                     } else {
-                        const double y0 = r2 > 0.0 ? rsq_est(r2) : 0.0;
+                        double y0 = rsq_est(r2);
+                        if constexpr (!PROXY) y0 = r2 > 0.0 ? y0 : 0.0;
                         y = y0 * fma(-(r2 * y0), y0, 3.0);            // 2 y0 (3 - r^2 y0^2)/2; q staged /2
                     }
                     sum = fma(v.w, y, sum);
@@ -184,11 +222,15 @@ __global__ __launch_bounds__(kBlock) void k_sym_pp(const DevItem* __restrict__ i
                 double t = 0.0;
                 for (int w = 0; w < 4; ++w)
                     if (64 * w < it.tn) t += (double)part_red[w][tid];
-                atomicAdd(phi + b0 + c0 + tid, t);
+                if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
+                else atomicAdd(phi + en.x + c0 + tid, t);
             }
         }
     }
-    if (mine) atomicAdd(phi + ti, acc);
+    if (mine) {
+        if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + ti, acc);
+        else atomicAdd(phi + ti, acc);
+    }
 }
 
 // Runtime-degree basis (m <= 13 nodes) for the degree-lifting kernel.
@@ -558,11 +600,19 @@ void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, 
     CHECK_LAUNCH();
 }
 
-void launch_sym_pp(bool fp32, const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
-                   double* phi, hipStream_t st) {
+void launch_sym(bool fp32, bool proxies, const DevItem* items, int n_items, const int2* entries, DevParticles p,
+                DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat, hipStream_t st) {
     if (n_items <= 0) return;
-    if (fp32) hipLaunchKernelGGL(k_sym_pp<true>, dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi);
-    else hipLaunchKernelGGL(k_sym_pp<false>, dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi);
+#define LAUNCH_SYM(F, PX) hipLaunchKernelGGL((k_sym<F, PX>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, \
+                                            tab, qhat, phihat)
+    if (fp32) {
+        if (proxies) LAUNCH_SYM(true, true);
+        else LAUNCH_SYM(true, false);
+    } else {
+        if (proxies) LAUNCH_SYM(false, true);
+        else LAUNCH_SYM(false, false);
+    }
+#undef LAUNCH_SYM
     CHECK_LAUNCH();
 }
 

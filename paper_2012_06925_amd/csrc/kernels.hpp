@@ -71,12 +71,13 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
                      const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
                      DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add = false);
 
-// Symmetric PP pass (Coulomb, targets = sources): items are tiles of a leaf A
-// with entries = source ranges of partner leaves B; adds q_j G to phi_i and
-// q_i G to phi_j with FP64 atomics (phi in tree order, already holding the
-// other terms).
-void launch_sym_pp(bool fp32, const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
-                   double* phi, hipStream_t st);
+// Symmetric passes (Coulomb, targets = sources): items are tiles of a target
+// cluster A (particles, or proxies of degree item.degree) with entries of
+// partner clusters B (particle ranges, or proxy entries); every kernel value
+// adds to both sides with FP64 atomics: phi (tree order) for particles,
+// phihat.p[degree] for proxies, which already hold the other terms.
+void launch_sym(bool fp32, bool proxies, const DevItem* items, int n_items, const int2* entries, DevParticles p,
+                DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat, hipStream_t st);
 
 // Per-pair relative error of degree-d proxy potentials phip[p] interpolated to
 // the particles of pair_tc[p], against exact[exact_off[p] + r].

@@ -161,9 +161,10 @@ struct bldtt_plan {
     PinnedBuf staging_near;
     Work work_near;
     DevBuf near_items, near_entries, sep_items;
-    // symmetric PP pairs (targets = sources, Coulomb): one evaluation for both directions
-    SymWork sym;
-    DevBuf sym_items, sym_entries;
+    // symmetric PP / CC pairs (targets = sources, Coulomb): one evaluation for both directions.
+    // sym: PP (and CC for a fixed degree); sym_sep: CC of the per-pair degree form
+    SymWork sym, sym_sep;
+    DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
     bool symmetric_pp() const {
         return aliased && kind == BLDTT_COULOMB && (flags & BLDTT_ONE_SIDED_PP) == 0;
     }

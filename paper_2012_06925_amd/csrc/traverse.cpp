@@ -274,7 +274,8 @@ void sort_items(std::vector<std::pair<double, Item>>& items, std::vector<Item>& 
 
 }  // namespace
 
-void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w) {
+void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w,
+               const std::vector<uint32_t>* extra) {
     w = Work();
     auto deg_of = [&](int ty, size_t e) { return L.deg[ty].empty() ? degree : (int)L.deg[ty][e]; };
     for (int ty = 0; ty < 4; ++ty) {
@@ -305,6 +306,11 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
             w.tgt_degrees |= td[k];
         }
     }
+    if (extra)
+        for (uint32_t m : *extra) {
+            w.src_degrees |= m;
+            w.tgt_degrees |= m;
+        }
     // Downward degree: the largest degree of any proxy potential (lower degrees
     // are lifted to it exactly), or the base degree when there are none.
     w.down_degree = degree;
@@ -333,7 +339,7 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
             double src = 0.0;
             bool far = false;
             for (int64_t c = leaf; c >= 0; c = T.parent[c]) {
-                if (prox.off[c + 1] > prox.off[c]) far = true;
+                if (prox.off[c + 1] > prox.off[c] || (extra && (*extra)[c])) far = true;
                 for (int64_t e = part.off[c]; e < part.off[c + 1]; ++e) {
                     int64_t sc = part.sc[e];
                     if (part.type[e] == PC) {
@@ -367,7 +373,8 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
         Block& B = blocks[bi];
         std::vector<std::pair<int64_t, int64_t>> rp, rg;
         for (int64_t c = bi * kBlockClusters; c < std::min(nc, (bi + 1) * kBlockClusters); ++c) {
-            if (prox.off[c + 1] == prox.off[c]) continue;
+            const uint32_t more = extra ? (*extra)[c] : 0u;
+            if (prox.off[c + 1] == prox.off[c] && !more) continue;
             uint32_t used = 0;
             for (int64_t e = prox.off[c]; e < prox.off[c + 1]; ++e) used |= 1u << prox.deg[e];
             for (int d = 0; d <= kMaxDegree; ++d) {
@@ -395,7 +402,7 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
                 }
             }
             // degrees of this cluster's proxy potentials that are lifted to the downward degree
-            uint32_t lift = used & ~(1u << down);
+            uint32_t lift = (used | more) & ~(1u << down);
             if (lift) B.prolong.push_back(Item{0, 0, 0, 0, (int32_t)c, (int32_t)lift, (int32_t)c});
         }
     });
@@ -403,108 +410,215 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
     sort_items(items, w.qitems);
 }
 
-void split_symmetric(const Tree& T, const Lists& L, Lists& rest, SymWork& sw) {
-    sw = SymWork();
-    const int64_t nc = T.size();
-    const std::vector<int64_t>& ptc = L.tc[PP];
-    const std::vector<int64_t>& psc = L.sc[PP];
-    const int64_t n = (int64_t)ptc.size();
-    // leaf-leaf PP partners of every cluster, sorted (CSR by target)
-    std::vector<int64_t> off(nc + 1, 0), part;
-    for (int64_t e = 0; e < n; ++e)
-        if (T.is_leaf(ptc[e]) && T.is_leaf(psc[e]) && ptc[e] != psc[e]) off[ptc[e] + 1]++;
-    for (int64_t c = 0; c < nc; ++c) off[c + 1] += off[c];
-    part.resize(off[nc]);
-    {
-        std::vector<int64_t> fill(off.begin(), off.end() - 1);
-        for (int64_t e = 0; e < n; ++e)
-            if (T.is_leaf(ptc[e]) && T.is_leaf(psc[e]) && ptc[e] != psc[e]) part[fill[ptc[e]]++] = psc[e];
-    }
-    constexpr int64_t kBlk = 256;
-    const int64_t nblk = (nc + kBlk - 1) / kBlk;
-    parallel_run(nblk, [&](int64_t b) {
-        for (int64_t c = b * kBlk; c < std::min(nc, (b + 1) * kBlk); ++c)
-            std::sort(part.begin() + off[c], part.begin() + off[c + 1]);
-    });
-    auto listed = [&](int64_t a, int64_t b) {
-        return std::binary_search(part.begin() + off[a], part.begin() + off[a + 1], b);
-    };
-    auto is_sym = [&](int64_t a, int64_t b) {
-        return a != b && T.is_leaf(a) && T.is_leaf(b) && listed(a, b) && listed(b, a);
-    };
-    // the rest: every list except the symmetric PP pairs (both directions)
-    for (int k = 0; k < 4; ++k) {
-        if (k == PP) continue;
-        rest.tc[k] = L.tc[k];
-        rest.sc[k] = L.sc[k];
-        rest.deg[k] = L.deg[k];
-    }
-    rest.tc[PP].clear();
-    rest.sc[PP].clear();
-    rest.deg[PP].clear();
-    for (int64_t e = 0; e < n; ++e) {
-        if (is_sym(ptc[e], psc[e])) continue;
-        rest.tc[PP].push_back(ptc[e]);
-        rest.sc[PP].push_back(psc[e]);
-        if (!L.deg[PP].empty()) rest.deg[PP].push_back(L.deg[PP][e]);
-    }
-    rest.sep_tc = L.sep_tc;
-    rest.sep_sc = L.sep_sc;
-    // items: per leaf A, the partners B > A as merged particle ranges
-    struct Blk {
-        std::vector<Entry> entries;
-        std::vector<std::pair<double, Item>> items;
-        double evals = 0.0;
-    };
-    std::vector<Blk> blks(nblk);
-    parallel_run(nblk, [&](int64_t bi) {
-        Blk& B = blks[bi];
-        std::vector<std::pair<int64_t, int64_t>> rng;
-        for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
-            if (!T.is_leaf(a)) continue;
-            rng.clear();
-            double src = 0.0;
-            for (int64_t k = off[a]; k < off[a + 1]; ++k) {
-                const int64_t b = part[k];
-                if (b > a && listed(b, a)) {
-                    rng.emplace_back(T.begin[b], T.count[b]);
-                    src += (double)T.count[b];
-                }
+namespace {
+
+// Pairs of one type as CSR by target cluster: partner key (source cluster,
+// degree) sorted per target; only pairs accepted by `take`.
+struct PairIndex {
+    std::vector<int64_t> off;
+    std::vector<std::pair<int64_t, int>> part;
+    template <class F>
+    void build(int64_t nc, const std::vector<int64_t>& tc, const std::vector<int64_t>& sc, const std::vector<int8_t>& dg,
+               int degree, F take) {
+        // counting sort by target with per-chunk counts (see group); the order
+        // within a target is fixed by the sort below
+        const int64_t n = (int64_t)tc.size();
+        const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), n / 16384 + 1));
+        const int64_t per = (n + nch - 1) / nch;
+        std::vector<int64_t> cnt(nch * nc, 0);
+        parallel_run(nch, [&](int64_t k) {
+            int64_t* c = cnt.data() + k * nc;
+            for (int64_t e = k * per; e < std::min(n, (k + 1) * per); ++e)
+                if (take(tc[e], sc[e])) c[tc[e]]++;
+        });
+        off.assign(nc + 1, 0);
+        for (int64_t c = 0; c < nc; ++c) {
+            int64_t run = off[c];
+            for (int64_t k = 0; k < nch; ++k) {
+                const int64_t m = cnt[k * nc + c];
+                cnt[k * nc + c] = run;
+                run += m;
             }
-            if (rng.empty()) continue;
-            std::sort(rng.begin(), rng.end());
-            const int64_t eb = (int64_t)B.entries.size();
-            size_t i = 0;
-            while (i < rng.size()) {
-                int64_t s0 = rng[i].first, s1 = rng[i].first + rng[i].second;
-                size_t j = i + 1;
-                while (j < rng.size() && rng[j].first == s1 && s1 - s0 + rng[j].second <= kCountMask) s1 += rng[j++].second;
-                B.entries.push_back(Entry{(int32_t)s0, (int32_t)(s1 - s0)});
-                i = j;
-            }
-            const int64_t ee = (int64_t)B.entries.size();
-            B.evals += 2.0 * (double)T.count[a] * src;
-            for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += 256) {
-                const int64_t tn = std::min<int64_t>(256, T.begin[a] + T.count[a] - tb);
-                B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
-                                                          (int32_t)a, 0, (int32_t)tb}});
-            }
+            off[c + 1] = run;
         }
-    });
+        part.resize(off[nc]);
+        parallel_run(nch, [&](int64_t k) {
+            int64_t* fill = cnt.data() + k * nc;
+            for (int64_t e = k * per; e < std::min(n, (k + 1) * per); ++e)
+                if (take(tc[e], sc[e])) part[fill[tc[e]]++] = {sc[e], dg.empty() ? degree : (int)dg[e]};
+        });
+        constexpr int64_t kBlk = 256;
+        parallel_run((nc + kBlk - 1) / kBlk, [&](int64_t b) {
+            for (int64_t c = b * kBlk; c < std::min(nc, (b + 1) * kBlk); ++c)
+                std::sort(part.begin() + off[c], part.begin() + off[c + 1]);
+        });
+    }
+    bool has(int64_t a, int64_t b, int d) const {
+        return std::binary_search(part.begin() + off[a], part.begin() + off[a + 1], std::make_pair(b, d));
+    }
+};
+
+struct SymBlock {
+    std::vector<Entry> entries;
+    std::vector<std::pair<double, Item>> items;
+    double evals = 0.0;
+};
+
+void gather(std::vector<SymBlock>& blks, std::vector<Entry>& entries, std::vector<Item>& out, double& evals) {
     std::vector<std::pair<double, Item>> items;
     for (auto& B : blks) {
-        const int32_t shift = (int32_t)sw.entries.size();
-        sw.entries.insert(sw.entries.end(), B.entries.begin(), B.entries.end());
+        const int32_t shift = (int32_t)entries.size();
+        entries.insert(entries.end(), B.entries.begin(), B.entries.end());
         for (auto& it : B.items) {
             it.second.eb += shift;
             it.second.ee += shift;
             items.push_back(it);
         }
-        sw.evaluations += B.evals;
+        evals += B.evals;
     }
     std::stable_sort(items.begin(), items.end(), [](auto& x, auto& y) { return x.first > y.first; });
-    sw.items.reserve(items.size());
-    for (auto& it : items) sw.items.push_back(it.second);
+    out.reserve(items.size());
+    for (auto& it : items) out.push_back(it.second);
+}
+
+}  // namespace
+
+std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw) {
+    std::vector<uint32_t> m(T.size(), 0u);
+    for (const Item& it : sw.cc_items) m[it.cluster] |= 1u << it.degree;
+    for (const Entry& e : sw.cc_entries) m[e.a] |= 1u << (e.b & kCountMask);
+    return m;
+}
+
+void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw) {
+    sw = SymWork();
+    const int64_t nc = T.size();
+    constexpr int64_t kBlk = 256, kTile = 256;
+    const int64_t nblk = (nc + kBlk - 1) / kBlk;
+    PairIndex ipp, icc;
+    const std::vector<int8_t> no_degrees;        // PP pairs are matched without their degree
+    if (pp)
+        ipp.build(nc, L.tc[PP], L.sc[PP], no_degrees, 0,
+                  [&](int64_t a, int64_t b) { return a != b && T.is_leaf(a) && T.is_leaf(b); });
+    if (cc) icc.build(nc, L.tc[CC], L.sc[CC], L.deg[CC], degree, [](int64_t a, int64_t b) { return a != b; });
+    auto sym_pp = [&](int64_t a, int64_t b) {
+        return pp && a != b && T.is_leaf(a) && T.is_leaf(b) && ipp.has(a, b, 0) && ipp.has(b, a, 0);
+    };
+    auto sym_cc = [&](int64_t a, int64_t b, int d) { return cc && a != b && icc.has(a, b, d) && icc.has(b, a, d); };
+    // the rest: every entry except both directions of the symmetric pairs,
+    // in list order (flags and per-chunk compaction on all threads)
+    for (int k = 0; k < 4; ++k) {
+        const bool typed = !L.deg[k].empty();
+        const int64_t n = (int64_t)L.tc[k].size();
+        const bool filter = (k == PP && pp) || (k == CC && cc);
+        if (!filter) {
+            rest.tc[k] = L.tc[k];
+            rest.sc[k] = L.sc[k];
+            rest.deg[k] = L.deg[k];
+            continue;
+        }
+        const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), n / 16384 + 1));
+        const int64_t per = (n + nch - 1) / nch;
+        std::vector<uint8_t> keep(n);
+        std::vector<int64_t> kept(nch + 1, 0);
+        parallel_run(nch, [&](int64_t c) {
+            int64_t m = 0;
+            for (int64_t e = c * per; e < std::min(n, (c + 1) * per); ++e) {
+                const int64_t a = L.tc[k][e], b = L.sc[k][e];
+                const int d = typed ? (int)L.deg[k][e] : degree;
+                keep[e] = !((k == PP && sym_pp(a, b)) || (k == CC && sym_cc(a, b, d)));
+                m += keep[e];
+            }
+            kept[c + 1] = m;
+        });
+        for (int64_t c = 0; c < nch; ++c) kept[c + 1] += kept[c];
+        rest.tc[k].resize(kept[nch]);
+        rest.sc[k].resize(kept[nch]);
+        rest.deg[k].resize(typed ? kept[nch] : 0);
+        parallel_run(nch, [&](int64_t c) {
+            int64_t o = kept[c];
+            for (int64_t e = c * per; e < std::min(n, (c + 1) * per); ++e) {
+                if (!keep[e]) continue;
+                rest.tc[k][o] = L.tc[k][e];
+                rest.sc[k][o] = L.sc[k][e];
+                if (typed) rest.deg[k][o] = L.deg[k][e];
+                ++o;
+            }
+        });
+    }
+    rest.sep_tc = L.sep_tc;
+    rest.sep_sc = L.sep_sc;
+    if (pp) {
+        // per leaf A: the partners B > A as merged particle ranges, tiles of A's particles
+        std::vector<SymBlock> blks(nblk);
+        parallel_run(nblk, [&](int64_t bi) {
+            SymBlock& B = blks[bi];
+            std::vector<std::pair<int64_t, int64_t>> rng;
+            for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
+                if (!T.is_leaf(a)) continue;
+                rng.clear();
+                double src = 0.0;
+                for (int64_t k = ipp.off[a]; k < ipp.off[a + 1]; ++k) {
+                    const int64_t b = ipp.part[k].first;
+                    if (b > a && ipp.has(b, a, 0)) {
+                        rng.emplace_back(T.begin[b], T.count[b]);
+                        src += (double)T.count[b];
+                    }
+                }
+                if (rng.empty()) continue;
+                std::sort(rng.begin(), rng.end());
+                const int64_t eb = (int64_t)B.entries.size();
+                size_t i = 0;
+                while (i < rng.size()) {
+                    int64_t s0 = rng[i].first, s1 = rng[i].first + rng[i].second;
+                    size_t j = i + 1;
+                    while (j < rng.size() && rng[j].first == s1 && s1 - s0 + rng[j].second <= kCountMask)
+                        s1 += rng[j++].second;
+                    B.entries.push_back(Entry{(int32_t)s0, (int32_t)(s1 - s0)});
+                    i = j;
+                }
+                const int64_t ee = (int64_t)B.entries.size();
+                B.evals += 2.0 * (double)T.count[a] * src;
+                for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {
+                    const int64_t tn = std::min<int64_t>(kTile, T.begin[a] + T.count[a] - tb);
+                    B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
+                                                              (int32_t)a, 0, (int32_t)tb}});
+                }
+            }
+        });
+        gather(blks, sw.pp_entries, sw.pp_items, sw.pp_evaluations);
+    }
+    if (cc) {
+        // per (cluster A, degree d): the partners B > A at d, tiles of A's proxies
+        std::vector<SymBlock> blks(nblk);
+        parallel_run(nblk, [&](int64_t bi) {
+            SymBlock& B = blks[bi];
+            for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
+                uint32_t used = 0;
+                for (int64_t q = icc.off[a]; q < icc.off[a + 1]; ++q) used |= 1u << icc.part[q].second;
+                for (int d = 0; d <= kMaxDegree; ++d) {
+                    if (!(used >> d & 1)) continue;
+                    const int64_t eb = (int64_t)B.entries.size();
+                    for (int64_t q = icc.off[a]; q < icc.off[a + 1]; ++q) {
+                        const int64_t b = icc.part[q].first;
+                        if (icc.part[q].second == d && b > a && icc.has(b, a, d))
+                            B.entries.push_back(Entry{(int32_t)b, (int32_t)((uint32_t)SRC_PROXY << 29 | (uint32_t)d)});
+                    }
+                    const int64_t ee = (int64_t)B.entries.size();
+                    if (ee == eb) continue;
+                    const int64_t np = (int64_t)(d + 1) * (d + 1) * (d + 1);
+                    B.evals += 2.0 * (double)np * (double)np * (double)(ee - eb);
+                    for (int64_t lb = 0; lb < np; lb += kTile) {
+                        const int64_t ln = std::min<int64_t>(kTile, np - lb);
+                        B.items.push_back({(double)np * (double)(ee - eb) * (double)ln,
+                                           Item{(int32_t)lb, (int32_t)ln, (int32_t)eb, (int32_t)ee, (int32_t)a,
+                                                (int32_t)d, (int32_t)a}});
+                    }
+                }
+            }
+        });
+        gather(blks, sw.cc_entries, sw.cc_items, sw.cc_evaluations);
+    }
 }
 
 }  // namespace bldtt

@@ -183,9 +183,10 @@ def test_determinism_and_recompute():
 
 @pytest.mark.parametrize("fp32", [False, True])
 def test_symmetric_pp_equals_one_sided(fp32):
-    # targets = sources, Coulomb: pairs of leaves listed in both directions are
-    # evaluated once for both (atomic adds); the result equals the one-sided
-    # form to rounding, recomputes agree to rounding, and FP64 matches the oracle
+    # targets = sources, Coulomb: pairs of leaves (PP) and of clusters (CC, one
+    # degree) listed in both directions are evaluated once for both (atomic
+    # adds); the result equals the one-sided form to rounding, recomputes agree
+    # to rounding, and FP64 matches the oracle
     p = inputs.particles(40_000, "uniform", seed=52)
     flags = 1 if fp32 else 0
     plan, sym1, _ = gpu_plan(p, p, True, theta=0.8, degree=6, leaf=150, flags=flags)
@@ -196,6 +197,8 @@ def test_symmetric_pp_equals_one_sided(fp32):
     st1 = one.stats()
     one.close()
     assert st["pass_interactions"][2] > 0.5 * st["interactions"]["PP"]
+    assert st["pass_interactions"][3] > 0.5 * st["interactions"]["CC"]
+    assert st1["pass_interactions"][2] == 0 and st1["pass_interactions"][3] == 0
     assert st["interactions"] == st1["interactions"]
     ref = core.bldtt(p, p, theta=0.8, degree=6, leaf=150)
     if not fp32:
