@@ -173,8 +173,9 @@ constexpr int kBlockThreads = 256;   // threads per interaction work group (4 wa
 
 inline int64_t cube(int d) { return (int64_t)(d + 1) * (d + 1) * (d + 1); }
 
-// Host arrays -> device buffers through one pinned staging buffer, on stream
-// st; `freed` marks when the copies have left the staging buffer.
+// Host arrays -> device buffers through one pinned staging buffer and one
+// copy into a device arena on stream st (the buffers become views into the
+// arena); `freed` marks when the copy has left the staging buffer.
 struct Upload {
     struct Part {
         DevBuf* dst;
@@ -187,22 +188,22 @@ struct Upload {
         parts.push_back(Part{&d, v.data(), sizeof(T) * v.size()});
         return *this;
     }
-    void run(PinnedBuf& staging, hipEvent_t freed, hipStream_t st) {
+    void run(PinnedBuf& staging, DevBuf& arena, hipEvent_t freed, hipStream_t st) {
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         size_t total = 0;
         for (auto& p : parts) total += al(p.n);
         HIPCHK(hipEventSynchronize(freed));      // the previous upload has left the staging buffer
         staging.reserve(total);
+        arena.reserve(total);
         char* h = static_cast<char*>(staging.p);
+        char* d = static_cast<char*>(arena.p);
         size_t o = 0;
         for (auto& p : parts) {
-            p.dst->reserve(p.n);
-            if (p.n) {
-                std::memcpy(h + o, p.src, p.n);
-                HIPCHK(hipMemcpyAsync(p.dst->p, h + o, p.n, hipMemcpyHostToDevice, st));
-            }
+            if (p.n) std::memcpy(h + o, p.src, p.n);
+            p.dst->alias(d + o, p.n);
             o += al(p.n);
         }
+        if (total) HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
         HIPCHK(hipEventRecord(freed, st));
     }
 };
@@ -230,6 +231,19 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         for (int d = 0; d <= kMaxDegree; ++d)
             if (pre >> d & 1) upward(pl, d, st);
     }
+    // ... and the proxy potentials are cleared now as well, for the degrees the
+    // last compute used (later kernels would otherwise wait for these small
+    // ones behind the big particle pass)
+    const uint32_t prefill = varied ? pl->fill_degrees_last : (1u << pl->degree);
+    auto clear_proxies = [&](uint32_t mask) {
+        for (int d = 0; d <= kMaxDegree; ++d) {
+            if (!(mask >> d & 1)) continue;
+            DevBuf& f = pl->phihat_deg[d];
+            f.reserve(sizeof(double) * T.size() * cube(d));
+            launch_fill(f.as<double>(), (int64_t)T.size() * cube(d), 0.0, st);
+        }
+    };
+    clear_proxies(prefill);
 
     // 2. traversal (Algorithm 2)
     do_traverse(pl);
@@ -251,7 +265,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         Upload un;
         un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
         if (symm) un.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
-        un.run(pl->staging_near, pl->staging_near_free, pl->side);
+        un.run(pl->staging_near, pl->arena_near, pl->staging_near_free, pl->side);
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
             launch_interact(ks, fp32, false, pl->tpt, pl->near_items.as<DevItem>(), (int)wn.pitems.size(),
@@ -309,7 +323,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     if (varied) up.add(pl->sep_items, sep_items);
     if (!varied && symm) up.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
     if (symm) up.add(pl->sym_cc_items, scc.cc_items).add(pl->sym_cc_entries, scc.cc_entries);
-    up.run(pl->staging, pl->staging_free, st);
+    up.run(pl->staging, pl->arena, pl->staging_free, st);
 
     if (varied) {
         const uint32_t rest = w.src_degrees & ~pre;
@@ -326,12 +340,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const int D = w.down_degree;
     {
         PhaseMark mark(pl, BLDTT_PH_CPCC, st);
-        for (int d = 0; d <= kMaxDegree; ++d) {
-            if (!((w.tgt_degrees | (1u << D)) >> d & 1)) continue;
-            DevBuf& f = pl->phihat_deg[d];
-            f.reserve(sizeof(double) * T.size() * cube(d));
-            launch_fill(f.as<double>(), (int64_t)T.size() * cube(d), 0.0, st);
-        }
+        const uint32_t need = w.tgt_degrees | (1u << D);
+        clear_proxies(need & ~prefill);
+        pl->fill_degrees_last = need;
         launch_interact(ks, fp32, true, pl->tpt_proxy, pl->qitems.as<DevItem>(), (int)w.qitems.size(),
                         pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         nullptr, deg_out(pl->phihat_deg), st);

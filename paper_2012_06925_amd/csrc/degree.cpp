@@ -226,6 +226,7 @@ int bldtt_set_degree_model(bldtt_plan* plan, const float* model, size_t n_floats
     return guarded([&] {
         DegreePolicy& p = plan->policy;
         plan->up_degrees_last = 0;           // the choice may change: no degree set to run ahead
+        plan->fill_degrees_last = 0;
         p.fallback = fallback_degree;
         p.tau = tau;
         if (!model) {
@@ -253,6 +254,7 @@ int bldtt_set_degree_test_rule(bldtt_plan* plan) {
     }
     plan->policy.mode = 2;
     plan->up_degrees_last = 0;
+    plan->fill_degrees_last = 0;
     return BLDTT_OK;
 }
 

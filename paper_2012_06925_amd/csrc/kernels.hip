@@ -520,7 +520,7 @@ struct DownLeaf {
 void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
     if (n <= 0) return;
     int64_t blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 1024) blocks = 1024;           // few groups: it may run beside a long kernel
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n, v);
     CHECK_LAUNCH();
 }

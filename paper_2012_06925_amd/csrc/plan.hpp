@@ -27,18 +27,20 @@ inline double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Device allocation owned by a plan.
+// Device allocation owned by a plan, or (alias) a view into another one.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool owned = true;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
     void alloc(size_t b) {
         release();
@@ -47,7 +49,13 @@ struct DevBuf {
         bytes = b;
     }
     void reserve(size_t b) {
-        if (b > bytes) alloc(b + b / 4);
+        if (b > bytes || !owned) alloc(b + b / 4);
+    }
+    void alias(void* q, size_t b) {
+        release();
+        p = q;
+        bytes = b;
+        owned = false;
     }
     template <class T>
     T* as() const { return static_cast<T*>(p); }
@@ -150,6 +158,8 @@ struct bldtt_plan {
     bool mfma_transfer() const { return (flags & BLDTT_VALU_PASSES) == 0; }
     bool mfma_leaf() const { return (flags & BLDTT_MFMA_LEAF) != 0; }
     PinnedBuf staging;
+    DevBuf arena, arena_near;                // device side of the per-compute uploads (one copy each)
+    uint32_t fill_degrees_last = 0;          // degrees of proxy potentials cleared by the last compute
     hipEvent_t staging_free = nullptr;
     hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
     uint32_t prof_mask = 0;                  // phases recorded by the last profiled compute
