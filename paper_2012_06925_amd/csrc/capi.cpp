@@ -274,7 +274,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
-            launch_sym(fp32, false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
+            launch_sym(fp32, pl->mfma_transfer(), false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
                        pl->sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
                        deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), pl->side);
         }
@@ -347,7 +347,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                         pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         nullptr, deg_out(pl->phihat_deg), st);
         if (symm)               // symmetric CC pairs add to the proxy potentials the pass above wrote
-            launch_sym(fp32, true, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
+            launch_sym(fp32, pl->mfma_transfer(), true, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
                        pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, nullptr, tab, deg_ptrs(pl->qhat_deg),
                        deg_out(pl->phihat_deg), st);
     }
@@ -372,7 +372,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
-            launch_sym(fp32, false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
+            launch_sym(fp32, pl->mfma_transfer(), false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
                        pl->sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
                        deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);
         }

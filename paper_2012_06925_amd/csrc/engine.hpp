@@ -137,7 +137,8 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
 // pairs listed as CC in both directions at one degree.  `rest` receives a copy
 // of L without both directions of those pairs.  The pairs with A < B are
 // packed into items over A's points in tiles of 256 (cluster = A): PP items
-// over A's particles with the merged particle ranges of A's partners, CC items
+// over A's particles with the merged particle ranges of A's partners (flagged
+// SRC_RANGE_GUARD where the two leaf boxes are near, see boxes_near), CC items
 // per (A, degree) over A's proxies with proxy entries of the partners; longest
 // first.  The evaluation counts are the kernel terms the items produce (both
 // directions).

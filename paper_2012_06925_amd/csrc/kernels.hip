@@ -233,6 +233,215 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same symmetric passes in FP32 evaluation with the squared distances on
+// the FP64 matrix cores.  With coordinates relative to the target cluster's
+// centre, |x_i - y_j|^2 = (x_i, |x_i|^2) . (-2 y_j, 1) + |y_j|^2, so one
+// v_mfma_f64_16x16x4f64 with A = (x, y, z, |x|^2) per target row, B = (-2y, 1)
+// per source column and C = |y_j|^2 gives 256 squared distances to FP64
+// accuracy (error ~1e-16 of the squared extent, far below the FP32 rounding of
+// G for every pair not closer than ~1e-4 of a leaf); the vector ALUs then take
+// per pair one conversion, one FP32 reciprocal square root and the two
+// products q_j G and q_i G.  A wave holds 64 targets as four 16-row blocks and
+// walks the sources 16 at a time, one B operand serving four products.  In
+// the result lane l holds column l mod 16 of rows l/16 + 4r: target sums are
+// per-lane partials (FP32 per chunk, then FP64) reduced over the 16 lanes of a
+// row at the end; each tile's source sums are per-lane partials written to LDS
+// and summed over the 4 lane groups and 4 waves after each chunk of up to 256
+// sources, then added with one FP64 atomic per source.  The next chunk's
+// sources are loaded into registers while the current one is evaluated.
+// Entries flagged SRC_RANGE_GUARD (leaf boxes within 2^-20 of their extent)
+// drop pairs whose computed squared distance is below the smallest normal
+// FP32 number (zero, or lost to rounding); elsewhere the box gap keeps it
+// far above.
+// ---------------------------------------------------------------------------
+constexpr int kSymChunk = 256;                  // sources per chunk: 16 tiles of 16
+constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q = 0)
+
+template <bool GUARD>
+__device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB)[64], const double* __restrict__ sN,
+                                          const float* __restrict__ sQ, float (*__restrict__ part)[64], int lane,
+                                          const double (&A)[4], const float (&qi)[4][4], float (&acc)[4][4]) {
+    const int col = lane & 15;
+    for (int t = 0; t < nt; ++t) {
+        const double bv = sB[t][lane];
+        const double n = sN[16 * t + col];
+        const float qj = sQ[16 * t + col];
+        const v4d C{n, n, n, n};
+        v4d d[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C);
+        float psi = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float rf = (float)d[b][r];
+                float y = __builtin_amdgcn_rsqf(rf);
+                if constexpr (GUARD) y = rf >= 0x1p-126f ? y : 0.0f;
+                acc[b][r] = fmaf(qj, y, acc[b][r]);
+                psi = fmaf(qi[b][r], y, psi);
+            }
+        }
+        part[t][lane] = psi;
+    }
+}
+
+template <bool PROXY>
+__global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__ items,
+                                                     const int2* __restrict__ entries, DevParticles p, DevTree T,
+                                                     double* __restrict__ phi, const double* __restrict__ tab,
+                                                     DegPtrs qhat, DegOut phihat) {
+    __shared__ double sT[4][kBlock];             // target tile: relative x, y, z and q
+    __shared__ double sB[16][64];                // B operands of the chunk's tiles, in lane order
+    __shared__ double sN[kSymChunk];             // |y|^2 of the chunk's sources
+    __shared__ float sQ[kSymChunk];              // source charges of the chunk
+    __shared__ float part[4][16][64];            // source partials per wave, tile and lane
+    const DevItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
+    const bool active = 64 * wave < it.tn;
+    const double* box = T.box + 6 * it.cluster;
+    const double cx = 0.5 * (box[0] + box[3]), cy = 0.5 * (box[1] + box[4]), cz = 0.5 * (box[2] + box[5]);
+    const int m = it.degree + 1, P = m * m * m;
+    const double* ptab = tab + 32 * it.degree;
+    const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
+    double* od = PROXY ? phihat.p[it.degree] : nullptr;
+
+    {
+        double x = kFarT, y = kFarT, z = kFarT, q = 0.0;
+        if (tid < it.tn) {
+            const int ti = it.t0 + tid;
+            if constexpr (PROXY) {
+                proxy_point(box, m, ptab, ti, x, y, z);
+                q = qd[(int64_t)it.cluster * P + ti];
+            } else {
+                x = p.x[ti];
+                y = p.y[ti];
+                z = p.z[ti];
+                q = p.q[ti];
+            }
+            x -= cx;
+            y -= cy;
+            z -= cz;
+        }
+        sT[0][tid] = x;
+        sT[1][tid] = y;
+        sT[2][tid] = z;
+        sT[3][tid] = q;
+    }
+    __syncthreads();
+    double A[4];
+    float qi[4][4], acc[4][4];
+    double acc64[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int base = 64 * wave + 16 * b;
+        if (grp < 3) {
+            A[b] = sT[grp][base + col];
+        } else {
+            const double x = sT[0][base + col], y = sT[1][base + col], z = sT[2][base + col];
+            A[b] = fma(x, x, fma(y, y, z * z));
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qi[b][r] = (float)sT[3][base + grp + 4 * r];
+            acc[b][r] = 0.0f;
+            acc64[b][r] = 0.0;
+        }
+    }
+
+    // this thread's source of a chunk (entry e, offset c0), relative to the centre
+    double nx = kFarS, ny = kFarS, nz = kFarS, nq = 0.0;
+    auto load = [&](int e, int c0) {
+        nx = kFarS;
+        ny = kFarS;
+        nz = kFarS;
+        nq = 0.0;
+        if (e >= it.ee) return;
+        const int2 en = entries[e];
+        const int bn = PROXY ? P : (en.y & ((1 << 29) - 1));
+        if (c0 + tid >= bn) return;
+        if constexpr (PROXY) {
+            proxy_point(T.box + 6 * en.x, m, ptab, c0 + tid, nx, ny, nz);
+            nq = qd[(int64_t)en.x * P + c0 + tid];
+        } else {
+            const int j = en.x + c0 + tid;
+            nx = p.x[j];
+            ny = p.y[j];
+            nz = p.z[j];
+            nq = p.q[j];
+        }
+        nx -= cx;
+        ny -= cy;
+        nz -= cz;
+    };
+    int e = it.eb, c0 = 0;
+    load(e, c0);
+    while (e < it.ee) {
+        const int2 en = entries[e];
+        const int bn = PROXY ? P : (en.y & ((1 << 29) - 1));
+        const bool guard = !PROXY && ((unsigned)en.y >> 29) == 1u;
+        const int nt = min(16, (bn - c0 + 15) >> 4);
+        {
+            const int t = tid >> 4, j = tid & 15;
+            sB[t][j] = -2.0 * nx;
+            sB[t][16 + j] = -2.0 * ny;
+            sB[t][32 + j] = -2.0 * nz;
+            sB[t][48 + j] = 1.0;
+            sN[tid] = fma(nx, nx, fma(ny, ny, nz * nz));
+            sQ[tid] = (float)nq;
+        }
+        __syncthreads();
+        int e2 = e, c2 = c0 + kSymChunk;
+        if (c2 >= bn) {
+            e2 = e + 1;
+            c2 = 0;
+        }
+        load(e2, c2);
+        if (active) {
+            if (guard) sym_tiles<true>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc);
+            else sym_tiles<false>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    acc64[b][r] += (double)acc[b][r];
+                    acc[b][r] = 0.0f;
+                }
+        }
+        __syncthreads();
+        if (c0 + tid < bn) {
+            const int t = tid >> 4, j = tid & 15;
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w)
+                if (64 * w < it.tn)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) s += (double)part[w][t][16 * k + j];
+            if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
+            else atomicAdd(phi + en.x + c0 + tid, s);
+        }
+        e = e2;
+        c0 = c2;
+    }
+    if (active) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double s = acc64[b][r];
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                v = col == 4 * b + r ? s : v;
+            }
+        const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
+        if (row < it.tn) {
+            if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
+            else atomicAdd(phi + it.t0 + row, v);
+        }
+    }
+}
+
 // Runtime-degree basis (m <= 13 nodes) for the degree-lifting kernel.
 __device__ __forceinline__ void basis1d_rt(int m, double lo, double hi, const double* __restrict__ tab, double y,
                                            double* L) {
@@ -600,9 +809,20 @@ void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, 
     CHECK_LAUNCH();
 }
 
-void launch_sym(bool fp32, bool proxies, const DevItem* items, int n_items, const int2* entries, DevParticles p,
-                DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat, hipStream_t st) {
+void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_items, const int2* entries,
+                DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
+                hipStream_t st) {
     if (n_items <= 0) return;
+    if (fp32 && mfma) {
+        if (proxies)
+            hipLaunchKernelGGL((k_sym_mfma<true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, tab,
+                               qhat, phihat);
+        else
+            hipLaunchKernelGGL((k_sym_mfma<false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi,
+                               tab, qhat, phihat);
+        CHECK_LAUNCH();
+        return;
+    }
 #define LAUNCH_SYM(F, PX) hipLaunchKernelGGL((k_sym<F, PX>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, \
                                             tab, qhat, phihat)
     if (fp32) {

@@ -75,9 +75,11 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
 // cluster A (particles, or proxies of degree item.degree) with entries of
 // partner clusters B (particle ranges, or proxy entries); every kernel value
 // adds to both sides with FP64 atomics: phi (tree order) for particles,
-// phihat.p[degree] for proxies, which already hold the other terms.
-void launch_sym(bool fp32, bool proxies, const DevItem* items, int n_items, const int2* entries, DevParticles p,
-                DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat, hipStream_t st);
+// phihat.p[degree] for proxies, which already hold the other terms.  With
+// fp32 and mfma the squared distances come from the FP64 matrix cores.
+void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_items, const int2* entries,
+                DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
+                hipStream_t st);
 
 // Per-pair relative error of degree-d proxy potentials phip[p] interpolated to
 // the particles of pair_tc[p], against exact[exact_off[p] + r].

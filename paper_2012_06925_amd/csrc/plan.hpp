@@ -155,7 +155,7 @@ struct bldtt_plan {
     std::vector<float> pe_feats, pe_errs;    // last bldtt_pair_errors result
     std::vector<int64_t> pe_pairs;
     bool varied_degree() const { return (flags & BLDTT_LEARNED_DEGREE) != 0; }
-    bool mfma_transfer() const { return (flags & BLDTT_VALU_PASSES) == 0; }
+    bool mfma_transfer() const { return (flags & BLDTT_VALU_PASSES) == 0; }   // and the FP32 symmetric passes
     bool mfma_leaf() const { return (flags & BLDTT_MFMA_LEAF) != 0; }
     PinnedBuf staging;
     DevBuf arena, arena_near;                // device side of the per-compute uploads (one copy each)

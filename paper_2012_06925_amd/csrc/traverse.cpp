@@ -201,6 +201,20 @@ ByTarget group(const Tree& T, const Lists& L, int t0, int t1, int degree) {
     return g;
 }
 
+// Two clusters of one tree whose boxes come within 2^-20 of the extent of
+// their union.  Squared distances formed as |x|^2 - 2 x.y + |y|^2 in FP64 carry
+// an error of ~1e-16 of the squared extent, so between leaves farther apart
+// they stay positive.
+bool boxes_near(const Tree& T, int64_t a, int64_t b) {
+    double d2 = 0.0, ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double gap = std::max({T.lo[3 * b + d] - T.hi[3 * a + d], T.lo[3 * a + d] - T.hi[3 * b + d], 0.0});
+        d2 += gap * gap;
+        ext = std::max(ext, std::max(T.hi[3 * a + d], T.hi[3 * b + d]) - std::min(T.lo[3 * a + d], T.lo[3 * b + d]));
+    }
+    return d2 <= 0x1p-40 * ext * ext;
+}
+
 bool boxes_touch(const Tree& T, int64_t t, const Tree& S, int64_t s) {
     for (int d = 0; d < 3; ++d)
         if (T.hi[3 * t + d] < S.lo[3 * s + d] || S.hi[3 * s + d] < T.lo[3 * t + d]) return false;
@@ -553,30 +567,20 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         std::vector<SymBlock> blks(nblk);
         parallel_run(nblk, [&](int64_t bi) {
             SymBlock& B = blks[bi];
-            std::vector<std::pair<int64_t, int64_t>> rng;
+            std::vector<std::pair<int64_t, int64_t>> rp, rg;
             for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
                 if (!T.is_leaf(a)) continue;
-                rng.clear();
                 double src = 0.0;
                 for (int64_t k = ipp.off[a]; k < ipp.off[a + 1]; ++k) {
                     const int64_t b = ipp.part[k].first;
                     if (b > a && ipp.has(b, a, 0)) {
-                        rng.emplace_back(T.begin[b], T.count[b]);
+                        (boxes_near(T, a, b) ? rg : rp).emplace_back(T.begin[b], T.count[b]);
                         src += (double)T.count[b];
                     }
                 }
-                if (rng.empty()) continue;
-                std::sort(rng.begin(), rng.end());
+                if (rp.empty() && rg.empty()) continue;
                 const int64_t eb = (int64_t)B.entries.size();
-                size_t i = 0;
-                while (i < rng.size()) {
-                    int64_t s0 = rng[i].first, s1 = rng[i].first + rng[i].second;
-                    size_t j = i + 1;
-                    while (j < rng.size() && rng[j].first == s1 && s1 - s0 + rng[j].second <= kCountMask)
-                        s1 += rng[j++].second;
-                    B.entries.push_back(Entry{(int32_t)s0, (int32_t)(s1 - s0)});
-                    i = j;
-                }
+                emit_ranges(rp, rg, B.entries);
                 const int64_t ee = (int64_t)B.entries.size();
                 B.evals += 2.0 * (double)T.count[a] * src;
                 for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {

@@ -213,6 +213,57 @@ def test_symmetric_pp_equals_one_sided(fp32):
         assert core.rel_l2(sym2, sym1) < 1e-12
 
 
+VALU_PASSES = 64
+
+
+def test_fp32_symmetric_matrix_core_distances_vs_vector_alu():
+    # FP32 symmetric passes: squared distances from the FP64 matrix cores (the
+    # default) or from FP32 differences on the vector ALUs (VALU_PASSES); both
+    # within the FP32 bound of the FP64 oracle, and close to each other
+    p = inputs.particles(60_000, "uniform", seed=53)
+    ref = core.bldtt(p, p, theta=0.8, degree=7, leaf=300)
+    out = {}
+    for name, flags in (("mfma", 1), ("valu", 1 | VALU_PASSES)):
+        plan, phi, _ = gpu_plan(p, p, True, theta=0.8, degree=7, leaf=300, flags=flags)
+        st = plan.stats()
+        plan.close()
+        assert st["pass_interactions"][2] > 0.5 * st["interactions"]["PP"]
+        out[name] = phi
+    e_m, e_v = core.rel_l2(out["mfma"], ref), core.rel_l2(out["valu"], ref)
+    print(f"\n  FP32 symmetric vs FP64 oracle: matrix-core distances {e_m:.2e}, vector-ALU {e_v:.2e}")
+    assert e_m < FP32_BOUND_CUBE and e_v < FP32_BOUND_CUBE
+    assert core.rel_l2(out["mfma"], out["valu"]) < FP32_BOUND_CUBE
+
+
+def test_fp32_symmetric_close_leaves_are_guarded():
+    # pairs of points 2e-15 apart on either side of the root's split plane x =
+    # 0.5 sit in two different leaves whose boxes nearly touch: their squared
+    # distance formed from |x|^2 - 2 x.y + |y|^2 is rounding noise, and the
+    # guarded entries drop it instead of taking a non-positive root.  Every
+    # other term is as usual.
+    rng = np.random.default_rng(62)
+    n = 20_000
+    pts = rng.uniform(0.0, 1.0, size=(3, n))
+    pts[:, 0] = 0.0
+    pts[:, 1] = 1.0                                  # root box [0, 1]^3: first split at 0.5
+    k = 16
+    yz = rng.uniform(0.1, 0.9, size=(2, k))
+    close = np.concatenate([np.stack([np.full(k, 0.5 - 1e-15), yz[0], yz[1]]),
+                            np.stack([np.full(k, 0.5 + 1e-15), yz[0], yz[1]])], axis=1)
+    xyz = np.concatenate([pts, close], axis=1)
+    q = rng.uniform(-1.0, 1.0, xyz.shape[1])
+    p = inputs.ParticleSet(xyz[0].copy(), xyz[1].copy(), xyz[2].copy(), q)
+    plan, phi32, _ = gpu_plan(p, p, True, theta=0.8, degree=5, leaf=100, flags=1)
+    st = plan.stats()
+    plan.close()
+    assert st["pass_interactions"][2] > 0
+    assert np.all(np.isfinite(phi32))
+    ref = core.bldtt(p, p, theta=0.8, degree=5, leaf=100)
+    keep = np.ones(p.n, dtype=bool)
+    keep[n:] = False
+    assert core.rel_l2(phi32[keep], ref[keep]) < FP32_BOUND_UNEQUAL
+
+
 def test_caller_stream_is_used():
     api = _api()
     p = inputs.particles(20_000, seed=51)
