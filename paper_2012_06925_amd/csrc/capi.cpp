@@ -248,7 +248,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // 2. traversal (Algorithm 2)
     do_traverse(pl);
     double tp = now_ms();
-    Lists sep;                          // per-pair degree form: the typed separated pairs
+    Lists& sep = pl->sep_lists;         // per-pair degree form: the typed separated pairs
     if (varied) {
         // 2a. The traversal deferred every separated pair, so the lists hold the
         //     near-field PP entries only.  Their particle pass starts now on the
@@ -256,7 +256,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     the rest.  It first waits for the work already on st (the
         //     previous compute still reads phi_tree).
         //     Symmetric pairs go to their own pass after it (atomic adds).
-        Lists near_rest;
+        Lists& near_rest = pl->near_rest;
         if (symm) split_symmetric(T, pl->lists, pl->degree, true, false, near_rest, pl->sym);
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
         const Work& wn = pl->work_near;
@@ -291,7 +291,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             sep.deg[k].assign(L.deg[k].begin() + n0[k], L.deg[k].end());
         }
     }
-    Lists rest;                         // the lists without their symmetric pairs
+    Lists& rest = pl->rest_lists;       // the lists without their symmetric pairs
     if (symm && !varied) split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym);
     if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep);
     const SymWork& scc = varied ? pl->sym_sep : pl->sym;          // symmetric CC pairs

@@ -120,6 +120,8 @@ struct Work {
     uint32_t src_degrees = 0, tgt_degrees = 0;  // bit d set: proxy charges / potentials of degree d used
     int down_degree = 0;                        // degree of the downward pass
     double interactions[4] = {0, 0, 0, 0};
+    void clear();                               // empty, keeping the capacity (repacking a plan
+                                                // then touches no fresh pages)
 };
 
 // tile: targets per particle item; ptile: proxies per proxy item.  Degrees come
@@ -135,7 +137,8 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
 // Symmetric pairs of a targets = sources plan (one tree): with `pp`, leaf
 // pairs (A, B), A != B, listed as PP in both directions; with `cc`, cluster
 // pairs listed as CC in both directions at one degree.  `rest` receives a copy
-// of L without both directions of those pairs.  The pairs with A < B are
+// of L's typed lists without both directions of those pairs (its deferred
+// separated pairs are left empty).  The pairs with A < B are
 // packed into items over A's points in tiles of 256 (cluster = A): PP items
 // over A's particles with the merged particle ranges of A's partners (flagged
 // SRC_RANGE_GUARD where the two leaf boxes are near, see boxes_near), CC items
@@ -146,6 +149,13 @@ struct SymWork {
     std::vector<Entry> pp_entries, cc_entries;
     std::vector<Item> pp_items, cc_items;
     double pp_evaluations = 0.0, cc_evaluations = 0.0;
+    void clear() {
+        pp_entries.clear();
+        cc_entries.clear();
+        pp_items.clear();
+        cc_items.clear();
+        pp_evaluations = cc_evaluations = 0.0;
+    }
 };
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw);
 

@@ -174,6 +174,7 @@ struct bldtt_plan {
     // symmetric PP / CC pairs (targets = sources, Coulomb): one evaluation for both directions.
     // sym: PP (and CC for a fixed degree); sym_sep: CC of the per-pair degree form
     SymWork sym, sym_sep;
+    Lists near_rest, rest_lists, sep_lists;      // per-compute list scratch, capacity kept
     DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
     bool symmetric_pp() const {
         return aliased && kind == BLDTT_COULOMB && (flags & BLDTT_ONE_SIDED_PP) == 0;

@@ -279,18 +279,41 @@ void append_blocks(std::vector<Block>& blocks, std::vector<Entry>& entries, std:
     }
 }
 
-void sort_items(std::vector<std::pair<double, Item>>& items, std::vector<Item>& out) {
+void sort_items(const std::vector<std::pair<double, Item>>& items, std::vector<Item>& out) {
     // Longest items first: the tail of the grid is then made of short items.
-    std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
-    out.reserve(items.size());
-    for (auto& it : items) out.push_back(it.second);
+    // A stable counting sort on the cost's exponent and top three mantissa
+    // bits (eighth-octave classes, descending): linear time, and the order
+    // among items of one class is their input order.
+    constexpr int kClasses = 2048;
+    auto code = [](double c) { return c > 0.0 ? (int64_t)(__builtin_bit_cast(uint64_t, c) >> 49) : (int64_t)0; };
+    int64_t top = 0;
+    for (auto& it : items) top = std::max(top, code(it.first));
+    auto cls = [&](double c) { return (int)std::min<int64_t>(kClasses - 1, top - code(c)); };
+    std::vector<int64_t> start(kClasses + 1, 0);
+    for (auto& it : items) start[cls(it.first) + 1]++;
+    for (int k = 0; k < kClasses; ++k) start[k + 1] += start[k];
+    const size_t o = out.size();
+    out.resize(o + items.size());
+    for (auto& it : items) out[o + start[cls(it.first)]++] = it.second;
 }
 
 }  // namespace
 
+void Work::clear() {
+    pentries.clear();
+    pitems.clear();
+    qentries.clear();
+    qitems.clear();
+    leaf_has_far.clear();
+    prolong.clear();
+    src_degrees = tgt_degrees = 0;
+    down_degree = 0;
+    for (double& v : interactions) v = 0.0;
+}
+
 void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int tile, int ptile, Work& w,
                const std::vector<uint32_t>* extra) {
-    w = Work();
+    w.clear();
     auto deg_of = [&](int ty, size_t e) { return L.deg[ty].empty() ? degree : (int)L.deg[ty][e]; };
     for (int ty = 0; ty < 4; ++ty) {
         const int64_t n = (int64_t)L.tc[ty].size();
@@ -429,7 +452,7 @@ namespace {
 // Pairs of one type as CSR by target cluster: partner key (source cluster,
 // degree) sorted per target; only pairs accepted by `take`.
 struct PairIndex {
-    std::vector<int64_t> off;
+    std::vector<int64_t> off, cnt;
     std::vector<std::pair<int64_t, int>> part;
     template <class F>
     void build(int64_t nc, const std::vector<int64_t>& tc, const std::vector<int64_t>& sc, const std::vector<int8_t>& dg,
@@ -439,7 +462,7 @@ struct PairIndex {
         const int64_t n = (int64_t)tc.size();
         const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), n / 16384 + 1));
         const int64_t per = (n + nch - 1) / nch;
-        std::vector<int64_t> cnt(nch * nc, 0);
+        cnt.assign(nch * nc, 0);
         parallel_run(nch, [&](int64_t k) {
             int64_t* c = cnt.data() + k * nc;
             for (int64_t e = k * per; e < std::min(n, (k + 1) * per); ++e)
@@ -479,7 +502,8 @@ struct SymBlock {
 };
 
 void gather(std::vector<SymBlock>& blks, std::vector<Entry>& entries, std::vector<Item>& out, double& evals) {
-    std::vector<std::pair<double, Item>> items;
+    static thread_local std::vector<std::pair<double, Item>> items;     // kept: no fresh pages per call
+    items.clear();
     for (auto& B : blks) {
         const int32_t shift = (int32_t)entries.size();
         entries.insert(entries.end(), B.entries.begin(), B.entries.end());
@@ -490,9 +514,7 @@ void gather(std::vector<SymBlock>& blks, std::vector<Entry>& entries, std::vecto
         }
         evals += B.evals;
     }
-    std::stable_sort(items.begin(), items.end(), [](auto& x, auto& y) { return x.first > y.first; });
-    out.reserve(items.size());
-    for (auto& it : items) out.push_back(it.second);
+    sort_items(items, out);
 }
 
 }  // namespace
@@ -505,11 +527,16 @@ std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw) {
 }
 
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw) {
-    sw = SymWork();
+    sw.clear();
     const int64_t nc = T.size();
     constexpr int64_t kBlk = 256, kTile = 256;
     const int64_t nblk = (nc + kBlk - 1) / kBlk;
-    PairIndex ipp, icc;
+    // kept per calling thread, so a plan repacked every compute touches no fresh
+    // pages; the workers reach the caller's copies through these references
+    static thread_local PairIndex tl_ipp, tl_icc;
+    static thread_local std::vector<uint8_t> tl_keep;
+    PairIndex &ipp = tl_ipp, &icc = tl_icc;
+    std::vector<uint8_t>& keep = tl_keep;
     const std::vector<int8_t> no_degrees;        // PP pairs are matched without their degree
     if (pp)
         ipp.build(nc, L.tc[PP], L.sc[PP], no_degrees, 0,
@@ -533,7 +560,7 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         }
         const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), n / 16384 + 1));
         const int64_t per = (n + nch - 1) / nch;
-        std::vector<uint8_t> keep(n);
+        keep.resize(n);
         std::vector<int64_t> kept(nch + 1, 0);
         parallel_run(nch, [&](int64_t c) {
             int64_t m = 0;
@@ -560,8 +587,8 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
             }
         });
     }
-    rest.sep_tc = L.sep_tc;
-    rest.sep_sc = L.sep_sc;
+    rest.sep_tc.clear();
+    rest.sep_sc.clear();
     if (pp) {
         // per leaf A: the partners B > A as merged particle ranges, tiles of A's particles
         std::vector<SymBlock> blks(nblk);
