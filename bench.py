@@ -148,9 +148,11 @@ class Bench:
         # the particle pass (near-field PP in the per-pair degree form), its
         # second pass (separated pairs' PP/PC), the symmetric PP pass (both
         # directions counted: the algorithmic count; it evaluates G once per
-        # pair of particles), and the proxy pass
+        # pair of particles), the proxy pass, and the pass over each leaf with
+        # itself that runs before the traversal
         work = {"pp_pc": st["pass_interactions"][0] * fl, "pp_pc_sep": st["pass_interactions"][1] * fl,
-                "pp_sym": st["pass_interactions"][2] * fl, "cp_cc": (inter["CP"] + inter["CC"]) * fl}
+                "pp_sym": st["pass_interactions"][2] * fl, "cp_cc": (inter["CP"] + inter["CC"]) * fl,
+                "pp_self": st["pass_interactions"][4] * fl}
         dom = max(work, key=lambda k: phase[k])
         achieved = work[dom] / (phase[dom] * 1e-3) / 1e12
         fp32 = mode != "plain"

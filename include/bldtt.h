@@ -183,9 +183,11 @@ int bldtt_get_phihat(const bldtt_plan *plan, double *host_out);
  * near-field PP entries only, it runs on a second stream while the host
  * chooses the per-pair degrees, and PPPC_SEP is the second particle pass that
  * adds the separated pairs' PP/PC terms.  PP_SYM is the pass over the PP pairs
- * evaluated once for both directions (see BLDTT_ONE_SIDED_PP). */
+ * evaluated once for both directions (see BLDTT_ONE_SIDED_PP).  PP_SELF, in
+ * the same symmetric plans, is the pass over every leaf paired with itself;
+ * it runs first, before the traversal (its list is known at setup). */
 enum { BLDTT_PH_UP = 0, BLDTT_PH_CPCC = 1, BLDTT_PH_DOWN_TRANSFER = 2, BLDTT_PH_PPPC = 3, BLDTT_PH_DOWN_LEAF = 4,
-       BLDTT_PH_PPPC_SEP = 5, BLDTT_PH_PP_SYM = 6, BLDTT_N_PHASES = 7 };
+       BLDTT_PH_PPPC_SEP = 5, BLDTT_PH_PP_SYM = 6, BLDTT_PH_PP_SELF = 7, BLDTT_N_PHASES = 8 };
 
 typedef struct {
     int64_t n_entries[4];          /* list lengths PP, PC, CP, CC                        */
@@ -204,9 +206,9 @@ typedef struct {
     int64_t sep_fallback;          /*   of which outside the model's range (fallback)    */
     int64_t sep_direct;            /*   of which evaluated directly (PP chosen)          */
     int64_t pairs_per_degree[13];  /*   approximated pairs per degree                     */
-    double pass_interactions[4];   /* kernel terms of the PPPC, PPPC_SEP and PP_SYM passes
-                                      and of the symmetric CC pairs (symmetric: both
-                                      directions counted)                                */
+    double pass_interactions[5];   /* kernel terms of the PPPC, PPPC_SEP and PP_SYM passes,
+                                      of the symmetric CC pairs (symmetric: both
+                                      directions counted) and of the PP_SELF pass        */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the

@@ -21,7 +21,7 @@ KERNELS = {"coulomb": 0, "yukawa": 1, "oscillatory": 2, "regcoulomb": 3, "poly":
 DEFAULT_PARAM = {"coulomb": 0.0, "yukawa": 0.5, "oscillatory": 0.0, "regcoulomb": 0.005, "poly": 0.0}
 FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE, VALU_PASSES, MFMA_LEAF, ONE_SIDED_PP = (
     1, 2, 4, 8, 16, 32, 64, 128, 256)
-PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf", "pp_pc_sep", "pp_sym")
+PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf", "pp_pc_sep", "pp_sym", "pp_self")
 TYPES = ("PP", "PC", "CP", "CC")
 
 _D = C.POINTER(C.c_double)
@@ -46,10 +46,10 @@ class Stats(C.Structure):
                 ("n_target_clusters", C.c_int64), ("n_source_clusters", C.c_int64),
                 ("target_depth", C.c_int32), ("source_depth", C.c_int32),
                 ("setup_ms", C.c_double), ("traverse_ms", C.c_double), ("compute_host_ms", C.c_double),
-                ("phase_ms", C.c_double * 7), ("profiled_computes", C.c_int64),
+                ("phase_ms", C.c_double * 8), ("profiled_computes", C.c_int64),
                 ("down_degree", C.c_int32), ("degree_mask", C.c_uint32), ("sep_pairs", C.c_int64),
                 ("sep_fallback", C.c_int64), ("sep_direct", C.c_int64), ("pairs_per_degree", C.c_int64 * 13),
-                ("pass_interactions", C.c_double * 4)]
+                ("pass_interactions", C.c_double * 5)]
 
 
 class BatchStats(C.Structure):

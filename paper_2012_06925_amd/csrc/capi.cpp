@@ -208,6 +208,41 @@ struct Upload {
     }
 };
 
+// The self pairs of a symmetric plan, packed for particle tiles of `tile`.
+void ensure_self_work(bldtt_plan* pl, int tile, int ptile) {
+    if (pl->self_tile == tile) return;
+    const Tree& T = pl->T();
+    Lists L;
+    double evals = 0.0;
+    for (int64_t c = 0; c < T.size(); ++c)
+        if (T.is_leaf(c)) {
+            L.push(PP, c, c, pl->degree);
+            evals += (double)T.count[c] * (double)T.count[c];
+        }
+    pack_work(T, pl->S, L, pl->degree, tile, ptile, pl->self_work);
+    upload_bytes(pl->self_items, pl->self_work.pitems.data(), sizeof(Item) * pl->self_work.pitems.size());
+    upload_bytes(pl->self_entries, pl->self_work.pentries.data(), sizeof(Entry) * pl->self_work.pentries.size());
+    pl->self_evaluations = evals;
+    pl->self_tile = tile;
+}
+
+// Remove the self pairs (c, c) from the PP list.
+void drop_self_pairs(Lists& L) {
+    auto &tc = L.tc[PP], &sc = L.sc[PP];
+    auto& dg = L.deg[PP];
+    size_t o = 0;
+    for (size_t e = 0; e < tc.size(); ++e) {
+        if (tc[e] == sc[e]) continue;
+        tc[o] = tc[e];
+        sc[o] = sc[e];
+        if (!dg.empty()) dg[o] = dg[e];
+        ++o;
+    }
+    tc.resize(o);
+    sc.resize(o);
+    if (!dg.empty()) dg.resize(o);
+}
+
 void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     double t0 = now_ms();
     const Tree& T = pl->T();
@@ -244,6 +279,15 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
     };
     clear_proxies(prefill);
+    // ... and the self pairs of the leaves (known before the traversal) write
+    // the particle potentials first; every later particle pass adds
+    if (symm) {
+        ensure_self_work(pl, tile, ptile);
+        PhaseMark mark(pl, BLDTT_PH_PP_SELF, st);
+        launch_interact(ks, fp32, false, pl->tpt, pl->self_items.as<DevItem>(), (int)pl->self_work.pitems.size(),
+                        pl->self_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                        pl->phi_tree.as<double>(), DegOut{}, st);
+    }
 
     // 2. traversal (Algorithm 2)
     do_traverse(pl);
@@ -257,7 +301,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     previous compute still reads phi_tree).
         //     Symmetric pairs go to their own pass after it (atomic adds).
         Lists& near_rest = pl->near_rest;
-        if (symm) split_symmetric(T, pl->lists, pl->degree, true, false, near_rest, pl->sym);
+        if (symm) {
+            split_symmetric(T, pl->lists, pl->degree, true, false, near_rest, pl->sym);
+            drop_self_pairs(near_rest);
+        }
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
         const Work& wn = pl->work_near;
         HIPCHK(hipEventRecord(pl->ev_fork, st));
@@ -270,7 +317,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
             launch_interact(ks, fp32, false, pl->tpt, pl->near_items.as<DevItem>(), (int)wn.pitems.size(),
                             pl->near_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                            pl->phi_tree.as<double>(), DegOut{}, pl->side);
+                            pl->phi_tree.as<double>(), DegOut{}, pl->side, symm);
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
@@ -292,7 +339,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
     }
     Lists& rest = pl->rest_lists;       // the lists without their symmetric pairs
-    if (symm && !varied) split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym);
+    if (symm && !varied) {
+        split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym);
+        drop_self_pairs(rest);
+    }
     if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep);
     const SymWork& scc = varied ? pl->sym_sep : pl->sym;          // symmetric CC pairs
     std::vector<uint32_t> scc_deg;
@@ -306,15 +356,17 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             if (it.ee > it.eb) sep_items.push_back(it);
     pl->stats.traverse_ms += now_ms() - tp;
     const double sym_w = symm ? pl->sym.pp_evaluations : 0.0, sym_c = symm ? scc.cc_evaluations : 0.0;
+    const double self_w = symm ? pl->self_evaluations : 0.0;
     for (int k = 0; k < 4; ++k)
         pl->stats.interactions[k] = w.interactions[k] + (varied ? pl->work_near.interactions[k] : 0.0);
-    pl->stats.interactions[PP] += sym_w;
+    pl->stats.interactions[PP] += sym_w + self_w;
     pl->stats.interactions[CC] += sym_c;
     const double pass_w = w.interactions[PP] + w.interactions[PC];
     pl->stats.pass_interactions[0] = varied ? pl->work_near.interactions[PP] : pass_w;
     pl->stats.pass_interactions[1] = varied ? pass_w : 0.0;
     pl->stats.pass_interactions[2] = sym_w;
     pl->stats.pass_interactions[3] = sym_c;
+    pl->stats.pass_interactions[4] = self_w;
     pl->stats.down_degree = w.down_degree;
     pl->stats.degree_mask = w.src_degrees | w.tgt_degrees;
     Upload up;
@@ -368,7 +420,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             PhaseMark mark(pl, BLDTT_PH_PPPC, st);
             launch_interact(ks, fp32, false, pl->tpt, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
                             pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                            pl->phi_tree.as<double>(), DegOut{}, st);
+                            pl->phi_tree.as<double>(), DegOut{}, st, symm);
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
@@ -453,6 +505,7 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     if (pl->flags & BLDTT_PROFILE)
         for (auto& e : pl->prof_ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(pl->staging_free, st));
+    if (pl->symmetric_pp()) ensure_self_work(pl, kBlockThreads * pl->tpt, kBlockThreads * pl->tpt_proxy);
     fill_stats_tree(pl);
     pl->stats.setup_ms = now_ms() - t0;
 }
