@@ -165,7 +165,8 @@ class Bench:
         rec = {"mode": mode, "theta": theta, "degree": degree, "particles_per_s": self.M / (ms * 1e-3),
                "ms_per_step": round(ms, 3), "wall_ms_per_step": round(wall_ms, 3), "error_vs_direct": err,
                "setup_ms": round(setup_ms, 1), "phase_ms": {k: round(v, 4) for k, v in phase.items()},
-               "traverse_ms": round(st["traverse_ms"], 3), "interactions": inter, "n_entries": st["n_entries"],
+               "traverse_ms": round(st["traverse_ms"], 3), "host_marks_ms": [round(v, 3) for v in st["host_marks_ms"]],
+               "interactions": inter, "n_entries": st["n_entries"],
                "roofline": roof}
         if mode == "tuned":
             rec.update(tau=tau, sep_pairs=st["sep_pairs"], sep_direct=st["sep_direct"],

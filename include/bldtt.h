@@ -209,6 +209,11 @@ typedef struct {
     double pass_interactions[5];   /* kernel terms of the PPPC, PPPC_SEP and PP_SYM passes,
                                       of the symmetric CC pairs (symmetric: both
                                       directions counted) and of the PP_SELF pass        */
+    double host_marks_ms[4];       /* host ms from the start of the last compute (after
+                                      any wait for the previous one's profile events) to:
+                                      the upward and self-pair launches enqueued, the
+                                      traversal done, the first pass over its lists
+                                      enqueued, and the return                           */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the

@@ -256,15 +256,17 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const int tile = kBlockThreads * pl->tpt, ptile = kBlockThreads * pl->tpt_proxy;
 
     collect_profile(pl);
+    t0 = now_ms();
+    auto mark_host = [&](int k) { pl->stats.host_marks_ms[k] = now_ms() - t0; };
     // 1. upward pass, overlapping the host traversal: at the base degree, or
     //    for a per-pair degree plan at the source degrees its last compute used
     //    (the same particles give the same choice); degrees missing from that
     //    set follow once the degrees are chosen
     const uint32_t pre = varied ? pl->up_degrees_last : (1u << pl->degree);
+    int have = -1;                      // degree whose charges are complete (the others restrict from it)
     if (pre) {
         PhaseMark mark(pl, BLDTT_PH_UP, st);
-        for (int d = 0; d <= kMaxDegree; ++d)
-            if (pre >> d & 1) upward(pl, d, st);
+        have = upward_degrees(pl, pre, -1, st);
     }
     // ... and the proxy potentials are cleared now as well, for the degrees the
     // last compute used (later kernels would otherwise wait for these small
@@ -289,8 +291,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                         pl->phi_tree.as<double>(), DegOut{}, st);
     }
 
+    mark_host(0);
     // 2. traversal (Algorithm 2)
     do_traverse(pl);
+    mark_host(1);
     double tp = now_ms();
     Lists& sep = pl->sep_lists;         // per-pair degree form: the typed separated pairs
     if (varied) {
@@ -326,6 +330,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                        deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), pl->side);
         }
         HIPCHK(hipEventRecord(pl->ev_near_done, pl->side));
+        mark_host(2);
         // 2b. per-pair (type, degree); select_degrees appends the typed pairs to
         //     the lists, the second pass packs those alone
         size_t n0[4];
@@ -381,8 +386,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         const uint32_t rest = w.src_degrees & ~pre;
         if (rest) {
             PhaseMark mark(pl, BLDTT_PH_UP, st);
-            for (int d = 0; d <= kMaxDegree; ++d)
-                if (rest >> d & 1) upward(pl, d, st);
+            upward_degrees(pl, rest, have, st);
         }
         pl->up_degrees_last = w.src_degrees;
     }
@@ -391,6 +395,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     //    downward transfer from the root
     const int D = w.down_degree;
     {
+        if (!varied) mark_host(2);
         PhaseMark mark(pl, BLDTT_PH_CPCC, st);
         const uint32_t need = w.tgt_degrees | (1u << D);
         clear_proxies(need & ~prefill);
@@ -445,6 +450,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     if (pl->flags & BLDTT_PROFILE) pl->prof_pending = true;
     if (pl->flags & BLDTT_SYNC) HIPCHK(hipStreamSynchronize(st));
     pl->stats.compute_host_ms = now_ms() - t0;
+    mark_host(3);
 }
 
 void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
@@ -560,6 +566,23 @@ void upward(bldtt_plan* pl, int d, hipStream_t st) {
         int64_t b = pl->up_off[l], e = pl->up_off[l + 1];
         launch_up_transfer(d, pl->mfma_transfer(), pl->up_parents.as<int32_t>() + b, (int)(e - b), dS, tab, q.as<double>(), st);
     }
+}
+
+int upward_degrees(bldtt_plan* pl, uint32_t mask, int have, hipStream_t st) {
+    if (!mask) return have;
+    const int top = 31 - __builtin_clz(mask);
+    if (have < top) {
+        upward(pl, top, st);
+        have = top;
+    }
+    mask &= ~(1u << have);
+    if (mask) {
+        for (int d = 0; d < have; ++d)
+            if (mask >> d & 1) pl->qhat_deg[d].reserve(sizeof(double) * pl->S.size() * cube(d));
+        launch_restrict((int)pl->S.size(), pl->dS.view(), pl->tab.as<double>(), pl->qhat_deg[have].as<double>(),
+                        have, deg_out(pl->qhat_deg), mask, st);
+    }
+    return have;
 }
 
 DegPtrs deg_ptrs(const DevBuf* bufs) {

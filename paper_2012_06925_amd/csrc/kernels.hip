@@ -520,6 +520,64 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const DevItem* __restrict__ 
 
 
 // ---------------------------------------------------------------------------
+// Degree restriction of proxy charges: a cluster's degree-d charges follow
+// exactly from its degree-D charges (d < D).  Each degree-d Lagrange
+// polynomial of the cluster's grid has degree d <= D, so it equals its own
+// degree-D interpolant, L^d_k = sum_m L^d_k(s^D_m) L^D_m, and summing over
+// the cluster's particles gives qhat_d[k] = sum_m L^d_k(s^D_m) qhat_D[m], per
+// axis -- the transpose of the lifting in k_prolong.  One work group per
+// cluster; the bit mask holds the degrees d to form.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_restrict(DevTree T, const double* __restrict__ tab,
+                                                     const double* __restrict__ from, int D, DegOut to,
+                                                     unsigned mask) {
+    constexpr int MX = 13;
+    __shared__ double mat[3][MX][MX];              // mat[dim][k (degree d)][kb (degree D)]
+    __shared__ double a[MX * MX * MX], b[MX * MX * MX], e[MX * MX * MX];
+    const int c = blockIdx.x;
+    const int mD = D + 1, PD = mD * mD * mD;
+    const double* box = T.box + 6 * c;
+    const double* tabD = tab + 32 * D;
+    for (int k = threadIdx.x; k < PD; k += kBlock) a[k] = from[(int64_t)c * PD + k];
+    for (int d = 0; d < D; ++d) {
+        if (!(mask >> d & 1u)) continue;
+        const int md = d + 1, Pd = md * md * md;
+        const double* tabd = tab + 32 * d;
+        __syncthreads();
+        if ((int)threadIdx.x < 3 * mD) {
+            int dim = threadIdx.x / mD, kb = threadIdx.x % mD;
+            double L[MX];
+            basis1d_rt(md, box[dim], box[3 + dim], tabd, node_at(box[dim], box[3 + dim], tabD[kb]), L);
+            for (int k = 0; k < md; ++k) mat[dim][k][kb] = L[k];
+        }
+        __syncthreads();
+        // x: (mD, mD, mD) -> (md, mD, mD)
+        for (int idx = threadIdx.x; idx < md * mD * mD; idx += kBlock) {
+            int k = idx % md, rest = idx / md;
+            double s = 0.0;
+            for (int kb = 0; kb < mD; ++kb) s = fma(mat[0][k][kb], a[kb + mD * rest], s);
+            b[idx] = s;
+        }
+        __syncthreads();
+        // y: (md, mD, mD) -> (md, md, mD)
+        for (int idx = threadIdx.x; idx < md * md * mD; idx += kBlock) {
+            int k1 = idx % md, k = (idx / md) % md, i3 = idx / (md * md);
+            double s = 0.0;
+            for (int kb = 0; kb < mD; ++kb) s = fma(mat[1][k][kb], b[k1 + md * (kb + mD * i3)], s);
+            e[idx] = s;
+        }
+        __syncthreads();
+        // z: (md, md, mD) -> (md, md, md)
+        for (int idx = threadIdx.x; idx < Pd; idx += kBlock) {
+            int k12 = idx % (md * md), k = idx / (md * md);
+            double s = 0.0;
+            for (int kb = 0; kb < mD; ++kb) s = fma(mat[2][k][kb], e[k12 + md * md * kb], s);
+            to.p[d][(int64_t)c * Pd + idx] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-pair error of the degree-d cluster-cluster approximation (training data
 // for the degree model): for separated pair p = (tc, sc), the pair's proxy
 // potentials phip[p] (target grid of tc, degree d) are interpolated to the
@@ -833,6 +891,13 @@ void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_
         else LAUNCH_SYM(false, false);
     }
 #undef LAUNCH_SYM
+    CHECK_LAUNCH();
+}
+
+void launch_restrict(int n_clusters, DevTree T, const double* tab, const double* from, int D, DegOut to,
+                     uint32_t mask, hipStream_t st) {
+    if (n_clusters <= 0 || mask == 0) return;
+    hipLaunchKernelGGL(k_restrict, dim3(n_clusters), dim3(kBlock), 0, st, T, tab, from, D, to, (unsigned)mask);
     CHECK_LAUNCH();
 }
 

@@ -81,6 +81,11 @@ void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_
                 DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
                 hipStream_t st);
 
+// Proxy charges of every degree d < D in mask, restricted exactly from the
+// degree-D charges of each of the n_clusters clusters of T: to.p[d][c].
+void launch_restrict(int n_clusters, DevTree T, const double* tab, const double* from, int D, DegOut to,
+                     uint32_t mask, hipStream_t st);
+
 // Per-pair relative error of degree-d proxy potentials phip[p] interpolated to
 // the particles of pair_tc[p], against exact[exact_off[p] + r].
 void launch_pair_error(int degree, const int32_t* pair_tc, int n_pairs, const int64_t* exact_off,

@@ -212,6 +212,11 @@ namespace bldtt {
 void select_degrees(bldtt_plan* pl, hipStream_t st);
 // Proxy charges of every source cluster at degree d into plan->qhat_deg[d].
 void upward(bldtt_plan* pl, int d, hipStream_t st);
+// Proxy charges of every degree in mask: the largest from the particles
+// (upward pass) unless the charges of a degree `have` at least as large are
+// complete already, the others restricted exactly from that degree.  Returns
+// the degree the charges came from (have, or the one computed).
+int upward_degrees(bldtt_plan* pl, uint32_t mask, int have, hipStream_t st);
 DegPtrs deg_ptrs(const DevBuf* bufs);
 DegOut deg_out(DevBuf* bufs);
 }  // namespace bldtt

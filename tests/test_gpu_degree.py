@@ -60,6 +60,10 @@ def test_mixed_degrees_match_oracle(case):
     err = core.rel_l2(phi, ref)
     print(f"\n  mixed degrees {case}: mask={st['degree_mask']:#x} down={st['down_degree']} gpu-vs-oracle={err:.2e}")
     assert err < 1e-12
+    # the next compute forms the charges of the last compute's degrees before
+    # the traversal (the largest from the particles, the rest by restriction)
+    phi2 = plan.compute().cpu().numpy()
+    assert core.rel_l2(phi2, ref) < 1e-12
 
 
 def test_fallback_policy_equals_plain_method():
