@@ -32,6 +32,22 @@ __device__ __forceinline__ void normalise(const float* __restrict__ M, const flo
     for (int k = 0; k < kNIn; ++k) x[k] = (f[k] - mean[k]) * scale[k];
 }
 
+// tanh(s) = sign(s) (1 - e^{-2|s|}) / (1 + e^{-2|s|}), branch free from the
+// hardware 2^x and reciprocal (absolute error ~1e-7; exactly +-1 once e^{-2|s|}
+// underflows).
+__device__ __forceinline__ float fast_tanh(float s) {
+    const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(s));
+    return copysignf((1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t), s);
+}
+
+// The model in LDS: all lanes read the same weight at once (a broadcast), and
+// the 20 KB of weights would not stay in the scalar cache.
+__device__ __forceinline__ const float* stage_model(const float* __restrict__ M, float* sM) {
+    for (int k = threadIdx.x; k < kNModel; k += kBlock) sM[k] = M[k];
+    __syncthreads();
+    return sM;
+}
+
 // Forward pass of one sample; a1, a2 receive the hidden activations when non-null.
 __device__ __forceinline__ void forward(const float* __restrict__ M, const float* x, float* y, float* a1,
                                         float* a2) {
@@ -41,7 +57,7 @@ __device__ __forceinline__ void forward(const float* __restrict__ M, const float
         float s = M[kOffB1 + o];
 #pragma unroll
         for (int k = 0; k < kNIn; ++k) s = fmaf(M[kOffW1 + o * kNIn + k], x[k], s);
-        h1[o] = tanhf(s);
+        h1[o] = fast_tanh(s);
         if (a1) a1[o] = h1[o];
     }
 #pragma unroll
@@ -50,7 +66,7 @@ __device__ __forceinline__ void forward(const float* __restrict__ M, const float
         float s = M[kOffB2 + j];
 #pragma unroll
         for (int i = 0; i < kNHid; ++i) s = fmaf(M[kOffW2 + j * kNHid + i], h1[i], s);
-        float a = tanhf(s);
+        float a = fast_tanh(s);
         if (a2) a2[j] = a;
 #pragma unroll
         for (int k = 0; k < kNOut; ++k) y[k] = fmaf(M[kOffW3 + k * kNHid + j], a, y[k]);
@@ -82,6 +98,8 @@ __device__ __forceinline__ double pair_cost(int type, int64_t ct, int64_t cs, in
 __global__ __launch_bounds__(kBlock) void k_mlp_select(const float* __restrict__ M, const float* __restrict__ feats,
                                                        const int64_t* __restrict__ counts, int64_t n, float log_tau,
                                                        int fallback, int pp_cc_only, uint8_t* __restrict__ choice) {
+    __shared__ float sM[kNModel];
+    M = stage_model(M, sM);
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const int64_t ct = counts[2 * p], cs = counts[2 * p + 1];
@@ -119,6 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_select(const float* __restrict__
 
 __global__ __launch_bounds__(kBlock) void k_mlp_forward(const float* __restrict__ M, const float* __restrict__ feats,
                                                         int64_t n, float* __restrict__ out) {
+    __shared__ float sM[kNModel];
+    M = stage_model(M, sM);
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     float f[kNIn], x[kNIn], y[kNOut];
@@ -142,6 +162,8 @@ struct WorkView {
 __global__ __launch_bounds__(kBlock) void k_train_forward(const float* __restrict__ M, const float* __restrict__ feats,
                                                           const float* __restrict__ tgt, int64_t n, float inv_valid,
                                                           float* __restrict__ work) {
+    __shared__ float sM[kNModel];
+    M = stage_model(M, sM);
     const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (b >= n) return;
     WorkView w(work, n);
