@@ -303,34 +303,42 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     second stream and overlaps the degree choice and the packing of
         //     the rest.  It first waits for the work already on st (the
         //     previous compute still reads phi_tree).
-        //     Symmetric pairs go to their own pass after it (atomic adds).
+        //     Symmetric pairs go to their own pass (atomic adds), launched as
+        //     soon as their items are packed; the remaining near-field pairs
+        //     (few: those listed one way only) follow on the same stream.
         Lists& near_rest = pl->near_rest;
+        auto fork = [&] {
+            HIPCHK(hipEventRecord(pl->ev_fork, st));
+            HIPCHK(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
+        };
         if (symm) {
-            split_symmetric(T, pl->lists, pl->degree, true, false, near_rest, pl->sym);
+            split_symmetric(T, pl->lists, pl->degree, true, false, near_rest, pl->sym, [&] {
+                fork();
+                Upload us;
+                us.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
+                us.run(pl->staging_near, pl->arena_near, pl->staging_near_free, pl->side);
+                PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
+                launch_sym(fp32, pl->mfma_transfer(), false, pl->sym_items.as<DevItem>(),
+                           (int)pl->sym.pp_items.size(), pl->sym_entries.as<int2>(), pl->dsrc(), dS,
+                           pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), pl->side);
+                mark_host(2);
+            });
             drop_self_pairs(near_rest);
         }
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
         const Work& wn = pl->work_near;
-        HIPCHK(hipEventRecord(pl->ev_fork, st));
-        HIPCHK(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
+        if (!symm) fork();
         Upload un;
         un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
-        if (symm) un.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
-        un.run(pl->staging_near, pl->arena_near, pl->staging_near_free, pl->side);
+        un.run(pl->staging_rest, pl->arena_rest, pl->staging_rest_free, pl->side);
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
             launch_interact(ks, fp32, false, pl->tpt, pl->near_items.as<DevItem>(), (int)wn.pitems.size(),
                             pl->near_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                             pl->phi_tree.as<double>(), DegOut{}, pl->side, symm);
         }
-        if (symm) {
-            PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
-            launch_sym(fp32, pl->mfma_transfer(), false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
-                       pl->sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
-                       deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), pl->side);
-        }
         HIPCHK(hipEventRecord(pl->ev_near_done, pl->side));
-        mark_host(2);
+        if (!symm) mark_host(2);
         // 2b. per-pair (type, degree); select_degrees appends the typed pairs to
         //     the lists, the second pass packs those alone
         size_t n0[4];
@@ -504,10 +512,12 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     pl->phi_tree.alloc(sizeof(double) * M);
     HIPCHK(hipEventCreateWithFlags(&pl->staging_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->staging_near_free, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->staging_rest_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_near_done, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
     HIPCHK(hipEventRecord(pl->staging_near_free, st));
+    HIPCHK(hipEventRecord(pl->staging_rest_free, st));
     if (pl->flags & BLDTT_PROFILE)
         for (auto& e : pl->prof_ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(pl->staging_free, st));

@@ -157,7 +157,10 @@ struct SymWork {
         pp_evaluations = cc_evaluations = 0.0;
     }
 };
-void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw);
+// pp_ready, when given, is called as soon as the PP items are complete (before
+// `rest` and the CC items are formed), so their pass can start early.
+void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
+                     const std::function<void()>& pp_ready = {});
 
 // Per-cluster degree masks of the symmetric CC pairs (both clusters of each pair).
 std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw);

@@ -158,7 +158,7 @@ struct bldtt_plan {
     bool mfma_transfer() const { return (flags & BLDTT_VALU_PASSES) == 0; }   // and the FP32 symmetric passes
     bool mfma_leaf() const { return (flags & BLDTT_MFMA_LEAF) != 0; }
     PinnedBuf staging;
-    DevBuf arena, arena_near;                // device side of the per-compute uploads (one copy each)
+    DevBuf arena, arena_near, arena_rest;                // device side of the per-compute uploads (one copy each)
     uint32_t fill_degrees_last = 0;          // degrees of proxy potentials cleared by the last compute
     hipEvent_t staging_free = nullptr;
     hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
@@ -167,8 +167,8 @@ struct bldtt_plan {
     // Per-pair degree form: the near-field PP pass runs on a second stream
     // while the host chooses the degrees (capi.cpp, compute).
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_near_done = nullptr, staging_near_free = nullptr;
-    PinnedBuf staging_near;
+    hipEvent_t ev_fork = nullptr, ev_near_done = nullptr, staging_near_free = nullptr, staging_rest_free = nullptr;
+    PinnedBuf staging_near, staging_rest;
     Work work_near;
     DevBuf near_items, near_entries, sep_items;
     // symmetric PP / CC pairs (targets = sources, Coulomb): one evaluation for both directions.
@@ -197,7 +197,7 @@ struct bldtt_plan {
     ~bldtt_plan() {
         if (policy.dev_model) (void)hipFree(policy.dev_model);
         if (staging_free) (void)hipEventDestroy(staging_free);
-        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free})
+        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free})
             if (e) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
         for (auto& e : prof_ev)

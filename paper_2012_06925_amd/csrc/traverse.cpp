@@ -526,7 +526,8 @@ std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw) {
     return m;
 }
 
-void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw) {
+void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
+                     const std::function<void()>& pp_ready) {
     sw.clear();
     const int64_t nc = T.size();
     constexpr int64_t kBlk = 256, kTile = 256;
@@ -546,6 +547,37 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         return pp && a != b && T.is_leaf(a) && T.is_leaf(b) && ipp.has(a, b, 0) && ipp.has(b, a, 0);
     };
     auto sym_cc = [&](int64_t a, int64_t b, int d) { return cc && a != b && icc.has(a, b, d) && icc.has(b, a, d); };
+    if (pp) {
+        // per leaf A: the partners B > A as merged particle ranges, tiles of A's particles
+        std::vector<SymBlock> blks(nblk);
+        parallel_run(nblk, [&](int64_t bi) {
+            SymBlock& B = blks[bi];
+            std::vector<std::pair<int64_t, int64_t>> rp, rg;
+            for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
+                if (!T.is_leaf(a)) continue;
+                double src = 0.0;
+                for (int64_t k = ipp.off[a]; k < ipp.off[a + 1]; ++k) {
+                    const int64_t b = ipp.part[k].first;
+                    if (b > a && ipp.has(b, a, 0)) {
+                        (boxes_near(T, a, b) ? rg : rp).emplace_back(T.begin[b], T.count[b]);
+                        src += (double)T.count[b];
+                    }
+                }
+                if (rp.empty() && rg.empty()) continue;
+                const int64_t eb = (int64_t)B.entries.size();
+                emit_ranges(rp, rg, B.entries);
+                const int64_t ee = (int64_t)B.entries.size();
+                B.evals += 2.0 * (double)T.count[a] * src;
+                for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {
+                    const int64_t tn = std::min<int64_t>(kTile, T.begin[a] + T.count[a] - tb);
+                    B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
+                                                              (int32_t)a, 0, (int32_t)tb}});
+                }
+            }
+        });
+        gather(blks, sw.pp_entries, sw.pp_items, sw.pp_evaluations);
+    }
+    if (pp_ready) pp_ready();
     // the rest: every entry except both directions of the symmetric pairs,
     // in list order (flags and per-chunk compaction on all threads)
     for (int k = 0; k < 4; ++k) {
@@ -589,36 +621,6 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
     }
     rest.sep_tc.clear();
     rest.sep_sc.clear();
-    if (pp) {
-        // per leaf A: the partners B > A as merged particle ranges, tiles of A's particles
-        std::vector<SymBlock> blks(nblk);
-        parallel_run(nblk, [&](int64_t bi) {
-            SymBlock& B = blks[bi];
-            std::vector<std::pair<int64_t, int64_t>> rp, rg;
-            for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
-                if (!T.is_leaf(a)) continue;
-                double src = 0.0;
-                for (int64_t k = ipp.off[a]; k < ipp.off[a + 1]; ++k) {
-                    const int64_t b = ipp.part[k].first;
-                    if (b > a && ipp.has(b, a, 0)) {
-                        (boxes_near(T, a, b) ? rg : rp).emplace_back(T.begin[b], T.count[b]);
-                        src += (double)T.count[b];
-                    }
-                }
-                if (rp.empty() && rg.empty()) continue;
-                const int64_t eb = (int64_t)B.entries.size();
-                emit_ranges(rp, rg, B.entries);
-                const int64_t ee = (int64_t)B.entries.size();
-                B.evals += 2.0 * (double)T.count[a] * src;
-                for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {
-                    const int64_t tn = std::min<int64_t>(kTile, T.begin[a] + T.count[a] - tb);
-                    B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
-                                                              (int32_t)a, 0, (int32_t)tb}});
-                }
-            }
-        });
-        gather(blks, sw.pp_entries, sw.pp_items, sw.pp_evaluations);
-    }
     if (cc) {
         // per (cluster A, degree d): the partners B > A at d, tiles of A's proxies
         std::vector<SymBlock> blks(nblk);

@@ -314,16 +314,17 @@ def test_cube1e7_bench_config_sampled():
 
 
 def test_cube1e7_tuned_form_meets_error_target():
-    # the timed tuned form (FP32 evaluation, learned degree, theta 0.8, tau 1e-6,
-    # fallback 8) on the same particles: relative l2 error against the direct sum
-    # on 0.1 % of the targets (the property bench.py reports) below 1e-6
+    # the timed tuned form (FP32 evaluation, learned degree, the workload's theta,
+    # tau and fallback degree) on the same particles: relative l2 error against
+    # the direct sum on 0.1 % of the targets (the property bench.py reports) below 1e-6
     from paper_2012_06925_amd.train_degree_model import load_model
     api = _api()
+    wl = inputs.WORKLOADS["cube1e7"]
     seed = inputs.workload_seed("cube1e7")
     p = inputs.particles(10_000_000, "uniform", seed=seed)
     s = [dev(a) for a in (p.x, p.y, p.z, p.q)]
-    plan = api.Plan(None, s, theta=0.8, degree=8, leaf=2000, flags=1 | 2)
-    plan.set_degree_model(load_model(), fallback=8, tau=1e-6)
+    plan = api.Plan(None, s, theta=wl["tuned_theta"], degree=wl["tuned_fallback"], leaf=wl["leaf"], flags=1 | 2)
+    plan.set_degree_model(load_model(), fallback=wl["tuned_fallback"], tau=wl["tau"])
     phi = plan.compute().cpu().numpy()
     st = plan.stats()
     plan.close()
