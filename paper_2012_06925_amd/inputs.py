@@ -85,7 +85,7 @@ WORKLOADS = {
                     tuned_theta=0.87, tau=1e-6, tuned_fallback=8),
     # 1E8: the learned-degree form; tau 7e-7 keeps the error below 1e-6 at this size (1e-6 gives 1.01e-6)
     "cube1e8": dict(id=5, M=100_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=8, leaf=2000,
-                    tuned_theta=0.85, tau=7e-7, tuned_fallback=8),
+                    tuned_theta=0.87, tau=7e-7, tuned_fallback=8),
     # 256 independent targets = sources problems, sizes log-uniform in [1E3, 1E5], distribution per
     # problem from {uniform cube, Gaussian, sphere surface}; Coulomb, theta 0.7, n 6, leaf 500
     "batch256": dict(id=4, count=256, lo_exp=3.0, hi_exp=5.0, kernel="coulomb", theta=0.7, degree=6, leaf=500),
