@@ -208,22 +208,50 @@ struct Upload {
     }
 };
 
-// The self pairs of a symmetric plan, packed for particle tiles of `tile`.
-void ensure_self_work(bldtt_plan* pl, int tile, int ptile) {
-    if (pl->self_tile == tile) return;
+// The self pairs of a symmetric plan (each leaf with itself, always PP when
+// targets = sources), packed once at setup in tiles of 256 particles, the
+// symmetric kernels' tile: the pairs inside a tile one-sided (guarded: i = j
+// and coincident points give r = 0), and each tile against the leaf's later
+// particles symmetric, once for both (longest first).
+void ensure_self_work(bldtt_plan* pl) {
+    if (pl->self_ready) return;
     const Tree& T = pl->T();
-    Lists L;
+    constexpr int64_t kTile = 256;
+    std::vector<Item> di;
+    std::vector<Entry> de, se;
+    std::vector<std::pair<int64_t, Item>> si;
     double evals = 0.0;
-    for (int64_t c = 0; c < T.size(); ++c)
-        if (T.is_leaf(c)) {
-            L.push(PP, c, c, pl->degree);
-            evals += (double)T.count[c] * (double)T.count[c];
+    auto range = [](int64_t a, int64_t n) {
+        return Entry{(int32_t)a, (int32_t)((uint32_t)SRC_RANGE_GUARD << 29 | (uint32_t)n)};
+    };
+    for (int64_t c = 0; c < T.size(); ++c) {
+        if (!T.is_leaf(c)) continue;
+        const int64_t b = T.begin[c], e = b + T.count[c];
+        evals += (double)T.count[c] * (double)T.count[c];
+        for (int64_t t0 = b; t0 < e; t0 += kTile) {
+            const int64_t tn = std::min(kTile, e - t0), t1 = t0 + tn;
+            di.push_back(Item{(int32_t)t0, (int32_t)tn, (int32_t)de.size(), (int32_t)de.size() + 1, (int32_t)c, 0,
+                              (int32_t)t0});
+            de.push_back(range(t0, tn));
+            if (t1 < e) {
+                si.push_back({tn * (e - t1), Item{(int32_t)t0, (int32_t)tn, (int32_t)se.size(), (int32_t)se.size() + 1,
+                                                  (int32_t)c, 0, (int32_t)t0}});
+                se.push_back(range(t1, e - t1));
+            }
         }
-    pack_work(T, pl->S, L, pl->degree, tile, ptile, pl->self_work);
-    upload_bytes(pl->self_items, pl->self_work.pitems.data(), sizeof(Item) * pl->self_work.pitems.size());
-    upload_bytes(pl->self_entries, pl->self_work.pentries.data(), sizeof(Entry) * pl->self_work.pentries.size());
+    }
+    std::stable_sort(si.begin(), si.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    std::vector<Item> sym;
+    sym.reserve(si.size());
+    for (auto& x : si) sym.push_back(x.second);
+    upload_bytes(pl->self_items, di.data(), sizeof(Item) * di.size());
+    upload_bytes(pl->self_entries, de.data(), sizeof(Entry) * de.size());
+    upload_bytes(pl->self_sym_items, sym.data(), sizeof(Item) * sym.size());
+    upload_bytes(pl->self_sym_entries, se.data(), sizeof(Entry) * se.size());
+    pl->n_self_items = (int)di.size();
+    pl->n_self_sym_items = (int)sym.size();
     pl->self_evaluations = evals;
-    pl->self_tile = tile;
+    pl->self_ready = true;
 }
 
 // Remove the self pairs (c, c) from the PP list.
@@ -284,11 +312,14 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // ... and the self pairs of the leaves (known before the traversal) write
     // the particle potentials first; every later particle pass adds
     if (symm) {
-        ensure_self_work(pl, tile, ptile);
+        ensure_self_work(pl);
         PhaseMark mark(pl, BLDTT_PH_PP_SELF, st);
-        launch_interact(ks, fp32, false, pl->tpt, pl->self_items.as<DevItem>(), (int)pl->self_work.pitems.size(),
+        launch_interact(ks, fp32, false, pl->tpt, pl->self_items.as<DevItem>(), pl->n_self_items,
                         pl->self_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         pl->phi_tree.as<double>(), DegOut{}, st);
+        launch_sym(fp32, pl->mfma_transfer(), false, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
+                   pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
+                   deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);
     }
 
     mark_host(0);
@@ -521,7 +552,7 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     if (pl->flags & BLDTT_PROFILE)
         for (auto& e : pl->prof_ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(pl->staging_free, st));
-    if (pl->symmetric_pp()) ensure_self_work(pl, kBlockThreads * pl->tpt, kBlockThreads * pl->tpt_proxy);
+    if (pl->symmetric_pp()) ensure_self_work(pl);
     fill_stats_tree(pl);
     pl->stats.setup_ms = now_ms() - t0;
 }

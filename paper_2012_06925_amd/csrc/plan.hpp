@@ -175,11 +175,12 @@ struct bldtt_plan {
     // sym: PP (and CC for a fixed degree); sym_sep: CC of the per-pair degree form
     SymWork sym, sym_sep;
     Lists near_rest, rest_lists, sep_lists;      // per-compute list scratch, capacity kept
-    // every leaf with itself (always PP when targets = sources): packed once per
-    // particle tile, run at the start of a compute while the host traverses
-    Work self_work;
-    DevBuf self_items, self_entries;
-    int self_tile = 0;
+    // every leaf with itself (always PP when targets = sources): packed once at
+    // setup, run at the start of a compute while the host traverses (pairs
+    // inside a 256-particle tile one-sided, the other pairs symmetric)
+    DevBuf self_items, self_entries, self_sym_items, self_sym_entries;
+    int n_self_items = 0, n_self_sym_items = 0;
+    bool self_ready = false;
     double self_evaluations = 0.0;
     DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
     bool symmetric_pp() const {
