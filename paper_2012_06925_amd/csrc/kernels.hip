@@ -250,10 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
 // and summed over the 4 lane groups and 4 waves after each chunk of up to 256
 // sources, then added with one FP64 atomic per source.  The next chunk's
 // sources are loaded into registers while the current one is evaluated.
-// Entries flagged SRC_RANGE_GUARD (leaf boxes within 2^-20 of their extent)
-// drop pairs whose computed squared distance is below the smallest normal
-// FP32 number (zero, or lost to rounding); elsewhere the box gap keeps it
-// far above.
+// Entries flagged SRC_RANGE_GUARD (a leaf with itself, or leaf boxes within
+// 2^-20 of their extent) drop pairs whose computed squared distance is at
+// most 2^-42 of the target box's squared diagonal: coincident points, whose
+// expansion leaves rounding noise instead of zero, and pairs closer than
+// FP32 coordinates relative to the box resolve; elsewhere the box gap keeps
+// the squared distance far above.
 // ---------------------------------------------------------------------------
 constexpr int kSymChunk = 256;                  // sources per chunk: 16 tiles of 16
 constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q = 0)
@@ -261,7 +263,8 @@ constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q 
 template <bool GUARD>
 __device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB)[64], const double* __restrict__ sN,
                                           const float* __restrict__ sQ, float (*__restrict__ part)[64], int lane,
-                                          const double (&A)[4], const float (&qi)[4][4], float (&acc)[4][4]) {
+                                          const double (&A)[4], const float (&qi)[4][4], float (&acc)[4][4],
+                                          float thr) {
     const int col = lane & 15;
     for (int t = 0; t < nt; ++t) {
         const double bv = sB[t][lane];
@@ -278,7 +281,7 @@ __device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB
             for (int r = 0; r < 4; ++r) {
                 const float rf = (float)d[b][r];
                 float y = __builtin_amdgcn_rsqf(rf);
-                if constexpr (GUARD) y = rf >= 0x1p-126f ? y : 0.0f;
+                if constexpr (GUARD) y = rf > thr ? y : 0.0f;
                 acc[b][r] = fmaf(qj, y, acc[b][r]);
                 psi = fmaf(qi[b][r], y, psi);
             }
@@ -306,6 +309,14 @@ __global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__
     const double* ptab = tab + 32 * it.degree;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
     double* od = PROXY ? phihat.p[it.degree] : nullptr;
+    // guarded entries: squared distances at or below 2^-42 of the squared box
+    // diagonal count as coincident (the rounding of the expansion stays below
+    // 2^-46 of it for sources within a few box sizes)
+    float thr;
+    {
+        const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
+        thr = fmaxf((float)(0x1p-42 * (ex * ex + ey * ey + ez * ez)), 0x1p-126f);
+    }
 
     {
         double x = kFarT, y = kFarT, z = kFarT, q = 0.0;
@@ -399,8 +410,8 @@ __global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc);
-            else sym_tiles<false>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc);
+            if (guard) sym_tiles<true>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc, thr);
+            else sym_tiles<false>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc, thr);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll

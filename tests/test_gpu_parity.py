@@ -394,12 +394,17 @@ def test_fp32_eval_cube1e6_config():
     assert e32_ds < 1e-6
 
 
-def test_fp32_eval_coincident_points_skipped():
-    # duplicates and the self term must be skipped in FP32 as well
+@pytest.mark.parametrize("leaf", [50, 700])
+def test_fp32_eval_coincident_points_skipped(leaf):
+    # duplicates and the self term must be skipped in FP32 as well; with leaf
+    # 700 the copies of a point also fall in different 256-particle tiles of
+    # one leaf, which the self pass pairs symmetrically
     rng = np.random.default_rng(61)
     x = np.repeat(rng.uniform(-1, 1, 2000), 3)
     p = inputs.ParticleSet(x.copy(), np.repeat(rng.uniform(-1, 1, 2000), 3), np.repeat(rng.uniform(-1, 1, 2000), 3),
                            rng.uniform(-1, 1, 6000))
-    p32, phi64, phi32 = _fp32_case(p, p, True, "coulomb", 0.8, 4, 50)
+    p32, phi64, phi32 = _fp32_case(p, p, True, "coulomb", 0.8, 4, leaf)
     assert np.all(np.isfinite(phi32))
     assert core.rel_l2(phi32, phi64) < FP32_BOUND_DUPLICATES
+    ref = core.bldtt(p, p, theta=0.8, degree=4, leaf=leaf)
+    assert core.rel_l2(phi64, ref) < PARITY
