@@ -57,14 +57,34 @@ def _positions(rng: np.random.Generator, n: int, dist: str) -> np.ndarray:
         return rng.uniform(0.0, 1.0, size=(n, 3)) * np.array([1.0, 10.0, 10.0])
     if dist == "rod":           # 1 x 1 x 10 box
         return rng.uniform(0.0, 1.0, size=(n, 3)) * np.array([1.0, 1.0, 10.0])
+    if dist == "plummer":
+        # radial density 3/(4 pi) (1 + r^2)^(-5/2) (Sec. 4.3): the mass inside r is
+        # r^3 / (1 + r^2)^(3/2), inverted for r; isotropic directions; points with
+        # a coordinate beyond +-100 are drawn again
+        out = np.empty((0, 3))
+        while out.shape[0] < n:
+            m = n - out.shape[0]
+            u = rng.uniform(0.0, 1.0, size=m)
+            with np.errstate(divide="ignore"):
+                r = 1.0 / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+            v = rng.normal(0.0, 1.0, size=(m, 3))
+            v *= (r / np.linalg.norm(v, axis=1))[:, None]
+            out = np.concatenate([out, v[np.all(np.abs(v) <= 100.0, axis=1)]])
+        return out
     raise ValueError(f"unknown distribution {dist!r}")
 
 
 def particles(n: int, dist: str = "uniform", seed: int = BASE_SEED, charges: bool = True) -> ParticleSet:
-    """n particles of one distribution; charges U[-1,1] drawn after positions."""
+    """n particles of one distribution; charges U[-1,1] drawn after positions
+    (Plummer particles carry 1/n each, as in Sec. 4.3)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     pos = _positions(rng, n, dist)
-    q = rng.uniform(-1.0, 1.0, size=n) if charges else None
+    if not charges:
+        q = None
+    elif dist == "plummer":
+        q = np.full(n, 1.0 / n)
+    else:
+        q = rng.uniform(-1.0, 1.0, size=n)
     return _split(pos, q)
 
 

@@ -158,6 +158,18 @@ def test_degenerate_inputs():
         full_parity(p, p, True, theta=0.8, degree=2, leaf=20)
 
 
+def test_plummer_distribution_parity():
+    # Sec. 4.3's concentrated distribution (charges 1/N): deep trees with
+    # leaves from dense to sparse; plain FP64 against the oracle, and the
+    # symmetric FP32 form within its bound of the FP64 result
+    p = inputs.particles(30_000, "plummer", seed=49)
+    full_parity(p, p, True, theta=0.7, degree=5, leaf=100)
+    p32, phi64, phi32 = _fp32_case(p, p, True, "coulomb", 0.7, 5, 100)
+    e = core.rel_l2(phi32, phi64)
+    print(f"\n  plummer FP32 vs FP64: {e:.2e}")
+    assert e < FP32_BOUND_CUBE
+
+
 def test_tiny_sets_and_single_leaf():
     one = inputs.ParticleSet(np.array([0.1]), np.array([0.2]), np.array([0.3]), np.array([0.5]))
     two = inputs.ParticleSet(np.array([1.0, 2.0]), np.array([0.0, 0.5]), np.array([0.0, 0.0]), np.array([1.0, -2.0]))

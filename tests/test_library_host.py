@@ -50,6 +50,7 @@ def _same_lists(la, lb):
     ("sphere", 20_000, 0.5, 3, 64),
     ("rod", 15_000, 0.9, 2, 40),
     ("slab", 15_000, 0.7, 5, 80),
+    ("plummer", 20_000, 0.7, 5, 100),
 ])
 def test_trees_and_lists_bit_exact_same_set(dist, n, theta, deg, leaf):
     p = inputs.particles(n, dist, seed=31)
