@@ -107,9 +107,11 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
 // targets of its wave.  The wave partials are summed in LDS and added to the
 // source's output with one FP64 atomic per source; each target's sum is added
 // with one atomic at the end.  Results are reproducible to rounding only: the
-// order of the atomics varies.  PP guards r^2 == 0 (distinct leaves never
-// share a point, but FP32 relative coordinates of two close points may round
-// together); CC pairs are separated, so their proxies never meet.
+// order of the atomics varies.  PP ranges flagged SRC_RANGE_GUARD (a leaf
+// with itself, or leaf boxes within 2^-20 of their extent) skip r^2 == 0
+// (coincident points; FP32 relative coordinates of two close points may round
+// together); elsewhere the gap between the boxes keeps r^2 > 0.  CC pairs are
+// separated, so their proxies never meet.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float rol1(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf, 0xf, true));
@@ -169,6 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
         const int2 en = entries[e];
         const int low = en.y & ((1 << 29) - 1);
         const int bn = PROXY ? P : low;                    // proxy entries: en.x = cluster B
+        // r^2 == 0 test only on ranges flagged SRC_RANGE_GUARD (a leaf with
+        // itself, or near leaf boxes); elsewhere the boxes keep the pairs apart
+        const bool guard = !PROXY && ((unsigned)en.y >> 29) == 1u;
         const double* sbox = T.box + 6 * en.x;
         for (int c0 = 0; c0 < bn; c0 += 64) {
             __syncthreads();
@@ -195,25 +200,30 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
             R psi = 0;
             if (active) {
                 R sum = 0;
+                // 64 steps: lane l pairs its target with source (l + s) mod 64
+                auto steps = [&](auto guard) {
 #pragma unroll
-                for (int s = 0; s < 64; ++s) {
-                    const V v = src[lane + s];
-                    const R dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
-                    R r2 = dz * dz;
-                    r2 = dy * dy + r2;
-                    r2 = dx * dx + r2;
-                    R y;
-                    if constexpr (F32) {
-                        y = __builtin_amdgcn_rsqf(r2);
-                        if constexpr (!PROXY) y = r2 > 0.0f ? y : 0.0f;
-                    } else {
-                        double y0 = rsq_est(r2);
-                        if constexpr (!PROXY) y0 = r2 > 0.0 ? y0 : 0.0;
-                        y = y0 * fma(-(r2 * y0), y0, 3.0);            // 2 y0 (3 - r^2 y0^2)/2; q staged /2
+                    for (int s = 0; s < 64; ++s) {
+                        const V v = src[lane + s];
+                        const R dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
+                        R r2 = dz * dz;
+                        r2 = dy * dy + r2;
+                        r2 = dx * dx + r2;
+                        R y;
+                        if constexpr (F32) {
+                            y = __builtin_amdgcn_rsqf(r2);
+                            if constexpr (decltype(guard)::value) y = r2 > 0.0f ? y : 0.0f;
+                        } else {
+                            double y0 = rsq_est(r2);
+                            if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
+                            y = y0 * fma(-(r2 * y0), y0, 3.0);        // 2 y0 (3 - r^2 y0^2)/2; q staged /2
+                        }
+                        sum = fma(v.w, y, sum);
+                        psi = rol1(psi) + qi * y;
                     }
-                    sum = fma(v.w, y, sum);
-                    psi = rol1(psi) + qi * y;
-                }
+                };
+                if (guard) steps(std::true_type{});
+                else steps(std::false_type{});
                 acc += (double)sum;
                 part_red[wave][(lane + 63) & 63] = psi;
             }
