@@ -310,6 +310,7 @@ def _sampled_parity(tgt, src, same, kernel, theta, degree, leaf, n_leaves=3, n_r
           f"stats={plan.stats()}")
     assert err < PARITY, err
     plan.close()
+    return phi
 
 
 def test_cube1e6_config_sampled():
@@ -352,6 +353,26 @@ def test_sphere_targets_gaussian_sources_yukawa_sampled():
     # the unequal Yukawa workload's shape at 1/10 size: 2E5 sphere targets, 1E6 Gaussian sources
     t, s = inputs.unequal_sets(200_000, "sphere", 1_000_000, "gaussian", seed=inputs.workload_seed("sphere2e6_gauss1e7"))
     _sampled_parity(t, s, False, "yukawa", 0.7, 8, 2000, seed=2)
+
+
+def test_unequal_yukawa_full_size_sampled():
+    # the unequal workload at its full size: 2E6 targets on the unit sphere,
+    # 1E7 Gaussian sources, Yukawa kappa 0.5, theta 0.7, n 8, leaf 2000.  Plain
+    # FP64: lists bit-exact and sampled targets against the oracle; the FP32
+    # evaluation form (the configuration's precision) within its bound of the
+    # FP64 result
+    t, s = inputs.unequal_sets(2_000_000, "sphere", 10_000_000, "gaussian",
+                               seed=inputs.workload_seed("sphere2e6_gauss1e7"))
+    phi64 = _sampled_parity(t, s, False, "yukawa", 0.7, 8, 2000, n_leaves=2, n_random=100, seed=4)
+    api = _api()
+    src = [dev(a) for a in (s.x, s.y, s.z, s.q)]
+    tgt = [dev(a) for a in (t.x, t.y, t.z)]
+    p32 = api.Plan(tgt, src, kernel="yukawa", theta=0.7, degree=8, leaf=2000, flags=1)
+    phi32 = p32.compute().cpu().numpy()
+    p32.close()
+    e = core.rel_l2(phi32, phi64)
+    print(f"\n  unequal Yukawa full size: FP32 vs FP64 {e:.2e}")
+    assert e < FP32_BOUND_UNEQUAL
 
 
 # --------------------------------------------------------------------------
