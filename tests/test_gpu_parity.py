@@ -349,6 +349,31 @@ def test_cube1e7_tuned_form_meets_error_target():
     assert st["sep_fallback"] < 0.01 * st["sep_pairs"]
 
 
+def test_cube1e8_tuned_form_meets_error_target():
+    # the 1E8 workload: FP32 evaluation and the learned per-pair degree at the
+    # workload's theta, tau and fallback; relative l2 error against the direct
+    # sum on 1E4 random targets below 1e-6
+    from paper_2012_06925_amd.train_degree_model import load_model
+    api = _api()
+    wl = inputs.WORKLOADS["cube1e8"]
+    seed = inputs.workload_seed("cube1e8")
+    p = inputs.particles(wl["M"], "uniform", seed=seed)
+    s = [dev(a) for a in (p.x, p.y, p.z, p.q)]
+    del p
+    plan = api.Plan(None, s, theta=wl["tuned_theta"], degree=wl["tuned_fallback"], leaf=wl["leaf"], flags=1 | 2)
+    plan.set_degree_model(load_model(), fallback=wl["tuned_fallback"], tau=wl["tau"])
+    phi = plan.compute()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    plan.close()
+    sel = inputs.error_sample(wl["M"], seed, fraction=1e-4)
+    sel_d = dev(sel)
+    ds = api.direct_sum(s[:3], s, sel=sel_d).cpu().numpy()
+    err = core.rel_l2(phi[sel_d].cpu().numpy(), ds)
+    print(f"\n  tuned 1E8: error vs direct {err:.3e}; degrees {st['pairs_per_degree']}")
+    assert err < 1e-6
+
+
 def test_sphere_targets_gaussian_sources_yukawa_sampled():
     # the unequal Yukawa workload's shape at 1/10 size: 2E5 sphere targets, 1E6 Gaussian sources
     t, s = inputs.unequal_sets(200_000, "sphere", 1_000_000, "gaussian", seed=inputs.workload_seed("sphere2e6_gauss1e7"))
