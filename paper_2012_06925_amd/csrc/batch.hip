@@ -8,8 +8,13 @@
 //   [up_xfer]  proxy charges of each source parent, deepest level first
 //   [q item]   CP + CC sums into target proxies (needs the upward pass)
 //   [p item]   PP + PC sums into target particles (PC needs the upward pass)
+//   [s item]   FP64 batches of targets = sources problems (Coulomb): pairs of
+//              distinct leaves listed as PP both ways, once for both; the
+//              particle sums start from zero and both kinds of item add with
+//              atomics, so they need no order between them
 //   [dn_xfer]  parent-to-child proxy potentials, shallowest level first (Sec. 2.7)
 //   [final]    leaf interpolation plus the PP/PC part, to the caller's buffers
+//              (after every symmetric item of its problem)
 //
 // Work groups take task numbers from a ticket counter, so a task starts only
 // after every smaller number has been taken by a running work group: waits
@@ -75,7 +80,7 @@ constexpr int cmax() { return A > B ? A : B; }
 
 template <int KIND, bool F32, int T, int M>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
-    constexpr int kLds = cmax<cmax<interact_lds_bytes<F32>(), up_leaf_lds_bytes<M>()>(),
+    constexpr int kLds = cmax<cmax<cmax<interact_lds_bytes<F32>(), up_leaf_lds_bytes<M>()>(), sym_lds_bytes<F32>()>(),
                               cmax<cmax<up_transfer_lds_bytes<M>(), down_transfer_lds_bytes<M>()>(),
                                    down_leaf_lds_bytes<M>()>()>();
     __shared__ double4 pool[(kLds + 31) / 32];
@@ -84,7 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
     using V = typename Stage<F32>::V;
     V* vl = reinterpret_cast<V*>(pool);
 
-    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, e2 = e1 + a.n_q, e3 = e2 + a.n_p, e4 = e3 + a.n_kids;
+    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, e2 = e1 + a.n_q, e3 = e2 + a.n_p, es = e3 + a.n_s,
+              e4 = es + a.n_kids;
     const int n_up = e1;
     bool up_seen = false;                     // this group has already acquired the finished upward pass
     for (;;) {
@@ -128,10 +134,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
                 up_seen = true;
             }
             interact_body<KIND, F32, T, false>(it, a.pentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
-                                               a.phi_tree, a.po, vl);
+                                               a.phi_tree, a.po, vl, a.n_s > 0 ? 2 : 0);
             signal(a.pdone + i);
+        } else if (t < es) {
+            if constexpr (!F32 && KIND == K_COULOMB) {
+                const DevItem it = a.sitems[t - e3];
+                sym_body<false, false>(it, a.sentries, a.src, a.S, a.phi_tree, a.tab_all, a.qp, a.po, pool);
+                signal(a.sdone + a.prob[it.cluster]);
+            }
         } else if (t < e4) {
-            const int c = a.kids[t - e3];
+            const int c = a.kids[t - es];
             const int par = a.T.parent[c];
             wait2(a, a.dn + par, a.nq[par] + (a.T.parent[par] >= 0 ? 1 : 0), a.dn + c, a.nq[c]);
             down_transfer_body<M>(c, a.T, a.tab, a.phihat, dl);
@@ -140,8 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
             const int i = t - e4;
             const DevItem it = a.pitems[i];
             const int c = it.cluster;
-            wait2(a, a.pdone + i, 1, a.dn + c, a.nq[c] + (a.T.parent[c] >= 0 ? 1 : 0));
             const int prob = a.prob[c];
+            if (a.n_s > 0) wait2(a, a.sdone + prob, a.s_need[prob], nullptr, 0);
+            wait2(a, a.pdone + i, 1, a.dn + c, a.nq[c] + (a.T.parent[c] >= 0 ? 1 : 0));
             down_leaf_body<M>(it, a.has_far[c] != 0, a.tgt, a.T, a.tab, a.phihat, a.phi_tree, a.perm,
                               a.outs[prob], a.caller0[prob], dl);
             __syncthreads();                  // LDS is reused by the next task

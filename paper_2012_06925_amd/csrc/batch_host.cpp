@@ -39,14 +39,19 @@ struct bldtt_batch {
     std::vector<int32_t> prob_of_cluster;     // target cluster -> problem
     Lists lists;
     Work work;
+    Lists rest;                               // the lists without the symmetric PP pairs
+    SymWork sym;                              // symmetric PP items (FP64 targets = sources, Coulomb)
     bldtt_batch_stats stats{};
+    bool symmetric() const {
+        return aliased && kind == BLDTT_COULOMB && (flags & (BLDTT_FP32_EVAL | BLDTT_ONE_SIDED_PP)) == 0;
+    }
 
     // device state
     DevBuf sx, sy, sz, sq, tx, ty, tz, perm, tab, qhat, phihat, phi_tree, tune_out;
     DevTreeBufs dS, dTt;
     const DevTreeBufs& dT() const { return aliased ? dS : dTt; }
     DevBuf leaves, parents, kids, qitems, qentries, qneeds, pitems, pentries, pneeds, has_far, nq, prob, caller0_d,
-        outs, counters;
+        outs, counters, sitems, sentries, s_need;
     int n_leaves = 0, n_parents = 0, n_kids = 0;
     int64_t n_counters = 0;
     PinnedBuf outs_host;
@@ -81,6 +86,7 @@ struct bldtt_batch {
 namespace {
 
 constexpr int kThreads = 256;   // work-group size of the batch kernel
+constexpr int kGlobalCounters = 4;   // ticket, upward done, error flag (one spare)
 
 // One problem's trees and tree-ordered arrays.
 struct ProblemHost {
@@ -232,12 +238,19 @@ void traverse_forest(bldtt_batch* b) {
 void pack(bldtt_batch* b, int tpt) {
     if (b->packed_tpt_valid && b->packed_tpt == tpt) return;
     Work& w = b->work;
-    pack_work(b->T(), b->S, b->lists, b->degree, kThreads * tpt, kThreads * tpt, w);
+    if (b->symmetric()) {
+        split_symmetric(b->T(), b->lists, b->degree, true, false, b->rest, b->sym);
+        pack_work(b->T(), b->S, b->rest, b->degree, kThreads * tpt, kThreads * tpt, w);
+    } else {
+        b->sym.clear();
+        pack_work(b->T(), b->S, b->lists, b->degree, kThreads * tpt, kThreads * tpt, w);
+    }
     for (int k = 0; k < 4; ++k) b->stats.interactions[k] = w.interactions[k];
+    b->stats.interactions[PP] += b->sym.pp_evaluations;
     b->packed_tpt = tpt;
     b->packed_tpt_valid = true;
     b->stats.n_tasks = (int64_t)b->n_leaves + b->n_parents + (int64_t)w.qitems.size() + 2 * (int64_t)w.pitems.size() +
-                       b->n_kids;
+                       (int64_t)b->sym.pp_items.size() + b->n_kids;
     if (b->host_only) return;
     auto needs = [](const std::vector<Item>& items, const std::vector<Entry>& entries) {
         std::vector<uint8_t> f(items.size(), 0);
@@ -259,7 +272,12 @@ void pack(bldtt_batch* b, int tpt) {
     upload(b->pneeds, needs(w.pitems, w.pentries));
     upload(b->has_far, w.leaf_has_far);
     upload(b->nq, nq);
-    b->n_counters = 4 + b->S.size() + b->T().size() + (int64_t)w.pitems.size();
+    upload(b->sitems, b->sym.pp_items);
+    upload(b->sentries, b->sym.pp_entries);
+    std::vector<int32_t> s_need(b->count, 0);
+    for (const Item& it : b->sym.pp_items) s_need[b->prob_of_cluster[it.cluster]] += 1;
+    upload(b->s_need, s_need);
+    b->n_counters = kGlobalCounters + b->S.size() + b->T().size() + (int64_t)w.pitems.size() + b->count;
     b->counters.alloc(sizeof(int32_t) * b->n_counters);
 }
 
@@ -294,15 +312,20 @@ BatchDev device_args(const bldtt_batch* b) {
     a.outs = b->outs.as<double*>();
     int32_t* c = b->counters.as<int32_t>();
     a.ctr = c;
-    a.up_cnt = c + 4;
+    a.up_cnt = c + kGlobalCounters;
     a.dn = a.up_cnt + b->S.size();
     a.pdone = a.dn + b->T().size();
     a.n_leaves = b->n_leaves;
     a.n_parents = b->n_parents;
     a.n_q = (int)w.qitems.size();
     a.n_p = (int)w.pitems.size();
+    a.sitems = b->sitems.as<DevItem>();
+    a.sentries = b->sentries.as<int2>();
+    a.sdone = a.pdone + w.pitems.size();
+    a.s_need = b->s_need.as<int32_t>();
+    a.n_s = (int)b->sym.pp_items.size();
     a.n_kids = b->n_kids;
-    a.n_tasks = a.n_leaves + a.n_parents + a.n_q + 2 * a.n_p + a.n_kids;
+    a.n_tasks = a.n_leaves + a.n_parents + a.n_q + 2 * a.n_p + a.n_s + a.n_kids;
     a.spin_limit = b->spin_limit;
     a.param = b->param;
     return a;
@@ -324,6 +347,7 @@ void capture(bldtt_batch* b, int tpt, int groups_per_cu) {
     try {
         launch_fill_i32(b->counters.as<int32_t>(), b->n_counters, 0, b->cap);
         launch_fill(b->phihat.as<double>(), (int64_t)b->T().size() * b->P(), 0.0, b->cap);
+        if (a.n_s > 0) launch_fill(b->phi_tree.as<double>(), b->T().n_particles, 0.0, b->cap);
         launch_batch(ks, fp32, tpt, b->degree, (int)grid, a, b->cap);
     } catch (...) {
         hipGraph_t g2 = nullptr;
@@ -343,7 +367,8 @@ void capture(bldtt_batch* b, int tpt, int groups_per_cu) {
 }
 
 std::string batch_tune_key(const bldtt_batch* b) {
-    return tune_key("batch", b->kind, (b->flags & BLDTT_FP32_EVAL) != 0, false, b->degree, b->leaf,
+    return tune_key(b->symmetric() ? "batch-sym" : "batch", b->kind, (b->flags & BLDTT_FP32_EVAL) != 0, false,
+                    b->degree, b->leaf,
                     b->stats.n_targets + b->stats.n_sources, b->count);
 }
 

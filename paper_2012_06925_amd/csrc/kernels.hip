@@ -92,155 +92,14 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric passes for targets = sources (Coulomb).  G(x, y) = G(y, x), so one
-// kernel value serves two terms:
-//   PP (pairs of distinct leaves {A, B}): phi_i += q_j G, phi_j += q_i G;
-//   CC (pairs of clusters {A, B} at one degree): phihat_A[l] += G qhat_B[k] and
-//      phihat_B[k] += G qhat_A[l] -- the proxy grids of a cluster are the same
-//      points whether it is the target or the source.
-// One work item = a tile of up to 256 target points of A (64 per wave) and the
-// entries of its partners B.  Sources are staged 64 at a time in LDS (twice,
-// so step s reads src[lane + s]); at step s lane l pairs its target with
-// source (l + s) mod 64 and adds q_i G to a running source partial that moves
-// one lane down per step (DPP wave_rol:1: lane l receives lane l + 1), so
-// after 64 steps lane l holds the partial of source (l - 1) mod 64 over the 64
-// targets of its wave.  The wave partials are summed in LDS and added to the
-// source's output with one FP64 atomic per source; each target's sum is added
-// with one atomic at the end.  Results are reproducible to rounding only: the
-// order of the atomics varies.  PP ranges flagged SRC_RANGE_GUARD (a leaf
-// with itself, or leaf boxes within 2^-20 of their extent) skip r^2 == 0
-// (coincident points; FP32 relative coordinates of two close points may round
-// together); elsewhere the gap between the boxes keeps r^2 > 0.  CC pairs are
-// separated, so their proxies never meet.
+// Symmetric passes on the vector ALUs (sym_body): one work group per item.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float rol1(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf, 0xf, true));
-}
-
-__device__ __forceinline__ double rol1(double v) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x134, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x134, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
-}
-
-constexpr float kFar = 1e18f;            // padding lanes sit here with charge 0
-
 template <bool F32, bool PROXY>
 __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ items, const int2* __restrict__ entries,
                                                 DevParticles p, DevTree T, double* __restrict__ phi,
                                                 const double* __restrict__ tab, DegPtrs qhat, DegOut phihat) {
-    using R = typename std::conditional<F32, float, double>::type;
-    using V = typename std::conditional<F32, float4, double4>::type;
-    // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
-    constexpr R qs = F32 ? (R)1 : (R)0.5;
-    __shared__ V src[128];
-    __shared__ R part_red[4][64];
-    const DevItem it = items[blockIdx.x];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool active = 64 * wave < it.tn;
-    const double* box = T.box + 6 * it.cluster;
-    const double cx = F32 ? 0.5 * (box[0] + box[3]) : 0.0, cy = F32 ? 0.5 * (box[1] + box[4]) : 0.0,
-                 cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
-    // proxies: degree of the item, grid size, per-degree tables and arrays
-    const int m = it.degree + 1, P = m * m * m;
-    const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
-    double* od = PROXY ? phihat.p[it.degree] : nullptr;
-    const int r = 64 * wave + lane;
-    const bool mine = r < it.tn;
-    const int ti = it.t0 + (mine ? r : 0);
-    R tx = (R)kFar, ty = (R)kFar, tz = (R)kFar, qi = 0;
-    if (mine) {
-        double x, y, z, q;
-        if constexpr (PROXY) {
-            proxy_point(box, m, tab + 32 * it.degree, ti, x, y, z);
-            q = qd[(int64_t)it.cluster * P + ti];
-        } else {
-            x = p.x[ti];
-            y = p.y[ti];
-            z = p.z[ti];
-            q = p.q[ti];
-        }
-        tx = (R)(x - cx);
-        ty = (R)(y - cy);
-        tz = (R)(z - cz);
-        qi = (R)(qs * q);
-    }
-    double acc = 0.0;
-    for (int e = it.eb; e < it.ee; ++e) {
-        const int2 en = entries[e];
-        const int low = en.y & ((1 << 29) - 1);
-        const int bn = PROXY ? P : low;                    // proxy entries: en.x = cluster B
-        // r^2 == 0 test only on ranges flagged SRC_RANGE_GUARD (a leaf with
-        // itself, or near leaf boxes); elsewhere the boxes keep the pairs apart
-        const bool guard = !PROXY && ((unsigned)en.y >> 29) == 1u;
-        const double* sbox = T.box + 6 * en.x;
-        for (int c0 = 0; c0 < bn; c0 += 64) {
-            __syncthreads();
-            if (tid < 64) {
-                V v{(R)kFar, (R)kFar, (R)kFar, (R)0};
-                if (c0 + tid < bn) {
-                    double x, y, z, q;
-                    if constexpr (PROXY) {
-                        proxy_point(sbox, m, tab + 32 * it.degree, c0 + tid, x, y, z);
-                        q = qd[(int64_t)en.x * P + c0 + tid];
-                    } else {
-                        const int j = en.x + c0 + tid;
-                        x = p.x[j];
-                        y = p.y[j];
-                        z = p.z[j];
-                        q = p.q[j];
-                    }
-                    v = V{(R)(x - cx), (R)(y - cy), (R)(z - cz), (R)(qs * q)};
-                }
-                src[tid] = v;
-                src[tid + 64] = v;
-            }
-            __syncthreads();
-            R psi = 0;
-            if (active) {
-                R sum = 0;
-                // 64 steps: lane l pairs its target with source (l + s) mod 64
-                auto steps = [&](auto guard) {
-#pragma unroll
-                    for (int s = 0; s < 64; ++s) {
-                        const V v = src[lane + s];
-                        const R dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
-                        R r2 = dz * dz;
-                        r2 = dy * dy + r2;
-                        r2 = dx * dx + r2;
-                        R y;
-                        if constexpr (F32) {
-                            y = __builtin_amdgcn_rsqf(r2);
-                            if constexpr (decltype(guard)::value) y = r2 > 0.0f ? y : 0.0f;
-                        } else {
-                            double y0 = rsq_est(r2);
-                            if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
-                            y = y0 * fma(-(r2 * y0), y0, 3.0);        // 2 y0 (3 - r^2 y0^2)/2; q staged /2
-                        }
-                        sum = fma(v.w, y, sum);
-                        psi = rol1(psi) + qi * y;
-                    }
-                };
-                if (guard) steps(std::true_type{});
-                else steps(std::false_type{});
-                acc += (double)sum;
-                part_red[wave][(lane + 63) & 63] = psi;
-            }
-            __syncthreads();
-            if (tid < 64 && c0 + tid < bn) {
-                double t = 0.0;
-                for (int w = 0; w < 4; ++w)
-                    if (64 * w < it.tn) t += (double)part_red[w][tid];
-                if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
-                else atomicAdd(phi + en.x + c0 + tid, t);
-            }
-        }
-    }
-    if (mine) {
-        if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + ti, acc);
-        else atomicAdd(phi + ti, acc);
-    }
+    __shared__ double4 pool[(sym_lds_bytes<F32>() + 31) / 32];
+    sym_body<F32, PROXY>(items[blockIdx.x], entries, p, T, phi, tab, qhat, phihat, pool);
 }
 
 // ---------------------------------------------------------------------------

@@ -136,7 +136,11 @@ struct BatchDev {
     int32_t* up_cnt;            // per source cluster: finished children
     int32_t* dn;                // per target cluster: finished proxy items (+1 when its transfer is done)
     int32_t* pdone;             // per particle item
-    int n_leaves, n_parents, n_q, n_p, n_kids, n_tasks;
+    const DevItem* sitems;      // symmetric PP items (FP64, targets = sources, Coulomb)
+    const int2* sentries;
+    int32_t* sdone;             // per problem: finished symmetric items
+    const int32_t* s_need;      // per problem: symmetric items
+    int n_leaves, n_parents, n_q, n_p, n_s, n_kids, n_tasks;
     int spin_limit;
     double param;
 };

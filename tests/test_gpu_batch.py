@@ -117,8 +117,9 @@ def test_batch_unequal_sets_equal_standalone():
 
 
 def test_graph_replays_and_tiles_give_identical_results():
+    # one-sided evaluation (no atomics): every replay is bit for bit the same
     probs = [_dev_problem(p) for p in _problems(8, inputs.BASE_SEED + 54)]
-    b = api.Batch(probs, theta=0.7, degree=6, leaf=100)
+    b = api.Batch(probs, theta=0.7, degree=6, leaf=100, flags=_lib.ONE_SIDED_PP)
     first = [o.cpu().numpy() for o in b.compute()]
     for rep in range(3):
         junk = torch.randn(1 << 20, device=DEV).sum()      # unrelated eager work between replays
@@ -151,7 +152,7 @@ def test_autotuner_measures_then_reads_its_cache(tmp_path):
         st = b.stats()
         assert st["tuned"] == 2 and st["tune_best_ms"] > 0
         text = cache.read_text()
-        assert text.startswith("batch:") and "\t" in text
+        assert text.startswith("batch") and "\t" in text
         outs = b.compute()
         b.check()
         for r, o in zip(ref, outs):
@@ -189,7 +190,29 @@ def test_bounded_wait_failure_is_reported_then_recovers():
     outs = b.compute()
     b.check()
     for r, o in zip(ref, outs):
-        assert np.array_equal(r, o.cpu().numpy())
+        assert _rel(o.cpu().numpy(), r) <= 1e-13          # symmetric pairs: atomics, equal to rounding
+    b.close()
+
+
+def test_symmetric_batch_equals_one_sided_batch_and_replays():
+    # FP64 batches of targets = sources Coulomb problems evaluate each pair of
+    # distinct leaves once for both (atomic adds after the particle items); the
+    # result equals the one-sided batch to rounding, on every graph replay
+    probs = [_dev_problem(p) for p in _problems(12, inputs.BASE_SEED + 58)]
+    kw = dict(theta=0.7, degree=6, leaf=100)
+    one = api.Batch(probs, flags=_lib.ONE_SIDED_PP, **kw)
+    ref = [o.cpu().numpy() for o in one.compute()]
+    one.check()
+    n_one = one.stats()["n_tasks"]
+    one.close()
+    b = api.Batch(probs, **kw)
+    st = b.stats()
+    assert st["n_tasks"] > n_one                              # the symmetric items are tasks of their own
+    for rep in range(3):
+        outs = b.compute()
+        b.check()
+        worst = max(_rel(o.cpu().numpy(), r) for r, o in zip(ref, outs))
+        assert worst <= 1e-13, (rep, worst)
     b.close()
 
 
