@@ -85,7 +85,9 @@ enum {
                                       for both (G is symmetric; a cluster's proxy grid
                                       is the same as target and as source), with FP64
                                       atomic adds: the result then varies run to run
-                                      at the rounding level                              */
+                                      at the rounding level.  FP64 batches of such
+                                      problems evaluate their PP pairs the same way
+                                      unless this flag is set                            */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host
