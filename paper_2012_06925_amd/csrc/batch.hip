@@ -7,6 +7,10 @@
 //   [up_leaf]  proxy charges of each source leaf (Sec. 2.5)
 //   [up_xfer]  proxy charges of each source parent, deepest level first
 //   [q item]   CP + CC sums into target proxies (needs the upward pass)
+//   [c item]   FP64 batches of targets = sources problems (Coulomb): pairs of
+//              clusters listed as CC both ways, once for both; the proxy
+//              potentials start from zero and both kinds of item add with
+//              atomics; each item counts for its cluster and its partners
 //   [p item]   PP + PC sums into target particles (PC needs the upward pass)
 //   [s item]   FP64 batches of targets = sources problems (Coulomb): pairs of
 //              distinct leaves listed as PP both ways, once for both; the
@@ -75,6 +79,15 @@ __device__ __forceinline__ void signal(int32_t* p) {
     if (threadIdx.x == 0) __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Same, counted in dn[first] and in dn[entries[e].x] for e in [eb, ee).
+__device__ __forceinline__ void signal_clusters(int32_t* dn, int first, const int2* entries, int eb, int ee) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(dn + first, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int e = eb + (int)threadIdx.x; e < ee; e += kBlock)
+        __hip_atomic_fetch_add(dn + entries[e].x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int A, int B>
 constexpr int cmax() { return A > B ? A : B; }
 
@@ -89,8 +102,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
     using V = typename Stage<F32>::V;
     V* vl = reinterpret_cast<V*>(pool);
 
-    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, e2 = e1 + a.n_q, e3 = e2 + a.n_p, es = e3 + a.n_s,
-              e4 = es + a.n_kids;
+    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, eq = e1 + a.n_q, e2 = eq + a.n_c, e3 = e2 + a.n_p,
+              es = e3 + a.n_s, e4 = es + a.n_kids;
     const int n_up = e1;
     bool up_seen = false;                     // this group has already acquired the finished upward pass
     for (;;) {
@@ -116,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
             signal(par >= 0 ? a.up_cnt + par : a.ctr + C_UP_DONE);
             if (par >= 0 && threadIdx.x == 0)
                 __hip_atomic_fetch_add(a.ctr + C_UP_DONE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (t < e2) {
+        } else if (t < eq) {
             const int i = t - e1;
             const DevItem it = a.qitems[i];
             if (a.qneeds[i] && !up_seen) {
@@ -124,8 +137,18 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
                 up_seen = true;
             }
             interact_body<KIND, F32, T, true>(it, a.qentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
-                                              nullptr, a.po, vl);
+                                              nullptr, a.po, vl, a.n_c > 0 ? 2 : 0);
             signal(a.dn + it.cluster);
+        } else if (t < e2) {
+            if constexpr (!F32 && KIND == K_COULOMB) {
+                const DevItem it = a.citems[t - eq];
+                if (!up_seen) {
+                    wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
+                    up_seen = true;
+                }
+                sym_body<false, true>(it, a.centries, a.src, a.S, nullptr, a.tab_all, a.qp, a.po, pool);
+                signal_clusters(a.dn, it.cluster, a.centries, it.eb, it.ee);
+            }
         } else if (t < e3) {
             const int i = t - e2;
             const DevItem it = a.pitems[i];

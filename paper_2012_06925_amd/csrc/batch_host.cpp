@@ -51,7 +51,7 @@ struct bldtt_batch {
     DevTreeBufs dS, dTt;
     const DevTreeBufs& dT() const { return aliased ? dS : dTt; }
     DevBuf leaves, parents, kids, qitems, qentries, qneeds, pitems, pentries, pneeds, has_far, nq, prob, caller0_d,
-        outs, counters, sitems, sentries, s_need;
+        outs, counters, sitems, sentries, s_need, citems, centries;
     int n_leaves = 0, n_parents = 0, n_kids = 0;
     int64_t n_counters = 0;
     PinnedBuf outs_host;
@@ -239,18 +239,20 @@ void pack(bldtt_batch* b, int tpt) {
     if (b->packed_tpt_valid && b->packed_tpt == tpt) return;
     Work& w = b->work;
     if (b->symmetric()) {
-        split_symmetric(b->T(), b->lists, b->degree, true, false, b->rest, b->sym);
-        pack_work(b->T(), b->S, b->rest, b->degree, kThreads * tpt, kThreads * tpt, w);
+        split_symmetric(b->T(), b->lists, b->degree, true, true, b->rest, b->sym);
+        const std::vector<uint32_t> extra = sym_cc_degrees(b->T(), b->sym);
+        pack_work(b->T(), b->S, b->rest, b->degree, kThreads * tpt, kThreads * tpt, w, &extra);
     } else {
         b->sym.clear();
         pack_work(b->T(), b->S, b->lists, b->degree, kThreads * tpt, kThreads * tpt, w);
     }
     for (int k = 0; k < 4; ++k) b->stats.interactions[k] = w.interactions[k];
     b->stats.interactions[PP] += b->sym.pp_evaluations;
+    b->stats.interactions[CC] += b->sym.cc_evaluations;
     b->packed_tpt = tpt;
     b->packed_tpt_valid = true;
     b->stats.n_tasks = (int64_t)b->n_leaves + b->n_parents + (int64_t)w.qitems.size() + 2 * (int64_t)w.pitems.size() +
-                       (int64_t)b->sym.pp_items.size() + b->n_kids;
+                       (int64_t)b->sym.pp_items.size() + (int64_t)b->sym.cc_items.size() + b->n_kids;
     if (b->host_only) return;
     auto needs = [](const std::vector<Item>& items, const std::vector<Entry>& entries) {
         std::vector<uint8_t> f(items.size(), 0);
@@ -262,8 +264,14 @@ void pack(bldtt_batch* b, int tpt) {
                 }
         return f;
     };
+    // contributions each target cluster's proxy potentials wait for: its proxy
+    // items, and every symmetric CC item of it or with it as a partner
     std::vector<int32_t> nq(b->T().size(), 0);
     for (const Item& it : w.qitems) nq[it.cluster] += 1;
+    for (const Item& it : b->sym.cc_items) {
+        nq[it.cluster] += 1;
+        for (int e = it.eb; e < it.ee; ++e) nq[b->sym.cc_entries[e].a] += 1;
+    }
     upload(b->qitems, w.qitems);
     upload(b->qentries, w.qentries);
     upload(b->qneeds, needs(w.qitems, w.qentries));
@@ -274,6 +282,8 @@ void pack(bldtt_batch* b, int tpt) {
     upload(b->nq, nq);
     upload(b->sitems, b->sym.pp_items);
     upload(b->sentries, b->sym.pp_entries);
+    upload(b->citems, b->sym.cc_items);
+    upload(b->centries, b->sym.cc_entries);
     std::vector<int32_t> s_need(b->count, 0);
     for (const Item& it : b->sym.pp_items) s_need[b->prob_of_cluster[it.cluster]] += 1;
     upload(b->s_need, s_need);
@@ -324,8 +334,11 @@ BatchDev device_args(const bldtt_batch* b) {
     a.sdone = a.pdone + w.pitems.size();
     a.s_need = b->s_need.as<int32_t>();
     a.n_s = (int)b->sym.pp_items.size();
+    a.citems = b->citems.as<DevItem>();
+    a.centries = b->centries.as<int2>();
+    a.n_c = (int)b->sym.cc_items.size();
     a.n_kids = b->n_kids;
-    a.n_tasks = a.n_leaves + a.n_parents + a.n_q + 2 * a.n_p + a.n_s + a.n_kids;
+    a.n_tasks = a.n_leaves + a.n_parents + a.n_q + a.n_c + 2 * a.n_p + a.n_s + a.n_kids;
     a.spin_limit = b->spin_limit;
     a.param = b->param;
     return a;

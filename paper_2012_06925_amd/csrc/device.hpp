@@ -307,8 +307,11 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
     for (int j = 0; j < T; ++j) {
         int r = slab + lane + 64 * j;
         if (r < it.tn) {
-            if (PROXY_TGT) pout.p[it.degree][(int64_t)it.slot * Pt + it.t0 + r] = acc[j];
-            else if (add == 2) atomicAdd(out + it.slot + r, acc[j]);     // others add to these targets too
+            if (PROXY_TGT) {
+                double* o = pout.p[it.degree] + (int64_t)it.slot * Pt + it.t0 + r;
+                if (add == 2) atomicAdd(o, acc[j]);                      // others add to these proxies too
+                else *o = acc[j];
+            } else if (add == 2) atomicAdd(out + it.slot + r, acc[j]);   // others add to these targets too
             else out[it.slot + r] = add ? out[it.slot + r] + acc[j] : acc[j];
         }
     }

@@ -140,6 +140,9 @@ struct BatchDev {
     const int2* sentries;
     int32_t* sdone;             // per problem: finished symmetric items
     const int32_t* s_need;      // per problem: symmetric items
+    const DevItem* citems;      // symmetric CC items (same batches), after the proxy items
+    const int2* centries;
+    int n_c;
     int n_leaves, n_parents, n_q, n_p, n_s, n_kids, n_tasks;
     int spin_limit;
     double param;
