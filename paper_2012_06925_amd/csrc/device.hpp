@@ -185,8 +185,11 @@ constexpr int interact_lds_bytes() { return kChunk * (int)sizeof(typename Stage<
 // ---------------------------------------------------------------------------
 // Interaction sums.  One work item = up to kBlock*T targets of one target
 // cluster (particles of a leaf: PP + PC; or proxies of a cluster: CP + CC)
-// and its list of source entries.  Thread (wave w, lane l) owns targets
-// w*64*T + l + 64 j, j < T; a wave with no target skips the arithmetic.
+// and its list of source entries.  The item's targets need nslab = 1, 2 or 4
+// waves of 64*T (3 counts as 4); the group's 4 waves form 4 / nslab copies of
+// that many waves, copy k taking the staged sources k, k + copies, ...: wave w
+// owns targets (w mod nslab)*64*T + l + 64 j, j < T, and the copies' sums are
+// added in LDS at the end (an item with few targets keeps every wave busy).
 // Sources are staged through LDS and read by all lanes at the same address.
 // Particle targets are written (out = sum) or, with `add`, accumulated
 // (out += sum) for a second pass over other entries of the same targets.
@@ -203,7 +206,9 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
 
     const int mt = it.degree + 1, Pt = mt * mt * mt;      // target proxies (PROXY_TGT)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slab = wave * 64 * T;
+    const int nslab = it.tn <= 64 * T ? 1 : (it.tn <= 128 * T ? 2 : 4);
+    const int copies = 4 / nslab, copy = wave / nslab;
+    const int slab = (wave % nslab) * 64 * T;
     const bool active = slab < it.tn;
     const double* tbox = Tt.box + 6 * it.cluster;
     const double cx = 0.5 * (tbox[0] + tbox[3]), cy = 0.5 * (tbox[1] + tbox[4]), cz = 0.5 * (tbox[2] + tbox[5]);
@@ -270,23 +275,23 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
             for (int s0 = 0; s0 < cnt; s0 += kSub32) {
                 const int s1 = min(cnt, s0 + kSub32);
                 if (guard) {
-                    for (int s = s0; s < s1; ++s) {
+                    for (int s = s0 + copy; s < s1; s += copies) {
                         const V v = lds[s];
 #pragma unroll
                         for (int j = 0; j < T; ++j) accumulate<Ev, true, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
                     }
                 } else {
-                    int s = s0;
-                    for (; s + 4 <= s1; s += 4) {
+                    int s = s0 + copy;
+                    for (; s + 3 * copies < s1; s += 4 * copies) {
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const V v = lds[s + u];
+                            const V v = lds[s + u * copies];
 #pragma unroll
                             for (int j = 0; j < T; ++j)
                                 accumulate<Ev, false, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
                         }
                     }
-                    for (; s < s1; ++s) {
+                    for (; s < s1; s += copies) {
                         const V v = lds[s];
 #pragma unroll
                         for (int j = 0; j < T; ++j) accumulate<Ev, false, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
@@ -301,6 +306,19 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
                 }
             }
         }
+    }
+    if (copies > 1) {                                     // add the other copies' sums to copy 0's
+        double* red = reinterpret_cast<double*>(lds);         // [copy - 1][slab wave][T][64]
+        __syncthreads();                                      // every wave is past the last staged chunk
+        if (copy > 0 && active) {
+#pragma unroll
+            for (int j = 0; j < T; ++j) red[(((copy - 1) * nslab + wave % nslab) * T + j) * 64 + lane] = acc[j];
+        }
+        __syncthreads();
+        if (copy > 0) return;
+        for (int k = 1; k < copies; ++k)
+#pragma unroll
+            for (int j = 0; j < T; ++j) acc[j] += red[(((k - 1) * nslab + wave % nslab) * T + j) * 64 + lane];
     }
     if (!active) return;
 #pragma unroll
