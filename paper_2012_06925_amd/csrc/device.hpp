@@ -831,11 +831,14 @@ constexpr float kFar = 1e18f;            // padding lanes sit here with charge 0
 
 template <bool F32>
 constexpr int sym_lds_bytes() {
-    return 128 * (int)sizeof(typename std::conditional<F32, float4, double4>::type) +
+    return 4 * 128 * (int)sizeof(typename std::conditional<F32, float4, double4>::type) +
            4 * 64 * (int)sizeof(typename std::conditional<F32, float, double>::type);
 }
 
-// One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.
+// One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  An item
+// whose targets fill nslab = 1 or 2 waves runs 4 / nslab copies of those
+// waves, each over its own 64 of the 64 * copies sources staged per round
+// (each copy adds its own target partials with its atomics).
 template <bool F32, bool PROXY>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, double* __restrict__ phi, const double* __restrict__ tab,
@@ -844,10 +847,14 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     using V = typename std::conditional<F32, float4, double4>::type;
     // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
     constexpr R qs = F32 ? (R)1 : (R)0.5;
-    V* src = static_cast<V*>(lds);                               // 128 staged sources (two copies of 64)
-    R (*part_red)[64] = reinterpret_cast<R (*)[64]>(src + 128);  // [4][64] wave partials
+    V* src = static_cast<V*>(lds);                               // per copy: 64 staged sources, twice
+    R (*part_red)[64] = reinterpret_cast<R (*)[64]>(src + 4 * 128);  // [4][64] wave partials
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool active = 64 * wave < it.tn;
+    const int nslab = it.tn <= 64 ? 1 : (it.tn <= 128 ? 2 : 4);
+    const int copies = 4 / nslab, copy = wave / nslab, sw = wave % nslab;
+    const int span = 64 * copies;                                // sources staged per round
+    const V* mysrc = src + 128 * copy;
+    const bool active = 64 * sw < it.tn;
     const double* box = T.box + 6 * it.cluster;
     const double cx = F32 ? 0.5 * (box[0] + box[3]) : 0.0, cy = F32 ? 0.5 * (box[1] + box[4]) : 0.0,
                  cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
@@ -855,7 +862,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     const int m = it.degree + 1, P = m * m * m;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
     double* od = PROXY ? phihat.p[it.degree] : nullptr;
-    const int r = 64 * wave + lane;
+    const int r = 64 * sw + lane;
     const bool mine = r < it.tn;
     const int ti = it.t0 + (mine ? r : 0);
     R tx = (R)kFar, ty = (R)kFar, tz = (R)kFar, qi = 0;
@@ -884,9 +891,9 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
         // itself, or near leaf boxes); elsewhere the boxes keep the pairs apart
         const bool guard = !PROXY && ((unsigned)en.y >> 29) == 1u;
         const double* sbox = T.box + 6 * en.x;
-        for (int c0 = 0; c0 < bn; c0 += 64) {
+        for (int c0 = 0; c0 < bn; c0 += span) {
             __syncthreads();
-            if (tid < 64) {
+            if (tid < span) {
                 V v{(R)kFar, (R)kFar, (R)kFar, (R)0};
                 if (c0 + tid < bn) {
                     double x, y, z, q;
@@ -902,8 +909,9 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                     }
                     v = V{(R)(x - cx), (R)(y - cy), (R)(z - cz), (R)(qs * q)};
                 }
-                src[tid] = v;
-                src[tid + 64] = v;
+                V* dst = src + 128 * (tid >> 6) + (tid & 63);
+                dst[0] = v;
+                dst[64] = v;
             }
             __syncthreads();
             R psi = 0;
@@ -913,7 +921,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 auto steps = [&](auto guard) {
 #pragma unroll
                     for (int s = 0; s < 64; ++s) {
-                        const V v = src[lane + s];
+                        const V v = mysrc[lane + s];
                         const R dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
                         R r2 = dz * dz;
                         r2 = dy * dy + r2;
@@ -937,10 +945,11 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 part_red[wave][(lane + 63) & 63] = psi;
             }
             __syncthreads();
-            if (tid < 64 && c0 + tid < bn) {
+            if (tid < span && c0 + tid < bn) {
+                const int k = tid >> 6, ms = tid & 63;           // copy and source of the round
                 double t = 0.0;
-                for (int w = 0; w < 4; ++w)
-                    if (64 * w < it.tn) t += (double)part_red[w][tid];
+                for (int w = 0; w < nslab; ++w)
+                    if (64 * w < it.tn) t += (double)part_red[k * nslab + w][ms];
                 if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
                 else atomicAdd(phi + en.x + c0 + tid, t);
             }
