@@ -272,7 +272,6 @@ void drop_self_pairs(Lists& L) {
 }
 
 void compute(bldtt_plan* pl, double* out, hipStream_t st) {
-    double t0 = now_ms();
     const Tree& T = pl->T();
     const Tree& S = pl->S;
     const DevTree dS = pl->dS.view(), dT = pl->dT().view();
@@ -283,8 +282,8 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const bool symm = pl->symmetric_pp();
     const int tile = kBlockThreads * pl->tpt, ptile = kBlockThreads * pl->tpt_proxy;
 
-    collect_profile(pl);
-    t0 = now_ms();
+    collect_profile(pl);                // waits for the previous compute's events (BLDTT_PROFILE)
+    const double t0 = now_ms();
     auto mark_host = [&](int k) { pl->stats.host_marks_ms[k] = now_ms() - t0; };
     // 1. upward pass, overlapping the host traversal: at the base degree, or
     //    for a per-pair degree plan at the source degrees its last compute used
