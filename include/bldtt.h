@@ -199,7 +199,8 @@ typedef struct {
     int32_t target_depth, source_depth;
     double setup_ms;               /* tree build and uploads                             */
     double traverse_ms;            /* host traversal + list packing of the last compute  */
-    double compute_host_ms;        /* host wall time inside the last bldtt_compute       */
+    double compute_host_ms;        /* host wall time inside the last bldtt_compute (after
+                                      any wait for the previous one's profile events)    */
     double phase_ms[BLDTT_N_PHASES];/* BLDTT_PROFILE: device time per phase, summed over
                                       every profiled compute so far (HIP events)         */
     int64_t profiled_computes;     /* number of computes summed in phase_ms              */
