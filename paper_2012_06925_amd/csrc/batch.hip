@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
                 up_seen = true;
             }
             interact_body<KIND, F32, T, true>(it, a.qentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
-                                              nullptr, a.po, vl, a.n_c > 0 ? 2 : 0);
+                                              nullptr, a.po, vl, a.n_c > 0 ? OUT_ATOMIC : OUT_WRITE);
             signal(a.dn + it.cluster);
         } else if (t < e2) {
             if constexpr (!F32 && KIND == K_COULOMB) {
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
                 up_seen = true;
             }
             interact_body<KIND, F32, T, false>(it, a.pentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
-                                               a.phi_tree, a.po, vl, a.n_s > 0 ? 2 : 0);
+                                               a.phi_tree, a.po, vl, a.n_s > 0 ? OUT_ATOMIC : OUT_WRITE);
             signal(a.pdone + i);
         } else if (t < es) {
             if constexpr (!F32 && KIND == K_COULOMB) {

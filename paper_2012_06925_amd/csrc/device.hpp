@@ -191,14 +191,18 @@ constexpr int interact_lds_bytes() { return kChunk * (int)sizeof(typename Stage<
 // owns targets (w mod nslab)*64*T + l + 64 j, j < T, and the copies' sums are
 // added in LDS at the end (an item with few targets keeps every wave busy).
 // Sources are staged through LDS and read by all lanes at the same address.
-// Particle targets are written (out = sum) or, with `add`, accumulated
-// (out += sum) for a second pass over other entries of the same targets.
+// `add` says how the sums are stored: written, added to what the outputs hold
+// (a second pass over the same targets), or added with atomics (other items
+// add to the same outputs concurrently).
 // ---------------------------------------------------------------------------
+enum { OUT_WRITE = 0, OUT_ADD = 1, OUT_ATOMIC = 2 };
+
 template <int KIND, bool F32, int T, bool PROXY_TGT>
 __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __restrict__ entries, DevParticles tgt,
                                               DevTree Tt, DevParticles src, DevTree S, const double* __restrict__ tab,
                                               const DegPtrs& qhat, double param, double* __restrict__ out,
-                                              const DegOut& pout, typename Stage<F32>::V* lds, int add = 0) {
+                                              const DegOut& pout, typename Stage<F32>::V* lds,
+                                              int add = OUT_WRITE) {
     using St = Stage<F32>;
     using V = typename St::V;
     using R = typename std::conditional<F32, float, double>::type;
@@ -327,10 +331,13 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
         if (r < it.tn) {
             if (PROXY_TGT) {
                 double* o = pout.p[it.degree] + (int64_t)it.slot * Pt + it.t0 + r;
-                if (add == 2) atomicAdd(o, acc[j]);                      // others add to these proxies too
+                if (add == OUT_ATOMIC) atomicAdd(o, acc[j]);
                 else *o = acc[j];
-            } else if (add == 2) atomicAdd(out + it.slot + r, acc[j]);   // others add to these targets too
-            else out[it.slot + r] = add ? out[it.slot + r] + acc[j] : acc[j];
+            } else if (add == OUT_ATOMIC) {
+                atomicAdd(out + it.slot + r, acc[j]);
+            } else {
+                out[it.slot + r] = add == OUT_ADD ? out[it.slot + r] + acc[j] : acc[j];
+            }
         }
     }
 }

@@ -726,7 +726,7 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
     if (n_items <= 0) return;
     if (add && proxy_targets) throw Error(-1, "accumulating mode is for particle targets");
     if (fp32 && k.kind == K_POLY) throw Error(-5, "the polynomial test kernel runs in FP64 only");
-#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, add ? 1 : 0, st)
+#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, add ? OUT_ADD : OUT_WRITE, st)
     if (fp32) {
         if (proxy_targets) { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, true)); }
         else { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, false)); }
