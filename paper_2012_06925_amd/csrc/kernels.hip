@@ -105,10 +105,10 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
 // ---------------------------------------------------------------------------
 // The same symmetric passes in FP32 evaluation with the squared distances on
 // the FP64 matrix cores.  With coordinates relative to the target cluster's
-// centre, |x_i - y_j|^2 = (x_i, |x_i|^2) . (-2 y_j, 1) + |y_j|^2, so one
-// v_mfma_f64_16x16x4f64 with A = (x, y, z, |x|^2) per target row, B = (-2y, 1)
-// per source column and C = |y_j|^2 gives 256 squared distances to FP64
-// accuracy (error ~1e-16 of the squared extent, far below the FP32 rounding of
+// centre, |x_i - y_j|^2 = (x_i, 1) . (-2 y_j, |y_j|^2) + |x_i|^2, so one
+// v_mfma_f64_16x16x4f64 with A = (x, y, z, 1) per target row, B = (-2y, |y|^2)
+// per source column and C = |x_i|^2 (per target row, held in registers for the
+// whole item) gives 256 squared distances to FP64 accuracy (error ~1e-16 of the squared extent, far below the FP32 rounding of
 // G for every pair not closer than ~1e-4 of a leaf); the vector ALUs then take
 // per pair one conversion, one FP32 reciprocal square root and the two
 // products q_j G and q_i G.  A wave holds 64 targets as four 16-row blocks and
@@ -130,19 +130,17 @@ constexpr int kSymChunk = 256;                  // sources per chunk: 16 tiles o
 constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q = 0)
 
 template <bool GUARD>
-__device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB)[64], const double* __restrict__ sN,
-                                          const float* __restrict__ sQ, float (*__restrict__ part)[64], int lane,
-                                          const double (&A)[4], const float (&qi)[4][4], float (&acc)[4][4],
+__device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB)[64], const float* __restrict__ sQ,
+                                          float (*__restrict__ part)[64], int lane, const double (&A)[4],
+                                          const v4d (&C)[4], const float (&qi)[4][4], float (&acc)[4][4],
                                           float thr) {
     const int col = lane & 15;
     for (int t = 0; t < nt; ++t) {
         const double bv = sB[t][lane];
-        const double n = sN[16 * t + col];
         const float qj = sQ[16 * t + col];
-        const v4d C{n, n, n, n};
         v4d d[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C);
+        for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C[b]);
         float psi = 0.0f;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -160,13 +158,12 @@ __device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB
 }
 
 template <bool PROXY>
-__global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__ items,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_mfma(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles p, DevTree T,
                                                      double* __restrict__ phi, const double* __restrict__ tab,
                                                      DegPtrs qhat, DegOut phihat) {
     __shared__ double sT[4][kBlock];             // target tile: relative x, y, z and q
     __shared__ double sB[16][64];                // B operands of the chunk's tiles, in lane order
-    __shared__ double sN[kSymChunk];             // |y|^2 of the chunk's sources
     __shared__ float sQ[kSymChunk];              // source charges of the chunk
     __shared__ float part[4][16][64];            // source partials per wave, tile and lane
     const DevItem it = items[blockIdx.x];
@@ -211,24 +208,27 @@ __global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__
     }
     __syncthreads();
     double A[4];
+    v4d C[4];
     float qi[4][4], acc[4][4];
-    double acc64[4][4];
+    // FP64 target sums of slots k = 8 h + j (k = 4 b + r, h = bit 3 of the lane's
+    // column), each over the lane pair {col, col ^ 8}
+    double acc64[8];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int base = 64 * wave + 16 * b;
-        if (grp < 3) {
-            A[b] = sT[grp][base + col];
-        } else {
-            const double x = sT[0][base + col], y = sT[1][base + col], z = sT[2][base + col];
-            A[b] = fma(x, x, fma(y, y, z * z));
-        }
+        A[b] = grp < 3 ? sT[grp][base + col] : 1.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            qi[b][r] = (float)sT[3][base + grp + 4 * r];
+            const int i = base + grp + 4 * r;
+            const double x = sT[0][i], y = sT[1][i], z = sT[2][i];
+            C[b][r] = fma(x, x, fma(y, y, z * z));
+            qi[b][r] = (float)sT[3][i];
             acc[b][r] = 0.0f;
-            acc64[b][r] = 0.0;
         }
     }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc64[j] = 0.0;
+    const bool hi = (col & 8) != 0;
 
     // this thread's source of a chunk (entry e, offset c0), relative to the centre
     double nx = kFarS, ny = kFarS, nz = kFarS, nq = 0.0;
@@ -267,8 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__
             sB[t][j] = -2.0 * nx;
             sB[t][16 + j] = -2.0 * ny;
             sB[t][32 + j] = -2.0 * nz;
-            sB[t][48 + j] = 1.0;
-            sN[tid] = fma(nx, nx, fma(ny, ny, nz * nz));
+            sB[t][48 + j] = fma(nx, nx, fma(ny, ny, nz * nz));
             sQ[tid] = (float)nq;
         }
         __syncthreads();
@@ -279,15 +278,21 @@ __global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc, thr);
-            else sym_tiles<false>(nt, sB, sN, sQ, part[wave], lane, A, qi, acc, thr);
+            if (guard) sym_tiles<true>(nt, sB, sQ, part[wave], lane, A, C, qi, acc, thr);
+            else sym_tiles<false>(nt, sB, sQ, part[wave], lane, A, C, qi, acc, thr);
+            // slots k and k + 8 of lanes col and col ^ 8 (row_ror:8 within a row of 16)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float lo = acc[j >> 2][j & 3], up = acc[2 + (j >> 2)][j & 3];
+                const float keep = hi ? up : lo, send = hi ? lo : up;
+                const float other = __builtin_bit_cast(
+                    float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xf, 0xf, true));
+                acc64[j] += (double)(keep + other);
+            }
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    acc64[b][r] += (double)acc[b][r];
-                    acc[b][r] = 0.0f;
-                }
+                for (int r = 0; r < 4; ++r) acc[b][r] = 0.0f;
         }
         __syncthreads();
         if (c0 + tid < bn) {
@@ -304,16 +309,15 @@ __global__ __launch_bounds__(kBlock) void k_sym_mfma(const DevItem* __restrict__
         c0 = c2;
     }
     if (active) {
+        // lane col keeps slot k = col, summed over the remaining lanes col ^ 1, 2, 4
         double v = 0.0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int j = 0; j < 8; ++j) {
+            double s = acc64[j];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double s = acc64[b][r];
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                v = col == 4 * b + r ? s : v;
-            }
+            for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            v = (col & 7) == j ? s : v;
+        }
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
         if (row < it.tn) {
             if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
