@@ -107,18 +107,21 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
 // the FP64 matrix cores.  With coordinates relative to the target cluster's
 // centre, |x_i - y_j|^2 = (x_i, 1) . (-2 y_j, |y_j|^2) + |x_i|^2, so one
 // v_mfma_f64_16x16x4f64 with A = (x, y, z, 1) per target row, B = (-2y, |y|^2)
-// per source column and C = |x_i|^2 (per target row, held in registers for the
-// whole item) gives 256 squared distances to FP64 accuracy (error ~1e-16 of the squared extent, far below the FP32 rounding of
-// G for every pair not closer than ~1e-4 of a leaf); the vector ALUs then take
-// per pair one conversion, one FP32 reciprocal square root and the two
-// products q_j G and q_i G.  A wave holds 64 targets as four 16-row blocks and
-// walks the sources 16 at a time, one B operand serving four products.  In
-// the result lane l holds column l mod 16 of rows l/16 + 4r: target sums are
-// per-lane partials (FP32 per chunk, then FP64) reduced over the 16 lanes of a
-// row at the end; each tile's source sums are per-lane partials written to LDS
-// and summed over the 4 lane groups and 4 waves after each chunk of up to 256
-// sources, then added with one FP64 atomic per source.  The next chunk's
-// sources are loaded into registers while the current one is evaluated.
+// per source column and C = |x_i|^2 (per target row, held in registers for
+// the whole item) gives 256 squared distances to FP64 accuracy (error ~1e-16
+// of the squared extent, far below the FP32 rounding of G for every pair not
+// closer than ~1e-4 of a leaf); the vector ALUs then take per pair one
+// conversion, one FP32 reciprocal square root and the two products q_j G and
+// q_i G.  A wave holds 64 targets as four 16-row blocks and walks the sources
+// 16 at a time, one B operand serving four products.  In the result lane l
+// holds column l mod 16 of rows l/16 + 4r.  Target sums are per-lane FP32
+// partials over a chunk of up to 256 sources, then added in FP64 pairwise
+// across lanes l and l ^ 8 (16 slots per lane become 8), and reduced over the
+// rest of the row at the end.  Each tile's source sums are per-lane partials
+// written to LDS; after the chunk one thread per source adds the 4 lane
+// groups' values in FP32 and the 4 waves' in FP64, in a fixed order, and adds
+// the sum with one FP64 atomic.  The next chunk's sources are loaded into registers
+// while the current one is evaluated.
 // Entries flagged SRC_RANGE_GUARD (a leaf with itself, or leaf boxes within
 // 2^-20 of their extent) drop pairs whose computed squared distance is at
 // most 2^-42 of the target box's squared diagonal: coincident points, whose
@@ -129,15 +132,19 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
 constexpr int kSymChunk = 256;                  // sources per chunk: 16 tiles of 16
 constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q = 0)
 
+// A lane's operands for one tile: its B entry and the charge of its source column
+struct alignas(16) SymB {
+    double b;
+    float q, pad;
+};
+
 template <bool GUARD>
-__device__ __forceinline__ void sym_tiles(int nt, const double (*__restrict__ sB)[64], const float* __restrict__ sQ,
-                                          float (*__restrict__ part)[64], int lane, const double (&A)[4],
-                                          const v4d (&C)[4], const float (&qi)[4][4], float (&acc)[4][4],
-                                          float thr) {
-    const int col = lane & 15;
+__device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[64], float (*__restrict__ part)[64],
+                                          int lane, const double (&A)[4], const v4d (&C)[4],
+                                          const float (&qi)[4][4], float (&acc)[4][4], float thr) {
     for (int t = 0; t < nt; ++t) {
-        const double bv = sB[t][lane];
-        const float qj = sQ[16 * t + col];
+        const double bv = sB[t][lane].b;
+        const float qj = sB[t][lane].q;
         v4d d[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C[b]);
@@ -163,8 +170,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                                                      double* __restrict__ phi, const double* __restrict__ tab,
                                                      DegPtrs qhat, DegOut phihat) {
     __shared__ double sT[4][kBlock];             // target tile: relative x, y, z and q
-    __shared__ double sB[16][64];                // B operands of the chunk's tiles, in lane order
-    __shared__ float sQ[kSymChunk];              // source charges of the chunk
+    __shared__ SymB sB[16][64];                  // the chunk's tiles, in lane order
     __shared__ float part[4][16][64];            // source partials per wave, tile and lane
     const DevItem it = items[blockIdx.x];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
@@ -264,11 +270,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int nt = min(16, (bn - c0 + 15) >> 4);
         {
             const int t = tid >> 4, j = tid & 15;
-            sB[t][j] = -2.0 * nx;
-            sB[t][16 + j] = -2.0 * ny;
-            sB[t][32 + j] = -2.0 * nz;
-            sB[t][48 + j] = fma(nx, nx, fma(ny, ny, nz * nz));
-            sQ[tid] = (float)nq;
+            const float q = (float)nq;
+            sB[t][j] = SymB{-2.0 * nx, q, 0.0f};
+            sB[t][16 + j] = SymB{-2.0 * ny, q, 0.0f};
+            sB[t][32 + j] = SymB{-2.0 * nz, q, 0.0f};
+            sB[t][48 + j] = SymB{fma(nx, nx, fma(ny, ny, nz * nz)), q, 0.0f};
         }
         __syncthreads();
         int e2 = e, c2 = c0 + kSymChunk;
@@ -278,8 +284,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true>(nt, sB, sQ, part[wave], lane, A, C, qi, acc, thr);
-            else sym_tiles<false>(nt, sB, sQ, part[wave], lane, A, C, qi, acc, thr);
+            if (guard) sym_tiles<true>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+            else sym_tiles<false>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
             // slots k and k + 8 of lanes col and col ^ 8 (row_ror:8 within a row of 16)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -300,8 +306,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             double s = 0.0;
             for (int w = 0; w < 4; ++w)
                 if (64 * w < it.tn)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) s += (double)part[w][t][16 * k + j];
+                    s += (double)((part[w][t][j] + part[w][t][16 + j]) + (part[w][t][32 + j] + part[w][t][48 + j]));
             if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
             else atomicAdd(phi + en.x + c0 + tid, s);
         }
