@@ -142,7 +142,8 @@ template <bool GUARD>
 __device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[64], float (*__restrict__ part)[64],
                                           int lane, const double (&A)[4], const v4d (&C)[4],
                                           const float (&qi)[4][4], float (&acc)[4][4], float thr) {
-    for (int t = 0; t < nt; ++t) {
+    // the first tile of a chunk starts the FP32 target partials
+    auto tile = [&](int t, auto first) {
         const double bv = sB[t][lane].b;
         const float qj = sB[t][lane].q;
         v4d d[4];
@@ -156,12 +157,15 @@ __device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[
                 const float rf = (float)d[b][r];
                 float y = __builtin_amdgcn_rsqf(rf);
                 if constexpr (GUARD) y = rf > thr ? y : 0.0f;
-                acc[b][r] = fmaf(qj, y, acc[b][r]);
+                if constexpr (decltype(first)::value) acc[b][r] = qj * y;
+                else acc[b][r] = fmaf(qj, y, acc[b][r]);
                 psi = fmaf(qi[b][r], y, psi);
             }
         }
         part[t][lane] = psi;
-    }
+    };
+    tile(0, std::true_type{});
+    for (int t = 1; t < nt; ++t) tile(t, std::false_type{});
 }
 
 template <bool PROXY>
@@ -295,10 +299,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xf, 0xf, true));
                 acc64[j] += (double)(keep + other);
             }
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[b][r] = 0.0f;
         }
         __syncthreads();
         if (c0 + tid < bn) {
