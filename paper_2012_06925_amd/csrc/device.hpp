@@ -144,9 +144,16 @@ struct E32 {
 };
 
 // Proxy point k of a cluster box (flat index k1 + m k2 + m^2 k3).
+// k div m for 0 <= k < 2^16 and 1 <= m <= 13: (k + 1/2) / m lies at least
+// 1/(2m) inside the interval of its quotient, far beyond FP32 rounding
+__device__ __forceinline__ int small_div(int k, int m) {
+    return (int)(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)m));
+}
+
 __device__ __forceinline__ void proxy_point(const double* __restrict__ box, int m, const double* __restrict__ tab,
                                             int k, double& x, double& y, double& z) {
-    int k1 = k % m, k2 = (k / m) % m, k3 = k / (m * m);
+    const int j = small_div(k, m), k3 = small_div(j, m);
+    const int k1 = k - j * m, k2 = j - k3 * m;
     x = node_at(box[0], box[3], tab[k1]);
     y = node_at(box[1], box[4], tab[k2]);
     z = node_at(box[2], box[5], tab[k3]);
