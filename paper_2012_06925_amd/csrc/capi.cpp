@@ -337,6 +337,16 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     soon as their items are packed; the remaining near-field pairs
         //     (few: those listed one way only) follow on the same stream.
         Lists& near_rest = pl->near_rest;
+        // The model's degree inference is small, but launched beside the
+        // near-field pass it gets the GPU only as that pass drains, some 10 ms
+        // in on a loaded MI355X: for a short near-field pass it goes first on
+        // the second stream (the pass starts a little later); for a long one
+        // it stays on st and the separated pairs still overlap the pass.
+        {
+            const double leaf = (double)T.n_particles / std::max<int64_t>(1, pl->n_tgt_leaves);
+            if ((double)pl->lists.tc[PP].size() * leaf * leaf < bldtt_plan::kEarlyInferencePairs)
+                select_degrees_begin(pl, pl->side);
+        }
         auto fork = [&] {
             HIPCHK(hipEventRecord(pl->ev_fork, st));
             HIPCHK(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
@@ -534,6 +544,8 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
         if (pl->S.is_leaf(c)) leaves.push_back((int32_t)c);
     upload(pl->src_leaves, leaves);
     pl->n_src_leaves = (int)leaves.size();
+    pl->n_tgt_leaves = 0;
+    for (int64_t c = 0; c < T.size(); ++c) pl->n_tgt_leaves += T.is_leaf(c) ? 1 : 0;
     std::vector<int32_t> ids;
     level_lists(pl->S, true, ids, pl->up_off);
     upload(pl->up_parents, ids);
@@ -545,6 +557,7 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     HIPCHK(hipEventCreateWithFlags(&pl->staging_rest_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_near_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->ev_select, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
     HIPCHK(hipEventRecord(pl->staging_near_free, st));
     HIPCHK(hipEventRecord(pl->staging_rest_free, st));

@@ -13,27 +13,86 @@
 
 namespace bldtt {
 
-void pair_features(double rt, double rs, double R, int64_t ct, int64_t cs, float f[4]) {
-    // radii below 1e-6 R (single points, flat boxes) are floored there
+namespace {
+
+// f0, f1: radii below 1e-6 R (single points, flat boxes) are floored there
+void geometry_features(double rt, double rs, double R, float f[2]) {
     const double floor_r = 1e-6 * R;
     const double a = std::max(rt, floor_r), b = std::max(rs, floor_r);
     f[0] = (float)std::log(a / b);
     f[1] = (float)std::log(R / std::max(rt + rs, floor_r));
+}
+
+}  // namespace
+
+void pair_features(double rt, double rs, double R, int64_t ct, int64_t cs, float f[4]) {
+    geometry_features(rt, rs, R, f);
     f[2] = (float)std::log((double)ct);
     f[3] = (float)std::log((double)cs);
 }
 
 namespace {
 
-void features_of(const Tree& T, const Tree& S, int64_t t, int64_t s, float f[4]) {
+// The features of pair (t, s), with the logarithms of the cluster sizes (f2,
+// f3) from per-cluster tables (the same values, two logarithms fewer per pair).
+void features_of(const Tree& T, const Tree& S, const float* lct, const float* lcs, int64_t t, int64_t s, float f[4]) {
     double dx = T.center[3 * t] - S.center[3 * s];
     double dy = T.center[3 * t + 1] - S.center[3 * s + 1];
     double dz = T.center[3 * t + 2] - S.center[3 * s + 2];
     double R = std::sqrt((dx * dx + dy * dy) + dz * dz);
-    pair_features(T.radius[t], S.radius[s], R, T.count[t], S.count[s], f);
+    geometry_features(T.radius[t], S.radius[s], R, f);
+    f[2] = lct[t];
+    f[3] = lcs[s];
+}
+
+void log_counts(const Tree& T, std::vector<float>& out) {
+    if ((int64_t)out.size() == T.size()) return;
+    out.resize(T.size());
+    for (int64_t c = 0; c < T.size(); ++c) out[c] = (float)std::log((double)T.count[c]);
 }
 
 }  // namespace
+
+void select_degrees_begin(bldtt_plan* pl, hipStream_t st) {
+    Lists& L = pl->lists;
+    const Tree& T = pl->T();
+    const Tree& S = pl->S;
+    const bool ppcc = (pl->flags & BLDTT_PP_CC_ONLY) != 0;
+    DegreePolicy& pol = pl->policy;
+    const int64_t n = (int64_t)L.sep_tc.size();
+    pl->select_pending = false;
+    if (pol.mode != 1 || n == 0) return;
+    // features and counts -> device -> MLP + choice -> host, ordered on st;
+    // select_degrees waits for the choices
+    HIPCHK(hipEventSynchronize(pl->staging_free));
+    const size_t bf = sizeof(float) * 4 * n, bc = sizeof(int64_t) * 2 * n;
+    pl->sel_in.reserve(bf + bc);
+    pl->sel_out.reserve(n);
+    float* hf = static_cast<float*>(pl->sel_in.p);
+    int64_t* hc = reinterpret_cast<int64_t*>(static_cast<char*>(pl->sel_in.p) + bf);
+    log_counts(T, pl->log_count_t);
+    log_counts(S, pl->log_count_s);
+    const float* lct = pl->log_count_t.data();
+    const float* lcs = pl->log_count_s.data();
+    parallel_run((n + 4095) / 4096, [&](int64_t blk) {
+        for (int64_t p = blk * 4096; p < std::min(n, (blk + 1) * 4096); ++p) {
+            features_of(T, S, lct, lcs, L.sep_tc[p], L.sep_sc[p], hf + 4 * p);
+            hc[2 * p] = T.count[L.sep_tc[p]];
+            hc[2 * p + 1] = S.count[L.sep_sc[p]];
+        }
+    });
+    pl->sel_feats.reserve(bf);
+    pl->sel_counts.reserve(bc);
+    pl->sel_choice.reserve(n);
+    HIPCHK(hipMemcpyAsync(pl->sel_feats.p, hf, bf, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(pl->sel_counts.p, hc, bc, hipMemcpyHostToDevice, st));
+    launch_mlp_select(static_cast<const float*>(pol.dev_model), pl->sel_feats.as<float>(),
+                      pl->sel_counts.as<int64_t>(), n, (float)std::log10(pol.tau), pol.fallback, ppcc ? 1 : 0,
+                      pl->sel_choice.as<uint8_t>(), st);
+    HIPCHK(hipMemcpyAsync(pl->sel_out.p, pl->sel_choice.p, n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(pl->ev_select, st));
+    pl->select_pending = true;
+}
 
 void select_degrees(bldtt_plan* pl, hipStream_t st) {
     Lists& L = pl->lists;
@@ -48,32 +107,12 @@ void select_degrees(bldtt_plan* pl, hipStream_t st) {
     std::fill(std::begin(pol.degree_count), std::end(pol.degree_count), 0);
     std::vector<uint8_t> choice(n);
     if (pol.mode == 1 && n > 0) {
-        // features and counts -> device -> MLP + choice -> host
-        HIPCHK(hipEventSynchronize(pl->staging_free));
-        const size_t bf = sizeof(float) * 4 * n, bc = sizeof(int64_t) * 2 * n;
-        pl->sel_in.reserve(bf + bc);
-        pl->sel_out.reserve(n);
-        float* hf = static_cast<float*>(pl->sel_in.p);
-        int64_t* hc = reinterpret_cast<int64_t*>(static_cast<char*>(pl->sel_in.p) + bf);
-        parallel_run((n + 4095) / 4096, [&](int64_t blk) {
-            for (int64_t p = blk * 4096; p < std::min(n, (blk + 1) * 4096); ++p) {
-                features_of(T, S, L.sep_tc[p], L.sep_sc[p], hf + 4 * p);
-                hc[2 * p] = T.count[L.sep_tc[p]];
-                hc[2 * p + 1] = S.count[L.sep_sc[p]];
-            }
-        });
-        pl->sel_feats.reserve(bf);
-        pl->sel_counts.reserve(bc);
-        pl->sel_choice.reserve(n);
-        HIPCHK(hipMemcpyAsync(pl->sel_feats.p, hf, bf, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(pl->sel_counts.p, hc, bc, hipMemcpyHostToDevice, st));
-        launch_mlp_select(static_cast<const float*>(pol.dev_model), pl->sel_feats.as<float>(),
-                          pl->sel_counts.as<int64_t>(), n, (float)std::log10(pol.tau), pol.fallback, ppcc ? 1 : 0,
-                          pl->sel_choice.as<uint8_t>(), st);
-        HIPCHK(hipMemcpyAsync(pl->sel_out.p, pl->sel_choice.p, n, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        if (!pl->select_pending) select_degrees_begin(pl, st);
+        HIPCHK(hipEventSynchronize(pl->ev_select));
+        pl->select_pending = false;
         std::memcpy(choice.data(), pl->sel_out.p, n);
         // pairs outside the training range took the fallback degree
+        const float* hf = static_cast<const float*>(pl->sel_in.p);
         const float* lo = pol.model.data() + kNParams + 2 * kNIn;
         const float* hi = lo + kNIn;
         for (int64_t p = 0; p < n; ++p) {

@@ -147,6 +147,7 @@ struct bldtt_plan {
     const DevTreeBufs& dT() const { return aliased ? dS : dTsep; }
     DevBuf src_leaves, up_parents, down_kids;
     int n_src_leaves = 0;
+    int64_t n_tgt_leaves = 0;
     std::vector<int64_t> up_off, down_off;   // per level offsets into up_parents / down_kids
     DevBuf pitems, pentries, qitems, qentries, has_far, prolong;
     DegreePolicy policy;                     // per-pair degree choice (BLDTT_LEARNED_DEGREE)
@@ -168,6 +169,13 @@ struct bldtt_plan {
     // while the host chooses the degrees (capi.cpp, compute).
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_near_done = nullptr, staging_near_free = nullptr, staging_rest_free = nullptr;
+    // near-field terms (PP list entries x mean leaf size^2, both directions of a
+    // pair counted) below which the degree inference runs before the near-field
+    // pass: about 25 ms of that pass on an MI355X
+    static constexpr double kEarlyInferencePairs = 1.5e11;
+    hipEvent_t ev_select = nullptr;          // the degree choices are on the host
+    bool select_pending = false;
+    std::vector<float> log_count_t, log_count_s;   // per cluster: log of its particle count
     PinnedBuf staging_near, staging_rest;
     Work work_near;
     DevBuf near_items, near_entries, sep_items;
@@ -198,7 +206,7 @@ struct bldtt_plan {
     ~bldtt_plan() {
         if (policy.dev_model) (void)hipFree(policy.dev_model);
         if (staging_free) (void)hipEventDestroy(staging_free);
-        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free})
+        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free, ev_select})
             if (e) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
         for (auto& e : prof_ev)
@@ -210,6 +218,9 @@ struct bldtt_plan {
 namespace bldtt {
 // Per-pair (type, degree) choice for the separated pairs of the last traversal
 // (BLDTT_LEARNED_DEGREE): moves plan->lists.sep_* into the typed lists.
+// select_degrees_begin enqueues the model's inference on st early (optional);
+// select_degrees waits for it, or runs it on st itself.
+void select_degrees_begin(bldtt_plan* pl, hipStream_t st);
 void select_degrees(bldtt_plan* pl, hipStream_t st);
 // Proxy charges of every source cluster at degree d into plan->qhat_deg[d].
 void upward(bldtt_plan* pl, int d, hipStream_t st);
