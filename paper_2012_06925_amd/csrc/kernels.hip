@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const DevItem* __restrict__ 
         __syncthreads();
         // x: (md, md, md) -> (mD, md, md)
         for (int idx = threadIdx.x; idx < mD * md * md; idx += kBlock) {
-            int kb = idx % mD, rest = idx / mD;
+            const int rest = small_div(idx, mD), kb = idx - rest * mD;
             double s = 0.0;
             for (int k = 0; k < md; ++k) s = fma(mat[0][k][kb], a[k + md * rest], s);
             b[idx] = s;
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const DevItem* __restrict__ 
         __syncthreads();
         // y: (mD, md, md) -> (mD, mD, md)
         for (int idx = threadIdx.x; idx < mD * mD * md; idx += kBlock) {
-            int i1 = idx % mD, kb = (idx / mD) % mD, i3 = idx / (mD * mD);
+            const int j = small_div(idx, mD), i3 = small_div(j, mD), i1 = idx - j * mD, kb = j - i3 * mD;
             double s = 0.0;
             for (int k = 0; k < md; ++k) s = fma(mat[1][k][kb], b[i1 + mD * (k + md * i3)], s);
             a[idx] = s;
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const DevItem* __restrict__ 
         __syncthreads();
         // z: (mD, mD, md) -> (mD, mD, mD), added to the degree-D proxy potentials
         for (int idx = threadIdx.x; idx < PD; idx += kBlock) {
-            int i12 = idx % (mD * mD), kb = idx / (mD * mD);
+            const int kb = small_div(small_div(idx, mD), mD), i12 = idx - kb * mD * mD;
             double s = 0.0;
             for (int k = 0; k < md; ++k) s = fma(mat[2][k][kb], a[i12 + mD * mD * k], s);
             to[(int64_t)c * PD + idx] += s;
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(DevTree T, const double* __
         __syncthreads();
         // x: (mD, mD, mD) -> (md, mD, mD)
         for (int idx = threadIdx.x; idx < md * mD * mD; idx += kBlock) {
-            int k = idx % md, rest = idx / md;
+            const int rest = small_div(idx, md), k = idx - rest * md;
             double s = 0.0;
             for (int kb = 0; kb < mD; ++kb) s = fma(mat[0][k][kb], a[kb + mD * rest], s);
             b[idx] = s;
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(DevTree T, const double* __
         __syncthreads();
         // y: (md, mD, mD) -> (md, md, mD)
         for (int idx = threadIdx.x; idx < md * md * mD; idx += kBlock) {
-            int k1 = idx % md, k = (idx / md) % md, i3 = idx / (md * md);
+            const int j = small_div(idx, md), i3 = small_div(j, md), k1 = idx - j * md, k = j - i3 * md;
             double s = 0.0;
             for (int kb = 0; kb < mD; ++kb) s = fma(mat[1][k][kb], b[k1 + md * (kb + mD * i3)], s);
             e[idx] = s;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(DevTree T, const double* __
         __syncthreads();
         // z: (md, md, mD) -> (md, md, md)
         for (int idx = threadIdx.x; idx < Pd; idx += kBlock) {
-            int k12 = idx % (md * md), k = idx / (md * md);
+            const int k = small_div(small_div(idx, md), md), k12 = idx - k * md * md;
             double s = 0.0;
             for (int kb = 0; kb < mD; ++kb) s = fma(mat[2][k][kb], e[k12 + md * md * kb], s);
             to.p[d][(int64_t)c * Pd + idx] = s;
