@@ -815,13 +815,13 @@ __device__ __forceinline__ void down_leaf_mfma_body(const DevItem& it, bool far,
 //   CC (pairs of clusters {A, B} at one degree): phihat_A[l] += G qhat_B[k] and
 //      phihat_B[k] += G qhat_A[l] -- the proxy grids of a cluster are the same
 //      points whether it is the target or the source.
-// One work item = a tile of up to 256 target points of A (64 per wave) and the
-// entries of its partners B.  Sources are staged 64 at a time in LDS (twice,
-// so step s reads src[lane + s]); at step s lane l pairs its target with
-// source (l + s) mod 64 and adds q_i G to a running source partial that moves
-// one lane down per step (DPP wave_rol:1: lane l receives lane l + 1), so
-// after 64 steps lane l holds the partial of source (l - 1) mod 64 over the 64
-// targets of its wave.  The wave partials are summed in LDS and added to the
+// One work item = a tile of up to 256 target points of A (128 per wave, two
+// per lane) and the entries of its partners B.  Sources are staged 64 at a
+// time in LDS (twice, so step s reads src[lane + s]); at step s lane l pairs
+// its targets with source (l + s) mod 64 and adds q_i G to a running source
+// partial that moves one lane down per step (DPP wave_rol:1: lane l receives
+// lane l + 1), so after 64 steps lane l holds the partial of source (l - 1)
+// mod 64 over the 128 targets of its wave.  The wave partials are summed in LDS and added to the
 // source's output with one FP64 atomic per source; each target's sum is added
 // with one atomic at the end.  Results are reproducible to rounding only: the
 // order of the atomics varies.  PP ranges flagged SRC_RANGE_GUARD (a leaf
@@ -849,10 +849,12 @@ constexpr int sym_lds_bytes() {
            4 * 64 * (int)sizeof(typename std::conditional<F32, float, double>::type);
 }
 
-// One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  An item
-// whose targets fill nslab = 1 or 2 waves runs 4 / nslab copies of those
-// waves, each over its own 64 of the 64 * copies sources staged per round
-// (each copy adds its own target partials with its atomics).
+// One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  Each lane
+// holds two targets (rows lane and 64 + lane of its wave's 128), so a staged
+// source and the move of its partial serve two pairs.  An item whose targets
+// fill nslab = 1 or 2 waves runs 4 / nslab copies of those waves, each over
+// its own 64 of the 64 * copies sources staged per round (each copy adds its
+// own target partials with its atomics).
 template <bool F32, bool PROXY>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, double* __restrict__ phi, const double* __restrict__ tab,
@@ -864,11 +866,11 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     V* src = static_cast<V*>(lds);                               // per copy: 64 staged sources, twice
     R (*part_red)[64] = reinterpret_cast<R (*)[64]>(src + 4 * 128);  // [4][64] wave partials
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nslab = it.tn <= 64 ? 1 : (it.tn <= 128 ? 2 : 4);
+    const int nslab = it.tn <= 128 ? 1 : 2;
     const int copies = 4 / nslab, copy = wave / nslab, sw = wave % nslab;
     const int span = 64 * copies;                                // sources staged per round
     const V* mysrc = src + 128 * copy;
-    const bool active = 64 * sw < it.tn;
+    const bool active = 128 * sw < it.tn;
     const double* box = T.box + 6 * it.cluster;
     const double cx = F32 ? 0.5 * (box[0] + box[3]) : 0.0, cy = F32 ? 0.5 * (box[1] + box[4]) : 0.0,
                  cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
@@ -876,27 +878,34 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     const int m = it.degree + 1, P = m * m * m;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
     double* od = PROXY ? phihat.p[it.degree] : nullptr;
-    const int r = 64 * sw + lane;
-    const bool mine = r < it.tn;
-    const int ti = it.t0 + (mine ? r : 0);
-    R tx = (R)kFar, ty = (R)kFar, tz = (R)kFar, qi = 0;
-    if (mine) {
-        double x, y, z, q;
-        if constexpr (PROXY) {
-            proxy_point(box, m, tab + 32 * it.degree, ti, x, y, z);
-            q = qd[(int64_t)it.cluster * P + ti];
-        } else {
-            x = p.x[ti];
-            y = p.y[ti];
-            z = p.z[ti];
-            q = p.q[ti];
+    R tx[2], ty[2], tz[2], qi[2];
+    int ti[2];
+    bool mine[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = 128 * sw + 64 * h + lane;
+        mine[h] = r < it.tn;
+        ti[h] = it.t0 + (mine[h] ? r : 0);
+        tx[h] = ty[h] = tz[h] = (R)kFar;
+        qi[h] = 0;
+        if (mine[h]) {
+            double x, y, z, q;
+            if constexpr (PROXY) {
+                proxy_point(box, m, tab + 32 * it.degree, ti[h], x, y, z);
+                q = qd[(int64_t)it.cluster * P + ti[h]];
+            } else {
+                x = p.x[ti[h]];
+                y = p.y[ti[h]];
+                z = p.z[ti[h]];
+                q = p.q[ti[h]];
+            }
+            tx[h] = (R)(x - cx);
+            ty[h] = (R)(y - cy);
+            tz[h] = (R)(z - cz);
+            qi[h] = (R)(qs * q);
         }
-        tx = (R)(x - cx);
-        ty = (R)(y - cy);
-        tz = (R)(z - cz);
-        qi = (R)(qs * q);
     }
-    double acc = 0.0;
+    double acc[2] = {0.0, 0.0};
     for (int e = it.eb; e < it.ee; ++e) {
         const int2 en = entries[e];
         const int low = en.y & ((1 << 29) - 1);
@@ -930,32 +939,36 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
             __syncthreads();
             R psi = 0;
             if (active) {
-                R sum = 0;
-                // 64 steps: lane l pairs its target with source (l + s) mod 64
+                R sum[2] = {0, 0};
+                // 64 steps: lane l pairs its two targets with source (l + s) mod 64
                 auto steps = [&](auto guard) {
 #pragma unroll
                     for (int s = 0; s < 64; ++s) {
                         const V v = mysrc[lane + s];
-                        const R dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
-                        R r2 = dz * dz;
-                        r2 = dy * dy + r2;
-                        r2 = dx * dx + r2;
-                        R y;
-                        if constexpr (F32) {
-                            y = __builtin_amdgcn_rsqf(r2);
-                            if constexpr (decltype(guard)::value) y = r2 > 0.0f ? y : 0.0f;
-                        } else {
-                            double y0 = rsq_est(r2);
-                            if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
-                            y = y0 * fma(-(r2 * y0), y0, 3.0);        // 2 y0 (3 - r^2 y0^2)/2; q staged /2
+                        R y[2];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const R dx = tx[h] - v.x, dy = ty[h] - v.y, dz = tz[h] - v.z;
+                            R r2 = dz * dz;
+                            r2 = dy * dy + r2;
+                            r2 = dx * dx + r2;
+                            if constexpr (F32) {
+                                y[h] = __builtin_amdgcn_rsqf(r2);
+                                if constexpr (decltype(guard)::value) y[h] = r2 > 0.0f ? y[h] : 0.0f;
+                            } else {
+                                double y0 = rsq_est(r2);
+                                if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
+                                y[h] = y0 * fma(-(r2 * y0), y0, 3.0);   // 2 y0 (3 - r^2 y0^2)/2; q staged /2
+                            }
+                            sum[h] = fma(v.w, y[h], sum[h]);
                         }
-                        sum = fma(v.w, y, sum);
-                        psi = rol1(psi) + qi * y;
+                        psi = rol1(psi) + qi[0] * y[0] + qi[1] * y[1];
                     }
                 };
                 if (guard) steps(std::true_type{});
                 else steps(std::false_type{});
-                acc += (double)sum;
+                acc[0] += (double)sum[0];
+                acc[1] += (double)sum[1];
                 part_red[wave][(lane + 63) & 63] = psi;
             }
             __syncthreads();
@@ -963,16 +976,18 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 const int k = tid >> 6, ms = tid & 63;           // copy and source of the round
                 double t = 0.0;
                 for (int w = 0; w < nslab; ++w)
-                    if (64 * w < it.tn) t += (double)part_red[k * nslab + w][ms];
+                    if (128 * w < it.tn) t += (double)part_red[k * nslab + w][ms];
                 if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
                 else atomicAdd(phi + en.x + c0 + tid, t);
             }
         }
     }
-    if (mine) {
-        if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + ti, acc);
-        else atomicAdd(phi + ti, acc);
-    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (mine[h]) {
+            if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + ti[h], acc[h]);
+            else atomicAdd(phi + ti[h], acc[h]);
+        }
 }
 
 }  // namespace dev
