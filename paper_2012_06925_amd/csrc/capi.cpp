@@ -313,9 +313,15 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     if (symm) {
         ensure_self_work(pl);
         PhaseMark mark(pl, BLDTT_PH_PP_SELF, st);
-        launch_interact(ks, fp32, false, pl->tpt, pl->self_items.as<DevItem>(), pl->n_self_items,
-                        pl->self_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                        pl->phi_tree.as<double>(), DegOut{}, st);
+        // FP32 evaluation: the tiles with themselves take their squared
+        // distances from the matrix cores too (closest pairs of the set)
+        if (fp32 && pl->mfma_transfer())
+            launch_self_tiles_mfma(pl->self_items.as<DevItem>(), pl->n_self_items, pl->self_entries.as<int2>(),
+                                   pl->dsrc(), dS, pl->phi_tree.as<double>(), tab, st);
+        else
+            launch_interact(ks, fp32, false, pl->tpt, pl->self_items.as<DevItem>(), pl->n_self_items,
+                            pl->self_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
+                            pl->phi_tree.as<double>(), DegOut{}, st);
         launch_sym(fp32, pl->mfma_transfer(), false, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
                    pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
                    deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);

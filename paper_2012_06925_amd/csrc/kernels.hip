@@ -138,7 +138,8 @@ struct alignas(16) SymB {
     float q, pad;
 };
 
-template <bool GUARD>
+// ONE_SIDED: target sums only (a tile with itself, every ordered pair once)
+template <bool GUARD, bool ONE_SIDED>
 __device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[64], float (*__restrict__ part)[64],
                                           int lane, const double (&A)[4], const v4d (&C)[4],
                                           const float (&qi)[4][4], float (&acc)[4][4], float thr) {
@@ -159,16 +160,18 @@ __device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[
                 if constexpr (GUARD) y = rf > thr ? y : 0.0f;
                 if constexpr (decltype(first)::value) acc[b][r] = qj * y;
                 else acc[b][r] = fmaf(qj, y, acc[b][r]);
-                psi = fmaf(qi[b][r], y, psi);
+                if constexpr (!ONE_SIDED) psi = fmaf(qi[b][r], y, psi);
             }
         }
-        part[t][lane] = psi;
+        if constexpr (!ONE_SIDED) part[t][lane] = psi;
     };
     tile(0, std::true_type{});
     for (int t = 1; t < nt; ++t) tile(t, std::false_type{});
 }
 
-template <bool PROXY>
+// ONE_SIDED (particles only): the items are tiles with their own particles;
+// each target's sum over the whole tile is stored, no source sums.
+template <bool PROXY, bool ONE_SIDED = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_mfma(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles p, DevTree T,
                                                      double* __restrict__ phi, const double* __restrict__ tab,
@@ -288,8 +291,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
-            else sym_tiles<false>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+            if (guard) sym_tiles<true, ONE_SIDED>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+            else sym_tiles<false, ONE_SIDED>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
             // slots k and k + 8 of lanes col and col ^ 8 (row_ror:8 within a row of 16)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             }
         }
         __syncthreads();
-        if (c0 + tid < bn) {
+        if (!ONE_SIDED && c0 + tid < bn) {
             const int t = tid >> 4, j = tid & 15;
             double s = 0.0;
             for (int w = 0; w < 4; ++w)
@@ -325,7 +328,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
         if (row < it.tn) {
-            if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
+            if constexpr (ONE_SIDED) phi[it.t0 + row] = v;
+            else if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
             else atomicAdd(phi + it.t0 + row, v);
         }
     }
@@ -753,6 +757,14 @@ void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, 
     if (n_items <= 0) return;
     by_degree<DownLeaf>(degree, mfma, items, n_items, has_far, tgt, T, tab + 32 * degree, phihat, phi_tree, perm,
                         out, st);
+    CHECK_LAUNCH();
+}
+
+void launch_self_tiles_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
+                            double* phi, const double* tab, hipStream_t st) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL((k_sym_mfma<false, true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, tab,
+                       DegPtrs{}, DegOut{});
     CHECK_LAUNCH();
 }
 

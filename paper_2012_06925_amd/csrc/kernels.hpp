@@ -81,6 +81,13 @@ void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_
                 DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
                 hipStream_t st);
 
+// FP32 evaluation with the squared distances from the FP64 matrix cores, one
+// sided: items are tiles of at most 256 particles, each with the single entry
+// of its own particle range; phi[t] is set to the target's sum over the tile
+// (coincident points skipped).
+void launch_self_tiles_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
+                            double* phi, const double* tab, hipStream_t st);
+
 // Proxy charges of every degree d < D in mask, restricted exactly from the
 // degree-D charges of each of the n_clusters clusters of T: to.p[d][c].
 void launch_restrict(int n_clusters, DevTree T, const double* tab, const double* from, int D, DegOut to,
