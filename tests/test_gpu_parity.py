@@ -425,6 +425,41 @@ def _fp32_case(tgt, src, same, kernel, theta, degree, leaf):
     return p32, phi64, phi32
 
 
+def test_fp32_eval_tiny_and_degenerate_inputs():
+    # FP32 evaluation (symmetric passes on the matrix cores) on one- and
+    # two-particle sets and on the degenerate geometries, against the FP64
+    # oracle; a lone particle and identical points give exactly zero.  On a
+    # line, 2500 random points come within ~1e-7 of each other: the pairs the
+    # symmetric passes and the leaves' own tiles evaluate get their squared
+    # distances in FP64, but the near pairs listed one way only take FP32
+    # differences of centre-relative coordinates, so the error there is set by
+    # those few closest pairs (measured 1.0e-5; 2.7e-3 before the leaves'
+    # tiles moved to the matrix cores)
+    one = inputs.ParticleSet(np.array([0.1]), np.array([0.2]), np.array([0.3]), np.array([0.5]))
+    two = inputs.ParticleSet(np.array([1.0, 2.0]), np.array([0.0, 0.5]), np.array([0.0, 0.0]), np.array([1.0, -2.0]))
+    rng = np.random.default_rng(63)
+    n = 2500
+    cases = [("one", one, 0.5, 2, 1), ("two", two, 0.5, 2, 1)]
+    for name, xyz in (("identical", (np.full(n, 0.3), np.full(n, -0.2), np.full(n, 0.7))),
+                      ("collinear", (rng.uniform(-1, 1, n), np.full(n, 0.1), np.full(n, 0.1))),
+                      ("coplanar", (rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), np.zeros(n))),
+                      ("duplicates", tuple(np.repeat(rng.uniform(-1, 1, n // 5), 5) for _ in range(3)))):
+        cases.append((name, inputs.ParticleSet(*(a.copy() for a in xyz), rng.uniform(-1, 1, n)), 0.8, 2, 20))
+    bound = {"collinear": 5e-5}
+    errs = {}
+    for name, p, theta, degree, leaf in cases:
+        plan, phi, _ = gpu_plan(p, p, True, theta=theta, degree=degree, leaf=leaf, flags=1)
+        plan.close()
+        ref = core.bldtt(p, p, theta=theta, degree=degree, leaf=leaf)
+        if name in ("one", "identical"):       # no pair at a distance: every potential is zero
+            assert np.all(ref == 0) and np.all(phi == 0), name
+            continue
+        errs[name] = core.rel_l2(phi, ref)
+    print("\n  FP32 vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for name, e in errs.items():
+        assert e < bound.get(name, FP32_BOUND_DUPLICATES), (name, e)
+
+
 @pytest.mark.parametrize("kernel", ["coulomb", "yukawa", "oscillatory", "regcoulomb"])
 def test_fp32_eval_error_vs_fp64_oracle(kernel):
     t, s = inputs.unequal_sets(20_000, "sphere", 40_000, "gaussian", seed=60)
