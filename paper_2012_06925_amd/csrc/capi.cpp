@@ -280,7 +280,18 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const bool fp32 = (pl->flags & BLDTT_FP32_EVAL) != 0;
     const bool varied = pl->varied_degree();
     const bool symm = pl->symmetric_pp();
-    const int tile = kBlockThreads * pl->tpt, ptile = kBlockThreads * pl->tpt_proxy;
+    const bool mfma_pp = pl->mfma_particle_passes();
+    const int tile = kBlockThreads * (mfma_pp ? 1 : pl->tpt), ptile = kBlockThreads * pl->tpt_proxy;
+    // PP + PC into particle targets (phi_tree): set, or add to what earlier passes wrote
+    auto particle_pass = [&](const DevBuf& items, int n, const DevBuf& entries, bool add, hipStream_t s) {
+        if (mfma_pp)
+            launch_pp_mfma(items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab,
+                           deg_ptrs(pl->qhat_deg), pl->phi_tree.as<double>(), add, s);
+        else
+            launch_interact(ks, fp32, false, pl->tpt, items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT,
+                            pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg), pl->phi_tree.as<double>(), DegOut{}, s,
+                            add);
+    };
 
     collect_profile(pl);                // waits for the previous compute's events (BLDTT_PROFILE)
     const double t0 = now_ms();
@@ -313,15 +324,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     if (symm) {
         ensure_self_work(pl);
         PhaseMark mark(pl, BLDTT_PH_PP_SELF, st);
-        // FP32 evaluation: the tiles with themselves take their squared
-        // distances from the matrix cores too (closest pairs of the set)
-        if (fp32 && pl->mfma_transfer())
-            launch_self_tiles_mfma(pl->self_items.as<DevItem>(), pl->n_self_items, pl->self_entries.as<int2>(),
-                                   pl->dsrc(), dS, pl->phi_tree.as<double>(), tab, st);
-        else
-            launch_interact(ks, fp32, false, pl->tpt, pl->self_items.as<DevItem>(), pl->n_self_items,
-                            pl->self_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                            pl->phi_tree.as<double>(), DegOut{}, st);
+        particle_pass(pl->self_items, pl->n_self_items, pl->self_entries, false, st);
         launch_sym(fp32, pl->mfma_transfer(), false, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
                    pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
                    deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);
@@ -379,9 +382,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         un.run(pl->staging_rest, pl->arena_rest, pl->staging_rest_free, pl->side);
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
-            launch_interact(ks, fp32, false, pl->tpt, pl->near_items.as<DevItem>(), (int)wn.pitems.size(),
-                            pl->near_entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                            pl->phi_tree.as<double>(), DegOut{}, pl->side, symm);
+            particle_pass(pl->near_items, (int)wn.pitems.size(), pl->near_entries, symm, pl->side);
         }
         HIPCHK(hipEventRecord(pl->ev_near_done, pl->side));
         if (!symm) mark_host(2);
@@ -477,9 +478,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     if (!varied) {
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, st);
-            launch_interact(ks, fp32, false, pl->tpt, pl->pitems.as<DevItem>(), (int)w.pitems.size(),
-                            pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                            pl->phi_tree.as<double>(), DegOut{}, st, symm);
+            particle_pass(pl->pitems, (int)w.pitems.size(), pl->pentries, symm, st);
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
@@ -490,9 +489,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     } else {
         HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));
         PhaseMark mark(pl, BLDTT_PH_PPPC_SEP, st);
-        launch_interact(ks, fp32, false, pl->tpt, pl->sep_items.as<DevItem>(), (int)sep_items.size(),
-                        pl->pentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
-                        pl->phi_tree.as<double>(), DegOut{}, st, true);
+        particle_pass(pl->sep_items, (int)sep_items.size(), pl->pentries, true, st);
     }
     // 5. leaves to targets, caller order
     {

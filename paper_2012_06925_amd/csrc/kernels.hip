@@ -138,7 +138,7 @@ struct alignas(16) SymB {
     float q, pad;
 };
 
-// ONE_SIDED: target sums only (a tile with itself, every ordered pair once)
+// ONE_SIDED: target sums only (the one-sided particle passes, k_pp_mfma)
 template <bool GUARD, bool ONE_SIDED>
 __device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[64], float (*__restrict__ part)[64],
                                           int lane, const double (&A)[4], const v4d (&C)[4],
@@ -169,9 +169,7 @@ __device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[
     for (int t = 1; t < nt; ++t) tile(t, std::false_type{});
 }
 
-// ONE_SIDED (particles only): the items are tiles with their own particles;
-// each target's sum over the whole tile is stored, no source sums.
-template <bool PROXY, bool ONE_SIDED = false>
+template <bool PROXY>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_mfma(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles p, DevTree T,
                                                      double* __restrict__ phi, const double* __restrict__ tab,
@@ -291,8 +289,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true, ONE_SIDED>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
-            else sym_tiles<false, ONE_SIDED>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+            if (guard) sym_tiles<true, false>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+            else sym_tiles<false, false>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
             // slots k and k + 8 of lanes col and col ^ 8 (row_ror:8 within a row of 16)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -304,7 +302,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             }
         }
         __syncthreads();
-        if (!ONE_SIDED && c0 + tid < bn) {
+        if (c0 + tid < bn) {
             const int t = tid >> 4, j = tid & 15;
             double s = 0.0;
             for (int w = 0; w < 4; ++w)
@@ -328,9 +326,153 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
         if (row < it.tn) {
-            if constexpr (ONE_SIDED) phi[it.t0 + row] = v;
-            else if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
+            if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
             else atomicAdd(phi + it.t0 + row, v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided particle passes (PP particle ranges and PC proxies of any degree)
+// in FP32 evaluation with the squared distances from the FP64 matrix cores,
+// Coulomb only: the same tiles as k_sym_mfma, target sums only.  Items are
+// tiles of at most 256 target particles of tree Tt (leaf `cluster`); entry
+// kinds as in the host packer (SRC_RANGE, SRC_RANGE_GUARD: particles of S at
+// positions [a, a + count); SRC_PROXY: the (d+1)^3 proxies of cluster a of S,
+// d in the low bits).  out[slot + r] is set to the target's sum, or increased
+// by it with `add` (each target belongs to one item of a pass).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_pp_mfma(
+    const DevItem* __restrict__ items, const int2* __restrict__ entries, DevParticles tgt, DevTree Tt,
+    DevParticles src, DevTree S, const double* __restrict__ tab, DegPtrs qhat, double* __restrict__ out, int add) {
+    __shared__ double sT[3][kBlock];             // target tile: relative x, y, z
+    __shared__ SymB sB[16][64];                  // the chunk's tiles, in lane order
+    __shared__ float part[4][16][64];            // unused partials of the shared tile loop
+    const DevItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
+    const bool active = 64 * wave < it.tn;
+    const double* box = Tt.box + 6 * it.cluster;
+    const double cx = 0.5 * (box[0] + box[3]), cy = 0.5 * (box[1] + box[4]), cz = 0.5 * (box[2] + box[5]);
+    float thr;                                   // guarded ranges: coincident below 2^-42 of the squared diagonal
+    {
+        const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
+        thr = fmaxf((float)(0x1p-42 * (ex * ex + ey * ey + ez * ez)), 0x1p-126f);
+    }
+    {
+        double x = kFarT, y = kFarT, z = kFarT;
+        if (tid < it.tn) {
+            const int ti = it.t0 + tid;
+            x = tgt.x[ti] - cx;
+            y = tgt.y[ti] - cy;
+            z = tgt.z[ti] - cz;
+        }
+        sT[0][tid] = x;
+        sT[1][tid] = y;
+        sT[2][tid] = z;
+    }
+    __syncthreads();
+    double A[4];
+    v4d C[4];
+    float qi[4][4], acc[4][4];
+    double acc64[8];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int base = 64 * wave + 16 * b;
+        A[b] = grp < 3 ? sT[grp][base + col] : 1.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = base + grp + 4 * r;
+            const double x = sT[0][i], y = sT[1][i], z = sT[2][i];
+            C[b][r] = fma(x, x, fma(y, y, z * z));
+            qi[b][r] = 0.0f;
+            acc[b][r] = 0.0f;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc64[j] = 0.0;
+    const bool hi = (col & 8) != 0;
+
+    // entry e: kind, source count (particles or proxies)
+    auto count_of = [&](int2 en) {
+        const int kind = (int)((unsigned)en.y >> 29), low = en.y & ((1 << 29) - 1);
+        return kind == 2 ? (low + 1) * (low + 1) * (low + 1) : low;
+    };
+    double nx = kFarS, ny = kFarS, nz = kFarS, nq = 0.0;
+    auto load = [&](int e, int c0) {
+        nx = kFarS;
+        ny = kFarS;
+        nz = kFarS;
+        nq = 0.0;
+        if (e >= it.ee) return;
+        const int2 en = entries[e];
+        const int bn = count_of(en);
+        if (c0 + tid >= bn) return;
+        if (((unsigned)en.y >> 29) == 2u) {
+            const int d = en.y & ((1 << 29) - 1), md = d + 1;
+            proxy_point(S.box + 6 * en.x, md, tab + 32 * d, c0 + tid, nx, ny, nz);
+            nq = qhat.p[d][(int64_t)en.x * bn + c0 + tid];
+        } else {
+            const int j = en.x + c0 + tid;
+            nx = src.x[j];
+            ny = src.y[j];
+            nz = src.z[j];
+            nq = src.q[j];
+        }
+        nx -= cx;
+        ny -= cy;
+        nz -= cz;
+    };
+    int e = it.eb, c0 = 0;
+    load(e, c0);
+    while (e < it.ee) {
+        const int2 en = entries[e];
+        const int bn = count_of(en);
+        const bool guard = ((unsigned)en.y >> 29) == 1u;
+        const int nt = min(16, (bn - c0 + 15) >> 4);
+        {
+            const int t = tid >> 4, j = tid & 15;
+            const float q = (float)nq;
+            sB[t][j] = SymB{-2.0 * nx, q, 0.0f};
+            sB[t][16 + j] = SymB{-2.0 * ny, q, 0.0f};
+            sB[t][32 + j] = SymB{-2.0 * nz, q, 0.0f};
+            sB[t][48 + j] = SymB{fma(nx, nx, fma(ny, ny, nz * nz)), q, 0.0f};
+        }
+        __syncthreads();
+        int e2 = e, c2 = c0 + kSymChunk;
+        if (c2 >= bn) {
+            e2 = e + 1;
+            c2 = 0;
+        }
+        load(e2, c2);
+        if (active) {
+            if (guard) sym_tiles<true, true>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+            else sym_tiles<false, true>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float lo = acc[j >> 2][j & 3], up = acc[2 + (j >> 2)][j & 3];
+                const float keep = hi ? up : lo, send = hi ? lo : up;
+                const float other = __builtin_bit_cast(
+                    float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xf, 0xf, true));
+                acc64[j] += (double)(keep + other);
+            }
+        }
+        __syncthreads();
+        e = e2;
+        c0 = c2;
+    }
+    if (active) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            double s = acc64[j];
+#pragma unroll
+            for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            v = (col & 7) == j ? s : v;
+        }
+        const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
+        if (row < it.tn) {
+            if (add) out[it.slot + row] += v;
+            else out[it.slot + row] = v;
         }
     }
 }
@@ -760,11 +902,11 @@ void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, 
     CHECK_LAUNCH();
 }
 
-void launch_self_tiles_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
-                            double* phi, const double* tab, hipStream_t st) {
+void launch_pp_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
+                    DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double* out, bool add, hipStream_t st) {
     if (n_items <= 0) return;
-    hipLaunchKernelGGL((k_sym_mfma<false, true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, tab,
-                       DegPtrs{}, DegOut{});
+    hipLaunchKernelGGL(k_pp_mfma, dim3(n_items), dim3(kBlock), 0, st, items, entries, tgt, Tt, src, S, tab, qhat, out,
+                       add ? 1 : 0);
     CHECK_LAUNCH();
 }
 

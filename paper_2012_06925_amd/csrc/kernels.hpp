@@ -81,12 +81,11 @@ void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_
                 DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
                 hipStream_t st);
 
-// FP32 evaluation with the squared distances from the FP64 matrix cores, one
-// sided: items are tiles of at most 256 particles, each with the single entry
-// of its own particle range; phi[t] is set to the target's sum over the tile
-// (coincident points skipped).
-void launch_self_tiles_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles p, DevTree T,
-                            double* phi, const double* tab, hipStream_t st);
+// One-sided particle-target pass (PP ranges and PC proxies) in FP32 evaluation
+// with the squared distances from the FP64 matrix cores, Coulomb kernel only.
+// Items must hold at most 256 targets; out[slot + r] = (add: +=) the sum.
+void launch_pp_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
+                    DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double* out, bool add, hipStream_t st);
 
 // Proxy charges of every degree d < D in mask, restricted exactly from the
 // degree-D charges of each of the n_clusters clusters of T: to.p[d][c].

@@ -191,6 +191,10 @@ struct bldtt_plan {
     bool self_ready = false;
     double self_evaluations = 0.0;
     DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
+    // FP32 Coulomb particle passes on the matrix cores (k_pp_mfma): tiles of 256 targets
+    bool mfma_particle_passes() const {
+        return (flags & BLDTT_FP32_EVAL) && kind == BLDTT_COULOMB && mfma_transfer();
+    }
     bool symmetric_pp() const {
         return aliased && kind == BLDTT_COULOMB && (flags & BLDTT_ONE_SIDED_PP) == 0;
     }

@@ -34,9 +34,13 @@ def _dev_problem(p, targets=None):
 
 
 def _alone(problem, **kw):
-    # the batch evaluates every PP pair one-sided: compare with the same arithmetic
+    # the batch evaluates every PP pair one-sided, FP32 on the vector ALUs:
+    # compare with the same arithmetic
     tgt, src = problem
-    kw = dict(kw, flags=kw.get("flags", 0) | _lib.ONE_SIDED_PP)
+    flags = kw.get("flags", 0) | _lib.ONE_SIDED_PP
+    if flags & _lib.FP32_EVAL:
+        flags |= _lib.VALU_PASSES
+    kw = dict(kw, flags=flags)
     plan = api.Plan(tgt, src, **kw)
     out = plan.compute()
     torch.cuda.synchronize()

@@ -91,6 +91,31 @@ def test_mixed_degrees_fp32_evaluation(case):
     assert err < FP32_MIXED
 
 
+@pytest.mark.parametrize("case", ["same", "unequal"])
+def test_model_choice_matches_oracle(case):
+    # the committed model chooses the degrees (its inference on the GPU, ahead
+    # of the near-field pass for a problem this small); the potentials equal
+    # the oracle's per-entry-degree evaluation of the chosen lists
+    from paper_2012_06925_amd.train_degree_model import load_model
+    if case == "same":
+        t = s = inputs.particles(40_000, "uniform", seed=80)
+    else:
+        t, s = inputs.unequal_sets(15_000, "sphere", 40_000, "gaussian", seed=81)
+    plan = _plan(t, s, case == "same", theta=0.8, degree=6, leaf=200, flags=LEARNED)
+    plan.set_degree_model(load_model(), fallback=6, tau=1e-6)
+    phi = plan.compute().cpu().numpy()
+    st = plan.stats()
+    assert st["sep_pairs"] > 0 and sum(st["pairs_per_degree"].values()) + st["sep_direct"] == st["sep_pairs"], st
+    L = _lists_with_degrees(plan)
+    run = core.Run(t, s, theta=0.8, degree=6, leaf=200, aliased=case == "same")
+    err = core.rel_l2(phi, run.eval_degrees(L))
+    print(f"\n  model choice {case}: degrees {st['pairs_per_degree']} direct {st['sep_direct']} gpu-vs-oracle={err:.2e}")
+    assert err < 1e-12
+    # a second compute chooses the same degrees and gives the same potentials
+    phi2 = plan.compute().cpu().numpy()
+    assert core.rel_l2(phi2, phi) < 1e-13
+
+
 def test_fallback_policy_equals_plain_method():
     p = inputs.particles(30_000, "uniform", seed=72)
     plain = _plan(p, p, True, theta=0.7, degree=5, leaf=150)

@@ -426,15 +426,15 @@ def _fp32_case(tgt, src, same, kernel, theta, degree, leaf):
 
 
 def test_fp32_eval_tiny_and_degenerate_inputs():
-    # FP32 evaluation (symmetric passes on the matrix cores) on one- and
+    # FP32 evaluation (particle passes on the matrix cores) on one- and
     # two-particle sets and on the degenerate geometries, against the FP64
     # oracle; a lone particle and identical points give exactly zero.  On a
-    # line, 2500 random points come within ~1e-7 of each other: the pairs the
-    # symmetric passes and the leaves' own tiles evaluate get their squared
-    # distances in FP64, but the near pairs listed one way only take FP32
-    # differences of centre-relative coordinates, so the error there is set by
-    # those few closest pairs (measured 1.0e-5; 2.7e-3 before the leaves'
-    # tiles moved to the matrix cores)
+    # line, 2500 random points come within ~1e-7 of each other; those pairs'
+    # squared distances are FP64, but their terms exceed the rest of their
+    # particles' potentials by ~1e4, and the FP32 partial sums (16 terms per
+    # lane before each FP64 fold) round the other terms at the dominant term's
+    # scale (measured 1.0e-5; 2.7e-3 while the leaves' own tiles took FP32
+    # differences of centre-relative coordinates)
     one = inputs.ParticleSet(np.array([0.1]), np.array([0.2]), np.array([0.3]), np.array([0.5]))
     two = inputs.ParticleSet(np.array([1.0, 2.0]), np.array([0.0, 0.5]), np.array([0.0, 0.0]), np.array([1.0, -2.0]))
     rng = np.random.default_rng(63)
