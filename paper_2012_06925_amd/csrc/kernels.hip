@@ -349,6 +349,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     __shared__ SymB sB[16][64];                  // the chunk's tiles, in lane order
     __shared__ float part[4][16][64];            // unused partials of the shared tile loop
     const DevItem it = items[blockIdx.x];
+    if (add && it.ee == it.eb) return;           // nothing to add (the whole group leaves together)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
     const bool active = 64 * wave < it.tn;
     const double* box = Tt.box + 6 * it.cluster;
