@@ -375,7 +375,11 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             drop_self_pairs(near_rest);
         }
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
-        const Work& wn = pl->work_near;
+        Work& wn = pl->work_near;
+        if (symm)           // this pass adds to the self pairs: leaf tiles without entries have nothing to add
+            wn.pitems.erase(std::remove_if(wn.pitems.begin(), wn.pitems.end(),
+                                           [](const Item& it) { return it.ee == it.eb; }),
+                            wn.pitems.end());
         if (!symm) fork();
         Upload un;
         un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
