@@ -414,8 +414,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     pack_work(T, S, symm ? rest : (varied ? sep : pl->lists), pl->degree, tile, ptile, pl->work,
               symm ? &scc_deg : nullptr);
     Work& w = pl->work;
-    std::vector<Item> sep_items;        // second particle pass: leaves with separated-pair entries
-    if (varied)
+    // particle items with entries: the second particle pass of the per-pair
+    // degree form, and the accumulating particle pass of a symmetric plan
+    std::vector<Item> sep_items;
+    if (varied || symm)
         for (const Item& it : w.pitems)
             if (it.ee > it.eb) sep_items.push_back(it);
     pl->stats.traverse_ms += now_ms() - tp;
@@ -436,7 +438,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     Upload up;
     up.add(pl->pitems, w.pitems).add(pl->pentries, w.pentries).add(pl->qitems, w.qitems)
         .add(pl->qentries, w.qentries).add(pl->has_far, w.leaf_has_far).add(pl->prolong, w.prolong);
-    if (varied) up.add(pl->sep_items, sep_items);
+    if (varied || symm) up.add(pl->sep_items, sep_items);
     if (!varied && symm) up.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
     if (symm) up.add(pl->sym_cc_items, scc.cc_items).add(pl->sym_cc_entries, scc.cc_entries);
     up.run(pl->staging, pl->arena, pl->staging_free, st);
@@ -482,7 +484,8 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     if (!varied) {
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, st);
-            particle_pass(pl->pitems, (int)w.pitems.size(), pl->pentries, symm, st);
+            if (symm) particle_pass(pl->sep_items, (int)sep_items.size(), pl->pentries, true, st);
+            else particle_pass(pl->pitems, (int)w.pitems.size(), pl->pentries, false, st);
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
