@@ -70,8 +70,9 @@ enum {
                                       PP otherwise                                       */
     BLDTT_VALU_PASSES = 1u << 6,   /* run the child-to-parent and parent-to-child
                                       transfers, and the squared distances of the FP32
-                                      symmetric passes, on the vector ALUs instead of
-                                      the FP64 matrix cores (the default)                */
+                                      Coulomb particle passes (symmetric and one-sided),
+                                      on the vector ALUs instead of the FP64 matrix
+                                      cores (the default)                                */
     BLDTT_MFMA_LEAF = 1u << 7,     /* run the leaf contractions (proxy charges from the
                                       particles, interpolation to the targets) on the
                                       FP64 matrix cores instead of the vector ALUs (the
