@@ -850,12 +850,12 @@ constexpr int sym_lds_bytes() {
 }
 
 // One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  Each lane
-// holds two targets (rows lane and 64 + lane of its wave's 128), so a staged
-// source and the move of its partial serve two pairs.  An item whose targets
-// fill nslab = 1 or 2 waves runs 4 / nslab copies of those waves, each over
-// its own 64 of the 64 * copies sources staged per round (each copy adds its
-// own target partials with its atomics).
-template <bool F32, bool PROXY>
+// holds H targets (rows 64 h + lane of its wave's 64 H), so a staged source and
+// the move of its partial serve H pairs.  An item whose targets fill nslab = 1
+// or 2 waves runs 4 / nslab copies of those waves, each over its own 64 of the
+// 64 * copies sources staged per round (each copy adds its own target partials
+// with its atomics).
+template <bool F32, bool PROXY, int H = 2>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, double* __restrict__ phi, const double* __restrict__ tab,
                                          DegPtrs qhat, DegOut phihat, void* lds) {
@@ -866,11 +866,11 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     V* src = static_cast<V*>(lds);                               // per copy: 64 staged sources, twice
     R (*part_red)[64] = reinterpret_cast<R (*)[64]>(src + 4 * 128);  // [4][64] wave partials
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nslab = it.tn <= 128 ? 1 : 2;
+    const int nslab = it.tn <= 64 * H ? 1 : 2;
     const int copies = 4 / nslab, copy = wave / nslab, sw = wave % nslab;
     const int span = 64 * copies;                                // sources staged per round
     const V* mysrc = src + 128 * copy;
-    const bool active = 128 * sw < it.tn;
+    const bool active = 64 * H * sw < it.tn;
     const double* box = T.box + 6 * it.cluster;
     const double cx = F32 ? 0.5 * (box[0] + box[3]) : 0.0, cy = F32 ? 0.5 * (box[1] + box[4]) : 0.0,
                  cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
@@ -878,12 +878,12 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     const int m = it.degree + 1, P = m * m * m;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
     double* od = PROXY ? phihat.p[it.degree] : nullptr;
-    R tx[2], ty[2], tz[2], qi[2];
-    int ti[2];
-    bool mine[2];
+    R tx[H], ty[H], tz[H], qi[H];
+    int ti[H];
+    bool mine[H];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = 128 * sw + 64 * h + lane;
+    for (int h = 0; h < H; ++h) {
+        const int r = 64 * H * sw + 64 * h + lane;
         mine[h] = r < it.tn;
         ti[h] = it.t0 + (mine[h] ? r : 0);
         tx[h] = ty[h] = tz[h] = (R)kFar;
@@ -905,7 +905,9 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
             qi[h] = (R)(qs * q);
         }
     }
-    double acc[2] = {0.0, 0.0};
+    double acc[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) acc[h] = 0.0;
     for (int e = it.eb; e < it.ee; ++e) {
         const int2 en = entries[e];
         const int low = en.y & ((1 << 29) - 1);
@@ -939,15 +941,17 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
             __syncthreads();
             R psi = 0;
             if (active) {
-                R sum[2] = {0, 0};
-                // 64 steps: lane l pairs its two targets with source (l + s) mod 64
+                R sum[H];
+#pragma unroll
+                for (int h = 0; h < H; ++h) sum[h] = 0;
+                // 64 steps: lane l pairs its H targets with source (l + s) mod 64
                 auto steps = [&](auto guard) {
 #pragma unroll
                     for (int s = 0; s < 64; ++s) {
                         const V v = mysrc[lane + s];
-                        R y[2];
+                        R y[H];
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
+                        for (int h = 0; h < H; ++h) {
                             const R dx = tx[h] - v.x, dy = ty[h] - v.y, dz = tz[h] - v.z;
                             R r2 = dz * dz;
                             r2 = dy * dy + r2;
@@ -962,13 +966,16 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                             }
                             sum[h] = fma(v.w, y[h], sum[h]);
                         }
-                        psi = rol1(psi) + qi[0] * y[0] + qi[1] * y[1];
+                        R t = rol1(psi);
+#pragma unroll
+                        for (int h = 0; h < H; ++h) t = t + qi[h] * y[h];
+                        psi = t;
                     }
                 };
                 if (guard) steps(std::true_type{});
                 else steps(std::false_type{});
-                acc[0] += (double)sum[0];
-                acc[1] += (double)sum[1];
+#pragma unroll
+                for (int h = 0; h < H; ++h) acc[h] += (double)sum[h];
                 part_red[wave][(lane + 63) & 63] = psi;
             }
             __syncthreads();
@@ -976,14 +983,14 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 const int k = tid >> 6, ms = tid & 63;           // copy and source of the round
                 double t = 0.0;
                 for (int w = 0; w < nslab; ++w)
-                    if (128 * w < it.tn) t += (double)part_red[k * nslab + w][ms];
+                    if (64 * H * w < it.tn) t += (double)part_red[k * nslab + w][ms];
                 if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
                 else atomicAdd(phi + en.x + c0 + tid, t);
             }
         }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < H; ++h)
         if (mine[h]) {
             if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + ti[h], acc[h]);
             else atomicAdd(phi + ti[h], acc[h]);

@@ -99,7 +99,10 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
                                                 DevParticles p, DevTree T, double* __restrict__ phi,
                                                 const double* __restrict__ tab, DegPtrs qhat, DegOut phihat) {
     __shared__ double4 pool[(sym_lds_bytes<F32>() + 31) / 32];
-    sym_body<F32, PROXY>(items[blockIdx.x], entries, p, T, phi, tab, qhat, phihat, pool);
+    // tiles of more than 128 targets: four per lane (one wave per copy)
+    const DevItem it = items[blockIdx.x];
+    if (it.tn > 128) sym_body<F32, PROXY, 4>(it, entries, p, T, phi, tab, qhat, phihat, pool);
+    else sym_body<F32, PROXY, 2>(it, entries, p, T, phi, tab, qhat, phihat, pool);
 }
 
 // ---------------------------------------------------------------------------
