@@ -815,14 +815,14 @@ __device__ __forceinline__ void down_leaf_mfma_body(const DevItem& it, bool far,
 //   CC (pairs of clusters {A, B} at one degree): phihat_A[l] += G qhat_B[k] and
 //      phihat_B[k] += G qhat_A[l] -- the proxy grids of a cluster are the same
 //      points whether it is the target or the source.
-// One work item = a tile of up to 256 target points of A (128 per wave, two
-// per lane) and the entries of its partners B.  Sources are staged 64 at a
+// One work item = a tile of up to 256 target points of A (H per lane, 64 H
+// per wave) and the entries of its partners B.  Sources are staged 64 at a
 // time in LDS (twice, so step s reads src[lane + s]); at step s lane l pairs
 // its targets with source (l + s) mod 64 and adds q_i G to a running source
 // partial that moves one lane down per step (DPP wave_rol:1: lane l receives
 // lane l + 1), so after 64 steps lane l holds the partial of source (l - 1)
-// mod 64 over the 128 targets of its wave.  The wave partials are summed in LDS and added to the
-// source's output with one FP64 atomic per source; each target's sum is added
+// mod 64 over the targets of its wave.  The wave partials are summed in LDS
+// and added to the source's output with one FP64 atomic per source; each target's sum is added
 // with one atomic at the end.  Results are reproducible to rounding only: the
 // order of the atomics varies.  PP ranges flagged SRC_RANGE_GUARD (a leaf
 // with itself, or leaf boxes within 2^-20 of their extent) skip r^2 == 0
