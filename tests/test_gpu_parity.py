@@ -193,6 +193,23 @@ def test_determinism_and_recompute():
     assert np.array_equal(phi1, phi2) and np.array_equal(phi2, phi3)
 
 
+def test_fp32_one_sided_matrix_core_passes_are_deterministic():
+    # unequal Coulomb sets in FP32: every particle pass is the one-sided
+    # matrix-core kernel (each target owned by one item, no atomics), so
+    # recomputes are bit-identical, and the result is within the FP32 bound
+    t, s = inputs.unequal_sets(12_000, "sphere", 30_000, "gaussian", seed=64)
+    plan, phi1, _ = gpu_plan(t, s, False, theta=0.7, degree=6, leaf=150, flags=1)
+    phi2 = plan.compute().cpu().numpy()
+    st = plan.stats()
+    plan.close()
+    assert np.array_equal(phi1, phi2)
+    assert st["interactions"]["PP"] > 0 and st["interactions"]["PC"] > 0, st["interactions"]
+    ref = core.bldtt(t, s, theta=0.7, degree=6, leaf=150)
+    e = core.rel_l2(phi1, ref)
+    print(f"\n  FP32 one-sided matrix-core passes vs FP64 oracle: {e:.2e}")
+    assert e < FP32_BOUND_UNEQUAL
+
+
 @pytest.mark.parametrize("fp32", [False, True])
 def test_symmetric_pp_equals_one_sided(fp32):
     # targets = sources, Coulomb: pairs of leaves (PP) and of clusters (CC, one
