@@ -405,12 +405,12 @@ def main() -> int:
     if args.mode in ("both", "tuned"):
         forms["tuned"] = bench.form("tuned", args.tuned_theta, args.tuned_fallback, args.tau)
 
-    # spot check of the GPU judge against the CPU oracle's compensated direct sum
-    judge_check = None
+    # spot check of the GPU direct sum against the CPU oracle's compensated direct sum
+    ds_check = None
     if not args.no_cpu:
         from oracle import core
         ref = core.direct_sum(p, p, kernel=wl["kernel"], sel=bench.sel[:8])
-        judge_check = float(np.max(np.abs(bench.ds[:8] - ref) / np.abs(ref)))
+        ds_check = float(np.max(np.abs(bench.ds[:8] - ref) / np.abs(ref)))
 
     ok = [f for f in forms.values() if f["error_vs_direct"] <= TARGET_ERR]
     head = forms.get("tuned") if forms.get("tuned") in ok else (ok[0] if ok else next(iter(forms.values())))
@@ -426,7 +426,7 @@ def main() -> int:
         "config": {"workload": args.workload, "M": M, "N": M, "distribution": wl["dist"], "kernel": wl["kernel"],
                    "leaf": args.leaf, "mode": head["mode"], "theta": head["theta"], "degree": head["degree"],
                    "tau": head.get("tau")},
-        "error_vs_direct": head["error_vs_direct"], "judge_cpu_check_maxrel": judge_check,
+        "error_vs_direct": head["error_vs_direct"], "direct_sum_cpu_check_maxrel": ds_check,
         "roofline": head["roofline"], "cpu_baseline": cpu, "setup_ms": head["setup_ms"],
         "forms": forms,
         "tuned_over_plain": (forms["tuned"]["particles_per_s"] / forms["plain"]["particles_per_s"]

@@ -225,7 +225,7 @@ typedef struct {
  * last compute (so it synchronizes with that compute's stream). */
 int bldtt_get_stats(bldtt_plan *plan, bldtt_stats *out);
 
-/* ---- Direct sum (the accuracy judge, Eq. 1) ----------------------------- */
+/* ---- Direct sum (the accuracy reference, Eq. 1) ------------------------- */
 
 /* phi at nsel targets sel[a] (device int64 caller indices; sel == NULL means
  * all M targets, nsel ignored) due to all N sources, FP64 with compensated

@@ -7,7 +7,7 @@
 //   cp_cc          CP and CC sums into the target proxies (Eqs. CP-proxy-potential, CC-proxy-potential)
 //   down_transfer  parent-to-child interpolation of proxy potentials (Sec. 2.7, Appendix C)
 //   down_leaf      leaf proxies to targets, plus the PP/PC part, scattered to caller order
-//   direct         the direct sum of Eq. (1), compensated, for the accuracy judge
+//   direct         the direct sum of Eq. (1), compensated, the accuracy reference
 //
 // Mapping: targets (particles or proxies) are the outer level of parallelism,
 // one per lane; sources (particles or proxies) are the inner level, staged
