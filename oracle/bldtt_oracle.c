@@ -355,33 +355,56 @@ typedef struct {
     or_lists *out;
 } dtt_ctx;
 
-static void dtt(dtt_ctx *x, int64_t t, int64_t s)
+/* Sec. 2.6: a well-separated pair is approximated on whichever side holds
+ * more particles than a cluster has proxies, n_p = (n+1)^3: both sides -> CC,
+ * the target side only -> CP, the source side only -> PC, neither -> PP.  The
+ * ablation of Sec. 4.3 keeps CC and turns the one-sided forms into PP. */
+static int separated_type(int64_t ct, int64_t cs, int64_t np, int pp_cc_only)
 {
-    const or_tree *T = x->T, *S = x->S;
+    int big_t = ct > np, big_s = cs > np;
+    if (big_t && big_s) return OR_CC;
+    if (pp_cc_only || (!big_t && !big_s)) return OR_PP;
+    return big_t ? OR_CP : OR_PC;
+}
+
+/* Sec. 2.6: of a pair that is not well separated and not two leaves, the
+ * larger cluster is refined (the target when it alone has children, the
+ * source when it alone has; on equal counts the source). */
+static int refine_target(int tleaf, int sleaf, int64_t ct, int64_t cs)
+{
+    if (sleaf) return 1;
+    if (tleaf) return 0;
+    return cs < ct;
+}
+
+/* MAC of Sec. 2.6: (r_t + r_s) / R < theta, R the distance of the centres;
+ * coincident centres are never separated. */
+static int well_separated(const or_tree *T, int64_t t, const or_tree *S, int64_t s, double theta)
+{
     double dx = T->center[3 * t] - S->center[3 * s];
     double dy = T->center[3 * t + 1] - S->center[3 * s + 1];
     double dz = T->center[3 * t + 2] - S->center[3 * s + 2];
     double R = sqrt((dx * dx + dy * dy) + dz * dz);
-    int sep = R > 0.0 && (T->radius[t] + S->radius[s]) / R < x->theta;
+    return R > 0.0 && (T->radius[t] + S->radius[s]) / R < theta;
+}
+
+/* Dual tree traversal (Algorithm 2): record every well-separated pair with
+ * its type, every pair of leaves that is not separated as PP, and otherwise
+ * recurse over the children of the cluster refine_target picks. */
+static void dtt(dtt_ctx *x, int64_t t, int64_t s)
+{
+    const or_tree *T = x->T, *S = x->S;
     int64_t ct = T->count[t], cs = S->count[s];
     int tleaf = T->nchild[t] == 0, sleaf = S->nchild[s] == 0;
-    if (sep) {
-        int type;
-        if (ct > x->np && cs > x->np) type = OR_CC;
-        else if (x->pp_cc_only) type = OR_PP;
-        else if (ct > x->np) type = OR_CP;
-        else if (cs > x->np) type = OR_PC;
-        else type = OR_PP;
-        lists_push(x->out, type, t, s);
+    if (well_separated(T, t, S, s, x->theta)) {
+        lists_push(x->out, separated_type(ct, cs, x->np, x->pp_cc_only), t, s);
         return;
     }
     if (tleaf && sleaf) {
         lists_push(x->out, OR_PP, t, s);
-    } else if (sleaf) {
-        for (int k = 0; k < T->nchild[t]; ++k) dtt(x, T->child[8 * t + k], s);
-    } else if (tleaf) {
-        for (int k = 0; k < S->nchild[s]; ++k) dtt(x, t, S->child[8 * s + k]);
-    } else if (cs < ct) {
+        return;
+    }
+    if (refine_target(tleaf, sleaf, ct, cs)) {
         for (int k = 0; k < T->nchild[t]; ++k) dtt(x, T->child[8 * t + k], s);
     } else {
         for (int k = 0; k < S->nchild[s]; ++k) dtt(x, t, S->child[8 * s + k]);

@@ -38,6 +38,41 @@ def test_direct_sum_two_particles_hand_values():
     assert phy[1] == pytest.approx(2.0 * math.exp(-2.5) / 5.0, rel=1e-14)
 
 
+def _pair(dist, q=1.0):
+    t = inputs.ParticleSet(np.array([0.0]), np.array([0.0]), np.array([0.0]), np.array([1.0]))
+    s = inputs.ParticleSet(np.array([dist]), np.array([0.0]), np.array([0.0]), np.array([q]))
+    return t, s
+
+
+@pytest.mark.parametrize("r,value", [(0.5, 2.0), (1.0 / 6.0, 3.0), (1.5, -2.0 / 3.0)])
+def test_oscillatory_kernel_hand_values(r, value):
+    # Sec. 4.6 oscillatory kernel sin(pi r)/r: sin(pi/2)/(1/2) = 2,
+    # sin(pi/6)/(1/6) = 3, sin(3 pi/2)/(3/2) = -2/3
+    t, s = _pair(r)
+    assert core.direct_sum(t, s, kernel="oscillatory")[0] == pytest.approx(value, rel=1e-14)
+    assert brute.direct_sum(t.xyz(), s.xyz(), s.q, "oscillatory")[0] == pytest.approx(value, rel=1e-14)
+    # the whole method with one leaf (a single PP pair) gives the same value
+    assert core.bldtt(t, s, kernel="oscillatory", theta=0.5, degree=2, leaf=4)[0] == pytest.approx(value, rel=1e-14)
+
+
+@pytest.mark.parametrize("r,eps,value", [(0.012, 0.005, 1.0 / 0.013), (4.0, 3.0, 0.2), (0.0048, 0.0014, 200.0)])
+def test_regularized_coulomb_hand_values(r, eps, value):
+    # Sec. 4.6 regularized Coulomb 1/sqrt(r^2 + eps^2), eps = 0.005 in the
+    # paper: (12, 5, 13) and (4, 3, 5) and (48, 14, 50) right triangles
+    t, s = _pair(r)
+    assert core.direct_sum(t, s, kernel="regcoulomb", param=eps)[0] == pytest.approx(value, rel=1e-14)
+    assert brute.direct_sum(t.xyz(), s.xyz(), s.q, "regcoulomb", eps)[0] == pytest.approx(value, rel=1e-14)
+    got = core.bldtt(t, s, kernel="regcoulomb", param=eps, theta=0.5, degree=2, leaf=4)[0]
+    assert got == pytest.approx(value, rel=1e-14)
+
+
+def test_regularized_coulomb_default_eps_is_paper_value():
+    # the paper's eps = 0.005: at r = 0.012 the kernel is 1/0.013, not 1/0.012
+    t, s = _pair(0.012)
+    assert core.DEFAULT_PARAM["regcoulomb"] == 0.005
+    assert core.direct_sum(t, s, kernel="regcoulomb")[0] == pytest.approx(1.0 / 0.013, rel=1e-14)
+
+
 def test_direct_sum_matches_numpy_matrix_form():
     t, s = inputs.unequal_sets(300, "sphere", 500, "gaussian", seed=7)
     for kernel, param in (("coulomb", 0.0), ("yukawa", 0.5), ("oscillatory", 0.0), ("regcoulomb", 0.005)):
@@ -309,6 +344,60 @@ def test_lists_mac_and_types(theta, n):
     assert counts["CC"] > 0 and counts["PP"] > 0
 
 
+def _ablation_runs(case, theta, n, leaf):
+    if case == "same":
+        t = s = inputs.particles(1500, "gaussian", seed=25)
+    else:
+        t, s = inputs.unequal_sets(900, "sphere", 1400, "uniform", seed=26)
+    full = core.Run(t, s, theta=theta, degree=n, leaf=leaf)
+    abl = core.Run(t, s, theta=theta, degree=n, leaf=leaf, pp_cc_only=True)
+    full.traverse()
+    abl.traverse()
+    return t, s, full, abl
+
+
+@pytest.mark.parametrize("case", ["same", "unequal"])
+@pytest.mark.parametrize("theta,n,leaf", [(0.7, 1, 10), (0.9, 2, 8)])
+def test_ablation_lists_cover_every_pair_once_and_keep_the_recursion(case, theta, n, leaf):
+    # Sec. 4.3 ablation (CC and PP only): the recursion of Algorithm 2 is the
+    # same, so the separated pairs are the same; a pair is CC when both
+    # clusters hold more than (n+1)^3 particles and PP otherwise.  Hence:
+    # every (i, j) covered once, no PC/CP, CC equal to the full traversal's
+    # CC, and PP = full PP + PC + CP.
+    t, s, full, abl = _ablation_runs(case, theta, n, leaf)
+    A, F = abl.lists(), full.lists()
+    cover = _coverage(abl, t.n, s.n)
+    assert cover.min() == 1 and cover.max() == 1
+    assert len(A["PC"][0]) == 0 and len(A["CP"][0]) == 0
+    assert len(F["PC"][0]) > 0 and len(F["CP"][0]) > 0 and len(F["CC"][0]) > 0
+    pairs = lambda L, k: set(zip(L[k][0].tolist(), L[k][1].tolist()))
+    assert pairs(A, "CC") == pairs(F, "CC")
+    assert pairs(A, "PP") == pairs(F, "PP") | pairs(F, "PC") | pairs(F, "CP")
+    assert len(A["PP"][0]) == len(pairs(A, "PP"))
+    tt, ts = abl.tree(0), abl.tree(1)
+    npx = (n + 1) ** 3
+    for tc, sc in zip(*A["CC"]):
+        assert tt["count"][tc] > npx and ts["count"][sc] > npx
+    for tc, sc in zip(*A["PP"]):
+        R = np.linalg.norm(tt["center"][tc] - ts["center"][sc])
+        sep = R > 0 and (tt["radius"][tc] + ts["radius"][sc]) / R < theta
+        leaves = tt["nchild"][tc] == 0 and ts["nchild"][sc] == 0
+        assert (sep and not (tt["count"][tc] > npx and ts["count"][sc] > npx)) or (not sep and leaves)
+
+
+@pytest.mark.parametrize("case", ["same", "unequal"])
+def test_ablation_potentials_equal_explicit_matrices(case):
+    # the ablation's potentials are the sum of exact PP blocks and CC
+    # interpolated blocks over its lists (explicit matrices, no up/down passes)
+    n = 2
+    t, s, full, abl = _ablation_runs(case, 0.9, n, 8)
+    phi = abl.run_all()
+    ref = brute.explicit_bldtt(t.xyz(), s.xyz(), s.q, abl.tree(0), abl.tree(1), abl.lists(), n)
+    assert core.rel_l2(phi, ref) < 1e-13
+    # and it differs from the four-type method only at the approximation level
+    assert 0 < core.rel_l2(phi, full.run_all()) < 1e-2
+
+
 def test_lists_tiny_theta_gives_leaf_leaf_pp_only():
     p = inputs.particles(2000, seed=9)
     run = core.Run(p, p, theta=1e-9, degree=2, leaf=100)
@@ -425,7 +514,7 @@ def test_polynomial_kernel_degree_one_is_not_exact():
     assert core.rel_l2(phi, ref) > 1e-8
 
 
-@pytest.mark.parametrize("kernel", ["coulomb", "yukawa"])
+@pytest.mark.parametrize("kernel", ["coulomb", "yukawa", "oscillatory", "regcoulomb"])
 @pytest.mark.parametrize("case", ["same", "unequal"])
 def test_explicit_matrix_brute_force(kernel, case):
     # sum over list entries of explicit approximated-kernel matrices (no up/down passes)
