@@ -58,8 +58,12 @@ enum { BLDTT_PP = 0, BLDTT_PC = 1, BLDTT_CP = 2, BLDTT_CC = 3 };
 
 /* Flags for bldtt_setup. */
 enum {
-    BLDTT_FP32_EVAL = 1u << 0,     /* evaluate G in FP32 on cluster-relative coordinates,
-                                      accumulate in FP64 (boxes, weights, proxies FP64)  */
+    BLDTT_FP32_EVAL = 1u << 0,     /* evaluate G in FP32 (cluster-relative coordinates;
+                                      the FP32 Coulomb particle passes take FP64 squared
+                                      distances from the matrix cores) and add every term
+                                      q_j G to FP64 sums; pairs closer than FP32 resolves
+                                      are evaluated in FP64 (counted in fp64_close_pairs);
+                                      boxes, weights, proxies and potentials stay FP64   */
     BLDTT_LEARNED_DEGREE = 1u << 1,/* per-pair degree from the model set by
                                       bldtt_set_degree_model                             */
     BLDTT_SYNC = 1u << 2,          /* bldtt_compute waits for its stream before returning */
@@ -219,10 +223,16 @@ typedef struct {
                                       the upward and self-pair launches enqueued, the
                                       traversal done, the first pass over its lists
                                       enqueued, and the return                           */
+    double fp64_close_pairs;       /* BLDTT_FP32_EVAL: kernel values of pairs of distinct
+                                      points that the last compute evaluated in FP64
+                                      because FP32 does not resolve them (a symmetric
+                                      pass counts a pair once for both terms; coincident
+                                      points are skipped as in FP64 and not counted)     */
 } bldtt_stats;
 
 /* Counters and timings.  Under BLDTT_PROFILE this waits for the events of the
- * last compute (so it synchronizes with that compute's stream). */
+ * last compute (so it synchronizes with that compute's stream); for a
+ * BLDTT_FP32_EVAL plan it waits for the device (fp64_close_pairs). */
 int bldtt_get_stats(bldtt_plan *plan, bldtt_stats *out);
 
 /* ---- Direct sum (the accuracy reference, Eq. 1) ------------------------- */

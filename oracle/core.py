@@ -262,3 +262,13 @@ def rel_l2(a, b) -> float:
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def max_rel(a, b) -> float:
+    """max_i |a_i - b_i| / max_i |b_i|: an element-wise bound that a single
+    wrong value cannot hide behind the norm (0 when both are all zero)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = float(np.max(np.abs(a - b))) if a.size else 0.0
+    s = float(np.max(np.abs(b))) if b.size else 0.0
+    return d / s if s > 0 else d

@@ -49,7 +49,8 @@ class Stats(C.Structure):
                 ("phase_ms", C.c_double * 8), ("profiled_computes", C.c_int64),
                 ("down_degree", C.c_int32), ("degree_mask", C.c_uint32), ("sep_pairs", C.c_int64),
                 ("sep_fallback", C.c_int64), ("sep_direct", C.c_int64), ("pairs_per_degree", C.c_int64 * 13),
-                ("pass_interactions", C.c_double * 5), ("host_marks_ms", C.c_double * 4)]
+                ("pass_interactions", C.c_double * 5), ("host_marks_ms", C.c_double * 4),
+                ("fp64_close_pairs", C.c_double)]
 
 
 class BatchStats(C.Structure):

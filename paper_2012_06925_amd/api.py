@@ -105,7 +105,8 @@ class _PlanBase:
                     down_degree=s.down_degree, degree_mask=s.degree_mask, sep_pairs=s.sep_pairs,
                     sep_fallback=s.sep_fallback, sep_direct=s.sep_direct,
                     pairs_per_degree={d: int(s.pairs_per_degree[d]) for d in range(13) if s.pairs_per_degree[d]},
-                    pass_interactions=list(s.pass_interactions), host_marks_ms=list(s.host_marks_ms))
+                    pass_interactions=list(s.pass_interactions), host_marks_ms=list(s.host_marks_ms),
+                    fp64_close_pairs=int(s.fp64_close_pairs))
 
     def traverse_host(self):
         check(lib().bldtt_traverse_host(self._handle))

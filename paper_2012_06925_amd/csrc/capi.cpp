@@ -283,18 +283,29 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const bool mfma_pp = pl->mfma_particle_passes();
     const int tile = kBlockThreads * (mfma_pp ? 1 : pl->tpt), ptile = kBlockThreads * pl->tpt_proxy;
     // PP + PC into particle targets (phi_tree): set, or add to what earlier passes wrote
+    double* nfp64 = pl->nfp64_ptr();
     auto particle_pass = [&](const DevBuf& items, int n, const DevBuf& entries, bool add, hipStream_t s) {
         if (mfma_pp)
             launch_pp_mfma(items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab,
-                           deg_ptrs(pl->qhat_deg), pl->phi_tree.as<double>(), add, s);
+                           deg_ptrs(pl->qhat_deg), pl->phi_tree.as<double>(), add, nfp64, s);
         else
             launch_interact(ks, fp32, false, pl->tpt, items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT,
                             pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg), pl->phi_tree.as<double>(), DegOut{}, s,
-                            add);
+                            add, nfp64);
+    };
+    // symmetric PP items: those without guarded ranges, then those with
+    auto sym_pp_pass = [&](const DevBuf& items, const DevBuf& entries, const SymWork& sw, hipStream_t s) {
+        const int n = (int)sw.pp_items.size(), n0 = (int)sw.pp_plain;
+        launch_sym(fp32, pl->mfma_transfer(), false, false, items.as<DevItem>(), n0, entries.as<int2>(), pl->dsrc(),
+                   dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64, s);
+        launch_sym(fp32, pl->mfma_transfer(), false, true, items.as<DevItem>() + n0, n - n0, entries.as<int2>(),
+                   pl->dsrc(), dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg),
+                   nfp64, s);
     };
 
     collect_profile(pl);                // waits for the previous compute's events (BLDTT_PROFILE)
     const double t0 = now_ms();
+    if (nfp64) launch_fill(nfp64, 1, 0.0, st);
     auto mark_host = [&](int k) { pl->stats.host_marks_ms[k] = now_ms() - t0; };
     // 1. upward pass, overlapping the host traversal: at the base degree, or
     //    for a per-pair degree plan at the source degrees its last compute used
@@ -325,9 +336,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         ensure_self_work(pl);
         PhaseMark mark(pl, BLDTT_PH_PP_SELF, st);
         particle_pass(pl->self_items, pl->n_self_items, pl->self_entries, false, st);
-        launch_sym(fp32, pl->mfma_transfer(), false, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
+        launch_sym(fp32, pl->mfma_transfer(), false, true, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
                    pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
-                   deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);
+                   deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64, st);
     }
 
     mark_host(0);
@@ -367,9 +378,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                 us.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
                 us.run(pl->staging_near, pl->arena_near, pl->staging_near_free, pl->side);
                 PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
-                launch_sym(fp32, pl->mfma_transfer(), false, pl->sym_items.as<DevItem>(),
-                           (int)pl->sym.pp_items.size(), pl->sym_entries.as<int2>(), pl->dsrc(), dS,
-                           pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), pl->side);
+                sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, pl->side);
                 mark_host(2);
             });
             drop_self_pairs(near_rest);
@@ -465,9 +474,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                         pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         nullptr, deg_out(pl->phihat_deg), st);
         if (symm)               // symmetric CC pairs add to the proxy potentials the pass above wrote
-            launch_sym(fp32, pl->mfma_transfer(), true, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
+            launch_sym(fp32, pl->mfma_transfer(), true, false, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
                        pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, nullptr, tab, deg_ptrs(pl->qhat_deg),
-                       deg_out(pl->phihat_deg), st);
+                       deg_out(pl->phihat_deg), nullptr, st);
     }
     {
         PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
@@ -489,9 +498,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         }
         if (symm) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
-            launch_sym(fp32, pl->mfma_transfer(), false, pl->sym_items.as<DevItem>(), (int)pl->sym.pp_items.size(),
-                       pl->sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
-                       deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), st);
+            sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, st);
         }
     } else {
         HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));
@@ -562,6 +569,10 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     level_lists(T, false, ids, pl->down_off);
     upload(pl->down_kids, ids);
     pl->phi_tree.alloc(sizeof(double) * M);
+    if (pl->flags & BLDTT_FP32_EVAL) {
+        pl->nfp64.alloc(sizeof(double));
+        launch_fill(pl->nfp64.as<double>(), 1, 0.0, st);
+    }
     HIPCHK(hipEventCreateWithFlags(&pl->staging_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->staging_near_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->staging_rest_free, hipEventDisableTiming));
@@ -824,6 +835,10 @@ int bldtt_get_stats(bldtt_plan* plan, bldtt_stats* out) {
     }
     return guarded([&] {
         if (!plan->host_only) collect_profile(plan);
+        if (!plan->host_only && plan->nfp64_ptr()) {
+            HIPCHK(hipDeviceSynchronize());
+            HIPCHK(hipMemcpy(&plan->stats.fp64_close_pairs, plan->nfp64.p, sizeof(double), hipMemcpyDeviceToHost));
+        }
         *out = plan->stats;
     });
 }

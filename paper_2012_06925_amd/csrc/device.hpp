@@ -23,7 +23,6 @@ namespace dev {
 
 constexpr int kBlock = 256;
 constexpr int kChunk = 512;                  // sources staged in LDS per round
-constexpr int kSub32 = 64;                   // FP32 partial sums folded into FP64 every kSub32 terms
 
 enum { K_COULOMB = 0, K_YUKAWA = 1, K_OSC = 2, K_REG = 3, K_POLY = 100 };
 
@@ -123,25 +122,51 @@ struct E64 {
 
 // FP32 evaluation on cluster-relative coordinates; sources are float4
 // (x - c, y - c, z - c, q) rounded from FP64, c the centre of the target box.
+// g() is the FP32 kernel value at a squared distance r2 > 0; the callers add
+// q_j g to FP64 sums (every term is accumulated in FP64).
 template <int KIND>
 struct E32 {
     using V = float4;
     static constexpr double charge_scale = 1.0;
-    template <bool GUARD>
-    __device__ __forceinline__ static void add(float& acc, float tx, float ty, float tz, const V& s, float param) {
-        float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-        float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        float y = __builtin_amdgcn_rsqf(r2);
-        if (GUARD) y = r2 > 0.0f ? y : 0.0f;
-        float g;
-        if (KIND == K_COULOMB) g = y;
-        else if (KIND == K_YUKAWA) g = __expf(-param * (r2 * y)) * y;
-        else if (KIND == K_OSC) g = sinpif(r2 * y) * y;
-        else g = GUARD ? (r2 > 0.0f ? __builtin_amdgcn_rsqf(fmaf(param, param, r2)) : 0.0f)
-                       : __builtin_amdgcn_rsqf(fmaf(param, param, r2));
-        acc = fmaf(s.w, g, acc);
+    __device__ __forceinline__ static float r2of(float tx, float ty, float tz, const V& s) {
+        const float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+        return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    }
+    __device__ __forceinline__ static float g(float r2, float param) {
+        const float y = __builtin_amdgcn_rsqf(r2);
+        if (KIND == K_COULOMB) return y;
+        if (KIND == K_YUKAWA) return __expf(-param * (r2 * y)) * y;
+        if (KIND == K_OSC) return sinpif(r2 * y) * y;
+        return __builtin_amdgcn_rsqf(fmaf(param, param, r2));
     }
 };
+
+// FP64 kernel value of two particles from their own (tree-order) coordinates,
+// 0 for coincident points (the self term and duplicates): the fallback of the
+// FP32 passes for pairs closer than their FP32 coordinates resolve.  Each
+// such pair of distinct points is counted in *nfp64 when it is not null.
+template <int KIND>
+__device__ __forceinline__ double g_fp64(const DevParticles& a, int i, const DevParticles& b, int j, double param,
+                                         double* nfp64) {
+    const double dx = a.x[i] - b.x[j], dy = a.y[i] - b.y[j], dz = a.z[i] - b.z[j];
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (r2 == 0.0) return 0.0;
+    if (nfp64) atomicAdd(nfp64, 1.0);
+    const double y = rsq_full(r2);
+    if (KIND == K_COULOMB) return y;
+    if (KIND == K_YUKAWA) return exp(-param * (r2 * y)) * y;
+    if (KIND == K_OSC) return sinpi(r2 * y) * y;
+    return rsq_full(fma(param, param, r2));
+}
+
+// Squared distance below which the vector-ALU FP32 passes evaluate a pair of
+// a guarded range in FP64: 2^-14 of the target box's squared half-diagonal
+// (pairs closer than 1/128 of it, where the rounding of FP32 coordinates
+// relative to the centre would exceed ~1.5e-5 of the distance).
+__device__ __forceinline__ float fp32_close_threshold(const double* box) {
+    const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
+    return (float)(0x1p-14 * 0.25 * (ex * ex + ey * ey + ez * ez));
+}
 
 // Proxy point k of a cluster box (flat index k1 + m k2 + m^2 k3).
 // k div m for 0 <= k < 2^16 and 1 <= m <= 13: (k + 1/2) / m lies at least
@@ -177,14 +202,6 @@ struct Stage<true> {
     }
 };
 
-// FP32 terms go to a per-target FP32 partial sum (folded into FP64 every
-// kSub32 terms); FP64 terms go straight to the FP64 sum.
-template <class Ev, bool GUARD, bool F32, class R, class V>
-__device__ __forceinline__ void accumulate(double& acc, R& part, R tx, R ty, R tz, const V& v, R param) {
-    if constexpr (F32) Ev::template add<GUARD>(part, tx, ty, tz, v, param);
-    else Ev::template add<GUARD>(acc, tx, ty, tz, v, param);
-}
-
 // LDS bytes of interact_body.
 template <bool F32>
 constexpr int interact_lds_bytes() { return kChunk * (int)sizeof(typename Stage<F32>::V); }
@@ -209,7 +226,7 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
                                               DevTree Tt, DevParticles src, DevTree S, const double* __restrict__ tab,
                                               const DegPtrs& qhat, double param, double* __restrict__ out,
                                               const DegOut& pout, typename Stage<F32>::V* lds,
-                                              int add = OUT_WRITE) {
+                                              int add = OUT_WRITE, double* nfp64 = nullptr) {
     using St = Stage<F32>;
     using V = typename St::V;
     using R = typename std::conditional<F32, float, double>::type;
@@ -226,7 +243,7 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
 
     R tx[T], ty[T], tz[T];
     double acc[T];
-    R part[T];
+    const float thr32 = F32 ? fp32_close_threshold(tbox) : 0.0f;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         int r = slab + lane + 64 * j;
@@ -249,7 +266,6 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
             tz[j] = (R)z;
         }
         acc[j] = 0.0;
-        part[j] = 0;
     }
     const R rparam = (R)param;
 
@@ -283,38 +299,39 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
             __syncthreads();
             if (!active) continue;
             const bool guard = kind == 1;
-            for (int s0 = 0; s0 < cnt; s0 += kSub32) {
-                const int s1 = min(cnt, s0 + kSub32);
-                if (guard) {
-                    for (int s = s0 + copy; s < s1; s += copies) {
-                        const V v = lds[s];
-#pragma unroll
-                        for (int j = 0; j < T; ++j) accumulate<Ev, true, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
-                    }
-                } else {
-                    int s = s0 + copy;
-                    for (; s + 3 * copies < s1; s += 4 * copies) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const V v = lds[s + u * copies];
-#pragma unroll
-                            for (int j = 0; j < T; ++j)
-                                accumulate<Ev, false, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
-                        }
-                    }
-                    for (; s < s1; s += copies) {
-                        const V v = lds[s];
-#pragma unroll
-                        for (int j = 0; j < T; ++j) accumulate<Ev, false, F32>(acc[j], part[j], tx[j], ty[j], tz[j], v, rparam);
-                    }
-                }
+            // one staged source against the lane's T targets; FP32 terms are
+            // added to the FP64 sums one by one
+            auto one = [&](int si, auto gd) {
+                constexpr bool G = decltype(gd)::value;
+                const V v = lds[si];
                 if constexpr (F32) {
+                    const double qd = (double)v.w;
 #pragma unroll
                     for (int j = 0; j < T; ++j) {
-                        acc[j] += (double)part[j];
-                        part[j] = 0;
+                        const float r2 = Ev::r2of(tx[j], ty[j], tz[j], v);
+                        double gv;
+                        if (G && !PROXY_TGT && r2 <= thr32) {
+                            const int r = slab + lane + 64 * j;
+                            gv = r < it.tn ? g_fp64<KIND>(tgt, it.t0 + r, src, en.x + c0 + si, param, nfp64) : 0.0;
+                        } else {
+                            gv = (double)Ev::g(r2, rparam);
+                        }
+                        acc[j] = fma(qd, gv, acc[j]);
                     }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < T; ++j) Ev::template add<G>(acc[j], tx[j], ty[j], tz[j], v, rparam);
                 }
+            };
+            if (guard) {
+                for (int si = copy; si < cnt; si += copies) one(si, std::true_type{});
+            } else {
+                int si = copy;
+                for (; si + 3 * copies < cnt; si += 4 * copies) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) one(si + u * copies, std::false_type{});
+                }
+                for (; si < cnt; si += copies) one(si, std::false_type{});
             }
         }
     }
@@ -830,10 +847,6 @@ __device__ __forceinline__ void down_leaf_mfma_body(const DevItem& it, bool far,
 // together); elsewhere the gap between the boxes keeps r^2 > 0.  CC pairs are
 // separated, so their proxies never meet.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float rol1(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xf, 0xf, true));
-}
-
 __device__ __forceinline__ double rol1(double v) {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
     const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x134, 0xf, 0xf, true);
@@ -845,8 +858,7 @@ constexpr float kFar = 1e18f;            // padding lanes sit here with charge 0
 
 template <bool F32>
 constexpr int sym_lds_bytes() {
-    return 4 * 128 * (int)sizeof(typename std::conditional<F32, float4, double4>::type) +
-           4 * 64 * (int)sizeof(typename std::conditional<F32, float, double>::type);
+    return 4 * 128 * (int)sizeof(typename std::conditional<F32, float4, double4>::type) + 4 * 64 * (int)sizeof(double);
 }
 
 // One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  Each lane
@@ -858,13 +870,13 @@ constexpr int sym_lds_bytes() {
 template <bool F32, bool PROXY, int H = 2>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, double* __restrict__ phi, const double* __restrict__ tab,
-                                         DegPtrs qhat, DegOut phihat, void* lds) {
+                                         DegPtrs qhat, DegOut phihat, void* lds, double* nfp64 = nullptr) {
     using R = typename std::conditional<F32, float, double>::type;
     using V = typename std::conditional<F32, float4, double4>::type;
     // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
     constexpr R qs = F32 ? (R)1 : (R)0.5;
     V* src = static_cast<V*>(lds);                               // per copy: 64 staged sources, twice
-    R (*part_red)[64] = reinterpret_cast<R (*)[64]>(src + 4 * 128);  // [4][64] wave partials
+    double (*part_red)[64] = reinterpret_cast<double (*)[64]>(src + 4 * 128);  // [4][64] wave partials
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nslab = it.tn <= 64 * H ? 1 : 2;
     const int copies = 4 / nslab, copy = wave / nslab, sw = wave % nslab;
@@ -878,9 +890,11 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     const int m = it.degree + 1, P = m * m * m;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
     double* od = PROXY ? phihat.p[it.degree] : nullptr;
-    R tx[H], ty[H], tz[H], qi[H];
+    R tx[H], ty[H], tz[H];
+    double qi[H];               // FP32 form: the charge rounded to FP32, held in FP64
     int ti[H];
     bool mine[H];
+    const float thr32 = F32 ? fp32_close_threshold(box) : 0.0f;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         const int r = 64 * H * sw + 64 * h + lane;
@@ -902,7 +916,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
             tx[h] = (R)(x - cx);
             ty[h] = (R)(y - cy);
             tz[h] = (R)(z - cz);
-            qi[h] = (R)(qs * q);
+            qi[h] = (double)(R)(qs * q);
         }
     }
     double acc[H];
@@ -939,17 +953,16 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 dst[64] = v;
             }
             __syncthreads();
-            R psi = 0;
+            double psi = 0.0;
             if (active) {
-                R sum[H];
+                double sum[H];
 #pragma unroll
-                for (int h = 0; h < H; ++h) sum[h] = 0;
-                // 64 steps: lane l pairs its H targets with source (l + s) mod 64
-                auto steps = [&](auto guard) {
-#pragma unroll
-                    for (int s = 0; s < 64; ++s) {
+                for (int h = 0; h < H; ++h) sum[h] = 0.0;
+                // 64 steps: lane l pairs its H targets with source (l + s) mod 64;
+                // every term goes to FP64 sums
+                auto step = [&](int s, auto guard) {
                         const V v = mysrc[lane + s];
-                        R y[H];
+                        double y[H];
 #pragma unroll
                         for (int h = 0; h < H; ++h) {
                             const R dx = tx[h] - v.x, dy = ty[h] - v.y, dz = tz[h] - v.z;
@@ -957,25 +970,43 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                             r2 = dy * dy + r2;
                             r2 = dx * dx + r2;
                             if constexpr (F32) {
-                                y[h] = __builtin_amdgcn_rsqf(r2);
-                                if constexpr (decltype(guard)::value) y[h] = r2 > 0.0f ? y[h] : 0.0f;
+                                y[h] = (double)__builtin_amdgcn_rsqf(r2);
+                                if constexpr (!PROXY && decltype(guard)::value) {
+                                    if (r2 <= thr32) {       // closer than FP32 resolves: FP64
+                                        const int sj = c0 + 64 * copy + ((lane + s) & 63);
+                                        y[h] = mine[h] && sj < bn ? g_fp64<K_COULOMB>(p, ti[h], p, en.x + sj, 0.0, nfp64)
+                                                                  : 0.0;
+                                    }
+                                }
                             } else {
                                 double y0 = rsq_est(r2);
                                 if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
                                 y[h] = y0 * fma(-(r2 * y0), y0, 3.0);   // 2 y0 (3 - r^2 y0^2)/2; q staged /2
                             }
-                            sum[h] = fma(v.w, y[h], sum[h]);
+                            sum[h] = fma((double)v.w, y[h], sum[h]);
                         }
-                        R t = rol1(psi);
+                        double t = rol1(psi);
 #pragma unroll
-                        for (int h = 0; h < H; ++h) t = t + qi[h] * y[h];
+                        for (int h = 0; h < H; ++h) {
+                            if constexpr (F32) t = fma(qi[h], y[h], t);
+                            else t = t + qi[h] * y[h];
+                        }
                         psi = t;
-                    }
                 };
-                if (guard) steps(std::true_type{});
-                else steps(std::false_type{});
+                if (guard && F32) {
+                    // FP32 guarded ranges (near leaves) take a rolled loop: the
+                    // FP64 fallback stays out of the unrolled one
+#pragma unroll 1
+                    for (int s = 0; s < 64; ++s) step(s, std::true_type{});
+                } else if (guard) {
 #pragma unroll
-                for (int h = 0; h < H; ++h) acc[h] += (double)sum[h];
+                    for (int s = 0; s < 64; ++s) step(s, std::true_type{});
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 64; ++s) step(s, std::false_type{});
+                }
+#pragma unroll
+                for (int h = 0; h < H; ++h) acc[h] += sum[h];
                 part_red[wave][(lane + 63) & 63] = psi;
             }
             __syncthreads();
@@ -983,7 +1014,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 const int k = tid >> 6, ms = tid & 63;           // copy and source of the round
                 double t = 0.0;
                 for (int w = 0; w < nslab; ++w)
-                    if (64 * H * w < it.tn) t += (double)part_red[k * nslab + w][ms];
+                    if (64 * H * w < it.tn) t += part_red[k * nslab + w][ms];
                 if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
                 else atomicAdd(phi + en.x + c0 + tid, t);
             }

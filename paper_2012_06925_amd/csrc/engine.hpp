@@ -94,7 +94,9 @@ int separated_type(int64_t ct, int64_t cs, int d, bool pp_cc_only);
 // ---------------------------------------------------------------------------
 // A source entry is two int32 {a, b}; kind = (uint32)b >> 29:
 //   SRC_RANGE, SRC_RANGE_GUARD: source particles at tree positions [a, a + (b & kCountMask));
-//       GUARD when the source box may contain a target, so r^2 == 0 terms are skipped;
+//       GUARD when the source box touches or nearly touches the target leaf's
+//       (range_guarded): r^2 == 0 terms are skipped, and the FP32 forms
+//       re-evaluate pairs closer than FP32 resolves in FP64;
 //   SRC_PROXY: the (d+1)^3 proxies of source cluster a with their proxy charges,
 //       d = b & kCountMask the interpolation degree.
 // Adjacent particle ranges of one work group are merged into one entry.
@@ -140,20 +142,23 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
 // of L's typed lists without both directions of those pairs (its deferred
 // separated pairs are left empty).  The pairs with A < B are
 // packed into items over A's points in tiles of 256 (cluster = A): PP items
-// over A's particles with the merged particle ranges of A's partners (flagged
-// SRC_RANGE_GUARD where the two leaf boxes are near, see boxes_near), CC items
+// over A's particles with the merged particle ranges of A's partners, CC items
 // per (A, degree) over A's proxies with proxy entries of the partners; longest
-// first.  The evaluation counts are the kernel terms the items produce (both
-// directions).
+// first.  A tile's partner ranges flagged SRC_RANGE_GUARD (the two leaf boxes
+// are near, see range_guarded) form an item of their own: the first pp_plain PP
+// items hold no guarded range, the rest only guarded ranges.  The evaluation
+// counts are the kernel terms the items produce (both directions).
 struct SymWork {
     std::vector<Entry> pp_entries, cc_entries;
     std::vector<Item> pp_items, cc_items;
+    int64_t pp_plain = 0;
     double pp_evaluations = 0.0, cc_evaluations = 0.0;
     void clear() {
         pp_entries.clear();
         cc_entries.clear();
         pp_items.clear();
         cc_items.clear();
+        pp_plain = 0;
         pp_evaluations = cc_evaluations = 0.0;
     }
 };

@@ -40,10 +40,10 @@ __global__ __launch_bounds__(kBlock) void k_interact(const DevItem* __restrict__
                                                      const int2* __restrict__ entries, DevParticles tgt, DevTree Tt,
                                                      DevParticles src, DevTree S, const double* __restrict__ tab,
                                                      DegPtrs qhat, double param, double* __restrict__ out,
-                                                     DegOut pout, int add) {
+                                                     DegOut pout, int add, double* __restrict__ nfp64) {
     __shared__ typename Stage<F32>::V lds[kChunk];
     interact_body<KIND, F32, T, PROXY_TGT>(items[blockIdx.x], entries, tgt, Tt, src, S, tab, qhat, param, out, pout,
-                                           lds, add != 0);
+                                           lds, add != 0, nfp64);
 }
 
 // MF selects the matrix-core form of the contraction (device.hpp).
@@ -97,40 +97,50 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
 template <bool F32, bool PROXY>
 __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ items, const int2* __restrict__ entries,
                                                 DevParticles p, DevTree T, double* __restrict__ phi,
-                                                const double* __restrict__ tab, DegPtrs qhat, DegOut phihat) {
+                                                const double* __restrict__ tab, DegPtrs qhat, DegOut phihat,
+                                                double* __restrict__ nfp64) {
     __shared__ double4 pool[(sym_lds_bytes<F32>() + 31) / 32];
     // tiles of more than 128 targets: four per lane (one wave per copy)
     const DevItem it = items[blockIdx.x];
-    if (it.tn > 128) sym_body<F32, PROXY, 4>(it, entries, p, T, phi, tab, qhat, phihat, pool);
-    else sym_body<F32, PROXY, 2>(it, entries, p, T, phi, tab, qhat, phihat, pool);
+    if (it.tn > 128) sym_body<F32, PROXY, 4>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64);
+    else sym_body<F32, PROXY, 2>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64);
 }
 
 // ---------------------------------------------------------------------------
 // The same symmetric passes in FP32 evaluation with the squared distances on
 // the FP64 matrix cores.  With coordinates relative to the target cluster's
-// centre, |x_i - y_j|^2 = (x_i, 1) . (-2 y_j, |y_j|^2) + |x_i|^2, so one
-// v_mfma_f64_16x16x4f64 with A = (x, y, z, 1) per target row, B = (-2y, |y|^2)
-// per source column and C = |x_i|^2 (per target row, held in registers for
-// the whole item) gives 256 squared distances to FP64 accuracy (error ~1e-16
-// of the squared extent, far below the FP32 rounding of G for every pair not
-// closer than ~1e-4 of a leaf); the vector ALUs then take per pair one
-// conversion, one FP32 reciprocal square root and the two products q_j G and
-// q_i G.  A wave holds 64 targets as four 16-row blocks and walks the sources
-// 16 at a time, one B operand serving four products.  In the result lane l
-// holds column l mod 16 of rows l/16 + 4r.  Target sums are per-lane FP32
-// partials over a chunk of up to 256 sources, then added in FP64 pairwise
-// across lanes l and l ^ 8 (16 slots per lane become 8), and reduced over the
-// rest of the row at the end.  Each tile's source sums are per-lane partials
-// written to LDS; after the chunk one thread per source adds the 4 lane
-// groups' values in FP32 and the 4 waves' in FP64, in a fixed order, and adds
-// the sum with one FP64 atomic.  The next chunk's sources are loaded into registers
-// while the current one is evaluated.
-// Entries flagged SRC_RANGE_GUARD (a leaf with itself, or leaf boxes within
-// 2^-20 of their extent) drop pairs whose computed squared distance is at
-// most 2^-42 of the target box's squared diagonal: coincident points, whose
-// expansion leaves rounding noise instead of zero, and pairs closer than
-// FP32 coordinates relative to the box resolve; elsewhere the box gap keeps
-// the squared distance far above.
+// centre, |x_i - y_j|^2 = (x_i, |x_i|^2) . (-2 y_j, 1) + |y_j|^2, so one
+// v_mfma_f64_16x16x4f64 with A = (x, y, z, |x|^2) per target row (held in
+// registers for the whole item), B = (-2y, 1) per source column and C =
+// |y_j|^2 (the same for the four rows a lane holds of a column, so one
+// accumulator input serves the four blocks) gives 256 squared distances to
+// FP64 accuracy: the rounding
+// of the expansion stays below 2^-49 (|x_i|^2 + |y_j|^2).  The vector ALUs
+// then take per pair one conversion to FP32, the FP32 reciprocal square root
+// (the FP32 evaluation of G) and one conversion back, and add q_j G to the
+// target's FP64 sum and q_i G to the source's FP64 partial: every term is
+// accumulated in FP64.  A wave holds 64 targets as four 16-row blocks and
+// walks the sources 16 at a time, one B operand serving four products.  In
+// the result lane l holds column l mod 16 of rows l/16 + 4r.  Each tile's
+// source partials (over the 16 rows of a lane) are added to a per-wave FP64
+// slot of their column in LDS (LDS atomics, nothing to wait for); after the
+// chunk one thread per source adds the four waves' slots in a fixed order
+// and adds the sum with one FP64 atomic.
+// The next chunk's sources are loaded into registers while the current one is
+// evaluated.
+//
+// Squared distances that FP32 cannot be trusted with.  Entries not flagged
+// SRC_RANGE_GUARD keep every pair farther apart than 2^-11.5 of the distance
+// from the target box's centre to the far side of either box, so their
+// squared distances exceed 2^-24 (|x_i|^2 + |y_j|^2) and carry a relative
+// error below 2^-25.  On flagged entries (a leaf with itself, near leaves) a
+// pair whose squared distance is at most 2^-24 (max |x|^2 + max |y|^2 of the
+// wave's rows and the tile's columns) is left out of the tile and evaluated
+// again after it in FP64 from the particles' own coordinates: coincident
+// points (the self term, duplicates) contribute nothing, as in the FP64 form;
+// any other such pair adds its FP64 terms (the target's through an LDS
+// accumulator read at the end of the item, the source's with an atomic) and
+// is counted in *nfp64 (when not null), so no distinct pair is ever dropped.
 // ---------------------------------------------------------------------------
 constexpr int kSymChunk = 256;                  // sources per chunk: 16 tiles of 16
 constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q = 0)
@@ -138,48 +148,172 @@ constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q 
 // A lane's operands for one tile: its B entry and the charge of its source column
 struct alignas(16) SymB {
     double b;
-    float q, pad;
+    double q;
 };
 
-// ONE_SIDED: target sums only (the one-sided particle passes, k_pp_mfma)
-template <bool GUARD, bool ONE_SIDED>
-__device__ __forceinline__ void sym_tiles(int nt, const SymB (*__restrict__ sB)[64], float (*__restrict__ part)[64],
-                                          int lane, const double (&A)[4], const v4d (&C)[4],
-                                          const float (&qi)[4][4], float (&acc)[4][4], float thr) {
-    // the first tile of a chunk starts the FP32 target partials
-    auto tile = [&](int t, auto first) {
-        const double bv = sB[t][lane].b;
-        const float qj = sB[t][lane].q;
+// Shared memory of the matrix-core passes (42.1 KB: three work groups per CU).
+struct MfmaLds {
+    double sT[4][kBlock];        // target tile: relative x, y, z and q
+    SymB sB[16][64];             // the chunk's tiles, in lane order
+    v4d y2[16][16];              // |y|^2 of each tile's columns, four copies: the accumulator input
+    double part[4][16][16];      // source partials per wave, tile and column (zero between chunks)
+    double ymax[16];             // guarded chunks: max |y|^2 of each tile's sources
+    double corr[kBlock];         // FP64 terms of the pairs re-evaluated in FP64, per target
+};
+
+// ONE_SIDED: target sums only (the one-sided particle passes, k_pp_mfma).
+// fix(k, t) adds the FP64 terms of slot k = 4 b + r against column
+// `lane mod 16` of tile t (guarded tiles, pairs below the threshold).
+template <bool GUARD, bool ONE_SIDED, class Fix>
+__device__ __forceinline__ void mfma_tiles(int nt, MfmaLds& L, double (*__restrict__ part)[16], int lane,
+                                           const double (&A)[4], const double (&qi)[4][4], double (&acc)[4][4],
+                                           double xmax2, Fix&& fix) {
+    for (int t = 0; t < nt; ++t) {
+        const double bv = L.sB[t][lane].b, qj = L.sB[t][lane].q;
+        const v4d C = L.y2[t][lane & 15];
+        float thr = 0.0f;
+        if constexpr (GUARD) thr = (float)(0x1p-24 * (xmax2 + L.ymax[t]));
         v4d d[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C[b]);
-        float psi = 0.0f;
+        for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C);
+        double psi = 0.0;
+        uint32_t low = 0;                    // slots below the threshold
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float rf = (float)d[b][r];
-                float y = __builtin_amdgcn_rsqf(rf);
-                if constexpr (GUARD) y = rf > thr ? y : 0.0f;
-                if constexpr (decltype(first)::value) acc[b][r] = qj * y;
-                else acc[b][r] = fmaf(qj, y, acc[b][r]);
-                if constexpr (!ONE_SIDED) psi = fmaf(qi[b][r], y, psi);
+                double y = (double)__builtin_amdgcn_rsqf(rf);
+                if constexpr (GUARD) {
+                    const bool f = rf <= thr;
+                    low |= (uint32_t)f << (4 * b + r);
+                    y = f ? 0.0 : y;
+                }
+                acc[b][r] = fma(qj, y, acc[b][r]);
+                if constexpr (!ONE_SIDED) psi = fma(qi[b][r], y, psi);
             }
         }
-        if constexpr (!ONE_SIDED) part[t][lane] = psi;
-    };
-    tile(0, std::true_type{});
-    for (int t = 1; t < nt; ++t) tile(t, std::false_type{});
+        if constexpr (GUARD) {
+            while (low) {                    // rare: close pairs and coincident points
+                const int k = __builtin_ctz(low);
+                low &= low - 1;
+                fix(k, t);
+            }
+        }
+        if constexpr (!ONE_SIDED) atomicAdd(&part[t][lane & 15], psi);
+    }
 }
 
+// FP64 kernel value (Coulomb) of two particles from their tree-order
+// coordinates; 0 for coincident points.
+__device__ __forceinline__ double coulomb_exact(const DevParticles& a, int i, const DevParticles& b, int j,
+                                                double* nfp64) {
+    const double dx = a.x[i] - b.x[j], dy = a.y[i] - b.y[j], dz = a.z[i] - b.z[j];
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (r2 == 0.0) return 0.0;
+    if (nfp64) atomicAdd(nfp64, 1.0);
+    return rsq_full(r2);
+}
+
+// Stage one chunk's sources (thread tid holds source c0 + tid, relative to the
+// target centre; padding at kFarS with charge 0) as tiles, and for guarded
+// entries each tile's largest |y|^2 over its real sources.
+__device__ __forceinline__ void stage_chunk(MfmaLds& L, int tid, double nx, double ny, double nz, double nq, bool real,
+                                            bool guard) {
+    const int t = tid >> 4, j = tid & 15;
+    const double y2 = fma(nx, nx, fma(ny, ny, nz * nz));
+    L.sB[t][j] = SymB{-2.0 * nx, nq};
+    L.sB[t][16 + j] = SymB{-2.0 * ny, nq};
+    L.sB[t][32 + j] = SymB{-2.0 * nz, nq};
+    L.sB[t][48 + j] = SymB{1.0, nq};
+    L.y2[t][j] = v4d{y2, y2, y2, y2};
+    if (guard) {                        // uniform over the group: the entry's flag
+        double m = real ? y2 : 0.0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) m = fmax(m, __shfl_xor(m, o, 16));
+        if (j == 0) L.ymax[t] = m;
+    }
+}
+
+// Row sums of the FP64 slots at the end of an item: lane col of row group grp
+// returns the sum over the 16 columns of slot k = col (row 16 (k >> 2) + grp + 4 (k & 3)).
+__device__ __forceinline__ double reduce_rows(double (&acc)[4][4], int col) {
+    const bool hi = (col & 8) != 0;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        // slots j and j + 8 of lanes col and col ^ 8 (row_ror:8 within a row of 16)
+        const double lo = acc[j >> 2][j & 3], up = acc[2 + (j >> 2)][j & 3];
+        const double keep = hi ? up : lo, send = hi ? lo : up;
+        const uint64_t u = __builtin_bit_cast(uint64_t, send);
+        const int a = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x128, 0xf, 0xf, true);
+        const int c = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x128, 0xf, 0xf, true);
+        double s = keep + __builtin_bit_cast(double, (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)c << 32));
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        v = (col & 7) == j ? s : v;
+    }
+    return v;
+}
+
+// Targets of an item into the LDS tile (relative to the centre c; padding at
+// kFarT with charge 0), then each lane's operands: A per block, C and q per slot.
 template <bool PROXY>
+__device__ __forceinline__ void load_targets(MfmaLds& L, const DevItem& it, const DevParticles& p, const double* box,
+                                             int m, const double* ptab, const double* qd, double cx, double cy,
+                                             double cz, bool charges) {
+    const int tid = threadIdx.x;
+    double x = kFarT, y = kFarT, z = kFarT, q = 0.0;
+    if (tid < it.tn) {
+        const int ti = it.t0 + tid;
+        if constexpr (PROXY) {
+            proxy_point(box, m, ptab, ti, x, y, z);
+            q = qd[(int64_t)it.cluster * (m * m * m) + ti];
+        } else {
+            x = p.x[ti];
+            y = p.y[ti];
+            z = p.z[ti];
+            if (charges) q = p.q[ti];
+        }
+        x -= cx;
+        y -= cy;
+        z -= cz;
+    }
+    L.sT[0][tid] = x;
+    L.sT[1][tid] = y;
+    L.sT[2][tid] = z;
+    L.sT[3][tid] = q;
+    L.corr[tid] = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) (&L.part[0][0][0])[w * kBlock + tid] = 0.0;
+}
+
+__device__ __forceinline__ void lane_operands(const MfmaLds& L, int wave, int grp, int col, double (&A)[4],
+                                              double (&qi)[4][4], double (&acc)[4][4]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int base = 64 * wave + 16 * b;
+        if (grp < 3) {
+            A[b] = L.sT[grp][base + col];
+        } else {
+            const double x = L.sT[0][base + col], y = L.sT[1][base + col], z = L.sT[2][base + col];
+            A[b] = fma(x, x, fma(y, y, z * z));
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qi[b][r] = L.sT[3][base + grp + 4 * r];
+            acc[b][r] = 0.0;
+        }
+    }
+}
+
+// GUARDED: every entry of the items is a guarded particle range (PP only).
+template <bool PROXY, bool GUARDED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_mfma(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles p, DevTree T,
                                                      double* __restrict__ phi, const double* __restrict__ tab,
-                                                     DegPtrs qhat, DegOut phihat) {
-    __shared__ double sT[4][kBlock];             // target tile: relative x, y, z and q
-    __shared__ SymB sB[16][64];                  // the chunk's tiles, in lane order
-    __shared__ float part[4][16][64];            // source partials per wave, tile and lane
+                                                     DegPtrs qhat, DegOut phihat, double* __restrict__ nfp64) {
+    __shared__ MfmaLds L;
     const DevItem it = items[blockIdx.x];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
     const bool active = 64 * wave < it.tn;
@@ -189,72 +323,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const double* ptab = tab + 32 * it.degree;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
     double* od = PROXY ? phihat.p[it.degree] : nullptr;
-    // guarded entries: squared distances at or below 2^-42 of the squared box
-    // diagonal count as coincident (the rounding of the expansion stays below
-    // 2^-46 of it for sources within a few box sizes)
-    float thr;
+    // largest |x - c|^2 of the item's targets: a quarter of the box's squared diagonal
+    double xmax2;
     {
         const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
-        thr = fmaxf((float)(0x1p-42 * (ex * ex + ey * ey + ez * ez)), 0x1p-126f);
+        xmax2 = 0.25 * (ex * ex + ey * ey + ez * ez);
     }
-
-    {
-        double x = kFarT, y = kFarT, z = kFarT, q = 0.0;
-        if (tid < it.tn) {
-            const int ti = it.t0 + tid;
-            if constexpr (PROXY) {
-                proxy_point(box, m, ptab, ti, x, y, z);
-                q = qd[(int64_t)it.cluster * P + ti];
-            } else {
-                x = p.x[ti];
-                y = p.y[ti];
-                z = p.z[ti];
-                q = p.q[ti];
-            }
-            x -= cx;
-            y -= cy;
-            z -= cz;
-        }
-        sT[0][tid] = x;
-        sT[1][tid] = y;
-        sT[2][tid] = z;
-        sT[3][tid] = q;
-    }
+    load_targets<PROXY>(L, it, p, box, m, ptab, qd, cx, cy, cz, true);
     __syncthreads();
-    double A[4];
-    v4d C[4];
-    float qi[4][4], acc[4][4];
-    // FP64 target sums of slots k = 8 h + j (k = 4 b + r, h = bit 3 of the lane's
-    // column), each over the lane pair {col, col ^ 8}
-    double acc64[8];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int base = 64 * wave + 16 * b;
-        A[b] = grp < 3 ? sT[grp][base + col] : 1.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = base + grp + 4 * r;
-            const double x = sT[0][i], y = sT[1][i], z = sT[2][i];
-            C[b][r] = fma(x, x, fma(y, y, z * z));
-            qi[b][r] = (float)sT[3][i];
-            acc[b][r] = 0.0f;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc64[j] = 0.0;
-    const bool hi = (col & 8) != 0;
+    double A[4], qi[4][4], acc[4][4];
+    lane_operands(L, wave, grp, col, A, qi, acc);
 
     // this thread's source of a chunk (entry e, offset c0), relative to the centre
     double nx = kFarS, ny = kFarS, nz = kFarS, nq = 0.0;
+    bool nreal = false;
     auto load = [&](int e, int c0) {
         nx = kFarS;
         ny = kFarS;
         nz = kFarS;
         nq = 0.0;
+        nreal = false;
         if (e >= it.ee) return;
         const int2 en = entries[e];
         const int bn = PROXY ? P : (en.y & ((1 << 29) - 1));
         if (c0 + tid >= bn) return;
+        nreal = true;
         if constexpr (PROXY) {
             proxy_point(T.box + 6 * en.x, m, ptab, c0 + tid, nx, ny, nz);
             nq = qd[(int64_t)en.x * P + c0 + tid];
@@ -274,16 +367,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     while (e < it.ee) {
         const int2 en = entries[e];
         const int bn = PROXY ? P : (en.y & ((1 << 29) - 1));
-        const bool guard = !PROXY && ((unsigned)en.y >> 29) == 1u;
         const int nt = min(16, (bn - c0 + 15) >> 4);
-        {
-            const int t = tid >> 4, j = tid & 15;
-            const float q = (float)nq;
-            sB[t][j] = SymB{-2.0 * nx, q, 0.0f};
-            sB[t][16 + j] = SymB{-2.0 * ny, q, 0.0f};
-            sB[t][32 + j] = SymB{-2.0 * nz, q, 0.0f};
-            sB[t][48 + j] = SymB{fma(nx, nx, fma(ny, ny, nz * nz)), q, 0.0f};
-        }
+        stage_chunk(L, tid, nx, ny, nz, nq, nreal, GUARDED);
         __syncthreads();
         int e2 = e, c2 = c0 + kSymChunk;
         if (c2 >= bn) {
@@ -292,42 +377,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true, false>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
-            else sym_tiles<false, false>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
-            // slots k and k + 8 of lanes col and col ^ 8 (row_ror:8 within a row of 16)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float lo = acc[j >> 2][j & 3], up = acc[2 + (j >> 2)][j & 3];
-                const float keep = hi ? up : lo, send = hi ? lo : up;
-                const float other = __builtin_bit_cast(
-                    float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xf, 0xf, true));
-                acc64[j] += (double)(keep + other);
-            }
+            auto fix = [&](int k, int t) {
+                const int row = 64 * wave + 16 * (k >> 2) + grp + 4 * (k & 3), sc = c0 + 16 * t + col;
+                if (row >= it.tn || sc >= bn) return;
+                const int i = it.t0 + row, j = en.x + sc;
+                const double g = coulomb_exact(p, i, p, j, nfp64);
+                if (g == 0.0) return;
+                atomicAdd(&L.corr[row], p.q[j] * g);
+                atomicAdd(phi + j, p.q[i] * g);
+            };
+            mfma_tiles<GUARDED, false>(nt, L, L.part[wave], lane, A, qi, acc, xmax2, fix);
         }
         __syncthreads();
-        if (c0 + tid < bn) {
+        {
+            // this thread's source: the four waves' slots, read and cleared
             const int t = tid >> 4, j = tid & 15;
             double s = 0.0;
-            for (int w = 0; w < 4; ++w)
-                if (64 * w < it.tn)
-                    s += (double)((part[w][t][j] + part[w][t][16 + j]) + (part[w][t][32 + j] + part[w][t][48 + j]));
-            if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
-            else atomicAdd(phi + en.x + c0 + tid, s);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                s += L.part[w][t][j];
+                L.part[w][t][j] = 0.0;
+            }
+            if (c0 + tid < bn) {
+                if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
+                else atomicAdd(phi + en.x + c0 + tid, s);
+            }
         }
         e = e2;
         c0 = c2;
     }
     if (active) {
-        // lane col keeps slot k = col, summed over the remaining lanes col ^ 1, 2, 4
-        double v = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            double s = acc64[j];
-#pragma unroll
-            for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            v = (col & 7) == j ? s : v;
-        }
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
+        const double v = reduce_rows(acc, col) + (row < it.tn ? L.corr[row] : 0.0);
         if (row < it.tn) {
             if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
             else atomicAdd(phi + it.t0 + row, v);
@@ -347,54 +428,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_pp_mfma(
     const DevItem* __restrict__ items, const int2* __restrict__ entries, DevParticles tgt, DevTree Tt,
-    DevParticles src, DevTree S, const double* __restrict__ tab, DegPtrs qhat, double* __restrict__ out, int add) {
-    __shared__ double sT[3][kBlock];             // target tile: relative x, y, z
-    __shared__ SymB sB[16][64];                  // the chunk's tiles, in lane order
-    __shared__ float part[4][16][64];            // unused partials of the shared tile loop
+    DevParticles src, DevTree S, const double* __restrict__ tab, DegPtrs qhat, double* __restrict__ out, int add,
+    double* __restrict__ nfp64) {
+    __shared__ MfmaLds L;
     const DevItem it = items[blockIdx.x];
     if (add && it.ee == it.eb) return;           // nothing to add (the whole group leaves together)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
     const bool active = 64 * wave < it.tn;
     const double* box = Tt.box + 6 * it.cluster;
     const double cx = 0.5 * (box[0] + box[3]), cy = 0.5 * (box[1] + box[4]), cz = 0.5 * (box[2] + box[5]);
-    float thr;                                   // guarded ranges: coincident below 2^-42 of the squared diagonal
+    double xmax2;
     {
         const double ex = box[3] - box[0], ey = box[4] - box[1], ez = box[5] - box[2];
-        thr = fmaxf((float)(0x1p-42 * (ex * ex + ey * ey + ez * ez)), 0x1p-126f);
+        xmax2 = 0.25 * (ex * ex + ey * ey + ez * ez);
     }
-    {
-        double x = kFarT, y = kFarT, z = kFarT;
-        if (tid < it.tn) {
-            const int ti = it.t0 + tid;
-            x = tgt.x[ti] - cx;
-            y = tgt.y[ti] - cy;
-            z = tgt.z[ti] - cz;
-        }
-        sT[0][tid] = x;
-        sT[1][tid] = y;
-        sT[2][tid] = z;
-    }
+    load_targets<false>(L, it, tgt, box, 0, nullptr, nullptr, cx, cy, cz, false);
     __syncthreads();
-    double A[4];
-    v4d C[4];
-    float qi[4][4], acc[4][4];
-    double acc64[8];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int base = 64 * wave + 16 * b;
-        A[b] = grp < 3 ? sT[grp][base + col] : 1.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = base + grp + 4 * r;
-            const double x = sT[0][i], y = sT[1][i], z = sT[2][i];
-            C[b][r] = fma(x, x, fma(y, y, z * z));
-            qi[b][r] = 0.0f;
-            acc[b][r] = 0.0f;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc64[j] = 0.0;
-    const bool hi = (col & 8) != 0;
+    double A[4], qi[4][4], acc[4][4];
+    lane_operands(L, wave, grp, col, A, qi, acc);
 
     // entry e: kind, source count (particles or proxies)
     auto count_of = [&](int2 en) {
@@ -402,15 +453,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         return kind == 2 ? (low + 1) * (low + 1) * (low + 1) : low;
     };
     double nx = kFarS, ny = kFarS, nz = kFarS, nq = 0.0;
+    bool nreal = false;
     auto load = [&](int e, int c0) {
         nx = kFarS;
         ny = kFarS;
         nz = kFarS;
         nq = 0.0;
+        nreal = false;
         if (e >= it.ee) return;
         const int2 en = entries[e];
         const int bn = count_of(en);
         if (c0 + tid >= bn) return;
+        nreal = true;
         if (((unsigned)en.y >> 29) == 2u) {
             const int d = en.y & ((1 << 29) - 1), md = d + 1;
             proxy_point(S.box + 6 * en.x, md, tab + 32 * d, c0 + tid, nx, ny, nz);
@@ -433,14 +487,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int bn = count_of(en);
         const bool guard = ((unsigned)en.y >> 29) == 1u;
         const int nt = min(16, (bn - c0 + 15) >> 4);
-        {
-            const int t = tid >> 4, j = tid & 15;
-            const float q = (float)nq;
-            sB[t][j] = SymB{-2.0 * nx, q, 0.0f};
-            sB[t][16 + j] = SymB{-2.0 * ny, q, 0.0f};
-            sB[t][32 + j] = SymB{-2.0 * nz, q, 0.0f};
-            sB[t][48 + j] = SymB{fma(nx, nx, fma(ny, ny, nz * nz)), q, 0.0f};
-        }
+        stage_chunk(L, tid, nx, ny, nz, nq, nreal, guard);
         __syncthreads();
         int e2 = e, c2 = c0 + kSymChunk;
         if (c2 >= bn) {
@@ -449,31 +496,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
         load(e2, c2);
         if (active) {
-            if (guard) sym_tiles<true, true>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
-            else sym_tiles<false, true>(nt, sB, part[wave], lane, A, C, qi, acc, thr);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float lo = acc[j >> 2][j & 3], up = acc[2 + (j >> 2)][j & 3];
-                const float keep = hi ? up : lo, send = hi ? lo : up;
-                const float other = __builtin_bit_cast(
-                    float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xf, 0xf, true));
-                acc64[j] += (double)(keep + other);
-            }
+            auto fix = [&](int k, int t) {
+                const int row = 64 * wave + 16 * (k >> 2) + grp + 4 * (k & 3), sc = c0 + 16 * t + col;
+                if (row >= it.tn || sc >= bn) return;
+                const int j = en.x + sc;
+                const double g = coulomb_exact(tgt, it.t0 + row, src, j, nfp64);
+                if (g != 0.0) atomicAdd(&L.corr[row], src.q[j] * g);
+            };
+            if (guard) mfma_tiles<true, true>(nt, L, L.part[wave], lane, A, qi, acc, xmax2, fix);
+            else mfma_tiles<false, true>(nt, L, L.part[wave], lane, A, qi, acc, xmax2, fix);
         }
         __syncthreads();
         e = e2;
         c0 = c2;
     }
     if (active) {
-        double v = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            double s = acc64[j];
-#pragma unroll
-            for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            v = (col & 7) == j ? s : v;
-        }
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
+        const double v = reduce_rows(acc, col) + (row < it.tn ? L.corr[row] : 0.0);
         if (row < it.tn) {
             if (add) out[it.slot + row] += v;
             else out[it.slot + row] = v;
@@ -866,14 +905,14 @@ namespace {
 template <int KK, bool F32, bool PROXY_TGT>
 void launch_interact_t(int tpt, const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
                        DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double param, double* out,
-                       DegOut pout, int add, hipStream_t st) {
+                       DegOut pout, int add, double* nfp64, hipStream_t st) {
     switch (tpt) {
     case 1: hipLaunchKernelGGL((k_interact<KK, F32, 1, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, param, out, pout, add); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout, add, nfp64); break;
     case 2: hipLaunchKernelGGL((k_interact<KK, F32, 2, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, param, out, pout, add); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout, add, nfp64); break;
     case 4: hipLaunchKernelGGL((k_interact<KK, F32, 4, PROXY_TGT>), dim3(n_items), dim3(kBlock), 0, st, items, entries,
-                               tgt, Tt, src, S, tab, qhat, param, out, pout, add); break;
+                               tgt, Tt, src, S, tab, qhat, param, out, pout, add, nfp64); break;
     default: throw Error(-1, "targets per thread must be 1, 2 or 4");
     }
 }
@@ -881,11 +920,11 @@ void launch_interact_t(int tpt, const DevItem* items, int n_items, const int2* e
 
 void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const DevItem* items, int n_items,
                      const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
-                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add) {
+                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add, double* nfp64) {
     if (n_items <= 0) return;
     if (add && proxy_targets) throw Error(-1, "accumulating mode is for particle targets");
     if (fp32 && k.kind == K_POLY) throw Error(-5, "the polynomial test kernel runs in FP64 only");
-#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, add ? OUT_ADD : OUT_WRITE, st)
+#define LAUNCH_ONE(F, PT) launch_interact_t<KK, F, PT>(tpt, items, n_items, entries, tgt, Tt, src, S, tab, qhat, k.param, out, pout, add ? OUT_ADD : OUT_WRITE, nfp64, st)
     if (fp32) {
         if (proxy_targets) { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, true)); }
         else { DISPATCH_KIND(k.kind, LAUNCH_ONE(true, false)); }
@@ -907,29 +946,34 @@ void launch_down_leaf(int degree, bool mfma, const DevItem* items, int n_items, 
 }
 
 void launch_pp_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
-                    DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double* out, bool add, hipStream_t st) {
+                    DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double* out, bool add, double* nfp64,
+                    hipStream_t st) {
     if (n_items <= 0) return;
     hipLaunchKernelGGL(k_pp_mfma, dim3(n_items), dim3(kBlock), 0, st, items, entries, tgt, Tt, src, S, tab, qhat, out,
-                       add ? 1 : 0);
+                       add ? 1 : 0, nfp64);
     CHECK_LAUNCH();
 }
 
-void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_items, const int2* entries,
-                DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
-                hipStream_t st) {
+void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem* items, int n_items,
+                const int2* entries, DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat,
+                DegOut phihat, double* nfp64, hipStream_t st) {
     if (n_items <= 0) return;
     if (fp32 && mfma) {
+        if (proxies && guarded) throw Error(-1, "proxy entries are never guarded");
         if (proxies)
-            hipLaunchKernelGGL((k_sym_mfma<true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, tab,
-                               qhat, phihat);
+            hipLaunchKernelGGL((k_sym_mfma<true, false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
+                               phi, tab, qhat, phihat, nfp64);
+        else if (guarded)
+            hipLaunchKernelGGL((k_sym_mfma<false, true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
+                               phi, tab, qhat, phihat, nfp64);
         else
-            hipLaunchKernelGGL((k_sym_mfma<false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi,
-                               tab, qhat, phihat);
+            hipLaunchKernelGGL((k_sym_mfma<false, false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
+                               phi, tab, qhat, phihat, nfp64);
         CHECK_LAUNCH();
         return;
     }
 #define LAUNCH_SYM(F, PX) hipLaunchKernelGGL((k_sym<F, PX>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, \
-                                            tab, qhat, phihat)
+                                            tab, qhat, phihat, nfp64)
     if (fp32) {
         if (proxies) LAUNCH_SYM(true, true);
         else LAUNCH_SYM(true, false);

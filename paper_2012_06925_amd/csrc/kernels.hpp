@@ -66,10 +66,13 @@ void launch_down_transfer(int degree, bool mfma, const int32_t* kids, int n_kids
 // Interaction sums: proxy_targets = false for PP + PC into the particles of a
 // leaf (out = potentials in tree order; with add, out += the sums), true for
 // CP + CC into the proxies of a cluster (pout = proxy potentials).  tpt:
-// targets per thread (1, 2 or 4).
+// targets per thread (1, 2 or 4).  nfp64 (device double, may be null): the
+// FP32 forms count there the pairs of distinct points they evaluate in FP64
+// because FP32 coordinates do not resolve them (here and below).
 void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const DevItem* items, int n_items,
                      const int2* entries, DevParticles tgt, DevTree Tt, DevParticles src, DevTree S, const double* tab,
-                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add = false);
+                     DegPtrs qhat, double* out, DegOut pout, hipStream_t st, bool add = false,
+                     double* nfp64 = nullptr);
 
 // Symmetric passes (Coulomb, targets = sources): items are tiles of a target
 // cluster A (particles, or proxies of degree item.degree) with entries of
@@ -77,15 +80,17 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
 // adds to both sides with FP64 atomics: phi (tree order) for particles,
 // phihat.p[degree] for proxies, which already hold the other terms.  With
 // fp32 and mfma the squared distances come from the FP64 matrix cores.
-void launch_sym(bool fp32, bool mfma, bool proxies, const DevItem* items, int n_items, const int2* entries,
-                DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat, DegOut phihat,
-                hipStream_t st);
+// guarded: the items' entries are all flagged SRC_RANGE_GUARD (else none is).
+void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem* items, int n_items,
+                const int2* entries, DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat,
+                DegOut phihat, double* nfp64, hipStream_t st);
 
 // One-sided particle-target pass (PP ranges and PC proxies) in FP32 evaluation
 // with the squared distances from the FP64 matrix cores, Coulomb kernel only.
 // Items must hold at most 256 targets; out[slot + r] = (add: +=) the sum.
 void launch_pp_mfma(const DevItem* items, int n_items, const int2* entries, DevParticles tgt, DevTree Tt,
-                    DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double* out, bool add, hipStream_t st);
+                    DevParticles src, DevTree S, const double* tab, DegPtrs qhat, double* out, bool add, double* nfp64,
+                    hipStream_t st);
 
 // Proxy charges of every degree d < D in mask, restricted exactly from the
 // degree-D charges of each of the n_clusters clusters of T: to.p[d][c].

@@ -191,6 +191,10 @@ struct bldtt_plan {
     bool self_ready = false;
     double self_evaluations = 0.0;
     DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
+    // FP32 evaluation: pairs of distinct points the last compute evaluated in
+    // FP64 because FP32 coordinates do not resolve them (one device double)
+    DevBuf nfp64;
+    double* nfp64_ptr() const { return (flags & BLDTT_FP32_EVAL) ? nfp64.as<double>() : nullptr; }
     // FP32 Coulomb particle passes on the matrix cores (k_pp_mfma): tiles of 256 targets
     bool mfma_particle_passes() const {
         return (flags & BLDTT_FP32_EVAL) && kind == BLDTT_COULOMB && mfma_transfer();

@@ -201,24 +201,24 @@ ByTarget group(const Tree& T, const Lists& L, int t0, int t1, int degree) {
     return g;
 }
 
-// Two clusters of one tree whose boxes come within 2^-20 of the extent of
-// their union.  Squared distances formed as |x|^2 - 2 x.y + |y|^2 in FP64 carry
-// an error of ~1e-16 of the squared extent, so between leaves farther apart
-// they stay positive.
-bool boxes_near(const Tree& T, int64_t a, int64_t b) {
-    double d2 = 0.0, ext = 0.0;
+// Whether the particle range of source cluster s, as seen from target leaf t,
+// is evaluated as a guarded range: the boxes touch (the two sets may share a
+// point), or their gap g is small against the distance R from t's box centre
+// to the farthest corner of either box, g^2 <= 2^-23 R^2.  Pairs of unguarded
+// ranges then lie farther apart than 2^-11.5 R, so in coordinates relative to
+// that centre r^2 > 2^-24 (|x|^2 + |y|^2): the FP64 expansion |x|^2 - 2 x.y +
+// |y|^2 of the FP32 matrix-core passes keeps a relative error below 2^-25 there.
+bool range_guarded(const Tree& T, int64_t t, const Tree& S, int64_t s) {
+    double g2 = 0.0, R2 = 0.0;
     for (int d = 0; d < 3; ++d) {
-        const double gap = std::max({T.lo[3 * b + d] - T.hi[3 * a + d], T.lo[3 * a + d] - T.hi[3 * b + d], 0.0});
-        d2 += gap * gap;
-        ext = std::max(ext, std::max(T.hi[3 * a + d], T.hi[3 * b + d]) - std::min(T.lo[3 * a + d], T.lo[3 * b + d]));
+        const double tlo = T.lo[3 * t + d], thi = T.hi[3 * t + d], slo = S.lo[3 * s + d], shi = S.hi[3 * s + d];
+        const double gap = std::max({slo - thi, tlo - shi, 0.0});
+        const double c = 0.5 * (tlo + thi);
+        const double far = std::max({c - tlo, thi - c, std::fabs(slo - c), std::fabs(shi - c)});
+        g2 += gap * gap;
+        R2 += far * far;
     }
-    return d2 <= 0x1p-40 * ext * ext;
-}
-
-bool boxes_touch(const Tree& T, int64_t t, const Tree& S, int64_t s) {
-    for (int d = 0; d < 3; ++d)
-        if (T.hi[3 * t + d] < S.lo[3 * s + d] || S.hi[3 * s + d] < T.lo[3 * t + d]) return false;
-    return true;
+    return g2 <= 0x1p-23 * R2;
 }
 
 // Particle ranges of one work group: sort by start and merge neighbours that
@@ -383,7 +383,7 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
                         B.entries.push_back(proxy_entry(sc, part.deg[e]));
                         src += (double)cube(part.deg[e]);
                     } else {
-                        (boxes_touch(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
+                        (range_guarded(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
                         src += (double)S.count[sc];
                     }
                 }
@@ -497,24 +497,31 @@ struct PairIndex {
 
 struct SymBlock {
     std::vector<Entry> entries;
-    std::vector<std::pair<double, Item>> items;
+    std::vector<std::pair<double, Item>> items, gitems;    // items without / with guarded ranges
     double evals = 0.0;
 };
 
-void gather(std::vector<SymBlock>& blks, std::vector<Entry>& entries, std::vector<Item>& out, double& evals) {
-    static thread_local std::vector<std::pair<double, Item>> items;     // kept: no fresh pages per call
+// The blocks' entries concatenated; their items sorted longest first, those
+// without guarded ranges ahead of those with (n_plain of them).
+void gather(std::vector<SymBlock>& blks, std::vector<Entry>& entries, std::vector<Item>& out, double& evals,
+            int64_t* n_plain = nullptr) {
+    static thread_local std::vector<std::pair<double, Item>> items, gitems;   // kept: no fresh pages per call
     items.clear();
+    gitems.clear();
     for (auto& B : blks) {
         const int32_t shift = (int32_t)entries.size();
         entries.insert(entries.end(), B.entries.begin(), B.entries.end());
-        for (auto& it : B.items) {
-            it.second.eb += shift;
-            it.second.ee += shift;
-            items.push_back(it);
-        }
+        for (auto* v : {&B.items, &B.gitems})
+            for (auto& it : *v) {
+                it.second.eb += shift;
+                it.second.ee += shift;
+                (v == &B.items ? items : gitems).push_back(it);
+            }
         evals += B.evals;
     }
     sort_items(items, out);
+    if (n_plain) *n_plain = (int64_t)out.size();
+    sort_items(gitems, out);
 }
 
 }  // namespace
@@ -552,30 +559,40 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         std::vector<SymBlock> blks(nblk);
         parallel_run(nblk, [&](int64_t bi) {
             SymBlock& B = blks[bi];
-            std::vector<std::pair<int64_t, int64_t>> rp, rg;
+            std::vector<std::pair<int64_t, int64_t>> rp, rg, none;
             for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
                 if (!T.is_leaf(a)) continue;
                 double src = 0.0;
                 for (int64_t k = ipp.off[a]; k < ipp.off[a + 1]; ++k) {
                     const int64_t b = ipp.part[k].first;
                     if (b > a && ipp.has(b, a, 0)) {
-                        (boxes_near(T, a, b) ? rg : rp).emplace_back(T.begin[b], T.count[b]);
+                        (range_guarded(T, a, T, b) ? rg : rp).emplace_back(T.begin[b], T.count[b]);
                         src += (double)T.count[b];
                     }
                 }
                 if (rp.empty() && rg.empty()) continue;
+                double src_g = 0.0;
+                for (auto& r : rg) src_g += (double)r.second;
                 const int64_t eb = (int64_t)B.entries.size();
-                emit_ranges(rp, rg, B.entries);
+                emit_ranges(rp, none, B.entries);
+                const int64_t em = (int64_t)B.entries.size();
+                emit_ranges(none, rg, B.entries);
                 const int64_t ee = (int64_t)B.entries.size();
                 B.evals += 2.0 * (double)T.count[a] * src;
+                // tiles of A's particles: one item over the plain ranges, one
+                // over the guarded ranges
                 for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {
                     const int64_t tn = std::min<int64_t>(kTile, T.begin[a] + T.count[a] - tb);
-                    B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
-                                                              (int32_t)a, 0, (int32_t)tb}});
+                    if (em > eb)
+                        B.items.push_back({(src - src_g) * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb,
+                                                                         (int32_t)em, (int32_t)a, 0, (int32_t)tb}});
+                    if (ee > em)
+                        B.gitems.push_back({src_g * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)em,
+                                                                   (int32_t)ee, (int32_t)a, 0, (int32_t)tb}});
                 }
             }
         });
-        gather(blks, sw.pp_entries, sw.pp_items, sw.pp_evaluations);
+        gather(blks, sw.pp_entries, sw.pp_items, sw.pp_evaluations, &sw.pp_plain);
     }
     if (pp_ready) pp_ready();
     // the rest: every entry except both directions of the symmetric pairs,

@@ -86,6 +86,7 @@ def test_batch_matches_oracle():
         got = o.cpu().numpy()
         err = np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2))
         assert err <= 1e-12, err
+        assert core.max_rel(got, ref) <= 1e-12
     b.close()
 
 
