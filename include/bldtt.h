@@ -307,6 +307,20 @@ int bldtt_mlp_forward(const float *model, const float *features, int64_t n, floa
 int bldtt_mlp_loss_grad(const float *model, const float *features, const float *targets, int64_t n, float *grad,
                         float *loss, void *hip_stream);
 
+/* bldtt_mlp_loss_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, with the work memory in a static
+ * device array of the library (4.25 MiB, one copy per GPU, held until the
+ * process ends) instead of a fresh allocation, and the count of valid targets
+ * taken on the device instead of on the host.  Enqueued on hip_stream without
+ * any synchronization; nothing is allocated, freed or copied to the host.
+ * n is limited to 1..4096 samples.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams or threads) race and
+ * must be serialized by the caller.  Errors: EINVAL (NULL pointer, n outside
+ * [1, 4096]); EDEVICE. */
+int bldtt_mlp_loss_grad_noalloc(const float *model, const float *features, const float *targets, int64_t n,
+                                float *grad, float *loss, void *hip_stream);
+
 /* Train a model on the GPU from host arrays features[n][4], targets[n][11]
  * (NaN entries ignored): input standardisation and feature range from the
  * data, Glorot-uniform initial weights from `seed`, Adam (beta 0.9, 0.999) on

@@ -90,6 +90,8 @@ SIGNATURES = {
     "bldtt_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "bldtt_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "bldtt_mlp_loss_grad_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                              C.c_void_p, C.c_void_p]),
     "bldtt_set_tune_cache": (C.c_int, [C.c_char_p]),
     "bldtt_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "bldtt_batch_setup": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Particles), C.c_int32, C.c_double,

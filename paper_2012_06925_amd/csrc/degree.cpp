@@ -378,6 +378,17 @@ int bldtt_mlp_loss_grad(const float* model, const float* features, const float* 
     });
 }
 
+int bldtt_mlp_loss_grad_noalloc(const float* model, const float* features, const float* targets, int64_t n,
+                                float* grad, float* loss, void* hip_stream) {
+    if (!model || !features || !targets || !grad || !loss || n < 1 || n > mlp_noalloc_max_samples()) {
+        set_error("bad argument to bldtt_mlp_loss_grad_noalloc (device pointers, 1 <= n <= 4096)");
+        return BLDTT_EINVAL;
+    }
+    return guarded([&] {
+        launch_mlp_loss_grad_noalloc(model, features, targets, n, grad, loss, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
 int bldtt_mlp_train(const float* features, const float* targets, int64_t n, int32_t epochs, int32_t batch, float lr,
                     uint64_t seed, float* model_out, float* loss_history, void* hip_stream) {
     if (!features || !targets || !model_out || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.f)) {

@@ -56,5 +56,10 @@ void launch_mlp_loss_grad(const float* model, const float* feats, const float* t
 void launch_adam(float* params, const float* grad, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                  int step, hipStream_t st);
 int64_t mlp_work_floats(int64_t batch);
+// The same loss and gradient with the work memory in the library's static
+// device array (no allocation): n in [1, mlp_noalloc_max_samples()].
+void launch_mlp_loss_grad_noalloc(const float* model, const float* feats, const float* targets, int64_t n, float* grad,
+                                  float* loss, hipStream_t st);
+int64_t mlp_noalloc_max_samples();
 
 }  // namespace bldtt

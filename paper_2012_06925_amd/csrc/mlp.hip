@@ -7,6 +7,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <string>
 
 #include "degree.hpp"
 #include "engine.hpp"
@@ -159,11 +161,13 @@ struct WorkView {
 };
 
 // Forward per sample; output error terms dY = 2 (y - t) / n_valid (0 for NaN targets).
+// inv_dev, when not null, holds 1/n_valid in device memory (it replaces inv_valid).
 __global__ __launch_bounds__(kBlock) void k_train_forward(const float* __restrict__ M, const float* __restrict__ feats,
                                                           const float* __restrict__ tgt, int64_t n, float inv_valid,
-                                                          float* __restrict__ work) {
+                                                          const float* __restrict__ inv_dev, float* __restrict__ work) {
     __shared__ float sM[kNModel];
     M = stage_model(M, sM);
+    if (inv_dev) inv_valid = *inv_dev;
     const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (b >= n) return;
     WorkView w(work, n);
@@ -234,8 +238,9 @@ __global__ __launch_bounds__(kBlock) void k_grads(int64_t n, const float* __rest
 
 // Loss = sum of squared errors / n_valid, summed in a fixed order by one block.
 __global__ __launch_bounds__(kBlock) void k_loss(int64_t n, const float* __restrict__ work, float inv_valid,
-                                                 float* __restrict__ loss) {
+                                                 const float* __restrict__ inv_dev, float* __restrict__ loss) {
     __shared__ float red[kBlock];
+    if (inv_dev) inv_valid = *inv_dev;
     WorkView w(const_cast<float*>(work), n);
     float s = 0.f;
     for (int64_t b = threadIdx.x; b < n; b += kBlock) s += w.sq[b];
@@ -247,6 +252,29 @@ __global__ __launch_bounds__(kBlock) void k_loss(int64_t n, const float* __restr
     }
     if (threadIdx.x == 0) *loss = red[0] * inv_valid;
 }
+
+// 1/n_valid of targets[n][11] (NaN entries excluded; 0 when none is valid),
+// counted by one block in a fixed order and rounded as the host computes it.
+__global__ __launch_bounds__(kBlock) void k_inv_valid(const float* __restrict__ tgt, int64_t n, float* __restrict__ out) {
+    __shared__ int64_t red[kBlock];
+    int64_t c = 0;
+    for (int64_t k = threadIdx.x; k < n * kNOut; k += kBlock) c += isnan(tgt[k]) ? 0 : 1;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] > 0 ? __fdiv_rn(1.0f, (float)red[0]) : 0.0f;
+}
+
+// Work memory of bldtt_mlp_loss_grad_noalloc, one copy per GPU for the life of
+// the process: the loss-gradient work of up to kNoAllocSamples samples, then
+// 1/n_valid.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device.
+constexpr int64_t kNoAllocSamples = 4096;
+constexpr int64_t kNoAllocWork = kNoAllocSamples * (kNIn + 4 * kNHid + kNOut + 1);
+static __device__ __align__(256) float scratch[kNoAllocWork + 64];
 
 __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                                                  float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
@@ -281,15 +309,57 @@ void launch_mlp_forward(const float* model, const float* feats, int64_t n, float
     CHECK_LAUNCH();
 }
 
-void launch_mlp_loss_grad(const float* model, const float* feats, const float* targets, int64_t n, float inv_valid,
-                          float* work, float* grad, float* loss, hipStream_t st) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_train_forward, dim3(blocks(n)), dim3(kBlock), 0, st, model, feats, targets, n, inv_valid, work);
+namespace {
+// The five kernels of the loss and gradient; inv_dev as in k_train_forward.
+void enqueue_loss_grad(const float* model, const float* feats, const float* targets, int64_t n, float inv_valid,
+                       const float* inv_dev, float* work, float* grad, float* loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_train_forward, dim3(blocks(n)), dim3(kBlock), 0, st, model, feats, targets, n, inv_valid,
+                       inv_dev, work);
     hipLaunchKernelGGL(k_back2, dim3(blocks(n * kNHid)), dim3(kBlock), 0, st, model, n, work);
     hipLaunchKernelGGL(k_back1, dim3(blocks(n * kNHid)), dim3(kBlock), 0, st, model, n, work);
     hipLaunchKernelGGL(k_grads, dim3(blocks(kNParams)), dim3(kBlock), 0, st, n, (const float*)work, grad);
-    hipLaunchKernelGGL(k_loss, dim3(1), dim3(kBlock), 0, st, n, (const float*)work, inv_valid, loss);
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(kBlock), 0, st, n, (const float*)work, inv_valid, inv_dev, loss);
     CHECK_LAUNCH();
+}
+
+// Device address of `scratch` per device, looked up once per device with that
+// device current (each GPU holds its own copy at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+
+float* scratch_on_current_device() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) throw Error(-3, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(-5, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw Error(-3, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<float*>(ptr);
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
+void launch_mlp_loss_grad(const float* model, const float* feats, const float* targets, int64_t n, float inv_valid,
+                          float* work, float* grad, float* loss, hipStream_t st) {
+    if (n <= 0) return;
+    enqueue_loss_grad(model, feats, targets, n, inv_valid, nullptr, work, grad, loss, st);
+}
+
+int64_t mlp_noalloc_max_samples() { return kNoAllocSamples; }
+
+void launch_mlp_loss_grad_noalloc(const float* model, const float* feats, const float* targets, int64_t n, float* grad,
+                                  float* loss, hipStream_t st) {
+    if (n < 1 || n > kNoAllocSamples) throw Error(-1, "bldtt_mlp_loss_grad_noalloc: n must lie in [1, 4096]");
+    float* work = scratch_on_current_device();
+    float* inv = work + kNoAllocWork;            // 1/n_valid, written before it is read
+    hipLaunchKernelGGL(k_inv_valid, dim3(1), dim3(kBlock), 0, st, targets, n, inv);
+    enqueue_loss_grad(model, feats, targets, n, 0.0f, inv, work, grad, loss, st);
 }
 
 void launch_adam(float* params, const float* grad, float* m, float* v, int n, float lr, float b1, float b2, float eps,
