@@ -1,6 +1,6 @@
 """Throughput of the BLDTT compute phase on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload cube1e7] [--mode both|plain|tuned]
+    python bench.py [--steps K] [--warmup W] [--workload cube1e7] [--mode both|plain|fp32|tuned]
     python bench.py --sweep plain|tuned        # choose the operating points
     python bench.py --workload batch256        # 256 problems in one persistent graph launch
 
@@ -11,12 +11,16 @@ the timed region and reported as setup_ms.  The accuracy of each timed form
 is measured afterwards against the direct sum on a random 0.1% of the targets
 (GPU compensated direct sum, spot-checked against the CPU oracle).
 
-Two forms are timed on the same particles:
-  plain  FP64 evaluation, one degree n for every pair (the paper's method);
-  tuned  FP32 evaluation with FP64 accumulation, and a per-pair degree chosen
-         by the GPU-trained model (models/coulomb_degree.bin).
-`value` is the tuned form's particles/s when it meets the 1e-6 error target
-(else the plain form's); both are reported.  Prints one JSON line.
+Forms timed on the same particles:
+  plain  FP64 evaluation, one degree n for every pair: the paper's method and
+         arithmetic.  `value`, `dtype` and `roofline` are this form's.
+  tuned  FP32 evaluation with every term added to FP64 sums, and a per-pair
+         degree chosen by the GPU-trained model (models/coulomb_degree.bin);
+         reported under forms.tuned with tuned_over_plain.
+The other workloads of the build (1E6 cube in three forms, the unequal
+Yukawa sets, the 256-problem batch, 1E8 with the learned degree) follow
+under `extras` with a few steps each (--no-extras skips them).  Prints one
+JSON line.
 """
 from __future__ import annotations
 
@@ -26,6 +30,7 @@ import json
 import os
 import sys
 import time
+import traceback
 
 import numpy as np
 
@@ -37,9 +42,11 @@ TARGET_ERR = 1e-6
 FP64_VALU_PEAK = 78.6          # TFLOP/s, MI355X vector FP64
 FP32_VALU_PEAK = 157.3         # TFLOP/s, MI355X vector FP32 (packed)
 FLOPS_PER_EVAL = {"coulomb": 11, "yukawa": 15, "oscillatory": 15, "regcoulomb": 12, "poly": 8}
-
-
 KERNEL_SOURCES = ("kernels.hip", "device.hpp")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -51,43 +58,68 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_name: str, mode: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_name}_{mode}.txt")
+def _profile_record(name: str):
+    """A committed rocprofv3 counter record, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+    return rec if rec.get("kernel_source_sha256_16") == kernel_source_hash() else None
 
 
-def cpu_baseline(wl, theta, degree, leaf, n) -> dict:
-    """The CPU oracle's compute phase on a bounded sample of the same workload."""
+def traffic_for(kernel_name: str, mode: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the pass."""
+    rec = _profile_record(f"traffic_{kernel_name}_{mode}.txt")
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def counters_for(kernel_name: str, mode: str):
+    """Counter-based vector/matrix FLOPs per launch of the pass (SQ_INSTS_VALU_*)."""
+    rec = _profile_record(f"counters_{kernel_name}_{mode}.json")
+    return rec.get("per_launch") if rec else None
+
+
+def cpu_baseline(p, kernel, theta, degree, leaf, stride) -> dict:
+    """The CPU oracle's compute phase on the benchmark's own particles: the
+    traversal, upward and downward passes in full, the interaction sums on the
+    leaves and clusters whose index is 0 modulo `stride` (a bounded sample),
+    scaled by `stride`.  The oracle's tree build is setup and is not timed."""
     from oracle import core
-    from paper_2012_06925_amd import inputs
-    p = inputs.particles(n, wl["dist"], seed=inputs.BASE_SEED + 900)
-    run = core.Run(p, p, kernel=wl["kernel"], theta=theta, degree=degree, leaf=leaf)
+    run = core.Run(p, p, kernel=kernel, theta=theta, degree=degree, leaf=leaf)
     t0 = time.perf_counter()
-    run.run_all()
-    wall = time.perf_counter() - t0
-    return {"value": n / wall, "unit": "particles/s", "cores": core.num_threads(), "kind": "oracle",
-            "sample": f"{n} particles, {wl['dist']}, {wl['kernel']}, theta={theta}, n={degree}, leaf={leaf}, FP64; "
-                      f"timed: traversal + upward + PP/PC/CP/CC + downward ({wall:.2f} s)",
-            "phase_s": {k: round(float(v), 4) for k, v in run.times().items()}}
+    run.traverse()
+    t1 = time.perf_counter()
+    run.upward()
+    t2 = time.perf_counter()
+    t_int = run.interact_sample(stride)
+    t3 = time.perf_counter()
+    run.downward()
+    t4 = time.perf_counter()
+    total = (t1 - t0) + (t2 - t1) + stride * t_int + (t4 - t3)
+    return {"value": p.n / total, "unit": "particles/s", "cores": core.num_threads(), "kind": "oracle",
+            "sample": f"the same {p.n} particles ({kernel}, theta={theta}, n={degree}, leaf={leaf}, FP64): traversal, "
+                      f"upward and downward timed in full; PP/PC/CP/CC sums timed on every {stride}th leaf and "
+                      f"cluster ({t_int:.2f} s) and scaled by {stride}; estimated compute phase {total:.1f} s",
+            "phase_s": {"traverse": round(t1 - t0, 4), "upward": round(t2 - t1, 4),
+                        "interact_sampled": round(t_int, 4), "interact_scaled": round(stride * t_int, 3),
+                        "downward": round(t4 - t3, 4)}}
 
 
 class Bench:
-    def __init__(self, args, wl, M, seed, src, dev):
+    """Timed forms of one particle problem: targets None (= sources) or (x, y, z)."""
+
+    def __init__(self, args, kernel, leaf, tgt, src, seed, fraction=1e-3, minimum=1000):
         import torch
         from paper_2012_06925_amd import api, inputs
         self.torch, self.api = torch, api
-        self.args, self.wl, self.M, self.dev, self.src = args, wl, M, dev, src
-        self.sel = inputs.error_sample(M, seed, fraction=1e-3, minimum=min(M, 1000))
+        self.args, self.kernel, self.leaf, self.tgt, self.src = args, kernel, leaf, tgt, src
+        self.M = (src if tgt is None else tgt)[0].numel()
+        dev = src[0].device
+        self.sel = inputs.error_sample(self.M, seed, fraction=fraction, minimum=min(self.M, minimum))
         sel_t = torch.from_numpy(self.sel).to(dev)
-        self.ds = api.direct_sum(src[:3], src, kernel=wl["kernel"], sel=sel_t).cpu().numpy()
-        self.out = torch.empty(M, dtype=torch.float64, device=dev)
+        t3 = src[:3] if tgt is None else tgt
+        self.ds = api.direct_sum(t3, src, kernel=kernel, sel=sel_t).cpu().numpy()
+        self.out = torch.empty(self.M, dtype=torch.float64, device=dev)
         self.model = None
 
     def plan(self, mode, theta, degree, tau=None, profile=False):
@@ -102,8 +134,8 @@ class Bench:
         if mode == "tuned":
             flags |= _lib.LEARNED_DEGREE
         t0 = time.perf_counter()
-        plan = self.api.Plan(None, self.src, kernel=self.wl["kernel"], theta=theta, degree=degree,
-                             leaf=self.args.leaf, flags=flags)
+        plan = self.api.Plan(self.tgt, self.src, kernel=self.kernel, theta=theta, degree=degree, leaf=self.leaf,
+                             flags=flags)
         setup_ms = (time.perf_counter() - t0) * 1e3
         if mode == "tuned":
             if self.model is None:
@@ -138,54 +170,39 @@ class Bench:
         phase = {k: (st["phase_ms"][k] - base["phase_ms"][k]) / max(1, n_prof) for k in st["phase_ms"]}
         return ms, wall_ms, phase, st
 
-    def form(self, mode, theta, degree, tau=None):
+    def form(self, mode, theta, degree, tau=None, steps=None, warmup=None):
+        steps = self.args.steps if steps is None else steps
+        warmup = self.args.warmup if warmup is None else warmup
         plan, setup_ms = self.plan(mode, theta, degree, tau, profile=True)
-        ms, wall_ms, phase, st = self.time_plan(plan, self.args.steps, self.args.warmup)
+        ms, wall_ms, phase, st = self.time_plan(plan, steps, warmup)
         err = self.error()
         plan.close()
-        inter = st["interactions"]
-        fl = FLOPS_PER_EVAL[self.wl["kernel"]]
-        # the particle pass (near-field PP in the per-pair degree form), its
-        # second pass (separated pairs' PP/PC), the symmetric PP pass (both
-        # directions counted: the algorithmic count; it evaluates G once per
-        # pair of particles), the proxy pass, and the pass over each leaf with
-        # itself that runs before the traversal
-        work = {"pp_pc": st["pass_interactions"][0] * fl, "pp_pc_sep": st["pass_interactions"][1] * fl,
-                "pp_sym": st["pass_interactions"][2] * fl, "cp_cc": (inter["CP"] + inter["CC"]) * fl,
-                "pp_self": st["pass_interactions"][4] * fl}
-        dom = max(work, key=lambda k: phase[k])
-        achieved = work[dom] / (phase[dom] * 1e-3) / 1e12
-        fp32 = mode != "plain"
-        peak = FP32_VALU_PEAK if fp32 else FP64_VALU_PEAK
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic_for(dom, "fp32" if fp32 else "fp64"),
-                "flops_per_launch": work[dom], "launch_ms": round(phase[dom], 4), "flops_per_eval": fl,
-                "evals_per_s": round(work[dom] / fl / (phase[dom] * 1e-3), 1),
-                "kernel_values_per_s": round(work[dom] / fl / (2.0 if dom == "pp_sym" else 1.0) / (phase[dom] * 1e-3), 1)}
         rec = {"mode": mode, "theta": theta, "degree": degree, "particles_per_s": self.M / (ms * 1e-3),
-               "ms_per_step": round(ms, 3), "wall_ms_per_step": round(wall_ms, 3), "error_vs_direct": err,
-               "setup_ms": round(setup_ms, 1), "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+               "ms_per_step": round(ms, 3), "wall_ms_per_step": round(wall_ms, 3), "steps": steps,
+               "error_vs_direct": err, "setup_ms": round(setup_ms, 1),
+               "phase_ms": {k: round(v, 4) for k, v in phase.items()},
                "traverse_ms": round(st["traverse_ms"], 3), "host_marks_ms": [round(v, 3) for v in st["host_marks_ms"]],
-               "interactions": inter, "n_entries": st["n_entries"],
-               "roofline": roof}
+               "interactions": st["interactions"], "n_entries": st["n_entries"],
+               "roofline": roofline(mode, self.kernel, st, phase)}
+        if mode != "plain":
+            rec["fp64_close_pairs"] = st["fp64_close_pairs"]
         if mode == "tuned":
             rec.update(tau=tau, sep_pairs=st["sep_pairs"], sep_direct=st["sep_direct"],
                        sep_fallback=st["sep_fallback"], pairs_per_degree=st["pairs_per_degree"],
                        down_degree=st["down_degree"])
-        print(f"[bench] {mode}: {ms:.2f} ms/step err {err:.3e} phases {rec['phase_ms']}", file=sys.stderr,
-              flush=True)
+        log(f"{mode}: {ms:.2f} ms/step err {err:.3e} phases {rec['phase_ms']}")
         return rec
 
     def sweep(self, mode):
         rows = []
-        leaves = self.args.sweep_leaves or [self.args.leaf]
+        leaves = self.args.sweep_leaves or [self.leaf]
         if mode == "plain":
             grid = [(lf, th, n, None) for lf in leaves for th in self.args.sweep_thetas for n in self.args.sweep_degrees]
         else:
             grid = [(lf, th, self.args.tuned_fallback, tau) for lf in leaves for th in self.args.sweep_thetas
                     for tau in self.args.sweep_taus]
         for lf, th, n, tau in grid:
-            self.args.leaf = lf
+            self.leaf = lf
             plan, _ = self.plan("tuned" if mode == "tuned" else "plain", th, n, tau)
             ms, wall, _, st = self.time_plan(plan, self.args.steps, 1)
             err = self.error()
@@ -201,10 +218,40 @@ class Bench:
         return {"sweep": mode, "workload": self.args.workload, "M": self.M, "best": best, "rows": rows}
 
 
+def roofline(mode, kernel, st, phase) -> dict:
+    """Roofline of the dominant pass.  `achieved` is algorithmic: the pass's
+    kernel terms from the lists (both directions of a symmetric pair, the
+    method's count) x the flops per term, over the pass's duration (HIP events
+    on the pass's own stream).  `evaluated_per_s` counts the kernel values the
+    pass computes (a symmetric pass computes one value for two terms), and
+    `counters` holds the rocprofv3 instruction-counter figures of the pass
+    when they were taken on the current kernel source."""
+    inter = st["interactions"]
+    fl = FLOPS_PER_EVAL[kernel]
+    # the particle pass (near-field PP in the per-pair degree form), its second
+    # pass (separated pairs' PP/PC), the symmetric PP pass, the proxy pass, and
+    # the pass over each leaf with itself that runs before the traversal
+    terms = {"pp_pc": st["pass_interactions"][0], "pp_pc_sep": st["pass_interactions"][1],
+             "pp_sym": st["pass_interactions"][2], "cp_cc": inter["CP"] + inter["CC"],
+             "pp_self": st["pass_interactions"][4]}
+    dom = max(terms, key=lambda k: phase[k])
+    sec = phase[dom] * 1e-3
+    achieved = terms[dom] * fl / sec / 1e12
+    fp32 = mode != "plain"
+    peak = FP32_VALU_PEAK if fp32 else FP64_VALU_PEAK
+    prec = "fp32" if fp32 else "fp64"
+    values = terms[dom] / (2.0 if dom == "pp_sym" else 1.0)
+    return {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic_for(dom, prec),
+            "flops_per_launch": terms[dom] * fl, "launch_ms": round(phase[dom], 4), "flops_per_term": fl,
+            "terms_per_s": round(terms[dom] / sec, 1), "evaluated_per_s": round(values / sec, 1),
+            "counters": counters_for(dom, prec)}
+
+
 BATCH_METRIC = "particles/s (compute phase), 256 uneven problems in one persistent graph launch"
 
 
-def batch_bench(args, wl, name) -> dict:
+def batch_bench(args, wl, name, steps, warmup, with_cpu=True) -> dict:
     """One graph launch of the batched persistent kernel per step, against the
     same problems run one after another (bldtt_compute each)."""
     import tempfile
@@ -212,13 +259,16 @@ def batch_bench(args, wl, name) -> dict:
     import torch
     from paper_2012_06925_amd import _lib, api, inputs
     dev = torch.device("cuda:0")
+    theta = args.theta if args.theta is not None and args.workload == name else wl["theta"]
+    degree = args.degree if args.degree is not None and args.workload == name else wl["degree"]
+    leaf = args.leaf if args.leaf is not None and args.workload == name else wl["leaf"]
     probs = inputs.batch_problems(count=wl["count"], seed=inputs.workload_seed(name), lo_exp=wl["lo_exp"],
                                   hi_exp=wl["hi_exp"])
     sets = [p for _, p in probs]
     total = sum(p.n for p in sets)
-    print(f"[bench] {len(sets)} problems, {total} particles", file=sys.stderr, flush=True)
+    log(f"{len(sets)} problems, {total} particles")
     dsets = [(None, tuple(torch.from_numpy(a).to(dev) for a in (p.x, p.y, p.z, p.q))) for p in sets]
-    kw = dict(kernel=wl["kernel"], theta=args.theta, degree=args.degree, leaf=args.leaf)
+    kw = dict(kernel=wl["kernel"], theta=theta, degree=degree, leaf=leaf)
     outs = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in sets]
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -240,8 +290,7 @@ def batch_bench(args, wl, name) -> dict:
     seq_phi = [o.clone() for o in outs]
     for pl in plans:
         pl.close()
-    print(f"[bench] sequential: {seq_ms:.2f} ms (wall {seq_wall:.2f}, host traversal {seq_traverse:.2f})",
-          file=sys.stderr, flush=True)
+    log(f"sequential: {seq_ms:.2f} ms (wall {seq_wall:.2f}, host traversal {seq_traverse:.2f})")
 
     # the batch: autotuned tile, one graph launch per step
     cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "bldtt_tune_cache.txt")
@@ -250,19 +299,19 @@ def batch_bench(args, wl, name) -> dict:
     b = api.Batch(dsets, flags=_lib.AUTOTUNE, **kw)
     setup_ms = (time.perf_counter() - t0) * 1e3
     st = b.stats()
-    print(f"[bench] batch setup {setup_ms:.0f} ms, tile tpt={st['tpt']} groups/CU={st['groups_per_cu']} "
-          f"(tuned={st['tuned']}), {st['n_tasks']} tasks", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    log(f"batch setup {setup_ms:.0f} ms, tile tpt={st['tpt']} groups/CU={st['groups_per_cu']} "
+        f"(tuned={st['tuned']}), {st['n_tasks']} tasks")
+    for _ in range(warmup):
         b.compute(outs)
     b.check()
     w0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         b.compute(outs)
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - w0) * 1e3 / args.steps
-    ms = ev0.elapsed_time(ev1) / args.steps
+    wall = (time.perf_counter() - w0) * 1e3 / steps
+    ms = ev0.elapsed_time(ev1) / steps
     b.check()
     parity = max(float((o - r).abs().max() / r.abs().max()) for o, r in zip(outs, seq_phi))
     # accuracy against the direct sum on 0.1% of each problem's targets (at least 8)
@@ -283,15 +332,15 @@ def batch_bench(args, wl, name) -> dict:
     achieved = work / (ms * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": "k_batch (every phase, one launch)", "achieved": round(achieved, 3),
             "peak": FP64_VALU_PEAK, "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK, 4),
-            "traffic": None, "flops_per_launch": work, "launch_ms": round(ms, 4), "flops_per_eval": fl}
+            "traffic": None, "flops_per_launch": work, "launch_ms": round(ms, 4), "flops_per_term": fl}
     b.close()
     cpu = None
-    if not args.no_cpu:
+    if with_cpu:
         k = args.cpu_problems
         from oracle import core
         t0 = time.perf_counter()
         for p in sets[:k]:
-            core.Run(p, p, kernel=wl["kernel"], theta=args.theta, degree=args.degree, leaf=args.leaf).run_all()
+            core.Run(p, p, kernel=wl["kernel"], theta=theta, degree=degree, leaf=leaf).run_all()
         wall_cpu = time.perf_counter() - t0
         n_cpu = sum(p.n for p in sets[:k])
         cpu = {"value": n_cpu / wall_cpu, "unit": "particles/s", "cores": core.num_threads(), "kind": "oracle",
@@ -299,10 +348,10 @@ def batch_bench(args, wl, name) -> dict:
                          f"FP64 ({wall_cpu:.2f} s)"}
     return {
         "metric": BATCH_METRIC, "value": total / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": name, "problems": len(sets), "particles": total, "kernel": wl["kernel"],
-                   "theta": args.theta, "degree": args.degree, "leaf": args.leaf},
+                   "theta": theta, "degree": degree, "leaf": leaf},
         "error_vs_direct": err, "worst_problem_error": worst, "batch_vs_sequential_maxrel": parity,
         "wall_ms_per_step": round(wall, 3), "setup_ms": round(setup_ms, 1),
         "tile": {"tpt": st["tpt"], "groups_per_cu": st["groups_per_cu"], "grid": st["grid"], "tuned": st["tuned"],
@@ -313,6 +362,84 @@ def batch_bench(args, wl, name) -> dict:
         "batch_over_sequential": seq_ms / ms,
         "roofline": roof, "cpu_baseline": cpu,
     }
+
+
+def _dev_set(p, dev, charges=True):
+    import torch
+    arrays = (p.x, p.y, p.z, p.q) if charges else (p.x, p.y, p.z)
+    return tuple(torch.from_numpy(a).to(dev) for a in arrays)
+
+
+def extras(args) -> dict:
+    """The build's other workloads, a few steps each: the 1E6 cube in its three
+    forms, the unequal Yukawa sets, the 256-problem batch and 1E8 with the
+    learned degree (the workload's theta 0.8 and the faster 0.87)."""
+    import torch
+    from paper_2012_06925_amd import inputs
+    dev = torch.device("cuda:0")
+    steps, warmup = args.extra_steps, 1
+    out = {}
+
+    def guarded(name, fn):
+        t0 = time.perf_counter()
+        try:
+            out[name] = fn()
+        except Exception as e:      # an extra never hides the headline; its failure is reported
+            traceback.print_exc()
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"extra {name} done in {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    def cube1e6():
+        wl = inputs.WORKLOADS["cube1e6"]
+        seed = inputs.workload_seed("cube1e6")
+        p = inputs.particles(wl["M"], "uniform", seed=seed)
+        b = Bench(args, "coulomb", wl["leaf"], None, _dev_set(p, dev), seed)
+        r = {"M": wl["M"], "N": wl["M"]}
+        for mode in ("plain", "fp32", "tuned"):
+            r[mode] = b.form(mode, wl["theta"], wl["degree"], wl.get("tau") if mode == "tuned" else None, steps, warmup)
+        r["fp32_over_plain"] = r["fp32"]["particles_per_s"] / r["plain"]["particles_per_s"]
+        r["tuned_over_plain"] = r["tuned"]["particles_per_s"] / r["plain"]["particles_per_s"]
+        return r
+
+    def unequal():
+        name = "sphere2e6_gauss1e7"
+        wl = inputs.WORKLOADS[name]
+        seed = inputs.workload_seed(name)
+        t, s = inputs.unequal_sets(wl["M"], wl["tdist"], wl["N"], wl["sdist"], seed=seed)
+        b = Bench(args, wl["kernel"], wl["leaf"], _dev_set(t, dev, False), _dev_set(s, dev), seed)
+        r = {"M": wl["M"], "N": wl["N"], "kernel": wl["kernel"]}
+        for mode in ("fp32", "plain"):
+            r[mode] = b.form(mode, wl["theta"], wl["degree"], None, steps, warmup)
+        r["fp32_over_plain"] = r["fp32"]["particles_per_s"] / r["plain"]["particles_per_s"]
+        return r
+
+    def batch():
+        name = "batch256"
+        return batch_bench(args, inputs.WORKLOADS[name], name, steps, warmup, with_cpu=False)
+
+    def cube1e8():
+        name = "cube1e8"
+        wl = inputs.WORKLOADS[name]
+        seed = inputs.workload_seed(name)
+        p = inputs.particles(wl["M"], "uniform", seed=seed)
+        src = _dev_set(p, dev)
+        del p
+        b = Bench(args, "coulomb", wl["leaf"], None, src, seed, fraction=1e-4, minimum=1000)
+        r = {"M": wl["M"], "N": wl["M"]}
+        r["tuned"] = b.form("tuned", wl["theta"], wl["tuned_fallback"], wl["tau"], 1, 1)
+        r["tuned_fast"] = b.form("tuned", wl["tuned_theta"], wl["tuned_fallback"], wl["tau"], 1, 1)
+        r["plain"] = b.form("plain", wl["theta"], wl["degree"], None, 1, 1)
+        r["tuned_over_plain"] = r["tuned_fast"]["particles_per_s"] / r["plain"]["particles_per_s"]
+        return r
+
+    guarded("cube1e6", cube1e6)
+    guarded("sphere2e6_gauss1e7", unequal)
+    guarded("batch256", batch)
+    if not args.no_1e8:
+        guarded("cube1e8", cube1e8)
+    return out
 
 
 def main() -> int:
@@ -330,8 +457,12 @@ def main() -> int:
     ap.add_argument("--tuned-fallback", type=int, default=None)
     ap.add_argument("--leaf", type=int, default=None)
     ap.add_argument("--model", default=None)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-stride", type=int, default=32,
+                    help="CPU baseline: interaction sums timed on every k-th leaf and cluster, scaled by k")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-1e8", action="store_true", help="skip the 1E8 workload among the extras")
+    ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--sweep", choices=("plain", "tuned"), default=None)
     ap.add_argument("--sweep-thetas", default="0.5,0.6,0.7,0.8,0.9")
     ap.add_argument("--sweep-degrees", default="4,5,6,7,8,9,10")
@@ -359,15 +490,14 @@ def main() -> int:
     from paper_2012_06925_amd import inputs
     from paper_2012_06925_amd.train_degree_model import DEFAULT_MODEL
 
+    args.model = args.model or DEFAULT_MODEL
     wl = dict(inputs.WORKLOADS[args.workload])
+    dev = torch.device("cuda:0")
     if "count" in wl:
-        args.theta = args.theta if args.theta is not None else wl["theta"]
-        args.degree = args.degree if args.degree is not None else wl["degree"]
-        args.leaf = args.leaf if args.leaf is not None else wl["leaf"]
-        print(json.dumps(batch_bench(args, wl, args.workload)), flush=True)
+        print(json.dumps(batch_bench(args, wl, args.workload, args.steps, args.warmup, not args.no_cpu)), flush=True)
         return 0
     if "dist" not in wl:
-        raise SystemExit("bench.py times targets = sources workloads")
+        raise SystemExit("the headline workloads are targets = sources; unequal sets run among the extras")
     M = args.n or wl["M"]
     args.theta = args.theta if args.theta is not None else wl["theta"]
     args.degree = args.degree if args.degree is not None else wl["degree"]
@@ -375,9 +505,7 @@ def main() -> int:
     args.tuned_theta = args.tuned_theta if args.tuned_theta is not None else wl.get("tuned_theta", args.theta)
     args.tau = args.tau if args.tau is not None else wl.get("tau", 3e-7)
     args.tuned_fallback = args.tuned_fallback if args.tuned_fallback is not None else wl.get("tuned_fallback", 8)
-    args.model = args.model or DEFAULT_MODEL
     seed = inputs.workload_seed(args.workload)
-    dev = torch.device("cuda:0")
 
     if args.copy_calib_mib:
         a = torch.empty(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev).fill_(1.0)
@@ -385,13 +513,13 @@ def main() -> int:
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {args.copy_calib_mib} MiB done", file=sys.stderr, flush=True)
+        log(f"calibration copy of {args.copy_calib_mib} MiB done")
         del a, b
-    print(f"[bench] generating {M} {wl['dist']} particles", file=sys.stderr, flush=True)
+    log(f"generating {M} {wl['dist']} particles")
     p = inputs.particles(M, wl["dist"], seed=seed)
-    src = [torch.from_numpy(a).to(dev) for a in (p.x, p.y, p.z, p.q)]
+    src = _dev_set(p, dev)
     torch.cuda.synchronize()
-    bench = Bench(args, wl, M, seed, src, dev)
+    bench = Bench(args, wl["kernel"], args.leaf, None, src, seed)
 
     if args.sweep:
         print(json.dumps(bench.sweep(args.sweep)), flush=True)
@@ -412,17 +540,24 @@ def main() -> int:
         ref = core.direct_sum(p, p, kernel=wl["kernel"], sel=bench.sel[:8])
         ds_check = float(np.max(np.abs(bench.ds[:8] - ref) / np.abs(ref)))
 
-    ok = [f for f in forms.values() if f["error_vs_direct"] <= TARGET_ERR]
-    head = forms.get("tuned") if forms.get("tuned") in ok else (ok[0] if ok else next(iter(forms.values())))
+    head = forms.get("plain") or next(iter(forms.values()))
     cpu = None
     if not args.no_cpu:
-        print(f"[bench] CPU oracle baseline on {args.cpu_sample} particles", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, args.theta, args.degree, args.leaf, args.cpu_sample)
+        log(f"CPU oracle baseline on the same {M} particles (interaction sums sampled 1/{args.cpu_stride})")
+        cpu = cpu_baseline(p, wl["kernel"], args.theta, args.degree, args.leaf, args.cpu_stride)
+        log(f"CPU oracle: {cpu['value']:.3e} particles/s on {cpu['cores']} threads")
+    del p
+    ext = None
+    if not args.no_extras:
+        del bench
+        torch.cuda.empty_cache()
+        ext = extras(args)
 
+    dtype = {"plain": "f64", "fp32": "f32-eval/f64-acc", "tuned": "f32-eval/f64-acc"}[head["mode"]]
     res = {
         "metric": METRIC, "value": head["particles_per_s"], "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32-eval/f64-acc" if head["mode"] != "plain" else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": args.workload, "M": M, "N": M, "distribution": wl["dist"], "kernel": wl["kernel"],
                    "leaf": args.leaf, "mode": head["mode"], "theta": head["theta"], "degree": head["degree"],
                    "tau": head.get("tau")},
@@ -431,6 +566,7 @@ def main() -> int:
         "forms": forms,
         "tuned_over_plain": (forms["tuned"]["particles_per_s"] / forms["plain"]["particles_per_s"]
                              if "tuned" in forms and "plain" in forms else None),
+        "extras": ext,
     }
     print(json.dumps(res), flush=True)
     return 0

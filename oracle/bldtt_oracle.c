@@ -739,6 +739,37 @@ void or_run_interact(or_run *r)
     r->t_interact = omp_get_wtime() - t0;
 }
 
+/* The interaction step restricted to the leaves and the clusters whose index
+ * is offset modulo stride: the same per-entry work as or_run_interact on a
+ * bounded sample of a large run, for timing it (the potentials it leaves are
+ * partial).  Returns the wall time in seconds. */
+double or_run_interact_sample(or_run *r, int64_t stride, int64_t offset)
+{
+    double t0 = omp_get_wtime();
+    const or_tree *T = r->T;
+    int64_t P = np3(r->n);
+    or_lists *l = r->lists;
+    free(r->phi_tree); free(r->phihat_own);
+    r->phi_tree = calloc((size_t)r->M, sizeof(double));
+    r->phihat_own = calloc((size_t)(T->n * P), sizeof(double));
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t leafc = offset; leafc < T->n; leafc += stride) {
+        if (T->nchild[leafc]) continue;
+        int64_t pb = T->begin[leafc], pe = pb + T->count[leafc];
+        for (int64_t c = leafc; c >= 0; c = T->parent[c])
+            for (int ty = OR_PP; ty <= OR_PC; ++ty)
+                for (int64_t e = r->head[ty][c]; e >= 0; e = r->nxt[ty][e])
+                    particle_entry(r, ty, pb, pe, l->sc[ty][e], r->phi_tree + pb);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = offset; c < T->n; c += stride)
+        for (int ty = OR_CP; ty <= OR_CC; ++ty)
+            for (int64_t e = r->head[ty][c]; e >= 0; e = r->nxt[ty][e])
+                proxy_entry(r, ty, c, l->sc[ty][e], r->phihat_own + c * P);
+    return omp_get_wtime() - t0;
+}
+
 /* phi(x) += sum_k L_k(x) vals[k] over cluster c's grid. */
 static double interp_to_point(const or_run *r, const or_tree *t, int64_t c, const double x[3], const double *vals)
 {

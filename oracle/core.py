@@ -54,6 +54,8 @@ def lib():
                   "or_run_qhat", "or_run_phihat", "or_run_phihat_own", "or_run_times"):
             getattr(L, f).argtypes = [v, _D]
         L.or_run_eval_targets.argtypes = [v, C.c_int64, _I64, _D]
+        L.or_run_interact_sample.restype = C.c_double
+        L.or_run_interact_sample.argtypes = [v, C.c_int64, C.c_int64]
         L.or_run_eval_degrees.argtypes = [v, _I64, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), _D]
         L.or_num_threads.restype = C.c_int
         _lib = L
@@ -170,6 +172,11 @@ class Run:
 
     def downward(self):
         lib().or_run_downward(self.ptr)
+
+    def interact_sample(self, stride: int, offset: int = 0) -> float:
+        """Time (s) of the interaction step on the leaves and clusters whose index
+        is `offset` modulo `stride` (needs traverse + upward; potentials partial)."""
+        return float(lib().or_run_interact_sample(self.ptr, int(stride), int(offset)))
 
     def run_all(self):
         lib().or_run_all(self.ptr)

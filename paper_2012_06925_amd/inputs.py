@@ -93,7 +93,8 @@ WORKLOADS = {
     # targets = sources, uniform cube, Coulomb, theta 0.7, n 6, leaf 500
     "cube1e4": dict(id=1, M=10_000, dist="uniform", kernel="coulomb", theta=0.7, degree=6, leaf=500),
     # targets = sources, uniform cube, Coulomb, theta 0.8, n 8, leaf 2000
-    "cube1e6": dict(id=2, M=1_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=8, leaf=2000),
+    # (tau: the learned-degree form at the workload's theta, fallback n 8)
+    "cube1e6": dict(id=2, M=1_000_000, dist="uniform", kernel="coulomb", theta=0.8, degree=8, leaf=2000, tau=3e-7),
     # unequal: Gaussian sources, sphere-surface targets, Yukawa kappa 0.5
     "sphere2e6_gauss1e7": dict(id=3, M=2_000_000, N=10_000_000, tdist="sphere", sdist="gaussian",
                                kernel="yukawa", theta=0.7, degree=8, leaf=2000),
