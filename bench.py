@@ -370,6 +370,41 @@ def _dev_set(p, dev, charges=True):
     return tuple(torch.from_numpy(a).to(dev) for a in arrays)
 
 
+def ablation(args) -> dict:
+    """Sec. 4.3's ablation: the BLDTT with all four interaction types against
+    the variant that keeps only CC and PP (PC/CP pairs become PP), plain
+    FP64, on a uniform and a Gaussian set: per-type list entries, kernel
+    evaluations (the pointwise-interaction counts), compute time and error."""
+    from paper_2012_06925_amd import _lib, inputs
+    dev = __import__("torch").device("cuda:0")
+    n = args.n or 1_000_000
+    theta = args.theta if args.theta is not None else 0.7
+    degree = args.degree if args.degree is not None else 8
+    leaf = args.leaf if args.leaf is not None else 2000
+    out = {"M": n, "theta": theta, "degree": degree, "leaf": leaf}
+    for dist in ("uniform", "gaussian"):
+        seed = inputs.BASE_SEED + 400 + (dist == "gaussian")
+        p = inputs.particles(n, dist, seed=seed)
+        b = Bench(args, "coulomb", leaf, None, _dev_set(p, dev), seed)
+        rows = {}
+        for name, extra in (("all_four", 0), ("pp_cc_only", _lib.PP_CC_ONLY)):
+            from paper_2012_06925_amd import api
+            flags = _lib.PROFILE | extra
+            pl = api.Plan(None, b.src, kernel="coulomb", theta=theta, degree=degree, leaf=leaf, flags=flags)
+            ms, _, phase, st = b.time_plan(pl, args.steps, args.warmup)
+            err = b.error()
+            pl.close()
+            rows[name] = {"ms_per_step": round(ms, 3), "particles_per_s": n / (ms * 1e-3), "error_vs_direct": err,
+                          "n_entries": st["n_entries"], "interactions": st["interactions"],
+                          "total_interactions": sum(st["interactions"].values()),
+                          "phase_ms": {k: round(v, 3) for k, v in phase.items()}}
+            log(f"ablation {dist} {name}: {ms:.2f} ms err {err:.2e} interactions {rows[name]['interactions']}")
+        rows["speedup_all_four"] = rows["pp_cc_only"]["ms_per_step"] / rows["all_four"]["ms_per_step"]
+        rows["interaction_ratio"] = rows["pp_cc_only"]["total_interactions"] / rows["all_four"]["total_interactions"]
+        out[dist] = rows
+    return {"ablation": out}
+
+
 def extras(args) -> dict:
     """The build's other workloads, a few steps each: the 1E6 cube in its three
     forms, the unequal Yukawa sets, the 256-problem batch and 1E8 with the
@@ -464,6 +499,8 @@ def main() -> int:
     ap.add_argument("--no-1e8", action="store_true", help="skip the 1E8 workload among the extras")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--sweep", choices=("plain", "tuned"), default=None)
+    ap.add_argument("--ablation", action="store_true",
+                    help="all four interaction types vs PP + CC only (plain FP64, uniform and Gaussian)")
     ap.add_argument("--sweep-thetas", default="0.5,0.6,0.7,0.8,0.9")
     ap.add_argument("--sweep-degrees", default="4,5,6,7,8,9,10")
     ap.add_argument("--sweep-taus", default="3e-8,1e-7,3e-7,1e-6,3e-6")
@@ -491,6 +528,9 @@ def main() -> int:
     from paper_2012_06925_amd.train_degree_model import DEFAULT_MODEL
 
     args.model = args.model or DEFAULT_MODEL
+    if args.ablation:
+        print(json.dumps(ablation(args)), flush=True)
+        return 0
     wl = dict(inputs.WORKLOADS[args.workload])
     dev = torch.device("cuda:0")
     if "count" in wl:

@@ -148,6 +148,20 @@ int bldtt_destroy(bldtt_plan *plan);
 /* Message of the last failure on the calling thread; never NULL. */
 const char *bldtt_last_error(void);
 
+/* Source of the device memory of plans and batches (process-wide).
+ *   alloc(bytes, ctx) returns device memory of the current device, at least
+ *   256-byte aligned, or NULL on failure; release(ptr, ctx) gives it back.
+ *   Both NULL: hipMalloc / hipFree (the default).
+ * Applies to every device allocation made after the call; a buffer is always
+ * released by the callbacks it was allocated with, after a device
+ * synchronization (as hipFree implies), so the callbacks and ctx must stay
+ * valid until the plans and batches using them are destroyed.  Pinned host
+ * staging memory is not affected.  A NULL from alloc makes the calling entry
+ * point fail with BLDTT_ENOMEM, every buffer it allocated released; memory not
+ * aligned to 256 bytes makes it fail with BLDTT_EINVAL.
+ * Errors: EINVAL when exactly one callback is NULL. */
+int bldtt_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*release)(void *ptr, void *ctx), void *ctx);
+
 /* ---- Introspection for parity tests ------------------------------------- */
 
 /* Host view of a tree, numbered in depth-first preorder with children in

@@ -423,6 +423,7 @@ int64_t or_lists_count(const or_lists *l, int type) { return l->n[type]; }
 
 void or_lists_export(const or_lists *l, int type, int64_t *tc, int64_t *sc)
 {
+    if (l->n[type] == 0) return;              /* an empty list has no arrays */
     memcpy(tc, l->tc[type], sizeof(int64_t) * l->n[type]);
     memcpy(sc, l->sc[type], sizeof(int64_t) * l->n[type]);
 }

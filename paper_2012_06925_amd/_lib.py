@@ -82,6 +82,7 @@ SIGNATURES = {
                                    C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     "bldtt_version": (C.c_char_p, []),
+    "bldtt_set_allocator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "bldtt_mlp_model_size": (C.c_int, []),
     "bldtt_set_degree_model": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_double]),
     "bldtt_set_degree_test_rule": (C.c_int, [C.c_void_p]),
@@ -112,6 +113,10 @@ SIGNATURES = {
 }
 
 _lib = None
+
+# Callback types of bldtt_set_allocator.
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class BldttError(RuntimeError):

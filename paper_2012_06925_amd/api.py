@@ -433,5 +433,41 @@ def mlp_train(features: np.ndarray, targets: np.ndarray, epochs: int = 200, batc
     return model, hist
 
 
+_allocator_refs = None       # the registered ctypes callbacks, kept alive
+
+
+def set_allocator(alloc, release) -> None:
+    """Device memory of plans and batches from alloc(nbytes) -> int pointer (0 on
+    failure) and release(pointer); both None restores hipMalloc / hipFree."""
+    global _allocator_refs
+    if alloc is None and release is None:
+        check(lib().bldtt_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+
+    def _alloc(n, _ctx):
+        try:
+            return int(alloc(int(n))) or None
+        except Exception:            # a failed allocation is reported as NULL (BLDTT_ENOMEM)
+            return None
+
+    def _release(ptr, _ctx):
+        release(int(ptr))
+
+    refs = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+    check(lib().bldtt_set_allocator(C.cast(refs[0], C.c_void_p), C.cast(refs[1], C.c_void_p), None))
+    _allocator_refs = refs
+
+
+def use_torch_allocator() -> None:
+    """Take the library's device memory from torch's caching allocator (the
+    current device and stream of each call); the binding does this on import."""
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                  lambda ptr: torch.cuda.caching_allocator_delete(ptr))
+
+
 def version() -> str:
     return lib().bldtt_version().decode()
+
+
+use_torch_allocator()

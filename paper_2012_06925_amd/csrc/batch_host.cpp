@@ -238,6 +238,7 @@ void traverse_forest(bldtt_batch* b) {
 void pack(bldtt_batch* b, int tpt) {
     if (b->packed_tpt_valid && b->packed_tpt == tpt) return;
     Work& w = b->work;
+    w.guard_near = (b->flags & BLDTT_FP32_EVAL) != 0;   // FP32 batches guard near particle ranges too
     if (b->symmetric()) {
         split_symmetric(b->T(), b->lists, b->degree, true, true, b->rest, b->sym);
         const std::vector<uint32_t> extra = sym_cc_degrees(b->T(), b->sym);

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,21 @@
 #include "tune.hpp"
 
 namespace bldtt {
+
+namespace {
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;
+}  // namespace
+
+DevAllocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+void set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = DevAllocator{alloc, release, ctx};
+}
 
 void upload_bytes(DevBuf& b, const void* src, size_t n) {
     b.alloc(n);
@@ -284,6 +300,8 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     const int tile = kBlockThreads * (mfma_pp ? 1 : pl->tpt), ptile = kBlockThreads * pl->tpt_proxy;
     // PP + PC into particle targets (phi_tree): set, or add to what earlier passes wrote
     double* nfp64 = pl->nfp64_ptr();
+    // the FP32 matrix-core symmetric pass runs guarded ranges as items of their own
+    const bool sep_guard = fp32 && pl->mfma_transfer();
     auto particle_pass = [&](const DevBuf& items, int n, const DevBuf& entries, bool add, hipStream_t s) {
         if (mfma_pp)
             launch_pp_mfma(items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab,
@@ -380,7 +398,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                 PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
                 sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, pl->side);
                 mark_host(2);
-            });
+            }, sep_guard);
             drop_self_pairs(near_rest);
         }
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
@@ -413,10 +431,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     }
     Lists& rest = pl->rest_lists;       // the lists without their symmetric pairs
     if (symm && !varied) {
-        split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym);
+        split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym, {}, sep_guard);
         drop_self_pairs(rest);
     }
-    if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep);
+    if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep, {}, sep_guard);
     const SymWork& scc = varied ? pl->sym_sep : pl->sym;          // symmetric CC pairs
     std::vector<uint32_t> scc_deg;
     if (symm) scc_deg = sym_cc_degrees(T, scc);
@@ -613,6 +631,9 @@ bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_par
     pl->N = p->N;
     pl->aliased = p->M == p->N && p->tx == p->sx && p->ty == p->sy && p->tz == p->sz;
     pl->policy.fallback = degree;
+    // FP32 forms guard near particle ranges too (FP32 cannot resolve their closest pairs)
+    const bool near = (flags & BLDTT_FP32_EVAL) != 0;
+    pl->work.guard_near = pl->work_near.guard_near = pl->sym.guard_near = pl->sym_sep.guard_near = near;
     TuneChoice tc;
     if (tune_lookup(plan_tune_key(pl.get()), tc) && valid_tpt(tc.tpt) && valid_tpt(tc.tpt_proxy)) {
         pl->tpt = tc.tpt;
@@ -742,6 +763,15 @@ int bldtt_destroy(bldtt_plan* plan) {
 }
 
 const char* bldtt_last_error(void) { return g_last_error.c_str(); }
+
+int bldtt_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) {
+        set_error("bldtt_set_allocator: give both callbacks, or neither");
+        return BLDTT_EINVAL;
+    }
+    set_allocator(alloc, release, ctx);
+    return BLDTT_OK;
+}
 
 int bldtt_get_tree(const bldtt_plan* plan, int which, bldtt_tree_view* out) {
     if (!plan || !out || (which != 0 && which != 1)) {

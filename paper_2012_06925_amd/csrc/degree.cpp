@@ -275,7 +275,8 @@ int bldtt_set_degree_model(bldtt_plan* plan, const float* model, size_t n_floats
         }
         p.model.assign(model, model + n_floats);
         if (!plan->host_only) {
-            if (!p.dev_model) HIPCHK(hipMalloc(&p.dev_model, sizeof(float) * kNModel));
+            plan->model_buf.reserve(sizeof(float) * kNModel);
+            p.dev_model = plan->model_buf.p;
             HIPCHK(hipMemcpy(p.dev_model, p.model.data(), sizeof(float) * kNModel, hipMemcpyHostToDevice));
         }
         p.mode = 1;

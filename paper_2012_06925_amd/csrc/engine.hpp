@@ -122,8 +122,10 @@ struct Work {
     uint32_t src_degrees = 0, tgt_degrees = 0;  // bit d set: proxy charges / potentials of degree d used
     int down_degree = 0;                        // degree of the downward pass
     double interactions[4] = {0, 0, 0, 0};
-    void clear();                               // empty, keeping the capacity (repacking a plan
-                                                // then touches no fresh pages)
+    bool guard_near = false;                    // setting: guard near ranges too (FP32 forms, see
+                                                // range_guarded), not only touching ones
+    void clear();                               // empty, keeping the capacity and the setting
+                                                // (repacking a plan then touches no fresh pages)
 };
 
 // tile: targets per particle item; ptile: proxies per proxy item.  Degrees come
@@ -144,15 +146,18 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
 // packed into items over A's points in tiles of 256 (cluster = A): PP items
 // over A's particles with the merged particle ranges of A's partners, CC items
 // per (A, degree) over A's proxies with proxy entries of the partners; longest
-// first.  A tile's partner ranges flagged SRC_RANGE_GUARD (the two leaf boxes
-// are near, see range_guarded) form an item of their own: the first pp_plain PP
-// items hold no guarded range, the rest only guarded ranges.  The evaluation
-// counts are the kernel terms the items produce (both directions).
+// first.  With separate_guarded, a tile's partner ranges flagged
+// SRC_RANGE_GUARD (the two leaf boxes are near, see range_guarded) form an
+// item of their own: the first pp_plain PP items hold no guarded range, the
+// rest only guarded ranges (without it pp_plain counts every item, and an
+// item's guarded ranges follow its plain ones).  The evaluation counts are the
+// kernel terms the items produce (both directions).
 struct SymWork {
     std::vector<Entry> pp_entries, cc_entries;
     std::vector<Item> pp_items, cc_items;
     int64_t pp_plain = 0;
     double pp_evaluations = 0.0, cc_evaluations = 0.0;
+    bool guard_near = false;                    // setting, as Work::guard_near
     void clear() {
         pp_entries.clear();
         cc_entries.clear();
@@ -165,7 +170,7 @@ struct SymWork {
 // pp_ready, when given, is called as soon as the PP items are complete (before
 // `rest` and the CC items are formed), so their pass can start early.
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
-                     const std::function<void()>& pp_ready = {});
+                     const std::function<void()>& pp_ready = {}, bool separate_guarded = false);
 
 // Per-cluster degree masks of the symmetric CC pairs (both clusters of each pair).
 std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw);

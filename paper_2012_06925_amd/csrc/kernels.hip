@@ -177,27 +177,30 @@ __device__ __forceinline__ void mfma_tiles(int nt, MfmaLds& L, double (*__restri
 #pragma unroll
         for (int b = 0; b < 4; ++b) d[b] = mfma_f64(A[b], bv, C);
         double psi = 0.0;
-        uint32_t low = 0;                    // slots below the threshold
+        float rmin = 3.0e38f;                // smallest squared distance of the lane's slots
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float rf = (float)d[b][r];
-                double y = (double)__builtin_amdgcn_rsqf(rf);
+                float yf = __builtin_amdgcn_rsqf(rf);
                 if constexpr (GUARD) {
-                    const bool f = rf <= thr;
-                    low |= (uint32_t)f << (4 * b + r);
-                    y = f ? 0.0 : y;
+                    yf = rf > thr ? yf : 0.0f;
+                    rmin = fminf(rmin, rf);
                 }
+                const double y = (double)yf;
                 acc[b][r] = fma(qj, y, acc[b][r]);
                 if constexpr (!ONE_SIDED) psi = fma(qi[b][r], y, psi);
             }
         }
         if constexpr (GUARD) {
-            while (low) {                    // rare: close pairs and coincident points
-                const int k = __builtin_ctz(low);
-                low &= low - 1;
-                fix(k, t);
+            if (rmin <= thr) {               // rare: close pairs and coincident points
+                for (int b = 0; b < 4; ++b) {
+                    const v4d e = mfma_f64(A[b], bv, C);   // the block's squared distances again
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if ((float)e[r] <= thr) fix(4 * b + r, t);
+                }
             }
         }
         if constexpr (!ONE_SIDED) atomicAdd(&part[t][lane & 15], psi);

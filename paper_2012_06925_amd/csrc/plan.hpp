@@ -27,25 +27,60 @@ inline double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Device allocation owned by a plan, or (alias) a view into another one.
+// Where plans and batches take their device memory (bldtt_set_allocator):
+// the caller's allocate / release pair, or hipMalloc / hipFree when both are
+// null.  current_allocator() returns the registration in force (capi.cpp).
+struct DevAllocator {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+DevAllocator current_allocator();
+void set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx);
+
+// Device allocation owned by a plan, or (alias) a view into another one.  A
+// buffer is released by the allocator it came from.  Before a caller's
+// release the device is synchronized (as hipFree does), so memory a pending
+// kernel may still read is never handed back early.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     bool owned = true;
+    DevAllocator from;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p && owned) (void)hipFree(p);
+        if (p && owned) {
+            if (from.release) {
+                (void)hipDeviceSynchronize();
+                from.release(p, from.ctx);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
         owned = true;
+        from = DevAllocator{};
     }
     void alloc(size_t b) {
         release();
         if (b == 0) b = 8;
-        HIPCHK(hipMalloc(&p, b));
+        const DevAllocator a = current_allocator();
+        if (a.alloc) {
+            void* q = a.alloc(b, a.ctx);
+            if (!q) throw Error(BLDTT_ENOMEM, "the registered allocator returned NULL for " + std::to_string(b) + " bytes");
+            if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+                a.release(q, a.ctx);
+                throw Error(BLDTT_EINVAL, "the registered allocator returned memory not aligned to 256 bytes");
+            }
+            p = q;
+            from = a;
+        } else {
+            HIPCHK(hipMalloc(&p, b));
+        }
         bytes = b;
     }
     void reserve(size_t b) {
@@ -191,6 +226,7 @@ struct bldtt_plan {
     bool self_ready = false;
     double self_evaluations = 0.0;
     DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
+    DevBuf model_buf;                        // device copy of the degree model (policy.dev_model)
     // FP32 evaluation: pairs of distinct points the last compute evaluated in
     // FP64 because FP32 coordinates do not resolve them (one device double)
     DevBuf nfp64;
@@ -212,7 +248,6 @@ struct bldtt_plan {
         return DevParticles{tx.as<double>(), ty.as<double>(), tz.as<double>(), nullptr};
     }
     ~bldtt_plan() {
-        if (policy.dev_model) (void)hipFree(policy.dev_model);
         if (staging_free) (void)hipEventDestroy(staging_free);
         for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free, ev_select})
             if (e) (void)hipEventDestroy(e);

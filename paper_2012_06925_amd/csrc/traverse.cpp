@@ -201,13 +201,19 @@ ByTarget group(const Tree& T, const Lists& L, int t0, int t1, int degree) {
     return g;
 }
 
-// Whether the particle range of source cluster s, as seen from target leaf t,
-// is evaluated as a guarded range: the boxes touch (the two sets may share a
-// point), or their gap g is small against the distance R from t's box centre
+// Guarded particle ranges.  FP64 needs the guard only where the boxes touch
+// (the two sets may share a point: r^2 == 0).  The FP32 forms also guard near
+// ranges (range_guarded): the boxes touch, or their gap g is small against the distance R from t's box centre
 // to the farthest corner of either box, g^2 <= 2^-23 R^2.  Pairs of unguarded
 // ranges then lie farther apart than 2^-11.5 R, so in coordinates relative to
 // that centre r^2 > 2^-24 (|x|^2 + |y|^2): the FP64 expansion |x|^2 - 2 x.y +
 // |y|^2 of the FP32 matrix-core passes keeps a relative error below 2^-25 there.
+bool boxes_touch(const Tree& T, int64_t t, const Tree& S, int64_t s) {
+    for (int d = 0; d < 3; ++d)
+        if (T.hi[3 * t + d] < S.lo[3 * s + d] || S.hi[3 * s + d] < T.lo[3 * t + d]) return false;
+    return true;
+}
+
 bool range_guarded(const Tree& T, int64_t t, const Tree& S, int64_t s) {
     double g2 = 0.0, R2 = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -383,7 +389,8 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
                         B.entries.push_back(proxy_entry(sc, part.deg[e]));
                         src += (double)cube(part.deg[e]);
                     } else {
-                        (range_guarded(T, leaf, S, sc) ? rg : rp).emplace_back(S.begin[sc], S.count[sc]);
+                        ((w.guard_near ? range_guarded(T, leaf, S, sc) : boxes_touch(T, leaf, S, sc)) ? rg : rp)
+                            .emplace_back(S.begin[sc], S.count[sc]);
                         src += (double)S.count[sc];
                     }
                 }
@@ -534,7 +541,7 @@ std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw) {
 }
 
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
-                     const std::function<void()>& pp_ready) {
+                     const std::function<void()>& pp_ready, bool separate_guarded) {
     sw.clear();
     const int64_t nc = T.size();
     constexpr int64_t kBlk = 256, kTile = 256;
@@ -566,7 +573,8 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
                 for (int64_t k = ipp.off[a]; k < ipp.off[a + 1]; ++k) {
                     const int64_t b = ipp.part[k].first;
                     if (b > a && ipp.has(b, a, 0)) {
-                        (range_guarded(T, a, T, b) ? rg : rp).emplace_back(T.begin[b], T.count[b]);
+                        ((sw.guard_near ? range_guarded(T, a, T, b) : boxes_touch(T, a, T, b)) ? rg : rp)
+                            .emplace_back(T.begin[b], T.count[b]);
                         src += (double)T.count[b];
                     }
                 }
@@ -579,10 +587,15 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
                 emit_ranges(none, rg, B.entries);
                 const int64_t ee = (int64_t)B.entries.size();
                 B.evals += 2.0 * (double)T.count[a] * src;
-                // tiles of A's particles: one item over the plain ranges, one
-                // over the guarded ranges
+                // tiles of A's particles: one item over every range, or one
+                // over the plain ranges and one over the guarded ranges
                 for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {
                     const int64_t tn = std::min<int64_t>(kTile, T.begin[a] + T.count[a] - tb);
+                    if (!separate_guarded) {
+                        B.items.push_back({src * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
+                                                                  (int32_t)a, 0, (int32_t)tb}});
+                        continue;
+                    }
                     if (em > eb)
                         B.items.push_back({(src - src_g) * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb,
                                                                          (int32_t)em, (int32_t)a, 0, (int32_t)tb}});

@@ -149,6 +149,11 @@ def test_argument_errors():
     assert L.bldtt_destroy(None) == _lib.OK
     assert L.bldtt_compute(None, None, None) == _lib.EINVAL
     assert b"NULL" in L.bldtt_last_error()
+    # the allocator hook takes both callbacks or neither
+    cb = _lib.ALLOC_FN(lambda n, ctx: None)
+    assert L.bldtt_set_allocator(C.cast(cb, C.c_void_p), None, None) == _lib.EINVAL
+    assert b"both" in L.bldtt_last_error()
+    api.use_torch_allocator()                       # the binding's registration, restored
 
 
 def test_host_plan_refuses_compute_and_lists_before_traversal():
