@@ -12,7 +12,10 @@
  *   - Chebyshev points of the 2nd kind and their barycentric weights (Sec. 2.1);
  *   - the 1D barycentric Lagrange basis, 2nd form (Eq. 2), tensor product in 3D;
  *   - target and source trees (Sec. 2.3);
- *   - the dual tree traversal, Algorithm 2, producing PP/PC/CP/CC lists (Sec. 2.6, Sec. 3.1);
+ *   - the dual tree traversal, Algorithm 2, producing PP/PC/CP/CC lists (Sec. 2.6, Sec. 3.1),
+ *     its PP+CC-only ablation (Sec. 4.3), and the lists of the two treecodes the
+ *     paper compares with: BLTC, PC and PP per target batch (Sec. 2.8), and
+ *     CP-BLTC, CP and PP per source batch (Sec. 4.5);
  *   - upward pass: leaf proxy charges (Eq. proxy-charges, Sec. 2.4) and the
  *     child-to-parent relation (Sec. 2.5, Appendix B);
  *   - the four interaction sums (Eqs. PP-potential, PC-potential,
@@ -347,11 +350,19 @@ static void lists_push(or_lists *l, int type, int64_t tc, int64_t sc)
     l->n[type]++;
 }
 
+/* Which method builds the lists: Algorithm 2, its ablation with PP and CC
+ * only (Sec. 4.3), the particle-cluster treecode BLTC (Sec. 2.8) or the
+ * cluster-particle treecode CP-BLTC (Sec. 4.5). */
+#define OR_SCHEME_DTT 0
+#define OR_SCHEME_PP_CC 1
+#define OR_SCHEME_BLTC 2
+#define OR_SCHEME_CP_BLTC 3
+
 typedef struct {
     const or_tree *T, *S;
     double theta;
     int64_t np;
-    int pp_cc_only;          /* ablation: only PP and CC (Sec. 4.3) */
+    int scheme;
     or_lists *out;
 } dtt_ctx;
 
@@ -397,7 +408,7 @@ static void dtt(dtt_ctx *x, int64_t t, int64_t s)
     int64_t ct = T->count[t], cs = S->count[s];
     int tleaf = T->nchild[t] == 0, sleaf = S->nchild[s] == 0;
     if (well_separated(T, t, S, s, x->theta)) {
-        lists_push(x->out, separated_type(ct, cs, x->np, x->pp_cc_only), t, s);
+        lists_push(x->out, separated_type(ct, cs, x->np, x->scheme == OR_SCHEME_PP_CC), t, s);
         return;
     }
     if (tleaf && sleaf) {
@@ -411,11 +422,58 @@ static void dtt(dtt_ctx *x, int64_t t, int64_t s)
     }
 }
 
-or_lists *or_traverse(const or_tree *T, const or_tree *S, double theta, int n, int pp_cc_only)
+/* BLTC (Sec. 2.8): target batch b, a leaf of the target tree, against the
+ * source subtree at s.  A source cluster well separated from the batch
+ * interacts with it through its proxy charges (PC) when it holds more
+ * particles than it has proxies, and directly (PP) otherwise; a source leaf
+ * that is not separated interacts directly; any other cluster that is not
+ * separated passes the batch on to its children. */
+static void bltc_walk(dtt_ctx *x, int64_t b, int64_t s)
+{
+    const or_tree *T = x->T, *S = x->S;
+    if (well_separated(T, b, S, s, x->theta)) {
+        lists_push(x->out, S->count[s] > x->np ? OR_PC : OR_PP, b, s);
+        return;
+    }
+    if (S->nchild[s] == 0) {
+        lists_push(x->out, OR_PP, b, s);
+        return;
+    }
+    for (int k = 0; k < S->nchild[s]; ++k) bltc_walk(x, b, S->child[8 * s + k]);
+}
+
+/* CP-BLTC (Sec. 4.5): the roles of the two sets exchanged.  Source batch b,
+ * a leaf of the source tree, against the target subtree at t: a separated
+ * target cluster holding more particles than proxies receives the batch at
+ * its proxy points (CP), a smaller one directly (PP); a target leaf that is
+ * not separated interacts directly; other clusters pass b to their children. */
+static void cp_bltc_walk(dtt_ctx *x, int64_t t, int64_t b)
+{
+    const or_tree *T = x->T, *S = x->S;
+    if (well_separated(T, t, S, b, x->theta)) {
+        lists_push(x->out, T->count[t] > x->np ? OR_CP : OR_PP, t, b);
+        return;
+    }
+    if (T->nchild[t] == 0) {
+        lists_push(x->out, OR_PP, t, b);
+        return;
+    }
+    for (int k = 0; k < T->nchild[t]; ++k) cp_bltc_walk(x, T->child[8 * t + k], b);
+}
+
+or_lists *or_traverse(const or_tree *T, const or_tree *S, double theta, int n, int scheme)
 {
     or_lists *l = calloc(1, sizeof(or_lists));
-    dtt_ctx x = {T, S, theta, (int64_t)(n + 1) * (n + 1) * (n + 1), pp_cc_only, l};
-    dtt(&x, 0, 0);
+    dtt_ctx x = {T, S, theta, (int64_t)(n + 1) * (n + 1) * (n + 1), scheme, l};
+    if (scheme == OR_SCHEME_BLTC) {
+        for (int64_t b = 0; b < T->n; ++b)          /* every target batch, from the source root */
+            if (T->nchild[b] == 0) bltc_walk(&x, b, 0);
+    } else if (scheme == OR_SCHEME_CP_BLTC) {
+        for (int64_t b = 0; b < S->n; ++b)          /* every source batch, from the target root */
+            if (S->nchild[b] == 0) cp_bltc_walk(&x, 0, b);
+    } else {
+        dtt(&x, 0, 0);
+    }
     return l;
 }
 
@@ -444,7 +502,7 @@ typedef struct {
     double param, theta;
     int n;                        /* degree */
     int64_t leaf;
-    int pp_cc_only;
+    int scheme;                   /* OR_SCHEME_* */
     int64_t M, N;
     const double *tx, *ty, *tz;   /* caller-order inputs (borrowed) */
     const double *sx, *sy, *sz, *q;
@@ -466,11 +524,11 @@ static int64_t np3(int n) { return (int64_t)(n + 1) * (n + 1) * (n + 1); }
 or_run *or_run_create(int kind, double param,
                       int64_t M, const double *tx, const double *ty, const double *tz,
                       int64_t N, const double *sx, const double *sy, const double *sz, const double *q,
-                      double theta, int n, int64_t leaf, int pp_cc_only)
+                      double theta, int n, int64_t leaf, int scheme)
 {
     or_run *r = calloc(1, sizeof(or_run));
     r->kind = kind; r->param = param; r->theta = theta; r->n = n; r->leaf = leaf;
-    r->pp_cc_only = pp_cc_only;
+    r->scheme = scheme;
     r->M = M; r->N = N;
     r->tx = tx; r->ty = ty; r->tz = tz;
     r->sx = sx; r->sy = sy; r->sz = sz; r->q = q;
@@ -501,7 +559,7 @@ void or_run_traverse(or_run *r)
 {
     double t0 = omp_get_wtime();
     or_lists_free(r->lists);
-    r->lists = or_traverse(r->T, r->S, r->theta, r->n, r->pp_cc_only);
+    r->lists = or_traverse(r->T, r->S, r->theta, r->n, r->scheme);
     group_entries(r);
     r->t_traverse = omp_get_wtime() - t0;
 }

@@ -11,6 +11,9 @@ from . import build as _build
 KINDS = {"coulomb": 0, "yukawa": 1, "oscillatory": 2, "regcoulomb": 3, "poly": 100}
 DEFAULT_PARAM = {"coulomb": 0.0, "yukawa": 0.5, "oscillatory": 0.0, "regcoulomb": 0.005, "poly": 0.0}
 TYPES = ("PP", "PC", "CP", "CC")
+# list-building methods: Algorithm 2, its PP+CC-only ablation (Sec. 4.3), and
+# the two treecodes the paper compares with (BLTC, Sec. 2.8; CP-BLTC, Sec. 4.5)
+SCHEMES = {"bldtt": 0, "pp_cc_only": 1, "bltc": 2, "cp_bltc": 3}
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -132,7 +135,10 @@ class Run:
     """One oracle BLDTT run; keeps the inputs alive for the C side."""
 
     def __init__(self, tgt, src, kernel="coulomb", theta=0.7, degree=6, leaf=500, param=None,
-                 pp_cc_only=False, aliased=None):
+                 pp_cc_only=False, aliased=None, scheme="bldtt"):
+        if pp_cc_only:
+            scheme = "pp_cc_only"
+        self.scheme = scheme
         self.kernel = kernel
         self.param = DEFAULT_PARAM[kernel] if param is None else param
         self.n = degree
@@ -146,7 +152,7 @@ class Run:
         tx, ty, tz = self._t
         sx, sy, sz, q = self._s
         self.ptr = lib().or_run_create(KINDS[kernel], self.param, self.M, _d(tx), _d(ty), _d(tz), self.N,
-                                       _d(sx), _d(sy), _d(sz), _d(q), theta, degree, leaf, int(pp_cc_only))
+                                       _d(sx), _d(sy), _d(sz), _d(q), theta, degree, leaf, SCHEMES[scheme])
         self._lists = None
 
     def __del__(self):
@@ -259,9 +265,9 @@ class Run:
 
 
 def bldtt(tgt, src, kernel="coulomb", theta=0.7, degree=6, leaf=500, param=None, pp_cc_only=False,
-          aliased=None) -> np.ndarray:
-    """Potentials in caller order from a full oracle BLDTT run."""
-    r = Run(tgt, src, kernel, theta, degree, leaf, param, pp_cc_only, aliased)
+          aliased=None, scheme="bldtt") -> np.ndarray:
+    """Potentials in caller order from a full oracle run (BLDTT unless `scheme` names a treecode)."""
+    r = Run(tgt, src, kernel, theta, degree, leaf, param, pp_cc_only, aliased, scheme)
     return r.run_all()
 
 

@@ -22,12 +22,12 @@ void or_basis1d(int n, double lo, double hi, double y, double *L);
 or_tree *or_tree_build(int64_t N, const double *x, const double *y, const double *z, int64_t leaf);
 void or_tree_free(or_tree *t);
 int64_t or_tree_size(const or_tree *t);
-or_lists *or_traverse(const or_tree *T, const or_tree *S, double theta, int n, int pp_cc_only);
+or_lists *or_traverse(const or_tree *T, const or_tree *S, double theta, int n, int scheme);
 int64_t or_lists_count(const or_lists *l, int type);
 void or_lists_free(or_lists *l);
 or_run *or_run_create(int kind, double param, int64_t M, const double *tx, const double *ty, const double *tz,
                       int64_t N, const double *sx, const double *sy, const double *sz, const double *q,
-                      double theta, int n, int64_t leaf, int pp_cc_only);
+                      double theta, int n, int64_t leaf, int scheme);
 void or_run_free(or_run *r);
 or_lists *or_run_lists(or_run *r);
 void or_run_all(or_run *r);
@@ -64,21 +64,21 @@ static void all_finite(const double *a, int64_t n, const char *what) {
         if (!isfinite(a[i])) { fprintf(stderr, "FAILED: %s not finite\n", what); ++failures; return; }
 }
 
-static void run_case(int n, int kind, double theta, int degree, int64_t leaf, int pp_cc_only, int kernel) {
+static void run_case(int n, int kind, double theta, int degree, int64_t leaf, int scheme, int kernel) {
     double *x = malloc(sizeof(double) * 4 * n), *y = x + n, *z = y + n, *q = z + n;
     double *phi = malloc(sizeof(double) * n), *phi2 = malloc(sizeof(double) * (n < 3 ? 3 : n));
     fill(n, kind, 1000u + (unsigned)kind, x, y, z, q);
     double param = kernel == 1 ? 0.5 : (kernel == 3 ? 0.005 : 0.0);
     or_direct_sum(kernel, param, n, x, y, z, n, x, y, z, q, 0, NULL, phi);
     all_finite(phi, n, "direct sum");
-    or_run *r = or_run_create(kernel, param, n, x, y, z, n, x, y, z, q, theta, degree, leaf, pp_cc_only);
+    or_run *r = or_run_create(kernel, param, n, x, y, z, n, x, y, z, q, theta, degree, leaf, scheme);
     or_run_all(r);
     or_run_potentials(r, phi);
     all_finite(phi, n, "bldtt");
     or_run_downward_direct(r, phi2);
     all_finite(phi2, n, "downward direct");
     or_tree *t1 = or_tree_build(n, x, y, z, leaf);
-    or_lists *l1 = or_traverse(t1, t1, theta, degree, pp_cc_only);
+    or_lists *l1 = or_traverse(t1, t1, theta, degree, scheme);
     if (or_tree_size(t1) < 1 || or_lists_count(l1, 0) < 1) { fprintf(stderr, "FAILED: tree/lists\n"); ++failures; }
     or_lists_free(l1);
     or_tree_free(t1);
@@ -122,6 +122,8 @@ int main(void) {
     run_case(900, 3, 0.8, 3, 30, 0, 3);
     run_case(700, 0, 0.6, 2, 1, 0, 100);
     run_case(1, 0, 0.5, 2, 1, 0, 0);
+    run_case(1200, 1, 0.8, 2, 15, 2, 0);   /* BLTC */
+    run_case(1200, 2, 0.8, 2, 15, 3, 1);   /* CP-BLTC */
     printf("oracle check: %d failure(s)\n", failures);
     return failures ? 1 : 0;
 }

@@ -398,6 +398,153 @@ def test_ablation_potentials_equal_explicit_matrices(case):
     assert 0 < core.rel_l2(phi, full.run_all()) < 1e-2
 
 
+# The two treecodes the paper compares with.  BLTC (Sec. 2.8): every target
+# batch (a target leaf) walks the source tree; CP-BLTC (Sec. 4.5): every source
+# batch (a source leaf) walks the target tree.  The walks are pinned against
+# their characterisation, written without a walk: batch b meets cluster c of
+# the walked tree iff no proper ancestor of c is separated from b; c is then a
+# list entry iff it is separated from b or a leaf, by proxies iff separated
+# and holding more than (n+1)^3 particles.
+
+def _treecode_sets(case, seed):
+    if case == "same":
+        t = s = inputs.particles(1500, "gaussian", seed=seed)
+    else:
+        t, s = inputs.unequal_sets(900, "sphere", 1400, "uniform", seed=seed + 1)
+    return t, s
+
+
+def _sep(ta, a, tb, b, theta):
+    R = np.linalg.norm(ta["center"][a] - tb["center"][b])
+    return R > 0 and (ta["radius"][a] + tb["radius"][b]) / R < theta
+
+
+def _ancestors(tree, c):
+    out = []
+    while tree["parent"][c] >= 0:
+        c = int(tree["parent"][c])
+        out.append(c)
+    return out
+
+
+def _treecode_lists_by_characterisation(tt, ts, theta, n, scheme):
+    npx = (n + 1) ** 3
+    batches, walked = (tt, ts) if scheme == "bltc" else (ts, tt)
+    out = {k: set() for k in ("PP", "PC", "CP", "CC")}
+    anc = [_ancestors(walked, c) for c in range(len(walked["count"]))]
+    for b in np.flatnonzero(batches["nchild"] == 0):
+        for c in range(len(walked["count"])):
+            sep = (lambda x: _sep(tt, b, ts, x, theta)) if scheme == "bltc" else (lambda x: _sep(tt, x, ts, b, theta))
+            if any(sep(a) for a in anc[c]):
+                continue                                  # the walk stopped above c
+            here = sep(c)
+            if not here and walked["nchild"][c] != 0:
+                continue                                  # passed on to the children
+            kind = ("PC" if scheme == "bltc" else "CP") if here and walked["count"][c] > npx else "PP"
+            out[kind].add((int(b), c) if scheme == "bltc" else (c, int(b)))
+    return out
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+@pytest.mark.parametrize("case", ["same", "unequal"])
+@pytest.mark.parametrize("theta,n,leaf", [(0.5, 1, 20), (0.7, 1, 10), (0.9, 2, 8)])
+def test_treecode_lists_equal_their_characterisation(scheme, case, theta, n, leaf):
+    t, s = _treecode_sets(case, 61)
+    run = core.Run(t, s, theta=theta, degree=n, leaf=leaf, scheme=scheme)
+    run.traverse()
+    L = run.lists()
+    got = {k: set(zip(L[k][0].tolist(), L[k][1].tolist())) for k in L}
+    assert all(len(got[k]) == len(L[k][0]) for k in L)            # no entry twice
+    want = _treecode_lists_by_characterisation(run.tree(0), run.tree(1), theta, n, scheme)
+    assert got == want
+    approx = "PC" if scheme == "bltc" else "CP"
+    assert len(got[approx]) > 0 and len(got["PP"]) > 0
+    cover = _coverage(run, t.n, s.n)
+    assert cover.min() == 1 and cover.max() == 1
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+def test_treecode_types_and_batches(scheme):
+    t, s = inputs.unequal_sets(3000, "uniform", 2500, "gaussian", seed=63)
+    theta, n = 0.7, 1
+    run = core.Run(t, s, theta=theta, degree=n, leaf=20, scheme=scheme)
+    run.traverse()
+    L = run.lists()
+    tt, ts = run.tree(0), run.tree(1)
+    npx = (n + 1) ** 3
+    forbidden = ("CP", "CC") if scheme == "bltc" else ("PC", "CC")
+    assert all(len(L[k][0]) == 0 for k in forbidden)
+    batch, batch_tree, walked_tree = (0, tt, ts) if scheme == "bltc" else (1, ts, tt)
+    approx = "PC" if scheme == "bltc" else "CP"
+    for name in ("PP", approx):
+        for tc, sc in zip(*L[name]):
+            b, c = (tc, sc) if scheme == "bltc" else (sc, tc)
+            assert batch_tree["nchild"][b] == 0                 # the batches are leaves
+            sep = _sep(tt, tc, ts, sc, theta)
+            if name == approx:
+                assert sep and walked_tree["count"][c] > npx
+            else:
+                assert (sep and walked_tree["count"][c] <= npx) or (not sep and walked_tree["nchild"][c] == 0)
+    # every batch starts at the root of the walked tree, so each batch has entries
+    batches = set(np.flatnonzero(batch_tree["nchild"] == 0).tolist())
+    seen = {int(e[batch]) for name in ("PP", approx) for e in zip(*L[name])}
+    assert seen == batches
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+@pytest.mark.parametrize("kernel", ["coulomb", "yukawa"])
+@pytest.mark.parametrize("case", ["same", "unequal"])
+def test_treecode_potentials_equal_explicit_matrices(scheme, kernel, case):
+    # the upward pass (BLTC) or downward pass (CP-BLTC) of the oracle against the
+    # approximated kernel written as explicit matrices per list entry
+    n = 2
+    t, s = _treecode_sets(case, 65)
+    run = core.Run(t, s, kernel=kernel, theta=0.9, degree=n, leaf=8, scheme=scheme)
+    phi = run.run_all()
+    L = run.lists()
+    assert len(L["PC" if scheme == "bltc" else "CP"][0]) > 0
+    ref = brute.explicit_bldtt(t.xyz(), s.xyz(), s.q, run.tree(0), run.tree(1), L, n, kernel,
+                               core.DEFAULT_PARAM[kernel])
+    assert core.rel_l2(phi, ref) < 1e-13 and core.max_rel(phi, ref) < 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+def test_treecode_polynomial_kernel_is_reproduced_exactly(scheme):
+    t, s = inputs.unequal_sets(2500, "uniform", 3000, "gaussian", seed=16)
+    run = core.Run(t, s, kernel="poly", theta=0.7, degree=2, leaf=40, scheme=scheme)
+    phi = run.run_all()
+    assert len(run.lists()["PC" if scheme == "bltc" else "CP"][0]) > 0
+    ref = brute.direct_sum(t.xyz(), s.xyz(), s.q, "poly")
+    assert core.rel_l2(phi, ref) < 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+def test_treecode_tiny_theta_is_the_direct_sum(scheme):
+    p = inputs.particles(2000, seed=67)
+    run = core.Run(p, p, theta=1e-9, degree=2, leaf=100, scheme=scheme)
+    phi = run.run_all()
+    L = run.lists()
+    leaves = int(np.sum(run.tree(0)["nchild"] == 0))
+    assert all(len(L[k][0]) == 0 for k in ("PC", "CP", "CC")) and len(L["PP"][0]) == leaves ** 2
+    assert core.rel_l2(phi, core.direct_sum(p, p)) < 1e-14
+
+
+def test_treecodes_differ_from_the_dual_tree_at_the_approximation_level():
+    # Sec. 4.2: at one (theta, n) the three methods are approximations of the
+    # same sum, of comparable error; the error falls with n for the treecodes too
+    p = inputs.particles(20000, seed=69)
+    sel = inputs.error_sample(20000, 69, fraction=0.05)
+    ref = core.direct_sum(p, p, sel=sel)
+    errs = {}
+    for scheme in ("bldtt", "bltc", "cp_bltc"):
+        e = [core.rel_l2(core.bldtt(p, p, theta=0.7, degree=n, leaf=100, scheme=scheme)[sel], ref) for n in (2, 4, 6)]
+        assert e[0] > e[1] > e[2], (scheme, e)
+        errs[scheme] = e
+    for n_i in range(3):
+        vals = [errs[k][n_i] for k in errs]
+        assert max(vals) < 10 * min(vals), errs
+
+
 def test_lists_tiny_theta_gives_leaf_leaf_pp_only():
     p = inputs.particles(2000, seed=9)
     run = core.Run(p, p, theta=1e-9, degree=2, leaf=100)
