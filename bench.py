@@ -79,6 +79,114 @@ def counters_for(kernel_name: str, mode: str):
     return rec.get("per_launch") if rec else None
 
 
+# rocprofv3 counter passes: SQ_INSTS_VALU_FLOPS_* count wave instructions (x64
+# lanes); SQ_INSTS_VALU_MFMA_MOPS_F64 counts FP64 matrix ops in units of 512.
+PMC_PASSES = {
+    "A": "SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU_FLOPS_FP64_TRANS "
+         "SQ_INSTS_VALU_FLOPS_FP32_TRANS SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_F64 SQ_INSTS_VALU "
+         "SQ_INSTS_VALU_CVT",
+    "B": "SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_VALU_MFMA_BUSY_CYCLES SQ_VALU_MFMA_COEXEC_CYCLES SQ_WAVE_CYCLES "
+         "SQ_WAVES SQ_INSTS_LDS SQ_ACTIVE_INST_LDS",
+    "C": "FETCH_SIZE",
+    "D": "WRITE_SIZE",
+}
+# the symmetric passes of the two timed forms, by kernel; where one kernel runs
+# two passes, its dispatch groups (by grid) are told apart by duration, longest first
+PMC_PASS_NAMES = {
+    "plain": {"k_sym<false, false>": ("pp_sym", "pp_self"), "k_sym<false, true>": ("cc_sym",)},
+    "tuned": {"k_sym_mfma<false, false>": ("pp_sym",), "k_sym_mfma<false, true>": ("pp_sym", "pp_self"),
+              "k_sym_mfma<true, false>": ("cc_sym",)},
+}
+
+
+def summarize_pmc(prefix: str, mode: str) -> None:
+    """Turn the four counter passes of `bench.py --mode MODE` (rocprofv3 output
+    under PREFIX_A .. PREFIX_D, counters as PMC_PASSES) into the per-launch
+    records the roofline reads (profiles/counters_<pass>_<prec>.json and
+    profiles/traffic_<pass>_<prec>.txt), and print a table of the kernels."""
+    import collections
+    import re
+    import sqlite3
+
+    def short(n):
+        n = re.sub(r"bldtt::\(anonymous namespace\)::", "", n)
+        return re.sub(r"\(.*", "", n).replace("void ", "")
+
+    groups = collections.defaultdict(lambda: collections.defaultdict(list))
+    copy = {}
+    for tag in PMC_PASSES:
+        con = sqlite3.connect(f"{prefix}_{tag}/pmc_results.db")
+        rows = con.execute("select dispatch_id, kernel_name, grid_size, counter_name, value, duration "
+                           "from counters_collection").fetchall()
+        per = collections.defaultdict(dict)
+        meta = {}
+        for d, k, g, c, v, dur in rows:
+            per[d][c] = per[d].get(c, 0.0) + v
+            meta[d] = (short(k), g // 256, dur / 1e6)
+        for d, cs in per.items():
+            k, g, dur = meta[d]
+            groups[(k, g)]["duration_ms"].append(dur)
+            for c, v in cs.items():
+                groups[(k, g)][c].append(v)
+                if k == "__amd_rocclr_copyBuffer" and c in ("FETCH_SIZE", "WRITE_SIZE"):
+                    copy[c] = max(copy.get(c, 0.0), v)
+    avg = {key: {c: sum(v) / len(v) for c, v in r.items()} for key, r in groups.items()}
+    calib_kib = (1 << 30) / 1024.0          # the 1024 MiB copy of --copy-calib-mib 1024
+    scale = {c: calib_kib / copy[c] for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    prec = "fp64" if mode == "plain" else "fp32"
+    src_hash = kernel_source_hash()
+
+    def derived(a):
+        dur = a["duration_ms"]
+        f64 = 64.0 * a.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0)
+        f64t = 64.0 * a.get("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0)
+        f32 = 64.0 * (a.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0) + a.get("SQ_INSTS_VALU_FLOPS_FP32_TRANS", 0.0))
+        mf = 512.0 * a.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        hbm = 1024.0 * (a["FETCH_SIZE"] * scale["FETCH_SIZE"] + a["WRITE_SIZE"] * scale["WRITE_SIZE"])
+        return {"duration_ms": round(dur, 4), "valu_fp64_flops": f64, "valu_fp64_trans_flops": f64t,
+                "valu_fp32_flops": f32, "mfma_f64_flops": mf,
+                "fp64_tflops": round((f64 + f64t + mf) / dur / 1e9, 3),
+                "fp64_frac_of_peak": round((f64 + f64t + mf) / dur / 1e9 / FP64_VALU_PEAK, 4),
+                "fp32_tflops": round(f32 / dur / 1e9, 3),
+                "hbm_bytes": hbm, "hbm_gb_per_s": round(hbm / dur / 1e6, 1),
+                "raw": {c: v for c, v in sorted(a.items()) if c != "duration_ms"}}
+
+    passes = collections.defaultdict(list)
+    for kname, names in PMC_PASS_NAMES[mode].items():
+        keys = sorted((k for k in avg if k[0] == kname), key=lambda k: -avg[k]["duration_ms"])
+        for name, key in zip(names, keys):
+            passes[name].append(key)
+    cmd = (f"python3 bench.py --summarize-pmc {prefix} --mode {mode}  (after: cd /tmp && timeout -s KILL 240 "
+           f"rocprofv3 --pmc <PMC_PASSES[X]> -d {prefix}_X -o pmc -- python3 $R/bench.py --mode {mode} --steps 2 "
+           f"--warmup 1 --no-cpu --no-extras [--copy-calib-mib 1024 for C, D], X = A B C D)")
+    for name, keys in passes.items():
+        tot = collections.Counter()
+        for k in keys:
+            tot.update(avg[k])
+        rec = derived(dict(tot))
+        raw = rec.pop("raw")
+        with open(os.path.join(ROOT, "profiles", f"counters_{name}_{prec}.json"), "w") as f:
+            json.dump({"pass": name, "mode": prec, "kernels": [f"{k}, grid {g} workgroups" for k, g in keys],
+                       "kernel_source_sha256_16": src_hash, "command": cmd, "per_launch": rec,
+                       "raw_counters_per_launch": raw}, f, indent=1)
+        with open(os.path.join(ROOT, "profiles", f"traffic_{name}_{prec}.txt"), "w") as f:
+            json.dump({"pass": name, "mode": prec, "kernel_source_sha256_16": src_hash,
+                       "bytes_per_launch": rec["hbm_bytes"], "fetch_kib": tot["FETCH_SIZE"],
+                       "write_kib": tot["WRITE_SIZE"], "fetch_scale": scale["FETCH_SIZE"],
+                       "write_scale": scale["WRITE_SIZE"], "command": cmd}, f, indent=1)
+    print(f"| kernel | grid (workgroups) | dispatches | avg ms | FP64 TFLOP/s (VALU + trans + MFMA) | "
+          f"FP32 TFLOP/s | HBM GB/s |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for key in sorted(avg, key=lambda k: -avg[k]["duration_ms"] * len(groups[k]["duration_ms"]))[:10]:
+        if "FETCH_SIZE" not in avg[key] or "SQ_INSTS_VALU" not in avg[key]:
+            continue
+        d = derived(avg[key])
+        print(f"| `{key[0]}` | {key[1]} | {len(groups[key]['duration_ms']) // len(PMC_PASSES)} | "
+              f"{d['duration_ms']:.3f} | {d['fp64_tflops']:.2f} | {d['fp32_tflops']:.2f} | {d['hbm_gb_per_s']:.0f} |")
+    print(f"calibration: FETCH_SIZE x {scale['FETCH_SIZE']:.4f}, WRITE_SIZE x {scale['WRITE_SIZE']:.4f}; "
+          f"passes {dict((k, [f'{a}@{b}' for a, b in v]) for k, v in passes.items())}")
+
+
 def cpu_baseline(p, kernel, theta, degree, leaf, stride) -> dict:
     """The CPU oracle's compute phase on the benchmark's own particles: the
     traversal, upward and downward passes in full, the interaction sums on the
@@ -405,6 +513,38 @@ def ablation(args) -> dict:
     return {"ablation": out}
 
 
+def treecodes(args) -> dict:
+    """Sec. 4.5's comparison on unequal uniform sets, (a) M = 2E7 targets with
+    N = 2E6 sources and (b) M = 2E6 with N = 2E7: the BLDTT against the
+    particle-cluster treecode BLTC (Sec. 2.8) and the cluster-particle treecode
+    CP-BLTC, plain FP64, one (theta, n) per --treecode-grid entry: compute
+    time, error against the direct sum and per-type interaction counts."""
+    from paper_2012_06925_amd import _lib, api, inputs
+    dev = __import__("torch").device("cuda:0")
+    leaf = args.leaf if args.leaf is not None else 2000
+    grid = [(float(a), int(b)) for a, b in (e.split(":") for e in args.treecode_grid.split(","))]
+    out = {"leaf": leaf, "grid": grid}
+    for name, M, N in (("a_M2e7_N2e6", 20_000_000, 2_000_000), ("b_M2e6_N2e7", 2_000_000, 20_000_000)):
+        seed = inputs.BASE_SEED + 500 + (name[0] == "b")
+        t, s = inputs.unequal_sets(M, "uniform", N, "uniform", seed=seed)
+        b = Bench(args, "coulomb", leaf, _dev_set(t, dev, charges=False), _dev_set(s, dev), seed)
+        del t, s
+        rows = []
+        for theta, degree in grid:
+            for method, flag in (("bldtt", 0), ("bltc", _lib.BLTC), ("cp_bltc", _lib.CP_BLTC)):
+                pl = api.Plan(b.tgt, b.src, kernel="coulomb", theta=theta, degree=degree, leaf=leaf,
+                              flags=_lib.PROFILE | flag)
+                ms, _, phase, st = b.time_plan(pl, args.steps, args.warmup)
+                err = b.error()
+                pl.close()
+                rows.append({"method": method, "theta": theta, "degree": degree, "ms_per_step": round(ms, 3),
+                             "error_vs_direct": err, "interactions": st["interactions"],
+                             "n_entries": st["n_entries"], "phase_ms": {k: round(v, 3) for k, v in phase.items()}})
+                log(f"treecodes {name} {method} theta={theta} n={degree}: {ms:.2f} ms err {err:.2e}")
+        out[name] = rows
+    return {"treecodes": out}
+
+
 def extras(args) -> dict:
     """The build's other workloads, a few steps each: the 1E6 cube in its three
     forms, the unequal Yukawa sets, the 256-problem batch and 1E8 with the
@@ -501,6 +641,11 @@ def main() -> int:
     ap.add_argument("--sweep", choices=("plain", "tuned"), default=None)
     ap.add_argument("--ablation", action="store_true",
                     help="all four interaction types vs PP + CC only (plain FP64, uniform and Gaussian)")
+    ap.add_argument("--summarize-pmc", default=None, metavar="PREFIX",
+                    help="write the profiles/ counter records from rocprofv3 passes PREFIX_A .. PREFIX_D of --mode")
+    ap.add_argument("--treecodes", action="store_true",
+                    help="Sec. 4.5: BLDTT vs BLTC vs CP-BLTC on unequal uniform sets (2E7/2E6 and 2E6/2E7)")
+    ap.add_argument("--treecode-grid", default="0.7:8", help="comma list of theta:degree for --treecodes")
     ap.add_argument("--sweep-thetas", default="0.5,0.6,0.7,0.8,0.9")
     ap.add_argument("--sweep-degrees", default="4,5,6,7,8,9,10")
     ap.add_argument("--sweep-taus", default="3e-8,1e-7,3e-7,1e-6,3e-6")
@@ -527,9 +672,15 @@ def main() -> int:
     from paper_2012_06925_amd import inputs
     from paper_2012_06925_amd.train_degree_model import DEFAULT_MODEL
 
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.mode)
+        return 0
     args.model = args.model or DEFAULT_MODEL
     if args.ablation:
         print(json.dumps(ablation(args)), flush=True)
+        return 0
+    if args.treecodes:
+        print(json.dumps(treecodes(args)), flush=True)
         return 0
     wl = dict(inputs.WORKLOADS[args.workload])
     dev = torch.device("cuda:0")

@@ -82,7 +82,7 @@ enum {
                                       FP64 matrix cores instead of the vector ALUs (the
                                       default, faster on gfx950: FP64 matrix and vector
                                       peaks are equal and 16x16 tiles pad n+1 rows)     */
-    BLDTT_ONE_SIDED_PP = 1u << 8   /* evaluate every PP and CC pair one-sided.  By
+    BLDTT_ONE_SIDED_PP = 1u << 8,  /* evaluate every PP and CC pair one-sided.  By
                                       default, for targets = sources with the Coulomb
                                       kernel, a pair of distinct leaves listed as PP in
                                       both directions, or of clusters listed as CC in
@@ -93,6 +93,26 @@ enum {
                                       at the rounding level.  FP64 batches of such
                                       problems evaluate their PP pairs the same way
                                       unless this flag is set                            */
+    BLDTT_BLTC = 1u << 9,          /* build the lists of the particle-cluster treecode
+                                      (BLTC, Sec. 2.8) instead of Algorithm 2: every
+                                      target leaf (a batch) walks the source tree from
+                                      its root under the same MAC; a separated source
+                                      cluster holding more than (n+1)^3 particles
+                                      interacts by PC, a smaller one by PP, a source
+                                      leaf that is not separated by PP, and other
+                                      clusters pass the batch to their children.  The
+                                      lists then hold PP and PC entries only and the
+                                      plan skips the downward pass                       */
+    BLDTT_CP_BLTC = 1u << 10       /* build the lists of the cluster-particle treecode
+                                      (CP-BLTC, Sec. 4.5): the walk of BLDTT_BLTC with
+                                      the two sets exchanged (every source leaf walks
+                                      the target tree; separated target clusters with
+                                      more than (n+1)^3 particles receive it by CP).
+                                      PP and CP entries only; the plan skips the
+                                      upward pass.  BLDTT_BLTC, BLDTT_CP_BLTC and
+                                      BLDTT_PP_CC_ONLY exclude each other (EINVAL);
+                                      neither treecode takes BLDTT_LEARNED_DEGREE, and
+                                      batches take neither (EUNSUPPORTED)               */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host

@@ -229,7 +229,7 @@ void build_forest(bldtt_batch* b, const bldtt_particles* problems, hipStream_t s
 
 void traverse_forest(bldtt_batch* b) {
     double t0 = now_ms();
-    traverse_roots(b->T(), b->S, b->roots, b->theta, b->degree, (b->flags & BLDTT_PP_CC_ONLY) != 0, b->lists, false);
+    traverse_roots(b->T(), b->S, b->roots, b->theta, b->degree, scheme_of(b->flags), b->lists, false);
     for (int k = 0; k < 4; ++k) b->stats.n_entries[k] = (int64_t)b->lists.tc[k].size();
     b->stats.traverse_ms = now_ms() - t0;
 }
@@ -473,8 +473,8 @@ std::unique_ptr<bldtt_batch> new_batch(int32_t count, const bldtt_particles* pro
         all_alias = all_alias && p.M == p.N && p.tx == p.sx && p.ty == p.sy && p.tz == p.sz;
     }
     if (sm >= INT32_MAX || sn >= INT32_MAX) throw Error(BLDTT_EINVAL, "the sums of M and of N must be < 2^31");
-    if (flags & (BLDTT_LEARNED_DEGREE | BLDTT_PROFILE))
-        throw Error(BLDTT_EUNSUPPORTED, "the batch runs one fixed degree and has no phase profile");
+    if (flags & (BLDTT_LEARNED_DEGREE | BLDTT_PROFILE | BLDTT_BLTC | BLDTT_CP_BLTC))
+        throw Error(BLDTT_EUNSUPPORTED, "the batch runs the dual tree traversal at one fixed degree and has no phase profile");
     auto b = std::make_unique<bldtt_batch>();
     b->kind = kernel;
     b->param = kernel_param;

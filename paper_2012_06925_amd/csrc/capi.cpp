@@ -147,8 +147,7 @@ void fill_stats_tree(bldtt_plan* pl) {
 
 void do_traverse(bldtt_plan* pl) {
     double t0 = now_ms();
-    traverse(pl->T(), pl->S, pl->theta, pl->degree, (pl->flags & BLDTT_PP_CC_ONLY) != 0, pl->lists,
-             pl->varied_degree());
+    traverse(pl->T(), pl->S, pl->theta, pl->degree, scheme_of(pl->flags), pl->lists, pl->varied_degree());
     pl->have_lists = true;
     for (int k = 0; k < 4; ++k) pl->stats.n_entries[k] = (int64_t)pl->lists.tc[k].size();
     pl->stats.traverse_ms = now_ms() - t0;
@@ -329,7 +328,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     //    for a per-pair degree plan at the source degrees its last compute used
     //    (the same particles give the same choice); degrees missing from that
     //    set follow once the degrees are chosen
-    const uint32_t pre = varied ? pl->up_degrees_last : (1u << pl->degree);
+    //    (the cluster-particle treecode has no PC or CC entries and needs none)
+    const int scheme = scheme_of(pl->flags);
+    const uint32_t pre = varied ? pl->up_degrees_last : (scheme == kSchemeCpBltc ? 0u : (1u << pl->degree));
     int have = -1;                      // degree whose charges are complete (the others restrict from it)
     if (pre) {
         PhaseMark mark(pl, BLDTT_PH_UP, st);
@@ -496,7 +497,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                        pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, nullptr, tab, deg_ptrs(pl->qhat_deg),
                        deg_out(pl->phihat_deg), nullptr, st);
     }
-    {
+    if (scheme != kSchemeBltc) {        // the particle-cluster treecode has no proxy potentials
         PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
         launch_prolong(pl->prolong.as<DevItem>(), (int)w.prolong.size(), dT, tab, deg_ptrs(pl->phihat_deg),
                        pl->phihat_deg[D].as<double>(), D, st);
@@ -620,6 +621,10 @@ bldtt_plan* new_plan(const bldtt_particles* p, int32_t kernel, double kernel_par
     validate(p, kernel, theta, degree, leaf_size);
     if ((flags & BLDTT_FP32_EVAL) && kernel == BLDTT_POLY_TEST)
         throw Error(BLDTT_EINVAL, "the polynomial test kernel runs in FP64 only");
+    if (((flags & BLDTT_BLTC) != 0) + ((flags & BLDTT_CP_BLTC) != 0) + ((flags & BLDTT_PP_CC_ONLY) != 0) > 1)
+        throw Error(BLDTT_EINVAL, "BLDTT_BLTC, BLDTT_CP_BLTC and BLDTT_PP_CC_ONLY exclude each other");
+    if ((flags & (BLDTT_BLTC | BLDTT_CP_BLTC)) && (flags & BLDTT_LEARNED_DEGREE))
+        throw Error(BLDTT_EUNSUPPORTED, "the treecodes run at one fixed degree");
     auto pl = std::make_unique<bldtt_plan>();
     pl->kind = kernel;
     pl->param = kernel_param;

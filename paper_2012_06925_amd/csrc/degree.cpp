@@ -311,7 +311,7 @@ int bldtt_pair_errors(bldtt_plan* plan, void* hip_stream, int64_t* n, const floa
     return guarded([&] {
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         Lists L;
-        traverse(plan->T(), plan->S, plan->theta, plan->degree, (plan->flags & BLDTT_PP_CC_ONLY) != 0, L, true);
+        traverse(plan->T(), plan->S, plan->theta, plan->degree, scheme_of(plan->flags), L, true);
         const int64_t np = (int64_t)L.sep_tc.size();
         std::vector<double> err((size_t)np * kNOut, 0.0);
         const Tree& T = plan->T();

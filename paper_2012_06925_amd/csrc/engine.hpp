@@ -70,16 +70,28 @@ struct Lists {
     }
 };
 
-// Algorithm 2.  With defer_separated, separated pairs are recorded in
-// sep_tc/sep_sc instead of being typed by the counts (their type then depends
-// on a per-pair degree chosen later); the recursion itself is unchanged.
-void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out,
+// How the lists are built: Algorithm 2; Algorithm 2 with PP and CC only (the
+// ablation of Sec. 4.3); the particle-cluster treecode BLTC (Sec. 2.8), where
+// every target leaf (a batch) walks the source tree from its root and meets
+// separated clusters by PC; or the cluster-particle treecode CP-BLTC
+// (Sec. 4.5), where every source leaf walks the target tree and separated
+// target clusters receive it by CP.
+enum Scheme : int { kSchemeDtt = 0, kSchemePpCc = 1, kSchemeBltc = 2, kSchemeCpBltc = 3 };
+
+// The scheme a set of bldtt_setup flags asks for.
+int scheme_of(uint32_t flags);
+
+// Builds the lists of one problem.  With defer_separated (Algorithm 2 only),
+// separated pairs are recorded in sep_tc/sep_sc instead of being typed by the
+// counts (their type then depends on a per-pair degree chosen later); the
+// recursion itself is unchanged.
+void traverse(const Tree& T, const Tree& S, double theta, int degree, int scheme, Lists& out,
               bool defer_separated = false);
 
-// Same, starting from every (target root, source root) pair of a forest of
-// independent problems (global cluster ids).
+// Algorithm 2 or its ablation from every (target root, source root) pair of a
+// forest of independent problems (global cluster ids).
 void traverse_roots(const Tree& T, const Tree& S, const std::vector<std::pair<int64_t, int64_t>>& roots,
-                    double theta, int degree, bool pp_cc_only, Lists& out, bool defer_separated);
+                    double theta, int degree, int scheme, Lists& out, bool defer_separated);
 
 // Append tree `t` (ids local to one problem) to forest `f` with cluster ids
 // shifted by f.size(), particle positions by `pos0` and caller indices by

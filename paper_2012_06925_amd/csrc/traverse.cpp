@@ -10,10 +10,20 @@
 // the children of the target when the source is a leaf, of the source when
 // the target is a leaf, and else of the larger cluster by particle count,
 // descending into the source on a tie.
+//
+// The two treecodes the paper compares with build their lists from the same
+// MAC.  BLTC (Sec. 2.8): each target leaf (a batch) starts at the source root;
+// a separated source cluster interacts by PC when it holds more than n_p
+// particles and by PP otherwise, a source leaf that is not separated by PP,
+// and any other source cluster passes the batch to its children.  CP-BLTC
+// (Sec. 4.5) is the same walk with the roles exchanged: each source leaf
+// starts at the target root, and separated target clusters with more than n_p
+// particles receive it by CP.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
 
+#include "bldtt.h"
 #include "engine.hpp"
 
 namespace bldtt {
@@ -36,9 +46,18 @@ struct Ctx {
     const Tree& S;
     double theta;
     int degree;
-    bool pp_cc_only;
+    int scheme;
     bool defer;
 };
+
+int scheme_type(const Ctx& x, int64_t ct, int64_t cs) {
+    const int64_t np = (int64_t)(x.degree + 1) * (x.degree + 1) * (x.degree + 1);
+    switch (x.scheme) {
+    case kSchemeBltc: return cs > np ? PC : PP;
+    case kSchemeCpBltc: return ct > np ? CP : PP;
+    default: return separated_type(ct, cs, x.degree, x.scheme == kSchemePpCc);
+    }
+}
 
 // One step of Algorithm 2.  Returns the list type for a terminal pair
 // (kSeparated when the choice is deferred), or -1 after passing the child
@@ -53,10 +72,19 @@ int step(const Ctx& x, int64_t t, int64_t s, Push&& push_pair) {
     double R = std::sqrt((dx * dx + dy * dy) + dz * dz);
     bool sep = R > 0.0 && (T.radius[t] + S.radius[s]) / R < x.theta;
     int64_t ct = T.count[t], cs = S.count[s];
-    if (sep) return x.defer ? kSeparated : separated_type(ct, cs, x.degree, x.pp_cc_only);
+    if (sep) return x.defer ? kSeparated : scheme_type(x, ct, cs);
     bool tl = T.is_leaf(t), sl = S.is_leaf(s);
-    if (tl && sl) return PP;
-    bool into_target = sl ? true : (tl ? false : (cs < ct));
+    bool into_target;
+    if (x.scheme == kSchemeBltc) {              // the batch t stays; the source side is refined
+        if (sl) return PP;
+        into_target = false;
+    } else if (x.scheme == kSchemeCpBltc) {     // the batch s stays; the target side is refined
+        if (tl) return PP;
+        into_target = true;
+    } else {
+        if (tl && sl) return PP;
+        into_target = sl ? true : (tl ? false : (cs < ct));
+    }
     if (into_target) {
         for (int k = 0; k < T.nchild[t]; ++k) push_pair(T.child[8 * t + k], s);
     } else {
@@ -81,9 +109,25 @@ void recurse(const Ctx& x, int64_t t, int64_t s, Lists& out) {
 
 }  // namespace
 
-void traverse(const Tree& T, const Tree& S, double theta, int degree, bool pp_cc_only, Lists& out,
+int scheme_of(uint32_t flags) {
+    if (flags & BLDTT_BLTC) return kSchemeBltc;
+    if (flags & BLDTT_CP_BLTC) return kSchemeCpBltc;
+    return (flags & BLDTT_PP_CC_ONLY) ? kSchemePpCc : kSchemeDtt;
+}
+
+void traverse(const Tree& T, const Tree& S, double theta, int degree, int scheme, Lists& out,
               bool defer_separated) {
-    traverse_roots(T, S, {{0, 0}}, theta, degree, pp_cc_only, out, defer_separated);
+    std::vector<std::pair<int64_t, int64_t>> roots;
+    if (scheme == kSchemeBltc) {                // every target batch from the source root
+        for (int64_t b = 0; b < T.size(); ++b)
+            if (T.is_leaf(b)) roots.emplace_back(b, 0);
+    } else if (scheme == kSchemeCpBltc) {       // every source batch from the target root
+        for (int64_t b = 0; b < S.size(); ++b)
+            if (S.is_leaf(b)) roots.emplace_back(0, b);
+    } else {
+        roots.emplace_back(0, 0);
+    }
+    traverse_roots(T, S, roots, theta, degree, scheme, out, defer_separated);
 }
 
 int64_t append_tree(Tree& f, const Tree& t, int64_t pos0, int64_t caller0) {
@@ -107,8 +151,8 @@ int64_t append_tree(Tree& f, const Tree& t, int64_t pos0, int64_t caller0) {
 }
 
 void traverse_roots(const Tree& T, const Tree& S, const std::vector<std::pair<int64_t, int64_t>>& roots,
-                    double theta, int degree, bool pp_cc_only, Lists& out, bool defer_separated) {
-    Ctx x{T, S, theta, degree, pp_cc_only, defer_separated};
+                    double theta, int degree, int scheme, Lists& out, bool defer_separated) {
+    Ctx x{T, S, theta, degree, scheme, defer_separated};
     out.clear();
     // Breadth-first expansion until there is enough independent work, then
     // depth-first recursion per frontier pair on all threads.  Per-pair lists

@@ -48,9 +48,15 @@ def _proxy_close(a, b, what):
     assert err < PROXY, f"{what}: {err:.3e}"
 
 
-def full_parity(tgt, src, same, kernel="coulomb", theta=0.7, degree=6, leaf=500, check_proxies=True, flags=0):
-    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf, flags=flags)
-    run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same)
+# bldtt_setup flags of the list-building schemes (the treecodes of Sec. 2.8 and Sec. 4.5)
+SCHEME_FLAGS = {"bldtt": 0, "bltc": 512, "cp_bltc": 1024}
+
+
+def full_parity(tgt, src, same, kernel="coulomb", theta=0.7, degree=6, leaf=500, check_proxies=True, flags=0,
+                scheme="bldtt"):
+    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf,
+                            flags=flags | SCHEME_FLAGS[scheme])
+    run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same, scheme=scheme)
     ref = run.run_all()
     for which in (0, 1):
         a, b = plan.tree(which), run.tree(which)
@@ -58,7 +64,8 @@ def full_parity(tgt, src, same, kernel="coulomb", theta=0.7, degree=6, leaf=500,
             assert np.array_equal(a[k], b[k]) if k != "depth" else a[k] == b[k], k
     _same_lists(plan.lists(), run.lists())
     if check_proxies:
-        _proxy_close(plan.qhat(), run.qhat(), "qhat")
+        if scheme != "cp_bltc":         # the cluster-particle treecode forms no proxy charges
+            _proxy_close(plan.qhat(), run.qhat(), "qhat")
         _proxy_close(plan.phihat(), run.phihat(), "phihat")
     # identical points skip every term: both sides must then be exactly zero
     err = core.rel_l2(phi, ref) if np.any(ref != 0) else float(np.abs(phi).max())
@@ -135,6 +142,42 @@ def test_ragged_tiles_and_ablation():
     assert core.rel_l2(phi, ref) < PARITY and core.max_rel(phi, ref) < PARITY
     L = plan.lists()
     assert len(L["PC"][0]) == 0 and len(L["CP"][0]) == 0
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+@pytest.mark.parametrize("case", ["same", "unequal"])
+def test_treecode_parity(scheme, case):
+    # the treecodes of Sec. 2.8 (BLTC: PC + PP per target batch) and Sec. 4.5
+    # (CP-BLTC: CP + PP per source batch) through the same passes: trees and
+    # lists bit-exact, proxies and potentials against the oracle's treecode
+    if case == "same":
+        t = s = inputs.particles(30_000, "gaussian", seed=inputs.BASE_SEED + 310)
+        kernel = "coulomb"
+    else:
+        t, s = inputs.unequal_sets(20_000, "sphere", 30_000, "uniform", seed=inputs.BASE_SEED + 311)
+        kernel = "yukawa"
+    phi, ref, _ = full_parity(t, s, case == "same", kernel=kernel, theta=0.7, degree=5, leaf=200, scheme=scheme)
+    sel = inputs.error_sample(t.n, 313, fraction=0.05)
+    e = core.rel_l2(phi[sel], core.direct_sum(t, s, kernel=kernel, sel=sel))
+    print(f"  {scheme} error against the direct sum: {e:.2e}")
+    assert e < 1e-4
+
+
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+def test_treecode_fp32_eval(scheme):
+    # FP32 evaluation of the treecode passes against the oracle's FP64 treecode
+    t, s = inputs.unequal_sets(20_000, "uniform", 25_000, "gaussian", seed=inputs.BASE_SEED + 312)
+    st = [dev(a) for a in (s.x, s.y, s.z, s.q)]
+    tt = [dev(a) for a in (t.x, t.y, t.z)]
+    ref = core.bldtt(t, s, theta=0.7, degree=6, leaf=150, scheme=scheme)
+    for same, tgt, refv in ((False, tt, ref), (True, None, core.bldtt(s, s, theta=0.7, degree=6, leaf=150,
+                                                                      scheme=scheme))):
+        plan = _api().Plan(tgt, st, theta=0.7, degree=6, leaf=150, flags=1 | SCHEME_FLAGS[scheme])
+        phi = plan.compute().cpu().numpy()
+        plan.close()
+        e = core.rel_l2(phi, refv)
+        print(f"\n  {scheme} FP32 vs FP64 oracle ({'same' if same else 'unequal'}): {e:.2e}")
+        assert e < FP32_BOUND_UNEQUAL
 
 
 def test_far_target_blob_root_interactions():
@@ -348,10 +391,11 @@ def test_caller_stream_is_used():
     assert core.rel_l2(out.cpu().numpy(), ref) < PARITY and core.max_rel(out.cpu().numpy(), ref) < PARITY
 
 
-def _sampled_parity(tgt, src, same, kernel, theta, degree, leaf, n_leaves=3, n_random=150, seed=0):
+def _sampled_parity(tgt, src, same, kernel, theta, degree, leaf, n_leaves=3, n_random=150, seed=0, scheme="bldtt"):
     """Full-size parity on every target of a few leaves plus random targets."""
-    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf)
-    run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same)
+    plan, phi, _ = gpu_plan(tgt, src, same, kernel=kernel, theta=theta, degree=degree, leaf=leaf,
+                            flags=SCHEME_FLAGS[scheme])
+    run = core.Run(tgt, src, kernel=kernel, theta=theta, degree=degree, leaf=leaf, aliased=same, scheme=scheme)
     run.traverse()
     _same_lists(plan.lists(), run.lists())
     run.upward()
@@ -435,6 +479,15 @@ def test_cube1e8_tuned_form_meets_error_target():
         print(f"\n  tuned 1E8 theta {theta}: error vs direct {err:.3e}; degrees {st['pairs_per_degree']}")
         assert err < 1e-6, (theta, err)
         del phi
+
+
+@pytest.mark.parametrize("scheme,M,N", [("bltc", 2_000_000, 20_000_000), ("cp_bltc", 20_000_000, 2_000_000)])
+def test_treecode_unequal_sizes_sampled(scheme, M, N):
+    # Sec. 4.5's unequal uniform sets, each treecode on the side where the paper
+    # expects it to be the faster one: lists bit-exact and sampled targets
+    # against the oracle at full size (theta 0.7, n 8, leaf 2000)
+    t, s = inputs.unequal_sets(M, "uniform", N, "uniform", seed=inputs.BASE_SEED + 320)
+    _sampled_parity(t, s, False, "coulomb", 0.7, 8, 2000, seed=7, scheme=scheme)
 
 
 def test_sphere_targets_gaussian_sources_yukawa_sampled():

@@ -80,6 +80,43 @@ def test_trees_and_lists_bit_exact_unequal(ablation):
         assert len(L["PC"][0]) == 0 and len(L["CP"][0]) == 0
 
 
+@pytest.mark.parametrize("scheme", ["bltc", "cp_bltc"])
+@pytest.mark.parametrize("case", ["same", "unequal"])
+def test_treecode_lists_bit_exact(scheme, case):
+    # the library's BLTC / CP-BLTC walks (Sec. 2.8, Sec. 4.5) against the oracle's
+    flags = _lib.BLTC if scheme == "bltc" else _lib.CP_BLTC
+    if case == "same":
+        t = s = inputs.particles(30_000, "gaussian", seed=35)
+        hp = api.HostPlan(None, (s.x, s.y, s.z, s.q), theta=0.7, degree=3, leaf=100, flags=flags)
+    else:
+        t, s = inputs.unequal_sets(25_000, "sphere", 40_000, "gaussian", seed=36)
+        hp = api.HostPlan((t.x, t.y, t.z), (s.x, s.y, s.z, s.q), theta=0.7, degree=3, leaf=100, flags=flags)
+    hp.traverse_host()
+    r = core.Run(t, s, theta=0.7, degree=3, leaf=100, scheme=scheme, aliased=case == "same")
+    r.traverse()
+    _same_lists(r.lists(), hp.lists())
+    L = hp.lists()
+    approx = "PC" if scheme == "bltc" else "CP"
+    assert len(L[approx][0]) > 0
+    assert all(len(L[k][0]) == 0 for k in ("PC", "CP", "CC") if k != approx)
+
+
+def test_treecode_flag_errors():
+    p = inputs.particles(2000, seed=37)
+    src = (p.x, p.y, p.z, p.q)
+    for bad in (_lib.BLTC | _lib.CP_BLTC, _lib.BLTC | _lib.PP_CC_ONLY, _lib.CP_BLTC | _lib.PP_CC_ONLY):
+        with pytest.raises(_lib.BldttError) as e:
+            api.HostPlan(None, src, theta=0.7, degree=3, leaf=100, flags=bad)
+        assert e.value.code == _lib.EINVAL
+    for scheme in (_lib.BLTC, _lib.CP_BLTC):
+        with pytest.raises(_lib.BldttError) as e:
+            api.HostPlan(None, src, theta=0.7, degree=3, leaf=100, flags=scheme | _lib.LEARNED_DEGREE)
+        assert e.value.code == _lib.EUNSUPPORTED
+        with pytest.raises(_lib.BldttError) as e:
+            api.HostBatch([(None, src), (None, src)], theta=0.7, degree=3, leaf=100, flags=scheme)
+        assert e.value.code == _lib.EUNSUPPORTED
+
+
 def test_large_tree_parallel_build_bit_exact():
     # above the serial cutoff: the multi-threaded partition must give the same tree
     p = inputs.particles(400_000, "gaussian", seed=33)
