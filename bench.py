@@ -237,6 +237,8 @@ class Bench:
             flags |= _lib.VALU_PASSES
         if self.args.mfma_leaf:
             flags |= _lib.MFMA_LEAF
+        if self.args.device_traversal:
+            flags |= _lib.DEVICE_TRAVERSAL
         if mode in ("fp32", "tuned"):
             flags |= _lib.FP32_EVAL
         if mode == "tuned":
@@ -652,6 +654,7 @@ def main() -> int:
     ap.add_argument("--sweep-leaves", default=None, help="comma list; default: the workload's leaf size")
     ap.add_argument("--valu-passes", action="store_true",
                     help="run the up/down transfers on the vector ALUs instead of the matrix cores")
+    ap.add_argument("--device-traversal", action="store_true", help="build the lists on the GPU (BLDTT_DEVICE_TRAVERSAL)")
     ap.add_argument("--mfma-leaf", action="store_true",
                     help="run the leaf contractions on the matrix cores instead of the vector ALUs")
     ap.add_argument("--cpu-problems", type=int, default=16, help="batch workloads: problems in the CPU sample")

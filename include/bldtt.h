@@ -103,7 +103,7 @@ enum {
                                       clusters pass the batch to their children.  The
                                       lists then hold PP and PC entries only and the
                                       plan skips the downward pass                       */
-    BLDTT_CP_BLTC = 1u << 10       /* build the lists of the cluster-particle treecode
+    BLDTT_CP_BLTC = 1u << 10,      /* build the lists of the cluster-particle treecode
                                       (CP-BLTC, Sec. 4.5): the walk of BLDTT_BLTC with
                                       the two sets exchanged (every source leaf walks
                                       the target tree; separated target clusters with
@@ -113,6 +113,15 @@ enum {
                                       BLDTT_PP_CC_ONLY exclude each other (EINVAL);
                                       neither treecode takes BLDTT_LEARNED_DEGREE, and
                                       batches take neither (EUNSUPPORTED)               */
+    BLDTT_DEVICE_TRAVERSAL = 1u << 11 /* build each compute's lists on the GPU instead of
+                                      the host: one generation of cluster pairs per
+                                      step (classify, scan, emit) on a stream of the
+                                      plan's own, beside the passes already queued.
+                                      Same MAC arithmetic, so the same lists as sets;
+                                      generation order instead of depth-first, so the
+                                      potentials agree with the host walk's to
+                                      rounding.  The host walk is the default: on a
+                                      GPU busy with the passes it finishes sooner    */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host

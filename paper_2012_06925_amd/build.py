@@ -33,6 +33,7 @@ HIP_HOST = ["-D__HIP_PLATFORM_AMD__"]
 UNITS = [
     ("kernels.hip", DEVICE, "kernels"),
     ("mlp.hip", DEVICE, "mlp"),
+    ("walk.hip", DEVICE + HOST_EXACT, "walk"),
 ] + [("batch.hip", DEVICE + [f"-DBATCH_PART={k}"], f"batch{k}") for k in range(6)] + [
     ("degree.cpp", HOST_EXACT + HIP_HOST, "degree"),
     ("tree.cpp", HOST_EXACT, "tree"),

@@ -147,26 +147,48 @@ void fill_stats_tree(bldtt_plan* pl) {
 
 void do_traverse(bldtt_plan* pl) {
     double t0 = now_ms();
-    traverse(pl->T(), pl->S, pl->theta, pl->degree, scheme_of(pl->flags), pl->lists, pl->varied_degree());
+    const int scheme = scheme_of(pl->flags);
+    if (pl->device_walk())
+        traverse_device(pl->walk, pl->dT().view(), pl->dS.view(), walk_roots(pl->T(), pl->S, scheme), pl->theta,
+                        pl->degree, scheme, pl->lists, pl->varied_degree());
+    else
+        traverse(pl->T(), pl->S, pl->theta, pl->degree, scheme, pl->lists, pl->varied_degree());
     pl->have_lists = true;
     for (int k = 0; k < 4; ++k) pl->stats.n_entries[k] = (int64_t)pl->lists.tc[k].size();
     pl->stats.traverse_ms = now_ms() - t0;
 }
 
 
-// Fold the events of the last profiled compute into the stats.
-void collect_profile(bldtt_plan* pl) {
-    if (!pl->prof_pending) return;
-    for (int ph = 0; ph < BLDTT_N_PHASES; ++ph) {
-        if (!(pl->prof_mask >> ph & 1)) continue;
-        HIPCHK(hipEventSynchronize(pl->prof_ev[2 * ph + 1]));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, pl->prof_ev[2 * ph], pl->prof_ev[2 * ph + 1]));
-        pl->stats.phase_ms[ph] += ms;
+// Fold the events of profiled computes into the stats, oldest first: every
+// set whose events have completed, and, waiting for them, as many more as it
+// takes to leave at most `keep` sets pending.  A compute waits only when all
+// the sets are in use, so the host runs ahead of the device as it does
+// without BLDTT_PROFILE.
+void collect_profile(bldtt_plan* pl, int keep) {
+    while (pl->prof_pending > 0) {
+        const int slot = (pl->prof_cur - pl->prof_pending + bldtt_plan::kProfRing) % bldtt_plan::kProfRing;
+        const uint32_t mask = pl->prof_mask[slot];
+        if (pl->prof_pending <= keep) {
+            bool done = true;
+            for (int ph = 0; ph < BLDTT_N_PHASES && done; ++ph) {
+                if (!(mask >> ph & 1)) continue;
+                const hipError_t q = hipEventQuery(pl->prof_ev[slot][2 * ph + 1]);
+                if (q == hipErrorNotReady) done = false;
+                else HIPCHK(q);
+            }
+            if (!done) break;
+        }
+        for (int ph = 0; ph < BLDTT_N_PHASES; ++ph) {
+            if (!(mask >> ph & 1)) continue;
+            HIPCHK(hipEventSynchronize(pl->prof_ev[slot][2 * ph + 1]));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pl->prof_ev[slot][2 * ph], pl->prof_ev[slot][2 * ph + 1]));
+            pl->stats.phase_ms[ph] += ms;
+        }
+        pl->stats.profiled_computes += 1;
+        pl->prof_mask[slot] = 0;
+        pl->prof_pending -= 1;
     }
-    pl->stats.profiled_computes += 1;
-    pl->prof_pending = false;
-    pl->prof_mask = 0;
 }
 
 struct PhaseMark {
@@ -175,12 +197,12 @@ struct PhaseMark {
     hipStream_t st;
     PhaseMark(bldtt_plan* p, int phase, hipStream_t s) : pl(p), ph(phase), st(s) {
         if (pl->flags & BLDTT_PROFILE) {
-            HIPCHK(hipEventRecord(pl->prof_ev[2 * ph], st));
-            pl->prof_mask |= 1u << ph;
+            HIPCHK(hipEventRecord(pl->prof_ev[pl->prof_cur][2 * ph], st));
+            pl->prof_mask[pl->prof_cur] |= 1u << ph;
         }
     }
     ~PhaseMark() noexcept(false) {
-        if (pl->flags & BLDTT_PROFILE) HIPCHK(hipEventRecord(pl->prof_ev[2 * ph + 1], st));
+        if (pl->flags & BLDTT_PROFILE) HIPCHK(hipEventRecord(pl->prof_ev[pl->prof_cur][2 * ph + 1], st));
     }
 };
 
@@ -263,6 +285,14 @@ void ensure_self_work(bldtt_plan* pl) {
     upload_bytes(pl->self_entries, de.data(), sizeof(Entry) * de.size());
     upload_bytes(pl->self_sym_items, sym.data(), sizeof(Item) * sym.size());
     upload_bytes(pl->self_sym_entries, se.data(), sizeof(Entry) * se.size());
+    SymFold fold;
+    build_fold(T, sym, se, false, fold);
+    DevFold& f = pl->fold_self;
+    f.slots.alloc(sizeof(double) * (size_t)std::max<int64_t>(fold.nslots, 1));
+    upload(f.ibase, fold.ibase);
+    upload(f.segs, fold.segs);
+    upload(f.parts, fold.parts);
+    f.n_segs = (int)fold.segs.size();
     pl->n_self_items = (int)di.size();
     pl->n_self_sym_items = (int)sym.size();
     pl->self_evaluations = evals;
@@ -310,17 +340,37 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                             pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg), pl->phi_tree.as<double>(), DegOut{}, s,
                             add, nfp64);
     };
-    // symmetric PP items: those without guarded ranges, then those with
+    // symmetric PP items: those without guarded ranges, then those with (their
+    // slot bases uploaded with them, the slots reserved by add_bases); the
+    // fold follows once its segments and parts are uploaded (add_parts)
     auto sym_pp_pass = [&](const DevBuf& items, const DevBuf& entries, const SymWork& sw, hipStream_t s) {
         const int n = (int)sw.pp_items.size(), n0 = (int)sw.pp_plain;
+        const DevFold& f = pl->fold_pp;
         launch_sym(fp32, pl->mfma_transfer(), false, false, items.as<DevItem>(), n0, entries.as<int2>(), pl->dsrc(),
-                   dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64, s);
+                   dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64,
+                   f.out(), s);
         launch_sym(fp32, pl->mfma_transfer(), false, true, items.as<DevItem>() + n0, n - n0, entries.as<int2>(),
                    pl->dsrc(), dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg),
-                   nfp64, s);
+                   nfp64, f.out_from(n0), s);
+    };
+    auto sym_pp_fold = [&](hipStream_t s) {
+        const DevFold& f = pl->fold_pp;
+        launch_sym_fold(f.segs.as<FoldSeg>(), f.n_segs, f.parts.as<FoldPart>(), f.slots.as<double>(),
+                        pl->phi_tree.as<double>(), DegOut{}, s);
+    };
+    auto add_bases = [](Upload& u, DevFold& d, const SymFold& f) {
+        d.slots.reserve(sizeof(double) * (size_t)std::max<int64_t>(f.nslots, 1));
+        u.add(d.ibase, f.ibase);
+    };
+    auto add_parts = [](Upload& u, DevFold& d, const SymFold& f) {
+        d.n_segs = (int)f.segs.size();
+        u.add(d.segs, f.segs).add(d.parts, f.parts);
     };
 
-    collect_profile(pl);                // waits for the previous compute's events (BLDTT_PROFILE)
+    // profiled computes: fold what has finished; wait only when every event set is in use
+    collect_profile(pl, bldtt_plan::kProfRing - 1);
+    pl->prof_mask[pl->prof_cur] = 0;    // a compute that failed part way left no pending set
+    if (varied && pl->done_recorded) HIPCHK(hipEventSynchronize(pl->ev_done));
     const double t0 = now_ms();
     if (nfp64) launch_fill(nfp64, 1, 0.0, st);
     auto mark_host = [&](int k) { pl->stats.host_marks_ms[k] = now_ms() - t0; };
@@ -355,9 +405,12 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         ensure_self_work(pl);
         PhaseMark mark(pl, BLDTT_PH_PP_SELF, st);
         particle_pass(pl->self_items, pl->n_self_items, pl->self_entries, false, st);
+        const DevFold& f = pl->fold_self;
         launch_sym(fp32, pl->mfma_transfer(), false, true, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
                    pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
-                   deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64, st);
+                   deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64, f.out(), st);
+        launch_sym_fold(f.segs.as<FoldSeg>(), f.n_segs, f.parts.as<FoldPart>(), f.slots.as<double>(),
+                        pl->phi_tree.as<double>(), DegOut{}, st);
     }
 
     mark_host(0);
@@ -395,6 +448,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                 fork();
                 Upload us;
                 us.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
+                add_bases(us, pl->fold_pp, pl->sym.pp_fold);
                 us.run(pl->staging_near, pl->arena_near, pl->staging_near_free, pl->side);
                 PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
                 sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, pl->side);
@@ -411,7 +465,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         if (!symm) fork();
         Upload un;
         un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
+        if (symm) add_parts(un, pl->fold_pp, pl->sym.pp_fold);
         un.run(pl->staging_rest, pl->arena_rest, pl->staging_rest_free, pl->side);
+        if (symm) sym_pp_fold(pl->side);    // the symmetric pairs' sums, before the near pass adds
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
             particle_pass(pl->near_items, (int)wn.pitems.size(), pl->near_entries, symm, pl->side);
@@ -467,8 +523,16 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     up.add(pl->pitems, w.pitems).add(pl->pentries, w.pentries).add(pl->qitems, w.qitems)
         .add(pl->qentries, w.qentries).add(pl->has_far, w.leaf_has_far).add(pl->prolong, w.prolong);
     if (varied || symm) up.add(pl->sep_items, sep_items);
-    if (!varied && symm) up.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
-    if (symm) up.add(pl->sym_cc_items, scc.cc_items).add(pl->sym_cc_entries, scc.cc_entries);
+    if (!varied && symm) {
+        up.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
+        add_bases(up, pl->fold_pp, pl->sym.pp_fold);
+        add_parts(up, pl->fold_pp, pl->sym.pp_fold);
+    }
+    if (symm) {
+        up.add(pl->sym_cc_items, scc.cc_items).add(pl->sym_cc_entries, scc.cc_entries);
+        add_bases(up, pl->fold_cc, scc.cc_fold);
+        add_parts(up, pl->fold_cc, scc.cc_fold);
+    }
     up.run(pl->staging, pl->arena, pl->staging_free, st);
 
     if (varied) {
@@ -492,10 +556,14 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         launch_interact(ks, fp32, true, pl->tpt_proxy, pl->qitems.as<DevItem>(), (int)w.qitems.size(),
                         pl->qentries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg),
                         nullptr, deg_out(pl->phihat_deg), st);
-        if (symm)               // symmetric CC pairs add to the proxy potentials the pass above wrote
+        if (symm) {             // symmetric CC pairs add to the proxy potentials the pass above wrote
+            const DevFold& f = pl->fold_cc;
             launch_sym(fp32, pl->mfma_transfer(), true, false, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
                        pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, nullptr, tab, deg_ptrs(pl->qhat_deg),
-                       deg_out(pl->phihat_deg), nullptr, st);
+                       deg_out(pl->phihat_deg), nullptr, f.out(), st);
+            launch_sym_fold(f.segs.as<FoldSeg>(), f.n_segs, f.parts.as<FoldPart>(), f.slots.as<double>(), nullptr,
+                            deg_out(pl->phihat_deg), st);
+        }
     }
     if (scheme != kSchemeBltc) {        // the particle-cluster treecode has no proxy potentials
         PhaseMark mark(pl, BLDTT_PH_DOWN_TRANSFER, st);
@@ -516,8 +584,11 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             else particle_pass(pl->pitems, (int)w.pitems.size(), pl->pentries, false, st);
         }
         if (symm) {
-            PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
-            sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, st);
+            {
+                PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
+                sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, st);
+            }
+            sym_pp_fold(st);
         }
     } else {
         HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));
@@ -531,7 +602,12 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                          pl->dtgt(), dT, tab, pl->phihat_deg[D].as<double>(), pl->phi_tree.as<double>(),
                          pl->perm.as<int32_t>(), out, st);
     }
-    if (pl->flags & BLDTT_PROFILE) pl->prof_pending = true;
+    HIPCHK(hipEventRecord(pl->ev_done, st));
+    pl->done_recorded = true;
+    if (pl->flags & BLDTT_PROFILE) {
+        pl->prof_pending += 1;
+        pl->prof_cur = (pl->prof_cur + 1) % bldtt_plan::kProfRing;
+    }
     if (pl->flags & BLDTT_SYNC) HIPCHK(hipStreamSynchronize(st));
     pl->stats.compute_host_ms = now_ms() - t0;
     mark_host(3);
@@ -598,13 +674,16 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     HIPCHK(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_near_done, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_select, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->ev_done, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
     HIPCHK(hipEventRecord(pl->staging_near_free, st));
     HIPCHK(hipEventRecord(pl->staging_rest_free, st));
     if (pl->flags & BLDTT_PROFILE)
-        for (auto& e : pl->prof_ev) HIPCHK(hipEventCreate(&e));
+        for (auto& set : pl->prof_ev)
+            for (auto& e : set) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(pl->staging_free, st));
     if (pl->symmetric_pp()) ensure_self_work(pl);
+    if (pl->device_walk()) walk_upload(pl->walk, T, pl->S, pl->aliased);
     fill_stats_tree(pl);
     pl->stats.setup_ms = now_ms() - t0;
 }
@@ -869,7 +948,7 @@ int bldtt_get_stats(bldtt_plan* plan, bldtt_stats* out) {
         return BLDTT_EINVAL;
     }
     return guarded([&] {
-        if (!plan->host_only) collect_profile(plan);
+        if (!plan->host_only) collect_profile(plan, 0);
         if (!plan->host_only && plan->nfp64_ptr()) {
             HIPCHK(hipDeviceSynchronize());
             HIPCHK(hipMemcpy(&plan->stats.fp64_close_pairs, plan->nfp64.p, sizeof(double), hipMemcpyDeviceToHost));

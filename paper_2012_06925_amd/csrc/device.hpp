@@ -865,12 +865,16 @@ constexpr int sym_lds_bytes() {
 // holds H targets (rows 64 h + lane of its wave's 64 H), so a staged source and
 // the move of its partial serve H pairs.  An item whose targets fill nslab = 1
 // or 2 waves runs 4 / nslab copies of those waves, each over its own 64 of the
-// 64 * copies sources staged per round (each copy adds its own target partials
-// with its atomics).
+// 64 * copies sources staged per round.  With slots (the deterministic form)
+// the copies' target sums are added in copy order in LDS and each target's
+// total written to its slot, as is each source's partial per entry; without,
+// every copy adds its target partials, and the sources' partials, with FP64
+// atomics.
 template <bool F32, bool PROXY, int H = 2>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, double* __restrict__ phi, const double* __restrict__ tab,
-                                         DegPtrs qhat, DegOut phihat, void* lds, double* nfp64 = nullptr) {
+                                         DegPtrs qhat, DegOut phihat, void* lds, double* nfp64 = nullptr,
+                                         double* __restrict__ slots = nullptr, int64_t base = 0) {
     using R = typename std::conditional<F32, float, double>::type;
     using V = typename std::conditional<F32, float4, double4>::type;
     // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
@@ -922,6 +926,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     double acc[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) acc[h] = 0.0;
+    int64_t run = base + it.tn;                            // slots of the current entry's sources
     for (int e = it.eb; e < it.ee; ++e) {
         const int2 en = entries[e];
         const int low = en.y & ((1 << 29) - 1);
@@ -1015,10 +1020,28 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                 double t = 0.0;
                 for (int w = 0; w < nslab; ++w)
                     if (64 * H * w < it.tn) t += part_red[k * nslab + w][ms];
-                if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
+                if (slots) slots[run + c0 + tid] = t;
+                else if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
                 else atomicAdd(phi + en.x + c0 + tid, t);
             }
         }
+        run += bn;
+    }
+    if (slots) {
+        // the copies hold the same targets against different sources: their
+        // sums meet in LDS (the staging area, free now) and are added in copy order
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(src);      // [copies][64 H nslab]
+        const int stride = 64 * H * nslab;
+#pragma unroll
+        for (int h = 0; h < H; ++h) red[copy * stride + 64 * H * sw + 64 * h + lane] = acc[h];
+        __syncthreads();
+        for (int r = tid; r < it.tn; r += kBlock) {
+            double t = 0.0;
+            for (int k = 0; k < copies; ++k) t += red[k * stride + r];
+            slots[base + r] = t;
+        }
+        return;
     }
 #pragma unroll
     for (int h = 0; h < H; ++h)

@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include "fold.hpp"
+
 namespace bldtt {
 
 constexpr int kMaxDegree = 12;
@@ -87,6 +89,11 @@ int scheme_of(uint32_t flags);
 // recursion itself is unchanged.
 void traverse(const Tree& T, const Tree& S, double theta, int degree, int scheme, Lists& out,
               bool defer_separated = false);
+
+// The pairs a walk starts from: (target root, source root) for Algorithm 2
+// and its ablation, (target leaf, source root) for every target leaf (BLTC),
+// (target root, source leaf) for every source leaf (CP-BLTC).
+std::vector<std::pair<int64_t, int64_t>> walk_roots(const Tree& T, const Tree& S, int scheme);
 
 // Algorithm 2 or its ablation from every (target root, source root) pair of a
 // forest of independent problems (global cluster ids).
@@ -164,9 +171,39 @@ void pack_work(const Tree& T, const Tree& S, const Lists& L, int degree, int til
 // rest only guarded ranges (without it pp_plain counts every item, and an
 // item's guarded ranges follow its plain ones).  The evaluation counts are the
 // kernel terms the items produce (both directions).
+// The fold of one symmetric pass (fold.hpp): slot base per item, slots in
+// all, and the segments with their ordered parts.
+struct SymFold {
+    std::vector<int64_t> ibase;
+    int64_t nslots = 0;
+    std::vector<FoldSeg> segs;
+    std::vector<FoldPart> parts;
+    void clear() {
+        ibase.clear();
+        segs.clear();
+        parts.clear();
+        nslots = 0;
+    }
+};
+
+// Slots and fold of the symmetric items `items` over `entries`: particle
+// items (tiles of a leaf, particle-range entries, outputs in tree order,
+// one segment per leaf) or proxy items (tiles of a cluster's proxies of
+// degree item.degree, proxy entries, one segment per cluster and degree).
+// Parts are ordered by item, an item's target part before its source parts
+// in entry order, so the fold adds in the same order every time.
+void build_fold(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
+                SymFold& f);
+// The two halves of build_fold: the slot bases (what the pass needs), and the
+// segments and parts (what the fold needs).
+void fold_bases(const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies, SymFold& f);
+void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
+                SymFold& f);
+
 struct SymWork {
     std::vector<Entry> pp_entries, cc_entries;
     std::vector<Item> pp_items, cc_items;
+    SymFold pp_fold, cc_fold;
     int64_t pp_plain = 0;
     double pp_evaluations = 0.0, cc_evaluations = 0.0;
     bool guard_near = false;                    // setting, as Work::guard_near
@@ -177,10 +214,13 @@ struct SymWork {
         cc_items.clear();
         pp_plain = 0;
         pp_evaluations = cc_evaluations = 0.0;
+        pp_fold.clear();
+        cc_fold.clear();
     }
 };
-// pp_ready, when given, is called as soon as the PP items are complete (before
-// `rest` and the CC items are formed), so their pass can start early.
+// pp_ready, when given, is called as soon as the PP items and their slot bases
+// are complete (before their fold's parts, `rest` and the CC items are
+// formed), so their pass can start early.
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
                      const std::function<void()>& pp_ready = {}, bool separate_guarded = false);
 

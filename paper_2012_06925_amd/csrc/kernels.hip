@@ -7,13 +7,19 @@
 //   cp_cc          CP and CC sums into the target proxies (Eqs. CP-proxy-potential, CC-proxy-potential)
 //   down_transfer  parent-to-child interpolation of proxy potentials (Sec. 2.7, Appendix C)
 //   down_leaf      leaf proxies to targets, plus the PP/PC part, scattered to caller order
+//   sym, sym_mfma  PP and CC pairs listed in both directions (targets = sources,
+//                  Coulomb), each evaluated once for both sides
+//   sym_fold       the symmetric passes' sums added to their outputs in a fixed order
 //   direct         the direct sum of Eq. (1), compensated, the accuracy reference
 //
 // Mapping: targets (particles or proxies) are the outer level of parallelism,
 // one per lane; sources (particles or proxies) are the inner level, staged
 // through LDS in chunks and read by every lane of the workgroup at the same
-// address (broadcast).  Each workgroup owns its outputs, so there are no
-// atomics and results do not depend on scheduling.
+// address (broadcast).  In the one-sided passes each workgroup owns its
+// outputs.  A symmetric pass also produces sums for its sources, which other
+// workgroups' targets share: it writes them to slots of its own and the fold
+// adds them in a stored order (atomic adds only where a caller asks for them:
+// the batch kernel), so every compute gives the same bits.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -98,12 +104,35 @@ template <bool F32, bool PROXY>
 __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ items, const int2* __restrict__ entries,
                                                 DevParticles p, DevTree T, double* __restrict__ phi,
                                                 const double* __restrict__ tab, DegPtrs qhat, DegOut phihat,
-                                                double* __restrict__ nfp64) {
+                                                double* __restrict__ nfp64, SymSlots out) {
     __shared__ double4 pool[(sym_lds_bytes<F32>() + 31) / 32];
     // tiles of more than 128 targets: four per lane (one wave per copy)
     const DevItem it = items[blockIdx.x];
-    if (it.tn > 128) sym_body<F32, PROXY, 4>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64);
-    else sym_body<F32, PROXY, 2>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64);
+    const int64_t base = out.slots ? out.ibase[blockIdx.x] : 0;
+    if (it.tn > 128)
+        sym_body<F32, PROXY, 4>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64, out.slots, base);
+    else
+        sym_body<F32, PROXY, 2>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64, out.slots, base);
+}
+
+// ---------------------------------------------------------------------------
+// Fold of a deterministic symmetric pass (fold.hpp): one work group per
+// segment; each output adds its parts in their stored order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sym_fold(const FoldSeg* __restrict__ segs,
+                                                     const FoldPart* __restrict__ parts,
+                                                     const double* __restrict__ slots, double* __restrict__ phi,
+                                                     DegOut phihat) {
+    const FoldSeg sg = segs[blockIdx.x];
+    double* out = (sg.deg < 0 ? phi : phihat.p[sg.deg]) + sg.off;
+    for (int k = threadIdx.x; k < sg.n; k += kBlock) {
+        double v = 0.0;
+        for (int q = sg.pb; q < sg.pe; ++q) {
+            const FoldPart pt = parts[q];
+            if (k >= pt.lo && k < pt.lo + pt.len) v += slots[pt.slot + (k - pt.lo)];
+        }
+        out[k] += v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -123,9 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
 // walks the sources 16 at a time, one B operand serving four products.  In
 // the result lane l holds column l mod 16 of rows l/16 + 4r.  Each tile's
 // source partials (over the 16 rows of a lane) are added to a per-wave FP64
-// slot of their column in LDS (LDS atomics, nothing to wait for); after the
-// chunk one thread per source adds the four waves' slots in a fixed order
-// and adds the sum with one FP64 atomic.
+// slot of their column in LDS (LDS atomics of one wave, nothing to wait
+// for); after the chunk one thread per source adds the four waves' slots in
+// a fixed order and writes the sum to the item's slot of that source.
 // The next chunk's sources are loaded into registers while the current one is
 // evaluated.
 //
@@ -139,8 +168,9 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
 // again after it in FP64 from the particles' own coordinates: coincident
 // points (the self term, duplicates) contribute nothing, as in the FP64 form;
 // any other such pair adds its FP64 terms (the target's through an LDS
-// accumulator read at the end of the item, the source's with an atomic) and
-// is counted in *nfp64 (when not null), so no distinct pair is ever dropped.
+// accumulator read at the end of the item, the source's to its column slot
+// of the tile) and is counted in *nfp64 (when not null), so no distinct pair
+// is ever dropped.
 // ---------------------------------------------------------------------------
 constexpr int kSymChunk = 256;                  // sources per chunk: 16 tiles of 16
 constexpr double kFarT = 1e18, kFarS = -1e18;   // padding targets / sources (q = 0)
@@ -315,9 +345,12 @@ template <bool PROXY, bool GUARDED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_mfma(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles p, DevTree T,
                                                      double* __restrict__ phi, const double* __restrict__ tab,
-                                                     DegPtrs qhat, DegOut phihat, double* __restrict__ nfp64) {
+                                                     DegPtrs qhat, DegOut phihat, double* __restrict__ nfp64,
+                                                     SymSlots out) {
     __shared__ MfmaLds L;
     const DevItem it = items[blockIdx.x];
+    const int64_t base = out.slots ? out.ibase[blockIdx.x] : 0;
+    int64_t run = base + it.tn;                  // slots of the current entry's sources
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
     const bool active = 64 * wave < it.tn;
     const double* box = T.box + 6 * it.cluster;
@@ -387,7 +420,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 const double g = coulomb_exact(p, i, p, j, nfp64);
                 if (g == 0.0) return;
                 atomicAdd(&L.corr[row], p.q[j] * g);
-                atomicAdd(phi + j, p.q[i] * g);
+                // the source's term joins its column slot of this wave and tile
+                if (out.slots) atomicAdd(&L.part[wave][t][col], p.q[i] * g);
+                else atomicAdd(phi + j, p.q[i] * g);
             };
             mfma_tiles<GUARDED, false>(nt, L, L.part[wave], lane, A, qi, acc, xmax2, fix);
         }
@@ -402,10 +437,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 L.part[w][t][j] = 0.0;
             }
             if (c0 + tid < bn) {
-                if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
+                if (out.slots) out.slots[run + c0 + tid] = s;
+                else if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
                 else atomicAdd(phi + en.x + c0 + tid, s);
             }
         }
+        if (e2 != e) run += bn;
         e = e2;
         c0 = c2;
     }
@@ -413,7 +450,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
         const double v = reduce_rows(acc, col) + (row < it.tn ? L.corr[row] : 0.0);
         if (row < it.tn) {
-            if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
+            if (out.slots) out.slots[base + row] = v;
+            else if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
             else atomicAdd(phi + it.t0 + row, v);
         }
     }
@@ -959,24 +997,24 @@ void launch_pp_mfma(const DevItem* items, int n_items, const int2* entries, DevP
 
 void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem* items, int n_items,
                 const int2* entries, DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat,
-                DegOut phihat, double* nfp64, hipStream_t st) {
+                DegOut phihat, double* nfp64, SymSlots out, hipStream_t st) {
     if (n_items <= 0) return;
     if (fp32 && mfma) {
         if (proxies && guarded) throw Error(-1, "proxy entries are never guarded");
         if (proxies)
             hipLaunchKernelGGL((k_sym_mfma<true, false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
-                               phi, tab, qhat, phihat, nfp64);
+                               phi, tab, qhat, phihat, nfp64, out);
         else if (guarded)
             hipLaunchKernelGGL((k_sym_mfma<false, true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
-                               phi, tab, qhat, phihat, nfp64);
+                               phi, tab, qhat, phihat, nfp64, out);
         else
             hipLaunchKernelGGL((k_sym_mfma<false, false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
-                               phi, tab, qhat, phihat, nfp64);
+                               phi, tab, qhat, phihat, nfp64, out);
         CHECK_LAUNCH();
         return;
     }
 #define LAUNCH_SYM(F, PX) hipLaunchKernelGGL((k_sym<F, PX>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, \
-                                            tab, qhat, phihat, nfp64)
+                                            tab, qhat, phihat, nfp64, out)
     if (fp32) {
         if (proxies) LAUNCH_SYM(true, true);
         else LAUNCH_SYM(true, false);
@@ -985,6 +1023,13 @@ void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem*
         else LAUNCH_SYM(false, false);
     }
 #undef LAUNCH_SYM
+    CHECK_LAUNCH();
+}
+
+void launch_sym_fold(const FoldSeg* segs, int n_segs, const FoldPart* parts, const double* slots, double* phi,
+                     DegOut phihat, hipStream_t st) {
+    if (n_segs <= 0) return;
+    hipLaunchKernelGGL(k_sym_fold, dim3(n_segs), dim3(kBlock), 0, st, segs, parts, slots, phi, phihat);
     CHECK_LAUNCH();
 }
 

@@ -13,6 +13,8 @@
 
 #include <cstdint>
 
+#include "fold.hpp"
+
 namespace bldtt {
 
 struct DevTree {
@@ -77,13 +79,25 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
 // Symmetric passes (Coulomb, targets = sources): items are tiles of a target
 // cluster A (particles, or proxies of degree item.degree) with entries of
 // partner clusters B (particle ranges, or proxy entries); every kernel value
-// adds to both sides with FP64 atomics: phi (tree order) for particles,
+// counts for both sides.  With out.slots set, item i writes its sums to the
+// slots of its fold (fold.hpp; out.ibase is aligned with `items`) and
+// launch_sym_fold adds them to the outputs in a fixed order, so the result
+// is the same bits every time; with out.slots null, the sums go to the
+// outputs with FP64 atomic adds.  Outputs: phi (tree order) for particles,
 // phihat.p[degree] for proxies, which already hold the other terms.  With
 // fp32 and mfma the squared distances come from the FP64 matrix cores.
 // guarded: the items' entries are all flagged SRC_RANGE_GUARD (else none is).
+struct SymSlots {
+    double* slots;
+    const int64_t* ibase;
+};
 void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem* items, int n_items,
                 const int2* entries, DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat,
-                DegOut phihat, double* nfp64, hipStream_t st);
+                DegOut phihat, double* nfp64, SymSlots out, hipStream_t st);
+
+// out[k] += the parts of every segment (fold.hpp), one work group per segment.
+void launch_sym_fold(const FoldSeg* segs, int n_segs, const FoldPart* parts, const double* slots, double* phi,
+                     DegOut phihat, hipStream_t st);
 
 // One-sided particle-target pass (PP ranges and PC proxies) in FP32 evaluation
 // with the squared distances from the FP64 matrix cores, Coulomb kernel only.

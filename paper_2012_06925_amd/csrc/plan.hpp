@@ -121,6 +121,37 @@ struct DevTreeBufs {
     }
 };
 
+// The list-building walk on the GPU (walk.hip): the centers and radii of
+// both trees, the frontier and scan buffers, and a stream of its own (the walk
+// reads only the trees, so it runs beside the passes queued on the caller's
+// stream).  walk_upload once after the trees are built; traverse_device builds
+// the lists of the walk starting at `roots` (the same result as traverse_roots
+// in traverse.cpp, as sets) into `out`, on the host.
+struct DevWalk {
+    DevBuf tcr, scr;                     // per cluster: center x, y, z, radius
+    DevBuf front[2], blk, tot, ent;
+    PinnedBuf sizes, host_ent;
+    bool aliased = false;
+    hipStream_t stream = nullptr;
+    DevWalk() = default;
+    DevWalk(const DevWalk&) = delete;
+    DevWalk& operator=(const DevWalk&) = delete;
+    ~DevWalk();
+};
+void walk_upload(DevWalk& w, const Tree& T, const Tree& S, bool aliased);
+void traverse_device(DevWalk& w, const DevTree& dT, const DevTree& dS,
+                     const std::vector<std::pair<int64_t, int64_t>>& roots, double theta, int degree, int scheme,
+                     Lists& out, bool defer_separated);
+
+// Device side of a symmetric pass's fold (fold.hpp): slots, slot base per
+// item, segments and parts.
+struct DevFold {
+    DevBuf slots, ibase, segs, parts;
+    int n_segs = 0;
+    SymSlots out() const { return SymSlots{slots.as<double>(), ibase.as<int64_t>()}; }
+    SymSlots out_from(int item) const { return SymSlots{slots.as<double>(), ibase.as<int64_t>() + item}; }
+};
+
 // Host helpers shared by the plan and the batch (capi.cpp).
 void upload_bytes(DevBuf& b, const void* src, size_t n);
 template <class T>
@@ -197,9 +228,12 @@ struct bldtt_plan {
     DevBuf arena, arena_near, arena_rest;                // device side of the per-compute uploads (one copy each)
     uint32_t fill_degrees_last = 0;          // degrees of proxy potentials cleared by the last compute
     hipEvent_t staging_free = nullptr;
-    hipEvent_t prof_ev[2 * BLDTT_N_PHASES] = {};
-    uint32_t prof_mask = 0;                  // phases recorded by the last profiled compute
-    bool prof_pending = false;
+    // BLDTT_PROFILE: a ring of event sets, one per compute not yet folded into the stats
+    static constexpr int kProfRing = 4;
+    hipEvent_t prof_ev[kProfRing][2 * BLDTT_N_PHASES] = {};
+    uint32_t prof_mask[kProfRing] = {};      // phases recorded in each set
+    int prof_cur = 0;                        // the set the next compute records into
+    int prof_pending = 0;                    // sets recorded and not yet folded
     // Per-pair degree form: the near-field PP pass runs on a second stream
     // while the host chooses the degrees (capi.cpp, compute).
     hipStream_t side = nullptr;
@@ -209,6 +243,11 @@ struct bldtt_plan {
     // pass: about 25 ms of that pass on an MI355X
     static constexpr double kEarlyInferencePairs = 1.5e11;
     hipEvent_t ev_select = nullptr;          // the degree choices are on the host
+    // end of the last compute on the caller's stream (a per-pair degree compute
+    // starts once it has passed: its host steps wait on the GPU twice, and two
+    // such computes in flight delay each other)
+    hipEvent_t ev_done = nullptr;
+    bool done_recorded = false;
     bool select_pending = false;
     std::vector<float> log_count_t, log_count_s;   // per cluster: log of its particle count
     PinnedBuf staging_near, staging_rest;
@@ -226,6 +265,8 @@ struct bldtt_plan {
     bool self_ready = false;
     double self_evaluations = 0.0;
     DevBuf sym_items, sym_entries, sym_cc_items, sym_cc_entries;
+    // folds of the symmetric passes: the main PP pass, the CC pass, the leaves' self pairs
+    DevFold fold_pp, fold_cc, fold_self;
     DevBuf model_buf;                        // device copy of the degree model (policy.dev_model)
     // FP32 evaluation: pairs of distinct points the last compute evaluated in
     // FP64 because FP32 coordinates do not resolve them (one device double)
@@ -235,6 +276,9 @@ struct bldtt_plan {
     bool mfma_particle_passes() const {
         return (flags & BLDTT_FP32_EVAL) && kind == BLDTT_COULOMB && mfma_transfer();
     }
+    // BLDTT_DEVICE_TRAVERSAL: the lists of each compute come from the walk on the GPU (walk.hip)
+    DevWalk walk;
+    bool device_walk() const { return !host_only && (flags & BLDTT_DEVICE_TRAVERSAL) != 0; }
     bool symmetric_pp() const {
         return aliased && kind == BLDTT_COULOMB && (flags & BLDTT_ONE_SIDED_PP) == 0;
     }
@@ -249,11 +293,12 @@ struct bldtt_plan {
     }
     ~bldtt_plan() {
         if (staging_free) (void)hipEventDestroy(staging_free);
-        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free, ev_select})
+        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free, ev_select, ev_done})
             if (e) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
-        for (auto& e : prof_ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto& set : prof_ev)
+            for (hipEvent_t e : set)
+                if (e) (void)hipEventDestroy(e);
     }
 };
 

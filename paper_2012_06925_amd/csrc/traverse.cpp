@@ -115,8 +115,7 @@ int scheme_of(uint32_t flags) {
     return (flags & BLDTT_PP_CC_ONLY) ? kSchemePpCc : kSchemeDtt;
 }
 
-void traverse(const Tree& T, const Tree& S, double theta, int degree, int scheme, Lists& out,
-              bool defer_separated) {
+std::vector<std::pair<int64_t, int64_t>> walk_roots(const Tree& T, const Tree& S, int scheme) {
     std::vector<std::pair<int64_t, int64_t>> roots;
     if (scheme == kSchemeBltc) {                // every target batch from the source root
         for (int64_t b = 0; b < T.size(); ++b)
@@ -127,7 +126,12 @@ void traverse(const Tree& T, const Tree& S, double theta, int degree, int scheme
     } else {
         roots.emplace_back(0, 0);
     }
-    traverse_roots(T, S, roots, theta, degree, scheme, out, defer_separated);
+    return roots;
+}
+
+void traverse(const Tree& T, const Tree& S, double theta, int degree, int scheme, Lists& out,
+              bool defer_separated) {
+    traverse_roots(T, S, walk_roots(T, S, scheme), theta, degree, scheme, out, defer_separated);
 }
 
 int64_t append_tree(Tree& f, const Tree& t, int64_t pos0, int64_t caller0) {
@@ -650,8 +654,10 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
             }
         });
         gather(blks, sw.pp_entries, sw.pp_items, sw.pp_evaluations, &sw.pp_plain);
+        fold_bases(sw.pp_items, sw.pp_entries, false, sw.pp_fold);
     }
     if (pp_ready) pp_ready();
+    if (pp) fold_parts(T, sw.pp_items, sw.pp_entries, false, sw.pp_fold);   // needed after the pass only
     // the rest: every entry except both directions of the symmetric pairs,
     // in list order (flags and per-chunk compaction on all threads)
     for (int k = 0; k < 4; ++k) {
@@ -725,7 +731,125 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
             }
         });
         gather(blks, sw.cc_entries, sw.cc_items, sw.cc_evaluations);
+        build_fold(T, sw.cc_items, sw.cc_entries, true, sw.cc_fold);
     }
+}
+
+void build_fold(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
+                SymFold& f) {
+    fold_bases(items, entries, proxies, f);
+    fold_parts(T, items, entries, proxies, f);
+}
+
+void fold_bases(const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies, SymFold& f) {
+    f.clear();
+    const int64_t ni = (int64_t)items.size();
+    // slot bases: per item its targets, then its sources in entry order
+    f.ibase.resize(ni);
+    int64_t slots = 0;
+    for (int64_t i = 0; i < ni; ++i) {
+        const Item& it = items[i];
+        f.ibase[i] = slots;
+        slots += it.tn;
+        if (proxies) {
+            slots += cube(it.degree) * (int64_t)(it.ee - it.eb);
+        } else {
+            for (int32_t e = it.eb; e < it.ee; ++e) slots += (int64_t)(entries[e].b & kCountMask);
+        }
+    }
+    f.nslots = slots;
+}
+
+void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
+                SymFold& f) {
+    f.segs.clear();
+    f.parts.clear();
+    const int64_t ni = (int64_t)items.size(), nc = T.size();
+    constexpr int D = kMaxDegree + 1;
+    // segments: every leaf in cluster order (particles), or every (cluster,
+    // degree) an item or an entry names, by degree then cluster (proxies)
+    std::vector<int32_t> seg_of;
+    std::vector<int64_t> leaf_begin, leaf_id;
+    if (!proxies) {
+        seg_of.assign(nc, -1);
+        for (int64_t c = 0; c < nc; ++c)
+            if (T.is_leaf(c)) {
+                seg_of[c] = (int32_t)f.segs.size();
+                f.segs.push_back(FoldSeg{T.begin[c], (int32_t)T.count[c], -1, 0, 0});
+                leaf_begin.push_back(T.begin[c]);
+                leaf_id.push_back(c);
+            }
+    } else {
+        std::vector<uint8_t> used(nc * D, 0);
+        for (int64_t i = 0; i < ni; ++i) {
+            const Item& it = items[i];
+            used[it.degree * nc + it.cluster] = 1;
+            for (int32_t e = it.eb; e < it.ee; ++e) used[it.degree * nc + entries[e].a] = 1;
+        }
+        seg_of.assign(nc * D, -1);
+        for (int d = 0; d < D; ++d)
+            for (int64_t c = 0; c < nc; ++c)
+                if (used[d * nc + c]) {
+                    seg_of[d * nc + c] = (int32_t)f.segs.size();
+                    f.segs.push_back(FoldSeg{c * cube(d), (int32_t)cube(d), d, 0, 0});
+                }
+    }
+    auto leaf_at = [&](int64_t pos) {
+        const size_t k = (size_t)(std::upper_bound(leaf_begin.begin(), leaf_begin.end(), pos) - leaf_begin.begin()) - 1;
+        return leaf_id[k];
+    };
+    // one item's parts in order: its target tile, then its sources entry by
+    // entry (particle ranges split at leaf boundaries)
+    auto emit = [&](int64_t i, auto&& put) {
+        const Item& it = items[i];
+        int64_t o = f.ibase[i];
+        if (proxies) {
+            const int64_t P = cube(it.degree);
+            put(seg_of[it.degree * nc + it.cluster], FoldPart{o, it.t0, it.tn});
+            o += it.tn;
+            for (int32_t e = it.eb; e < it.ee; ++e, o += P)
+                put(seg_of[it.degree * nc + entries[e].a], FoldPart{o, 0, (int32_t)P});
+            return;
+        }
+        put(seg_of[it.cluster], FoldPart{o, (int32_t)(it.t0 - T.begin[it.cluster]), it.tn});
+        o += it.tn;
+        for (int32_t e = it.eb; e < it.ee; ++e) {
+            const int64_t a = entries[e].a, len = entries[e].b & kCountMask;
+            for (int64_t pos = a; pos < a + len;) {
+                const int64_t L = leaf_at(pos);
+                const int64_t end = std::min(a + len, T.begin[L] + T.count[L]);
+                put(seg_of[L], FoldPart{o + (pos - a), (int32_t)(pos - T.begin[L]), (int32_t)(end - pos)});
+                pos = end;
+            }
+            o += len;
+        }
+    };
+    // parts grouped by segment, chunks of items in order (a parallel counting
+    // sort: chunk k's parts of a segment follow those of chunks < k)
+    const int64_t ns = (int64_t)f.segs.size();
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(4 * num_threads(), ni / 64 + 1));
+    const int64_t per = (ni + nch - 1) / nch;
+    std::vector<int32_t> cnt(nch * ns, 0);
+    parallel_run(nch, [&](int64_t k) {
+        int32_t* c = cnt.data() + k * ns;
+        for (int64_t i = k * per; i < std::min(ni, (k + 1) * per); ++i) emit(i, [&](int32_t sg, const FoldPart&) { c[sg]++; });
+    });
+    int32_t run = 0;
+    for (int64_t sg = 0; sg < ns; ++sg) {
+        f.segs[sg].pb = run;
+        for (int64_t k = 0; k < nch; ++k) {
+            const int32_t n = cnt[k * ns + sg];
+            cnt[k * ns + sg] = run;
+            run += n;
+        }
+        f.segs[sg].pe = run;
+    }
+    f.parts.resize(run);
+    parallel_run(nch, [&](int64_t k) {
+        int32_t* fill = cnt.data() + k * ns;
+        for (int64_t i = k * per; i < std::min(ni, (k + 1) * per); ++i)
+            emit(i, [&](int32_t sg, const FoldPart& pt) { f.parts[fill[sg]++] = pt; });
+    });
 }
 
 }  // namespace bldtt

@@ -113,8 +113,29 @@ def test_model_choice_matches_oracle(case):
     print(f"\n  model choice {case}: degrees {st['pairs_per_degree']} direct {st['sep_direct']} gpu-vs-oracle={err:.2e}")
     assert err < 1e-12 and core.max_rel(phi, ref) < 1e-12
     # a second compute chooses the same degrees and gives the same potentials
+    # (to rounding: it restricts charges the first formed from the particles);
+    # from then on every compute gives the same bits
     phi2 = plan.compute().cpu().numpy()
     assert core.rel_l2(phi2, phi) < 1e-13
+    phi3 = plan.compute().cpu().numpy()
+    assert np.array_equal(phi2, phi3)
+
+
+def test_tuned_form_recompute_is_bit_identical():
+    # the timed tuned form (FP32 evaluation, learned degree, symmetric passes
+    # with their folds): computes after the first give the same bits
+    from paper_2012_06925_amd.train_degree_model import load_model
+    p = inputs.particles(80_000, "uniform", seed=inputs.BASE_SEED + 342)
+    plan = _plan(p, p, True, theta=0.87, degree=8, leaf=400, flags=LEARNED | FP32)
+    plan.set_degree_model(load_model(), fallback=8, tau=7e-7)
+    phis = [plan.compute().cpu().numpy() for _ in range(4)]
+    st = plan.stats()
+    plan.close()
+    assert st["pass_interactions"][2] > 0
+    for later in phis[2:]:
+        assert np.array_equal(phis[1], later)
+    ref = core.bldtt(p, p, theta=0.87, degree=8, leaf=400)
+    assert core.rel_l2(phis[1], ref) < 1e-5
 
 
 def test_fallback_policy_equals_plain_method():
