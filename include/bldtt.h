@@ -88,11 +88,13 @@ enum {
                                       both directions, or of clusters listed as CC in
                                       both directions at one degree, is evaluated once
                                       for both (G is symmetric; a cluster's proxy grid
-                                      is the same as target and as source), with FP64
-                                      atomic adds: the result then varies run to run
-                                      at the rounding level.  FP64 batches of such
-                                      problems evaluate their PP pairs the same way
-                                      unless this flag is set                            */
+                                      is the same as target and as source); its sums
+                                      go to per-item slots that a fold adds in a stored
+                                      order, so every compute gives the same bits.
+                                      FP64 batches of such problems evaluate their PP
+                                      pairs once for both too, with FP64 atomic adds
+                                      (results vary at the rounding level), unless
+                                      this flag is set                                   */
     BLDTT_BLTC = 1u << 9,          /* build the lists of the particle-cluster treecode
                                       (BLTC, Sec. 2.8) instead of Algorithm 2: every
                                       target leaf (a batch) walks the source tree from
