@@ -42,7 +42,7 @@ TARGET_ERR = 1e-6
 FP64_VALU_PEAK = 78.6          # TFLOP/s, MI355X vector FP64
 FP32_VALU_PEAK = 157.3         # TFLOP/s, MI355X vector FP32 (packed)
 FLOPS_PER_EVAL = {"coulomb": 11, "yukawa": 15, "oscillatory": 15, "regcoulomb": 12, "poly": 8}
-KERNEL_SOURCES = ("kernels.hip", "device.hpp")
+KERNEL_SOURCES = ("kernels.hip", "device.hpp", "batch.hip")
 
 
 def log(msg: str) -> None:
@@ -50,7 +50,7 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    """First 16 hex digits of the SHA-256 of the interaction kernel's sources."""
+    """First 16 hex digits of the SHA-256 of the interaction kernels' sources."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2012_06925_amd", "csrc", name), "rb") as f:
@@ -96,7 +96,10 @@ PMC_PASS_NAMES = {
     "plain": {"k_sym<false, false>": ("pp_sym", "pp_self"), "k_sym<false, true>": ("cc_sym",)},
     "tuned": {"k_sym_mfma<false, false>": ("pp_sym",), "k_sym_mfma<false, true>": ("pp_sym", "pp_self"),
               "k_sym_mfma<true, false>": ("cc_sym",)},
+    "batch": {},                # the configuration of the last k_batch dispatch (the timed one)
 }
+# kernels whose records are kept, per mode (batch: every k_batch instance)
+PMC_BATCH_PREFIX = "k_batch<"
 
 
 def summarize_pmc(prefix: str, mode: str) -> None:
@@ -114,6 +117,7 @@ def summarize_pmc(prefix: str, mode: str) -> None:
 
     groups = collections.defaultdict(lambda: collections.defaultdict(list))
     copy = {}
+    last_batch = (-1, None)
     for tag in PMC_PASSES:
         con = sqlite3.connect(f"{prefix}_{tag}/pmc_results.db")
         rows = con.execute("select dispatch_id, kernel_name, grid_size, counter_name, value, duration "
@@ -125,6 +129,8 @@ def summarize_pmc(prefix: str, mode: str) -> None:
             meta[d] = (short(k), g // 256, dur / 1e6)
         for d, cs in per.items():
             k, g, dur = meta[d]
+            if k.startswith(PMC_BATCH_PREFIX) and d > last_batch[0]:
+                last_batch = (d, (k, g))
             groups[(k, g)]["duration_ms"].append(dur)
             for c, v in cs.items():
                 groups[(k, g)][c].append(v)
@@ -133,7 +139,7 @@ def summarize_pmc(prefix: str, mode: str) -> None:
     avg = {key: {c: sum(v) / len(v) for c, v in r.items()} for key, r in groups.items()}
     calib_kib = (1 << 30) / 1024.0          # the 1024 MiB copy of --copy-calib-mib 1024
     scale = {c: calib_kib / copy[c] for c in ("FETCH_SIZE", "WRITE_SIZE")}
-    prec = "fp64" if mode == "plain" else "fp32"
+    prec = "fp64" if mode in ("plain", "batch") else "fp32"
     src_hash = kernel_source_hash()
 
     def derived(a):
@@ -152,13 +158,17 @@ def summarize_pmc(prefix: str, mode: str) -> None:
                 "raw": {c: v for c, v in sorted(a.items()) if c != "duration_ms"}}
 
     passes = collections.defaultdict(list)
+    if mode == "batch" and last_batch[1]:
+        passes["batch"].append(last_batch[1])
     for kname, names in PMC_PASS_NAMES[mode].items():
         keys = sorted((k for k in avg if k[0] == kname), key=lambda k: -avg[k]["duration_ms"])
         for name, key in zip(names, keys):
             passes[name].append(key)
+    run = "--workload batch256 --steps 2 --warmup 1 --no-cpu" if mode == "batch" else \
+        f"--mode {mode} --steps 2 --warmup 1 --no-cpu --no-extras"
     cmd = (f"python3 bench.py --summarize-pmc {prefix} --mode {mode}  (after: cd /tmp && timeout -s KILL 240 "
-           f"rocprofv3 --pmc <PMC_PASSES[X]> -d {prefix}_X -o pmc -- python3 $R/bench.py --mode {mode} --steps 2 "
-           f"--warmup 1 --no-cpu --no-extras [--copy-calib-mib 1024 for C, D], X = A B C D)")
+           f"rocprofv3 --pmc <PMC_PASSES[X]> -d {prefix}_X -o pmc -- python3 $R/bench.py {run} "
+           f"[--copy-calib-mib 1024 for C, D], X = A B C D)")
     for name, keys in passes.items():
         tot = collections.Counter()
         for k in keys:
@@ -442,7 +452,8 @@ def batch_bench(args, wl, name, steps, warmup, with_cpu=True) -> dict:
     achieved = work / (ms * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": "k_batch (every phase, one launch)", "achieved": round(achieved, 3),
             "peak": FP64_VALU_PEAK, "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK, 4),
-            "traffic": None, "flops_per_launch": work, "launch_ms": round(ms, 4), "flops_per_term": fl}
+            "traffic": traffic_for("batch", "fp64"), "flops_per_launch": work, "launch_ms": round(ms, 4),
+            "flops_per_term": fl, "counters": counters_for("batch", "fp64")}
     b.close()
     cpu = None
     if with_cpu:
@@ -626,7 +637,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube1e7")
     ap.add_argument("--n", type=int, default=None, help="override the particle count")
-    ap.add_argument("--mode", default="both", choices=("both", "plain", "fp32", "tuned"))
+    ap.add_argument("--mode", default="both", choices=("both", "plain", "fp32", "tuned", "batch"),
+                    help="batch: only with --summarize-pmc")
     ap.add_argument("--theta", type=float, default=None, help="plain form")
     ap.add_argument("--degree", type=int, default=None, help="plain form")
     ap.add_argument("--tuned-theta", type=float, default=None)
@@ -687,6 +699,14 @@ def main() -> int:
         return 0
     wl = dict(inputs.WORKLOADS[args.workload])
     dev = torch.device("cuda:0")
+    if args.copy_calib_mib:
+        a = torch.empty(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calib_mib} MiB done")
+        del a, b
     if "count" in wl:
         print(json.dumps(batch_bench(args, wl, args.workload, args.steps, args.warmup, not args.no_cpu)), flush=True)
         return 0
@@ -701,14 +721,6 @@ def main() -> int:
     args.tuned_fallback = args.tuned_fallback if args.tuned_fallback is not None else wl.get("tuned_fallback", 8)
     seed = inputs.workload_seed(args.workload)
 
-    if args.copy_calib_mib:
-        a = torch.empty(args.copy_calib_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"calibration copy of {args.copy_calib_mib} MiB done")
-        del a, b
     log(f"generating {M} {wl['dist']} particles")
     p = inputs.particles(M, wl["dist"], seed=seed)
     src = _dev_set(p, dev)

@@ -92,7 +92,7 @@ template <int A, int B>
 constexpr int cmax() { return A > B ? A : B; }
 
 template <int KIND, bool F32, int T, int M>
-__global__ __launch_bounds__(kBlock) void k_batch(BatchDev a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchDev a) {
     constexpr int kLds = cmax<cmax<cmax<interact_lds_bytes<F32>(), up_leaf_lds_bytes<M>()>(), sym_lds_bytes<F32>()>(),
                               cmax<cmax<up_transfer_lds_bytes<M>(), down_transfer_lds_bytes<M>()>(),
                                    down_leaf_lds_bytes<M>()>()>();
