@@ -465,9 +465,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         if (!symm) fork();
         Upload un;
         un.add(pl->near_items, wn.pitems).add(pl->near_entries, wn.pentries);
-        if (symm) add_parts(un, pl->fold_pp, pl->sym.pp_fold);
         un.run(pl->staging_rest, pl->arena_rest, pl->staging_rest_free, pl->side);
-        if (symm) sym_pp_fold(pl->side);    // the symmetric pairs' sums, before the near pass adds
         {
             PhaseMark mark(pl, BLDTT_PH_PPPC, pl->side);
             particle_pass(pl->near_items, (int)wn.pitems.size(), pl->near_entries, symm, pl->side);
@@ -489,6 +487,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     Lists& rest = pl->rest_lists;       // the lists without their symmetric pairs
     if (symm && !varied) {
         split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym, {}, sep_guard);
+        fold_parts(T, pl->sym.pp_items, pl->sym.pp_entries, false, pl->sym.pp_fold);
         drop_self_pairs(rest);
     }
     if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep, {}, sep_guard);
@@ -591,7 +590,17 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             sym_pp_fold(st);
         }
     } else {
+        // the symmetric near-field pairs' fold: its parts are built now, while
+        // the passes run, and it follows the near-field passes (the side
+        // stream's event) on st, before the separated pairs add
+        if (symm) {
+            fold_parts(T, pl->sym.pp_items, pl->sym.pp_entries, false, pl->sym.pp_fold);
+            Upload uf;
+            add_parts(uf, pl->fold_pp, pl->sym.pp_fold);
+            uf.run(pl->staging_fold, pl->arena_fold, pl->staging_fold_free, st);
+        }
         HIPCHK(hipStreamWaitEvent(st, pl->ev_near_done, 0));
+        if (symm) sym_pp_fold(st);
         PhaseMark mark(pl, BLDTT_PH_PPPC_SEP, st);
         particle_pass(pl->sep_items, (int)sep_items.size(), pl->pentries, true, st);
     }
@@ -671,6 +680,7 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     HIPCHK(hipEventCreateWithFlags(&pl->staging_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->staging_near_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->staging_rest_free, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->staging_fold_free, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_near_done, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pl->ev_select, hipEventDisableTiming));
@@ -678,6 +688,7 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     HIPCHK(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
     HIPCHK(hipEventRecord(pl->staging_near_free, st));
     HIPCHK(hipEventRecord(pl->staging_rest_free, st));
+    HIPCHK(hipEventRecord(pl->staging_fold_free, st));
     if (pl->flags & BLDTT_PROFILE)
         for (auto& set : pl->prof_ev)
             for (auto& e : set) HIPCHK(hipEventCreate(&e));

@@ -219,8 +219,10 @@ struct SymWork {
     }
 };
 // pp_ready, when given, is called as soon as the PP items and their slot bases
-// are complete (before their fold's parts, `rest` and the CC items are
-// formed), so their pass can start early.
+// are complete (before `rest` and the CC items are formed), so their pass can
+// start early.  The PP fold's parts are left to the caller (fold_parts: the
+// fold runs after the pass, so they can be built while it runs); the CC
+// fold is built whole.
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
                      const std::function<void()>& pp_ready = {}, bool separate_guarded = false);
 

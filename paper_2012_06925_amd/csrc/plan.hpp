@@ -250,7 +250,9 @@ struct bldtt_plan {
     bool done_recorded = false;
     bool select_pending = false;
     std::vector<float> log_count_t, log_count_s;   // per cluster: log of its particle count
-    PinnedBuf staging_near, staging_rest;
+    PinnedBuf staging_near, staging_rest, staging_fold;
+    DevBuf arena_fold;                       // the symmetric near-field fold's parts (per-pair degree form)
+    hipEvent_t staging_fold_free = nullptr;
     Work work_near;
     DevBuf near_items, near_entries, sep_items;
     // symmetric PP / CC pairs (targets = sources, Coulomb): one evaluation for both directions.
@@ -293,7 +295,8 @@ struct bldtt_plan {
     }
     ~bldtt_plan() {
         if (staging_free) (void)hipEventDestroy(staging_free);
-        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free, ev_select, ev_done})
+        for (hipEvent_t e : {ev_fork, ev_near_done, staging_near_free, staging_rest_free, staging_fold_free, ev_select,
+                             ev_done})
             if (e) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
         for (auto& set : prof_ev)

@@ -657,7 +657,6 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         fold_bases(sw.pp_items, sw.pp_entries, false, sw.pp_fold);
     }
     if (pp_ready) pp_ready();
-    if (pp) fold_parts(T, sw.pp_items, sw.pp_entries, false, sw.pp_fold);   // needed after the pass only
     // the rest: every entry except both directions of the symmetric pairs,
     // in list order (flags and per-chunk compaction on all threads)
     for (int k = 0; k < 4; ++k) {
