@@ -249,6 +249,8 @@ class Bench:
             flags |= _lib.MFMA_LEAF
         if self.args.device_traversal:
             flags |= _lib.DEVICE_TRAVERSAL
+        if not self.args.host_tree:
+            flags |= _lib.DEVICE_TREE
         if mode in ("fp32", "tuned"):
             flags |= _lib.FP32_EVAL
         if mode == "tuned":
@@ -667,6 +669,8 @@ def main() -> int:
     ap.add_argument("--valu-passes", action="store_true",
                     help="run the up/down transfers on the vector ALUs instead of the matrix cores")
     ap.add_argument("--device-traversal", action="store_true", help="build the lists on the GPU (BLDTT_DEVICE_TRAVERSAL)")
+    ap.add_argument("--host-tree", action="store_true",
+                    help="build the trees on the host at setup (default: on the GPU, BLDTT_DEVICE_TREE)")
     ap.add_argument("--mfma-leaf", action="store_true",
                     help="run the leaf contractions on the matrix cores instead of the vector ALUs")
     ap.add_argument("--cpu-problems", type=int, default=16, help="batch workloads: problems in the CPU sample")

@@ -115,7 +115,7 @@ enum {
                                       BLDTT_PP_CC_ONLY exclude each other (EINVAL);
                                       neither treecode takes BLDTT_LEARNED_DEGREE, and
                                       batches take neither (EUNSUPPORTED)               */
-    BLDTT_DEVICE_TRAVERSAL = 1u << 11 /* build each compute's lists on the GPU instead of
+    BLDTT_DEVICE_TRAVERSAL = 1u << 11,/* build each compute's lists on the GPU instead of
                                       the host: one generation of cluster pairs per
                                       step (classify, scan, emit) on a stream of the
                                       plan's own, beside the passes already queued.
@@ -124,6 +124,13 @@ enum {
                                       potentials agree with the host walk's to
                                       rounding.  The host walk is the default: on a
                                       GPU busy with the passes it finishes sooner    */
+    BLDTT_DEVICE_TREE = 1u << 12   /* build the trees at setup on the GPU (the same
+                                      trees, bit for bit, as the host build: the host
+                                      applies the split rule per level, the GPU
+                                      partitions the particles stably and reduces the
+                                      boxes); the particles never leave the device.
+                                      Device plans only (bldtt_setup_host: EINVAL);
+                                      batches: EUNSUPPORTED                            */
 };
 
 /* Particle sets.  Pointers are device pointers for bldtt_setup and host

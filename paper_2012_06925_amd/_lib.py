@@ -21,7 +21,7 @@ KERNELS = {"coulomb": 0, "yukawa": 1, "oscillatory": 2, "regcoulomb": 3, "poly":
 DEFAULT_PARAM = {"coulomb": 0.0, "yukawa": 0.5, "oscillatory": 0.0, "regcoulomb": 0.005, "poly": 0.0}
 FP32_EVAL, LEARNED_DEGREE, SYNC, PROFILE, PP_CC_ONLY, AUTOTUNE, VALU_PASSES, MFMA_LEAF, ONE_SIDED_PP = (
     1, 2, 4, 8, 16, 32, 64, 128, 256)
-BLTC, CP_BLTC, DEVICE_TRAVERSAL = 512, 1024, 2048
+BLTC, CP_BLTC, DEVICE_TRAVERSAL, DEVICE_TREE = 512, 1024, 2048, 4096
 PHASES = ("up", "cp_cc", "down_transfer", "pp_pc", "down_leaf", "pp_pc_sep", "pp_sym", "pp_self")
 TYPES = ("PP", "PC", "CP", "CC")
 

@@ -34,6 +34,7 @@ UNITS = [
     ("kernels.hip", DEVICE, "kernels"),
     ("mlp.hip", DEVICE, "mlp"),
     ("walk.hip", DEVICE + HOST_EXACT, "walk"),
+    ("treebuild.hip", DEVICE + HOST_EXACT, "treebuild"),
 ] + [("batch.hip", DEVICE + [f"-DBATCH_PART={k}"], f"batch{k}") for k in range(6)] + [
     ("degree.cpp", HOST_EXACT + HIP_HOST, "degree"),
     ("tree.cpp", HOST_EXACT, "tree"),

@@ -473,8 +473,9 @@ std::unique_ptr<bldtt_batch> new_batch(int32_t count, const bldtt_particles* pro
         all_alias = all_alias && p.M == p.N && p.tx == p.sx && p.ty == p.sy && p.tz == p.sz;
     }
     if (sm >= INT32_MAX || sn >= INT32_MAX) throw Error(BLDTT_EINVAL, "the sums of M and of N must be < 2^31");
-    if (flags & (BLDTT_LEARNED_DEGREE | BLDTT_PROFILE | BLDTT_BLTC | BLDTT_CP_BLTC))
-        throw Error(BLDTT_EUNSUPPORTED, "the batch runs the dual tree traversal at one fixed degree and has no phase profile");
+    if (flags & (BLDTT_LEARNED_DEGREE | BLDTT_PROFILE | BLDTT_BLTC | BLDTT_CP_BLTC | BLDTT_DEVICE_TREE))
+        throw Error(BLDTT_EUNSUPPORTED, "the batch builds its trees on the host, runs the dual tree traversal at one fixed "
+                                        "degree and has no phase profile");
     auto b = std::make_unique<bldtt_batch>();
     b->kind = kernel;
     b->param = kernel_param;

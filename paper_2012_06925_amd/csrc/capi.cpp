@@ -622,9 +622,10 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     mark_host(3);
 }
 
-void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
-    double t0 = now_ms();
-    HIPCHK(hipStreamSynchronize(st));
+// Trees built on the host: the particles copied down, the trees built, the
+// permuted particles copied up.
+void setup_host_tree(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
+    (void)st;
     const int64_t M = p->M, N = p->N;
     std::vector<double> hs[4], ht[3];
     for (int k = 0; k < 4; ++k) hs[k].resize(N);
@@ -654,6 +655,32 @@ void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
         upload(pl->ty, txs[1]);
         upload(pl->tz, txs[2]);
         upload_tree(pl->dTsep, pl->Tsep);
+    }
+}
+
+void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
+    double t0 = now_ms();
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t M = p->M, N = p->N;
+    if (pl->flags & BLDTT_DEVICE_TREE) {
+        // trees built on the GPU (treebuild.hip): the particles never leave the device
+        const double* src[4] = {p->sx, p->sy, p->sz, p->q};
+        if (!all_finite_device(src, 4, N, st)) throw Error(BLDTT_EINVAL, "non-finite source coordinate or charge");
+        if (!pl->aliased) {
+            const double* tgt[3] = {p->tx, p->ty, p->tz};
+            if (!all_finite_device(tgt, 3, M, st)) throw Error(BLDTT_EINVAL, "non-finite target coordinate");
+        }
+        DevBuf sidx, tidx;
+        build_tree_device(N, p->sx, p->sy, p->sz, pl->leaf, pl->S, pl->sx, pl->sy, pl->sz, sidx, st);
+        gather_device(p->q, sidx, N, pl->sq, st);
+        upload_tree(pl->dS, pl->S);
+        if (!pl->aliased) {
+            build_tree_device(M, p->tx, p->ty, p->tz, pl->leaf, pl->Tsep, pl->tx, pl->ty, pl->tz, tidx, st);
+            upload_tree(pl->dTsep, pl->Tsep);
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    } else {
+        setup_host_tree(pl, p, st);
     }
     const Tree& T = pl->T();
     std::vector<int32_t> perm(M);
@@ -813,6 +840,7 @@ int bldtt_setup_host(bldtt_plan** out, const bldtt_particles* p, int32_t kernel,
     }
     *out = nullptr;
     return guarded([&] {
+        if (flags & BLDTT_DEVICE_TREE) throw Error(BLDTT_EINVAL, "BLDTT_DEVICE_TREE needs a device plan");
         std::unique_ptr<bldtt_plan> pl(new_plan(p, kernel, kernel_param, theta, degree, leaf_size, flags));
         pl->host_only = true;
         double t0 = now_ms();

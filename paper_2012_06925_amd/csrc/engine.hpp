@@ -51,6 +51,25 @@ struct Tree {
 void build_tree(int64_t n, const double* x, const double* y, const double* z, int64_t leaf, Tree& t,
                 std::vector<double>& xs, std::vector<double>& ys, std::vector<double>& zs);
 
+// The split rules of the build, shared by the host build and the GPU build
+// (treebuild.hip): which dimensions of a cluster with box [lo, hi] and cnt
+// particles are split (bit d for dimension d; 0 = the cluster is a leaf).
+int split_mask(const double lo[3], const double hi[3], int64_t cnt, int64_t leaf);
+
+// A cluster of a tree under construction: box, particle range [b, e), level,
+// children (indices into the same array, in increasing child code).
+struct BuildNode {
+    double lo[3], hi[3];
+    int64_t b, e;
+    int32_t level;
+    int32_t nchild;
+    int64_t child[8];
+};
+
+// The tree of `nodes` (node 0 the root) numbered in depth-first preorder, with
+// perm[p] = the caller index at tree position p.
+void tree_from_nodes(const std::vector<BuildNode>& nodes, int64_t n, std::vector<int64_t> perm, Tree& t);
+
 // ---------------------------------------------------------------------------
 // Dual tree traversal (Algorithm 2) into the four interaction lists.
 // ---------------------------------------------------------------------------

@@ -152,6 +152,17 @@ struct DevFold {
     SymSlots out_from(int item) const { return SymSlots{slots.as<double>(), ibase.as<int64_t>() + item}; }
 };
 
+// The trees built on the GPU (treebuild.hip, BLDTT_DEVICE_TREE): the same
+// tree as build_tree (tree.cpp) from device coordinates in caller order; on
+// return xs, ys, zs hold the coordinates in tree order and idx (int32) the
+// caller index at each tree position, all on the device.
+void build_tree_device(int64_t n, const double* x, const double* y, const double* z, int64_t leaf, Tree& t,
+                       DevBuf& xs, DevBuf& ys, DevBuf& zs, DevBuf& idx, hipStream_t st);
+// Whether every value of `count` device arrays of n doubles is finite.
+bool all_finite_device(const double* const* arrays, int count, int64_t n, hipStream_t st);
+// to[i] = from[idx[i]] on the device (to allocated here).
+void gather_device(const double* from, const DevBuf& idx, int64_t n, DevBuf& to, hipStream_t st);
+
 // Host helpers shared by the plan and the batch (capi.cpp).
 void upload_bytes(DevBuf& b, const void* src, size_t n);
 template <class T>

@@ -148,6 +148,8 @@ struct BuildBufs {
     int64_t leaf;
 };
 
+}  // namespace
+
 // Which dimensions to split; 0 means the cluster is a leaf.
 int split_mask(const double lo[3], const double hi[3], int64_t cnt, int64_t leaf) {
     double L[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
@@ -168,6 +170,8 @@ int split_mask(const double lo[3], const double hi[3], int64_t cnt, int64_t leaf
     }
     return mask;
 }
+
+namespace {
 
 inline int code_of(const BuildBufs& w, int64_t p, int mask, const double mid[3]) {
     int c = 0;
@@ -332,6 +336,42 @@ struct Builder {
 };
 
 }  // namespace
+
+void tree_from_nodes(const std::vector<BuildNode>& nodes, int64_t n, std::vector<int64_t> perm, Tree& t) {
+    const int64_t total = (int64_t)nodes.size();
+    t = Tree();
+    t.n_particles = n;
+    t.lo.resize(3 * total); t.hi.resize(3 * total); t.center.resize(3 * total);
+    t.radius.resize(total);
+    t.begin.resize(total); t.count.resize(total); t.parent.resize(total);
+    t.child.assign(8 * total, -1);
+    t.level.resize(total); t.nchild.resize(total);
+    int64_t next = 0;
+    int32_t depth = 0;
+    std::function<int64_t(int64_t, int64_t)> emit = [&](int64_t li, int64_t par) -> int64_t {
+        const BuildNode& nd = nodes[li];
+        int64_t g = next++;
+        double L[3];
+        for (int d = 0; d < 3; ++d) {
+            t.lo[3 * g + d] = nd.lo[d];
+            t.hi[3 * g + d] = nd.hi[d];
+            t.center[3 * g + d] = 0.5 * (nd.lo[d] + nd.hi[d]);
+            L[d] = nd.hi[d] - nd.lo[d];
+        }
+        t.radius[g] = 0.5 * std::sqrt((L[0] * L[0] + L[1] * L[1]) + L[2] * L[2]);
+        t.begin[g] = nd.b;
+        t.count[g] = nd.e - nd.b;
+        t.parent[g] = par;
+        t.level[g] = nd.level;
+        t.nchild[g] = nd.nchild;
+        if (nd.level > depth) depth = nd.level;
+        for (int k = 0; k < nd.nchild; ++k) t.child[8 * g + k] = emit(nd.child[k], g);
+        return g;
+    };
+    emit(0, -1);
+    t.depth = depth;
+    t.perm = std::move(perm);
+}
 
 void build_tree(int64_t n, const double* x, const double* y, const double* z, int64_t leaf, Tree& t,
                 std::vector<double>& xs, std::vector<double>& ys, std::vector<double>& zs) {

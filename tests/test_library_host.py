@@ -117,6 +117,16 @@ def test_treecode_flag_errors():
         assert e.value.code == _lib.EUNSUPPORTED
 
 
+def test_device_tree_flag_needs_a_device_plan():
+    p = inputs.particles(2000, seed=38)
+    with pytest.raises(_lib.BldttError) as e:
+        api.HostPlan(None, (p.x, p.y, p.z, p.q), theta=0.7, degree=3, leaf=100, flags=_lib.DEVICE_TREE)
+    assert e.value.code == _lib.EINVAL
+    with pytest.raises(_lib.BldttError) as e:
+        api.HostBatch([(None, (p.x, p.y, p.z, p.q))] * 2, theta=0.7, degree=3, leaf=100, flags=_lib.DEVICE_TREE)
+    assert e.value.code == _lib.EUNSUPPORTED
+
+
 def test_large_tree_parallel_build_bit_exact():
     # above the serial cutoff: the multi-threaded partition must give the same tree
     p = inputs.particles(400_000, "gaussian", seed=33)

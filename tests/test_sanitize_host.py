@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2012_06925_amd", "csrc")
 SAN = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", "-g", "-O1"]
 HOST_UNITS = ("capi", "batch_host", "tree", "traverse", "degree", "tune")
-DEVICE_OBJECTS = ("kernels", "mlp", "walk") + tuple(f"batch{k}" for k in range(6))
+DEVICE_OBJECTS = ("kernels", "mlp", "walk", "treebuild") + tuple(f"batch{k}" for k in range(6))
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
