@@ -8,17 +8,24 @@
 //   [up_xfer]  proxy charges of each source parent, deepest level first
 //   [q item]   CP + CC sums into target proxies (needs the upward pass)
 //   [c item]   FP64 batches of targets = sources problems (Coulomb): pairs of
-//              clusters listed as CC both ways, once for both; the proxy
-//              potentials start from zero and both kinds of item add with
-//              atomics; each item counts for its cluster and its partners
+//              clusters listed as CC both ways, once for both; the sums go to
+//              the item's slots (fold.hpp); each item counts for its cluster
+//              and its partners
 //   [p item]   PP + PC sums into target particles (PC needs the upward pass)
 //   [s item]   FP64 batches of targets = sources problems (Coulomb): pairs of
-//              distinct leaves listed as PP both ways, once for both; the
-//              particle sums start from zero and both kinds of item add with
-//              atomics, so they need no order between them
-//   [dn_xfer]  parent-to-child proxy potentials, shallowest level first (Sec. 2.7)
-//   [final]    leaf interpolation plus the PP/PC part, to the caller's buffers
-//              (after every symmetric item of its problem)
+//              distinct leaves listed as PP both ways, once for both, into
+//              the item's slots
+//   [dn_xfer]  a cluster's symmetric CC slots folded into its proxy
+//              potentials in their stored order, then parent-to-child proxy
+//              potentials, shallowest level first (Sec. 2.7)
+//   [final]    a particle item's symmetric PP slots folded into its targets'
+//              sums, then leaf interpolation plus the PP/PC part, to the
+//              caller's buffers (after every symmetric item of its problem)
+//
+// The one-way items each own their outputs (one proxy item per proxy, one
+// particle item per target), which start from zero and take one atomic add;
+// every symmetric sum arrives through a fold in a fixed order, so a launch
+// gives the same bits every time.
 //
 // Work groups take task numbers from a ticket counter, so a task starts only
 // after every smaller number has been taken by a running work group: waits
@@ -146,7 +153,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
                     up_seen = true;
                 }
-                sym_body<false, true>(it, a.centries, a.src, a.S, nullptr, a.tab_all, a.qp, a.po, pool);
+                sym_body<false, true>(it, a.centries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.cslots,
+                                      a.cbase[t - eq]);
                 signal_clusters(a.dn, it.cluster, a.centries, it.eb, it.ee);
             }
         } else if (t < e3) {
@@ -162,13 +170,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         } else if (t < es) {
             if constexpr (!F32 && KIND == K_COULOMB) {
                 const DevItem it = a.sitems[t - e3];
-                sym_body<false, false>(it, a.sentries, a.src, a.S, a.phi_tree, a.tab_all, a.qp, a.po, pool);
+                sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
+                                       a.sbase[t - e3]);
                 signal(a.sdone + a.prob[it.cluster]);
             }
         } else if (t < e4) {
             const int c = a.kids[t - es];
             const int par = a.T.parent[c];
             wait2(a, a.dn + par, a.nq[par] + (a.T.parent[par] >= 0 ? 1 : 0), a.dn + c, a.nq[c]);
+            if (a.n_c > 0 && a.cseg[c] >= 0) {
+                const FoldSeg sg = a.csegs[a.cseg[c]];
+                fold_body(sg, a.cparts, a.cslots, a.phihat + sg.off, 0, sg.n);
+                __syncthreads();              // the transfer reads what other threads folded
+            }
             down_transfer_body<M>(c, a.T, a.tab, a.phihat, dl);
             signal(a.dn + c);
         } else {
@@ -178,6 +192,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const int prob = a.prob[c];
             if (a.n_s > 0) wait2(a, a.sdone + prob, a.s_need[prob], nullptr, 0);
             wait2(a, a.pdone + i, 1, a.dn + c, a.nq[c] + (a.T.parent[c] >= 0 ? 1 : 0));
+            if (a.n_s > 0 && a.pseg[i] >= 0) {
+                const FoldSeg sg = a.psegs[a.pseg[i]];
+                const int k0 = it.t0 - (int)sg.off;
+                fold_body(sg, a.pparts, a.sslots, a.phi_tree + sg.off, k0, k0 + it.tn);
+                __syncthreads();              // the interpolation reads what other threads folded
+            }
             down_leaf_body<M>(it, a.has_far[c] != 0, a.tgt, a.T, a.tab, a.phihat, a.phi_tree, a.perm,
                               a.outs[prob], a.caller0[prob], dl);
             __syncthreads();                  // LDS is reused by the next task

@@ -52,6 +52,9 @@ struct bldtt_batch {
     const DevTreeBufs& dT() const { return aliased ? dS : dTt; }
     DevBuf leaves, parents, kids, qitems, qentries, qneeds, pitems, pentries, pneeds, has_far, nq, prob, caller0_d,
         outs, counters, sitems, sentries, s_need, citems, centries;
+    // folds of the symmetric items: slots, slot bases, segments, parts, and the
+    // segment of each particle item (PP) and of each target cluster (CC)
+    DevBuf sslots, sbase, psegs, pparts, pseg, cslots, cbase, csegs, cparts, cseg;
     int n_leaves = 0, n_parents = 0, n_kids = 0;
     int64_t n_counters = 0;
     PinnedBuf outs_host;
@@ -234,6 +237,52 @@ void traverse_forest(bldtt_batch* b) {
     b->stats.traverse_ms = now_ms() - t0;
 }
 
+// The symmetric items' folds (fold.hpp) for the batch kernel: the PP
+// segments are the leaves, each folded by the final task of the particle item
+// that owns the targets; the CC segments are the clusters, each folded by the
+// downward task of the cluster before its parent's potentials are added.
+void upload_folds(bldtt_batch* b) {
+    const Tree& T = b->T();
+    const Work& w = b->work;
+    SymFold& pf = b->sym.pp_fold;
+    SymFold& cf = b->sym.cc_fold;
+    fold_parts(T, b->sym.pp_items, b->sym.pp_entries, false, pf);
+    // the PP segments are the leaves in cluster order
+    std::vector<int32_t> leaf_seg(T.size(), -1);
+    size_t k = 0;
+    for (int64_t c = 0; c < T.size(); ++c) {
+        if (!T.is_leaf(c)) continue;
+        if (k >= pf.segs.size() || pf.segs[k].off != T.begin[c])
+            throw Error(BLDTT_EDEVICE, "batch: internal error, the PP fold segments are not the leaves");
+        if (pf.segs[k].pe > pf.segs[k].pb) leaf_seg[c] = (int32_t)k;
+        ++k;
+    }
+    std::vector<int32_t> pseg(w.pitems.size(), -1);
+    for (size_t i = 0; i < w.pitems.size(); ++i) pseg[i] = leaf_seg[w.pitems[i].cluster];
+    std::vector<int32_t> cseg(T.size(), -1);
+    const int64_t P = b->P();
+    for (size_t k = 0; k < cf.segs.size(); ++k) {
+        const FoldSeg& sg = cf.segs[k];
+        if (sg.deg != b->degree || sg.off % P != 0)
+            throw Error(BLDTT_EDEVICE, "batch: internal error, a CC fold segment is not of the batch degree");
+        const int64_t c = sg.off / P;
+        // every CC pair lies below the roots (the two clusters of a pair are
+        // separated, and no cluster is separated from its own root)
+        if (T.parent[c] < 0) throw Error(BLDTT_EDEVICE, "batch: internal error, a root has symmetric CC sums");
+        cseg[c] = (int32_t)k;
+    }
+    b->sslots.alloc(sizeof(double) * std::max<int64_t>(1, pf.nslots));
+    upload(b->sbase, pf.ibase);
+    upload(b->psegs, pf.segs);
+    upload(b->pparts, pf.parts);
+    upload(b->pseg, pseg);
+    b->cslots.alloc(sizeof(double) * std::max<int64_t>(1, cf.nslots));
+    upload(b->cbase, cf.ibase);
+    upload(b->csegs, cf.segs);
+    upload(b->cparts, cf.parts);
+    upload(b->cseg, cseg);
+}
+
 // Work items for tile size tpt, their flags and the per-cluster counts.
 void pack(bldtt_batch* b, int tpt) {
     if (b->packed_tpt_valid && b->packed_tpt == tpt) return;
@@ -288,6 +337,7 @@ void pack(bldtt_batch* b, int tpt) {
     std::vector<int32_t> s_need(b->count, 0);
     for (const Item& it : b->sym.pp_items) s_need[b->prob_of_cluster[it.cluster]] += 1;
     upload(b->s_need, s_need);
+    if (b->symmetric()) upload_folds(b);
     b->n_counters = kGlobalCounters + b->S.size() + b->T().size() + (int64_t)w.pitems.size() + b->count;
     b->counters.alloc(sizeof(int32_t) * b->n_counters);
 }
@@ -338,6 +388,18 @@ BatchDev device_args(const bldtt_batch* b) {
     a.citems = b->citems.as<DevItem>();
     a.centries = b->centries.as<int2>();
     a.n_c = (int)b->sym.cc_items.size();
+    if (b->symmetric()) {
+        a.sslots = b->sslots.as<double>();
+        a.sbase = b->sbase.as<int64_t>();
+        a.psegs = b->psegs.as<FoldSeg>();
+        a.pparts = b->pparts.as<FoldPart>();
+        a.pseg = b->pseg.as<int32_t>();
+        a.cslots = b->cslots.as<double>();
+        a.cbase = b->cbase.as<int64_t>();
+        a.csegs = b->csegs.as<FoldSeg>();
+        a.cparts = b->cparts.as<FoldPart>();
+        a.cseg = b->cseg.as<int32_t>();
+    }
     a.n_kids = b->n_kids;
     a.n_tasks = a.n_leaves + a.n_parents + a.n_q + a.n_c + 2 * a.n_p + a.n_s + a.n_kids;
     a.spin_limit = b->spin_limit;

@@ -347,11 +347,9 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         const int n = (int)sw.pp_items.size(), n0 = (int)sw.pp_plain;
         const DevFold& f = pl->fold_pp;
         launch_sym(fp32, pl->mfma_transfer(), false, false, items.as<DevItem>(), n0, entries.as<int2>(), pl->dsrc(),
-                   dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64,
-                   f.out(), s);
+                   dS, tab, deg_ptrs(pl->qhat_deg), nfp64, f.out(), s);
         launch_sym(fp32, pl->mfma_transfer(), false, true, items.as<DevItem>() + n0, n - n0, entries.as<int2>(),
-                   pl->dsrc(), dS, pl->phi_tree.as<double>(), tab, deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg),
-                   nfp64, f.out_from(n0), s);
+                   pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg), nfp64, f.out_from(n0), s);
     };
     auto sym_pp_fold = [&](hipStream_t s) {
         const DevFold& f = pl->fold_pp;
@@ -407,8 +405,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         particle_pass(pl->self_items, pl->n_self_items, pl->self_entries, false, st);
         const DevFold& f = pl->fold_self;
         launch_sym(fp32, pl->mfma_transfer(), false, true, pl->self_sym_items.as<DevItem>(), pl->n_self_sym_items,
-                   pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, pl->phi_tree.as<double>(), tab,
-                   deg_ptrs(pl->qhat_deg), deg_out(pl->phihat_deg), nfp64, f.out(), st);
+                   pl->self_sym_entries.as<int2>(), pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg), nfp64, f.out(), st);
         launch_sym_fold(f.segs.as<FoldSeg>(), f.n_segs, f.parts.as<FoldPart>(), f.slots.as<double>(),
                         pl->phi_tree.as<double>(), DegOut{}, st);
     }
@@ -558,8 +555,8 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         if (symm) {             // symmetric CC pairs add to the proxy potentials the pass above wrote
             const DevFold& f = pl->fold_cc;
             launch_sym(fp32, pl->mfma_transfer(), true, false, pl->sym_cc_items.as<DevItem>(), (int)scc.cc_items.size(),
-                       pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, nullptr, tab, deg_ptrs(pl->qhat_deg),
-                       deg_out(pl->phihat_deg), nullptr, f.out(), st);
+                       pl->sym_cc_entries.as<int2>(), pl->dsrc(), dS, tab, deg_ptrs(pl->qhat_deg), nullptr, f.out(),
+                       st);
             launch_sym_fold(f.segs.as<FoldSeg>(), f.n_segs, f.parts.as<FoldPart>(), f.slots.as<double>(), nullptr,
                             deg_out(pl->phihat_deg), st);
         }

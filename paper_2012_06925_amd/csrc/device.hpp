@@ -7,6 +7,7 @@
 //   interact_body       PP/PC sums into particles, CP/CC sums into proxies
 //   up_leaf_body        proxy charges of a source leaf, Eq. (proxy-charges)
 //   up_transfer_body    parent proxy charges from the children (Sec. 2.5, Appendix B)
+//   fold_body           fixed-order sums of the symmetric passes' slots (fold.hpp)
 //   down_transfer_body  parent-to-child interpolation of proxy potentials (Sec. 2.7, Appendix C)
 //   down_leaf_body      leaf proxies to targets plus the PP/PC part, caller order
 #pragma once
@@ -511,6 +512,40 @@ __device__ __forceinline__ void up_transfer_body(int c, DevTree S, const double*
     for (int k = threadIdx.x; k < P; k += kBlock) qhat[(int64_t)c * P + k] = acc[k];
 }
 
+// Outputs [k0, k1) of fold segment sg (fold.hpp; out points at the segment's
+// output 0): each adds the slots of its parts in their stored order, so the
+// sums do not depend on which item finished first.  The group's threads share
+// the outputs; the caller synchronises before other threads read them.  The
+// parts go eight at a time: eight independent loads (a part that does not
+// cover the output reads its own first slot, which exists, and is not added),
+// then the eight adds in order.
+__device__ __forceinline__ void fold_body(const FoldSeg& sg, const FoldPart* __restrict__ parts,
+                                          const double* __restrict__ slots, double* __restrict__ out, int k0, int k1) {
+    constexpr int U = 8;
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) {
+        double v = 0.0;
+        int q = sg.pb;
+        for (; q + U <= sg.pe; q += U) {
+            double s[U];
+            bool in[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const FoldPart pt = parts[q + u];
+                const unsigned r = (unsigned)(k - pt.lo);
+                in[u] = r < (unsigned)pt.len;
+                s[u] = slots[pt.slot + (in[u] ? r : 0u)];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) v = in[u] ? v + s[u] : v;
+        }
+        for (; q < sg.pe; ++q) {
+            const FoldPart pt = parts[q];
+            if (k >= pt.lo && k < pt.lo + pt.len) v += slots[pt.slot + (k - pt.lo)];
+        }
+        out[k] += v;
+    }
+}
+
 template <int M>
 constexpr int down_transfer_lds_bytes() { return (int)sizeof(double) * (3 * M * M + 2 * M * M * M); }
 
@@ -839,9 +874,9 @@ __device__ __forceinline__ void down_leaf_mfma_body(const DevItem& it, bool far,
 // partial that moves one lane down per step (DPP wave_rol:1: lane l receives
 // lane l + 1), so after 64 steps lane l holds the partial of source (l - 1)
 // mod 64 over the targets of its wave.  The wave partials are summed in LDS
-// and added to the source's output with one FP64 atomic per source; each target's sum is added
-// with one atomic at the end.  Results are reproducible to rounding only: the
-// order of the atomics varies.  PP ranges flagged SRC_RANGE_GUARD (a leaf
+// and written to the source's slot of the entry, each target's sum to its
+// slot at the end (fold.hpp): a fold adds the slots to the outputs in a fixed
+// order, so the result is the same bits every run.  PP ranges flagged SRC_RANGE_GUARD (a leaf
 // with itself, or leaf boxes within 2^-20 of their extent) skip r^2 == 0
 // (coincident points; FP32 relative coordinates of two close points may round
 // together); elsewhere the gap between the boxes keeps r^2 > 0.  CC pairs are
@@ -858,29 +893,29 @@ constexpr float kFar = 1e18f;            // padding lanes sit here with charge 0
 
 template <bool F32>
 constexpr int sym_lds_bytes() {
-    return 4 * 128 * (int)sizeof(typename std::conditional<F32, float4, double4>::type) + 4 * 64 * (int)sizeof(double);
+    return 4 * 128 * (int)sizeof(typename std::conditional<F32, float4, double4>::type) + 4 * 64 * (int)sizeof(double) +
+           4 * 64 * (int)sizeof(int);
 }
 
 // One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  Each lane
 // holds H targets (rows 64 h + lane of its wave's 64 H), so a staged source and
 // the move of its partial serve H pairs.  An item whose targets fill nslab = 1
 // or 2 waves runs 4 / nslab copies of those waves, each over its own 64 of the
-// 64 * copies sources staged per round.  With slots (the deterministic form)
-// the copies' target sums are added in copy order in LDS and each target's
-// total written to its slot, as is each source's partial per entry; without,
-// every copy adds its target partials, and the sources' partials, with FP64
-// atomics.
+// 64 * copies sources staged per round.  The copies' target sums are added in
+// copy order in LDS and each target's total written to slots[base + r]; each
+// source's partial goes to its slot of the entry (after the targets, entry
+// by entry).
 template <bool F32, bool PROXY, int H = 2>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
-                                         DevTree T, double* __restrict__ phi, const double* __restrict__ tab,
-                                         DegPtrs qhat, DegOut phihat, void* lds, double* nfp64 = nullptr,
-                                         double* __restrict__ slots = nullptr, int64_t base = 0) {
+                                         DevTree T, const double* __restrict__ tab, DegPtrs qhat, void* lds,
+                                         double* nfp64, double* __restrict__ slots, int64_t base) {
     using R = typename std::conditional<F32, float, double>::type;
     using V = typename std::conditional<F32, float4, double4>::type;
     // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
     constexpr R qs = F32 ? (R)1 : (R)0.5;
     V* src = static_cast<V*>(lds);                               // per copy: 64 staged sources, twice
     double (*part_red)[64] = reinterpret_cast<double (*)[64]>(src + 4 * 128);  // [4][64] wave partials
+    int* sidx = reinterpret_cast<int*>(part_red + 4);            // [4 * 64] staged particle index, -1: none
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nslab = it.tn <= 64 * H ? 1 : 2;
     const int copies = 4 / nslab, copy = wave / nslab, sw = wave % nslab;
@@ -893,7 +928,6 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     // proxies: degree of the item, grid size, per-degree tables and arrays
     const int m = it.degree + 1, P = m * m * m;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
-    double* od = PROXY ? phihat.p[it.degree] : nullptr;
     R tx[H], ty[H], tz[H];
     double qi[H];               // FP32 form: the charge rounded to FP32, held in FP64
     int ti[H];
@@ -926,129 +960,139 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     double acc[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) acc[h] = 0.0;
-    int64_t run = base + it.tn;                            // slots of the current entry's sources
-    for (int e = it.eb; e < it.ee; ++e) {
-        const int2 en = entries[e];
-        const int low = en.y & ((1 << 29) - 1);
-        const int bn = PROXY ? P : low;                    // proxy entries: en.x = cluster B
-        // r^2 == 0 test only on ranges flagged SRC_RANGE_GUARD (a leaf with
-        // itself, or near leaf boxes); elsewhere the boxes keep the pairs apart
-        const bool guard = !PROXY && ((unsigned)en.y >> 29) == 1u;
-        const double* sbox = T.box + 6 * en.x;
-        for (int c0 = 0; c0 < bn; c0 += span) {
-            __syncthreads();
-            if (tid < span) {
-                V v{(R)kFar, (R)kFar, (R)kFar, (R)0};
-                if (c0 + tid < bn) {
-                    double x, y, z, q;
-                    if constexpr (PROXY) {
-                        proxy_point(sbox, m, tab + 32 * it.degree, c0 + tid, x, y, z);
-                        q = qd[(int64_t)en.x * P + c0 + tid];
-                    } else {
-                        const int j = en.x + c0 + tid;
-                        x = p.x[j];
-                        y = p.y[j];
-                        z = p.z[j];
-                        q = p.q[j];
-                    }
-                    v = V{(R)(x - cx), (R)(y - cy), (R)(z - cz), (R)(qs * q)};
-                }
-                V* dst = src + 128 * (tid >> 6) + (tid & 63);
-                dst[0] = v;
-                dst[64] = v;
+    // The item's sources are its entries' sources one after another, the
+    // order of their slots (after the targets'); rounds of `span` run across
+    // entry boundaries, so only the last round has idle lanes.
+    constexpr int kLow = (1 << 29) - 1;
+    int G = 0;
+    for (int e = it.eb; e < it.ee; ++e) G += PROXY ? P : (entries[e].y & kLow);
+    int ec = it.eb, oc = 0;                                // entry and offset of the round's first source
+    for (int r0 = 0; r0 < G; r0 += span) {
+        // where the next round starts; the round guards r^2 == 0 if any entry
+        // it touches is flagged SRC_RANGE_GUARD (a leaf with itself, or near
+        // leaf boxes): elsewhere the boxes keep the pairs apart
+        bool guard = false;
+        int e1 = ec, o1 = oc + span;
+        while (e1 < it.ee) {
+            const int2 en = entries[e1];
+            guard |= !PROXY && ((unsigned)en.y >> 29) == 1u;
+            const int bn = PROXY ? P : (en.y & kLow);
+            if (o1 < bn) break;
+            o1 -= bn;
+            ++e1;
+        }
+        __syncthreads();
+        if (tid < span) {
+            V v{(R)kFar, (R)kFar, (R)kFar, (R)0};
+            int j = -1;
+            int e = ec, o = oc + tid;
+            int2 en = make_int2(0, 0);
+            while (e < it.ee) {
+                en = entries[e];
+                const int bn = PROXY ? P : (en.y & kLow);
+                if (o < bn) break;
+                o -= bn;
+                ++e;
             }
-            __syncthreads();
-            double psi = 0.0;
-            if (active) {
-                double sum[H];
-#pragma unroll
-                for (int h = 0; h < H; ++h) sum[h] = 0.0;
-                // 64 steps: lane l pairs its H targets with source (l + s) mod 64;
-                // every term goes to FP64 sums
-                auto step = [&](int s, auto guard) {
-                        const V v = mysrc[lane + s];
-                        double y[H];
-#pragma unroll
-                        for (int h = 0; h < H; ++h) {
-                            const R dx = tx[h] - v.x, dy = ty[h] - v.y, dz = tz[h] - v.z;
-                            R r2 = dz * dz;
-                            r2 = dy * dy + r2;
-                            r2 = dx * dx + r2;
-                            if constexpr (F32) {
-                                y[h] = (double)__builtin_amdgcn_rsqf(r2);
-                                if constexpr (!PROXY && decltype(guard)::value) {
-                                    if (r2 <= thr32) {       // closer than FP32 resolves: FP64
-                                        const int sj = c0 + 64 * copy + ((lane + s) & 63);
-                                        y[h] = mine[h] && sj < bn ? g_fp64<K_COULOMB>(p, ti[h], p, en.x + sj, 0.0, nfp64)
-                                                                  : 0.0;
-                                    }
-                                }
-                            } else {
-                                double y0 = rsq_est(r2);
-                                if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
-                                y[h] = y0 * fma(-(r2 * y0), y0, 3.0);   // 2 y0 (3 - r^2 y0^2)/2; q staged /2
-                            }
-                            sum[h] = fma((double)v.w, y[h], sum[h]);
-                        }
-                        double t = rol1(psi);
-#pragma unroll
-                        for (int h = 0; h < H; ++h) {
-                            if constexpr (F32) t = fma(qi[h], y[h], t);
-                            else t = t + qi[h] * y[h];
-                        }
-                        psi = t;
-                };
-                if (guard && F32) {
-                    // FP32 guarded ranges (near leaves) take a rolled loop: the
-                    // FP64 fallback stays out of the unrolled one
-#pragma unroll 1
-                    for (int s = 0; s < 64; ++s) step(s, std::true_type{});
-                } else if (guard) {
-#pragma unroll
-                    for (int s = 0; s < 64; ++s) step(s, std::true_type{});
+            if (e < it.ee) {
+                double x, y, z, q;
+                if constexpr (PROXY) {                     // proxy entries: en.x = cluster B
+                    proxy_point(T.box + 6 * en.x, m, tab + 32 * it.degree, o, x, y, z);
+                    q = qd[(int64_t)en.x * P + o];
                 } else {
-#pragma unroll
-                    for (int s = 0; s < 64; ++s) step(s, std::false_type{});
+                    j = en.x + o;
+                    x = p.x[j];
+                    y = p.y[j];
+                    z = p.z[j];
+                    q = p.q[j];
                 }
-#pragma unroll
-                for (int h = 0; h < H; ++h) acc[h] += sum[h];
-                part_red[wave][(lane + 63) & 63] = psi;
+                v = V{(R)(x - cx), (R)(y - cy), (R)(z - cz), (R)(qs * q)};
             }
-            __syncthreads();
-            if (tid < span && c0 + tid < bn) {
-                const int k = tid >> 6, ms = tid & 63;           // copy and source of the round
-                double t = 0.0;
-                for (int w = 0; w < nslab; ++w)
-                    if (64 * H * w < it.tn) t += part_red[k * nslab + w][ms];
-                if (slots) slots[run + c0 + tid] = t;
-                else if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, t);
-                else atomicAdd(phi + en.x + c0 + tid, t);
-            }
+            V* dst = src + 128 * (tid >> 6) + (tid & 63);
+            dst[0] = v;
+            dst[64] = v;
+            sidx[tid] = j;
         }
-        run += bn;
-    }
-    if (slots) {
-        // the copies hold the same targets against different sources: their
-        // sums meet in LDS (the staging area, free now) and are added in copy order
         __syncthreads();
-        double* red = reinterpret_cast<double*>(src);      // [copies][64 H nslab]
-        const int stride = 64 * H * nslab;
+        double psi = 0.0;
+        if (active) {
+            double sum[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) red[copy * stride + 64 * H * sw + 64 * h + lane] = acc[h];
+            for (int h = 0; h < H; ++h) sum[h] = 0.0;
+            // 64 steps: lane l pairs its H targets with source (l + s) mod 64;
+            // every term goes to FP64 sums
+            auto step = [&](int s, auto guard) {
+                    const V v = mysrc[lane + s];
+                    double y[H];
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        const R dx = tx[h] - v.x, dy = ty[h] - v.y, dz = tz[h] - v.z;
+                        R r2 = dz * dz;
+                        r2 = dy * dy + r2;
+                        r2 = dx * dx + r2;
+                        if constexpr (F32) {
+                            y[h] = (double)__builtin_amdgcn_rsqf(r2);
+                            if constexpr (!PROXY && decltype(guard)::value) {
+                                if (r2 <= thr32) {       // closer than FP32 resolves: FP64
+                                    const int sj = sidx[64 * copy + ((lane + s) & 63)];
+                                    y[h] = mine[h] && sj >= 0 ? g_fp64<K_COULOMB>(p, ti[h], p, sj, 0.0, nfp64) : 0.0;
+                                }
+                            }
+                        } else {
+                            double y0 = rsq_est(r2);
+                            if constexpr (decltype(guard)::value) y0 = r2 > 0.0 ? y0 : 0.0;
+                            y[h] = y0 * fma(-(r2 * y0), y0, 3.0);   // 2 y0 (3 - r^2 y0^2)/2; q staged /2
+                        }
+                        sum[h] = fma((double)v.w, y[h], sum[h]);
+                    }
+                    double t = rol1(psi);
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        if constexpr (F32) t = fma(qi[h], y[h], t);
+                        else t = t + qi[h] * y[h];
+                    }
+                    psi = t;
+            };
+            if (guard && F32) {
+                // FP32 guarded ranges (near leaves) take a rolled loop: the
+                // FP64 fallback stays out of the unrolled one
+#pragma unroll 1
+                for (int s = 0; s < 64; ++s) step(s, std::true_type{});
+            } else if (guard) {
+#pragma unroll
+                for (int s = 0; s < 64; ++s) step(s, std::true_type{});
+            } else {
+#pragma unroll
+                for (int s = 0; s < 64; ++s) step(s, std::false_type{});
+            }
+#pragma unroll
+            for (int h = 0; h < H; ++h) acc[h] += sum[h];
+            part_red[wave][(lane + 63) & 63] = psi;
+        }
         __syncthreads();
-        for (int r = tid; r < it.tn; r += kBlock) {
+        if (tid < span && r0 + tid < G) {
+            const int k = tid >> 6, ms = tid & 63;           // copy and source of the round
             double t = 0.0;
-            for (int k = 0; k < copies; ++k) t += red[k * stride + r];
-            slots[base + r] = t;
+            for (int w = 0; w < nslab; ++w)
+                if (64 * H * w < it.tn) t += part_red[k * nslab + w][ms];
+            slots[base + it.tn + r0 + tid] = t;
         }
-        return;
+        ec = e1;
+        oc = o1;
     }
+    // the copies hold the same targets against different sources: their sums
+    // meet in LDS (the staging area, free now) and are added in copy order
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(src);          // [copies][64 H nslab]
+    const int stride = 64 * H * nslab;
 #pragma unroll
-    for (int h = 0; h < H; ++h)
-        if (mine[h]) {
-            if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + ti[h], acc[h]);
-            else atomicAdd(phi + ti[h], acc[h]);
-        }
+    for (int h = 0; h < H; ++h) red[copy * stride + 64 * H * sw + 64 * h + lane] = acc[h];
+    __syncthreads();
+    for (int r = tid; r < it.tn; r += kBlock) {
+        double t = 0.0;
+        for (int k = 0; k < copies; ++k) t += red[k * stride + r];
+        slots[base + r] = t;
+    }
 }
 
 }  // namespace dev

@@ -102,17 +102,16 @@ __global__ __launch_bounds__(kBlock) void k_down_leaf(const DevItem* __restrict_
 // ---------------------------------------------------------------------------
 template <bool F32, bool PROXY>
 __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ items, const int2* __restrict__ entries,
-                                                DevParticles p, DevTree T, double* __restrict__ phi,
-                                                const double* __restrict__ tab, DegPtrs qhat, DegOut phihat,
-                                                double* __restrict__ nfp64, SymSlots out) {
+                                                DevParticles p, DevTree T, const double* __restrict__ tab,
+                                                DegPtrs qhat, double* __restrict__ nfp64, SymSlots out) {
     __shared__ double4 pool[(sym_lds_bytes<F32>() + 31) / 32];
     // tiles of more than 128 targets: four per lane (one wave per copy)
     const DevItem it = items[blockIdx.x];
-    const int64_t base = out.slots ? out.ibase[blockIdx.x] : 0;
+    const int64_t base = out.ibase[blockIdx.x];
     if (it.tn > 128)
-        sym_body<F32, PROXY, 4>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64, out.slots, base);
+        sym_body<F32, PROXY, 4>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base);
     else
-        sym_body<F32, PROXY, 2>(it, entries, p, T, phi, tab, qhat, phihat, pool, nfp64, out.slots, base);
+        sym_body<F32, PROXY, 2>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base);
 }
 
 // ---------------------------------------------------------------------------
@@ -124,15 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_sym_fold(const FoldSeg* __restrict__
                                                      const double* __restrict__ slots, double* __restrict__ phi,
                                                      DegOut phihat) {
     const FoldSeg sg = segs[blockIdx.x];
-    double* out = (sg.deg < 0 ? phi : phihat.p[sg.deg]) + sg.off;
-    for (int k = threadIdx.x; k < sg.n; k += kBlock) {
-        double v = 0.0;
-        for (int q = sg.pb; q < sg.pe; ++q) {
-            const FoldPart pt = parts[q];
-            if (k >= pt.lo && k < pt.lo + pt.len) v += slots[pt.slot + (k - pt.lo)];
-        }
-        out[k] += v;
-    }
+    fold_body(sg, parts, slots, (sg.deg < 0 ? phi : phihat.p[sg.deg]) + sg.off, 0, sg.n);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,12 +335,11 @@ __device__ __forceinline__ void lane_operands(const MfmaLds& L, int wave, int gr
 template <bool PROXY, bool GUARDED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_mfma(const DevItem* __restrict__ items,
                                                      const int2* __restrict__ entries, DevParticles p, DevTree T,
-                                                     double* __restrict__ phi, const double* __restrict__ tab,
-                                                     DegPtrs qhat, DegOut phihat, double* __restrict__ nfp64,
-                                                     SymSlots out) {
+                                                     const double* __restrict__ tab, DegPtrs qhat,
+                                                     double* __restrict__ nfp64, SymSlots out) {
     __shared__ MfmaLds L;
     const DevItem it = items[blockIdx.x];
-    const int64_t base = out.slots ? out.ibase[blockIdx.x] : 0;
+    const int64_t base = out.ibase[blockIdx.x];
     int64_t run = base + it.tn;                  // slots of the current entry's sources
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane >> 4, col = lane & 15;
     const bool active = 64 * wave < it.tn;
@@ -358,7 +348,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int m = it.degree + 1, P = m * m * m;
     const double* ptab = tab + 32 * it.degree;
     const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
-    double* od = PROXY ? phihat.p[it.degree] : nullptr;
     // largest |x - c|^2 of the item's targets: a quarter of the box's squared diagonal
     double xmax2;
     {
@@ -421,8 +410,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 if (g == 0.0) return;
                 atomicAdd(&L.corr[row], p.q[j] * g);
                 // the source's term joins its column slot of this wave and tile
-                if (out.slots) atomicAdd(&L.part[wave][t][col], p.q[i] * g);
-                else atomicAdd(phi + j, p.q[i] * g);
+                atomicAdd(&L.part[wave][t][col], p.q[i] * g);
             };
             mfma_tiles<GUARDED, false>(nt, L, L.part[wave], lane, A, qi, acc, xmax2, fix);
         }
@@ -436,11 +424,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 s += L.part[w][t][j];
                 L.part[w][t][j] = 0.0;
             }
-            if (c0 + tid < bn) {
-                if (out.slots) out.slots[run + c0 + tid] = s;
-                else if constexpr (PROXY) atomicAdd(od + (int64_t)en.x * P + c0 + tid, s);
-                else atomicAdd(phi + en.x + c0 + tid, s);
-            }
+            if (c0 + tid < bn) out.slots[run + c0 + tid] = s;
         }
         if (e2 != e) run += bn;
         e = e2;
@@ -449,11 +433,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     if (active) {
         const int row = 64 * wave + 16 * (col >> 2) + grp + 4 * (col & 3);
         const double v = reduce_rows(acc, col) + (row < it.tn ? L.corr[row] : 0.0);
-        if (row < it.tn) {
-            if (out.slots) out.slots[base + row] = v;
-            else if constexpr (PROXY) atomicAdd(od + (int64_t)it.cluster * P + it.t0 + row, v);
-            else atomicAdd(phi + it.t0 + row, v);
-        }
+        if (row < it.tn) out.slots[base + row] = v;
     }
 }
 
@@ -996,25 +976,26 @@ void launch_pp_mfma(const DevItem* items, int n_items, const int2* entries, DevP
 }
 
 void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem* items, int n_items,
-                const int2* entries, DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat,
-                DegOut phihat, double* nfp64, SymSlots out, hipStream_t st) {
+                const int2* entries, DevParticles p, DevTree T, const double* tab, DegPtrs qhat, double* nfp64,
+                SymSlots out, hipStream_t st) {
     if (n_items <= 0) return;
+    if (!out.slots || !out.ibase) throw Error(-1, "symmetric pass without slots");
     if (fp32 && mfma) {
         if (proxies && guarded) throw Error(-1, "proxy entries are never guarded");
         if (proxies)
             hipLaunchKernelGGL((k_sym_mfma<true, false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
-                               phi, tab, qhat, phihat, nfp64, out);
+                               tab, qhat, nfp64, out);
         else if (guarded)
             hipLaunchKernelGGL((k_sym_mfma<false, true>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
-                               phi, tab, qhat, phihat, nfp64, out);
+                               tab, qhat, nfp64, out);
         else
             hipLaunchKernelGGL((k_sym_mfma<false, false>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T,
-                               phi, tab, qhat, phihat, nfp64, out);
+                               tab, qhat, nfp64, out);
         CHECK_LAUNCH();
         return;
     }
-#define LAUNCH_SYM(F, PX) hipLaunchKernelGGL((k_sym<F, PX>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, phi, \
-                                            tab, qhat, phihat, nfp64, out)
+#define LAUNCH_SYM(F, PX) hipLaunchKernelGGL((k_sym<F, PX>), dim3(n_items), dim3(kBlock), 0, st, items, entries, p, T, \
+                                            tab, qhat, nfp64, out)
     if (fp32) {
         if (proxies) LAUNCH_SYM(true, true);
         else LAUNCH_SYM(true, false);

@@ -79,23 +79,23 @@ void launch_interact(KernelSpec k, bool fp32, bool proxy_targets, int tpt, const
 // Symmetric passes (Coulomb, targets = sources): items are tiles of a target
 // cluster A (particles, or proxies of degree item.degree) with entries of
 // partner clusters B (particle ranges, or proxy entries); every kernel value
-// counts for both sides.  With out.slots set, item i writes its sums to the
-// slots of its fold (fold.hpp; out.ibase is aligned with `items`) and
+// counts for both sides.  Item i writes its sums to the slots of its fold
+// (fold.hpp; out.ibase is aligned with `items`, both required) and
 // launch_sym_fold adds them to the outputs in a fixed order, so the result
-// is the same bits every time; with out.slots null, the sums go to the
-// outputs with FP64 atomic adds.  Outputs: phi (tree order) for particles,
-// phihat.p[degree] for proxies, which already hold the other terms.  With
-// fp32 and mfma the squared distances come from the FP64 matrix cores.
+// is the same bits every time.  With fp32 and mfma the squared distances
+// come from the FP64 matrix cores.
 // guarded: the items' entries are all flagged SRC_RANGE_GUARD (else none is).
 struct SymSlots {
     double* slots;
     const int64_t* ibase;
 };
 void launch_sym(bool fp32, bool mfma, bool proxies, bool guarded, const DevItem* items, int n_items,
-                const int2* entries, DevParticles p, DevTree T, double* phi, const double* tab, DegPtrs qhat,
-                DegOut phihat, double* nfp64, SymSlots out, hipStream_t st);
+                const int2* entries, DevParticles p, DevTree T, const double* tab, DegPtrs qhat, double* nfp64,
+                SymSlots out, hipStream_t st);
 
-// out[k] += the parts of every segment (fold.hpp), one work group per segment.
+// out[k] += the parts of every segment (fold.hpp), one work group per segment:
+// phi (tree order) for particle segments, phihat.p[degree] for proxy ones,
+// which already hold the other terms.
 void launch_sym_fold(const FoldSeg* segs, int n_segs, const FoldPart* parts, const double* slots, double* phi,
                      DegOut phihat, hipStream_t st);
 
@@ -168,6 +168,17 @@ struct BatchDev {
     const DevItem* citems;      // symmetric CC items (same batches), after the proxy items
     const int2* centries;
     int n_c;
+    // folds of the symmetric items (fold.hpp; set when n_s or n_c is nonzero)
+    double* sslots;             // symmetric PP items' slots, slot base per item, segments per leaf
+    const int64_t* sbase;
+    const FoldSeg* psegs;
+    const FoldPart* pparts;
+    const int32_t* pseg;        // per particle item: the segment of its leaf
+    double* cslots;             // symmetric CC items' slots, slot base per item, segments per cluster
+    const int64_t* cbase;
+    const FoldSeg* csegs;
+    const FoldPart* cparts;
+    const int32_t* cseg;        // per target cluster: its segment, or -1
     int n_leaves, n_parents, n_q, n_p, n_s, n_kids, n_tasks;
     int spin_limit;
     double param;
