@@ -92,9 +92,9 @@ enum {
                                       go to per-item slots that a fold adds in a stored
                                       order, so every compute gives the same bits.
                                       FP64 batches of such problems evaluate their PP
-                                      pairs once for both too, with FP64 atomic adds
-                                      (results vary at the rounding level), unless
-                                      this flag is set                                   */
+                                      and CC pairs once for both too, folded the same
+                                      way inside the batch kernel, unless this flag is
+                                      set                                                */
     BLDTT_BLTC = 1u << 9,          /* build the lists of the particle-cluster treecode
                                       (BLTC, Sec. 2.8) instead of Algorithm 2: every
                                       target leaf (a batch) walks the source tree from

@@ -22,9 +22,9 @@
 //              sums, then leaf interpolation plus the PP/PC part, to the
 //              caller's buffers (after every symmetric item of its problem)
 //
-// The one-way items each own their outputs (one proxy item per proxy, one
-// particle item per target), which start from zero and take one atomic add;
-// every symmetric sum arrives through a fold in a fixed order, so a launch
+// The one-way items each own their outputs (one proxy item per proxy at the
+// batch's one degree, one particle item per target) and write them; the
+// symmetric sums arrive later through folds in a fixed order, so a launch
 // gives the same bits every time.
 //
 // Work groups take task numbers from a ticket counter, so a task starts only
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 up_seen = true;
             }
             interact_body<KIND, F32, T, true>(it, a.qentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
-                                              nullptr, a.po, vl, a.n_c > 0 ? OUT_ATOMIC : OUT_WRITE);
+                                              nullptr, a.po, vl, OUT_WRITE);
             signal(a.dn + it.cluster);
         } else if (t < e2) {
             if constexpr (!F32 && KIND == K_COULOMB) {
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 up_seen = true;
             }
             interact_body<KIND, F32, T, false>(it, a.pentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
-                                               a.phi_tree, a.po, vl, a.n_s > 0 ? OUT_ATOMIC : OUT_WRITE);
+                                               a.phi_tree, a.po, vl, OUT_WRITE);
             signal(a.pdone + i);
         } else if (t < es) {
             if constexpr (!F32 && KIND == K_COULOMB) {

@@ -422,8 +422,9 @@ void capture(bldtt_batch* b, int tpt, int groups_per_cu) {
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     try {
         launch_fill_i32(b->counters.as<int32_t>(), b->n_counters, 0, b->cap);
+        // proxy potentials of clusters without proxy items start from zero; every
+        // target particle belongs to one particle item, which writes it
         launch_fill(b->phihat.as<double>(), (int64_t)b->T().size() * b->P(), 0.0, b->cap);
-        if (a.n_s > 0) launch_fill(b->phi_tree.as<double>(), b->T().n_particles, 0.0, b->cap);
         launch_batch(ks, fp32, tpt, b->degree, (int)grid, a, b->cap);
     } catch (...) {
         hipGraph_t g2 = nullptr;

@@ -216,11 +216,11 @@ constexpr int interact_lds_bytes() { return kChunk * (int)sizeof(typename Stage<
 // owns targets (w mod nslab)*64*T + l + 64 j, j < T, and the copies' sums are
 // added in LDS at the end (an item with few targets keeps every wave busy).
 // Sources are staged through LDS and read by all lanes at the same address.
-// `add` says how the sums are stored: written, added to what the outputs hold
-// (a second pass over the same targets), or added with atomics (other items
-// add to the same outputs concurrently).
+// `add` says how particle sums are stored: written, or added to what the
+// outputs hold (a second pass over the same targets); proxy sums are written.
+// Each item owns its outputs.
 // ---------------------------------------------------------------------------
-enum { OUT_WRITE = 0, OUT_ADD = 1, OUT_ATOMIC = 2 };
+enum { OUT_WRITE = 0, OUT_ADD = 1 };
 
 template <int KIND, bool F32, int T, bool PROXY_TGT>
 __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __restrict__ entries, DevParticles tgt,
@@ -355,11 +355,7 @@ __device__ __forceinline__ void interact_body(const DevItem& it, const int2* __r
         int r = slab + lane + 64 * j;
         if (r < it.tn) {
             if (PROXY_TGT) {
-                double* o = pout.p[it.degree] + (int64_t)it.slot * Pt + it.t0 + r;
-                if (add == OUT_ATOMIC) atomicAdd(o, acc[j]);
-                else *o = acc[j];
-            } else if (add == OUT_ATOMIC) {
-                atomicAdd(out + it.slot + r, acc[j]);
+                pout.p[it.degree][(int64_t)it.slot * Pt + it.t0 + r] = acc[j];
             } else {
                 out[it.slot + r] = add == OUT_ADD ? out[it.slot + r] + acc[j] : acc[j];
             }

@@ -171,26 +171,47 @@ __global__ __launch_bounds__(kTB) void k_tb_scan(int64_t* __restrict__ blk, int 
     }
 }
 
-// The count of each code before flattened index j (j <= total).
+// The count of each code before flattened index j (j <= total), by the whole
+// group: the block's scanned counts plus the group's count of the block's
+// particles before j (lds: 8 * kTB / 64 ints).
 __device__ __forceinline__ void codes_before(const TBCluster* __restrict__ cl, int nc, TBCoords c,
-                                             const int64_t* __restrict__ blk, int64_t j, int64_t (&out)[8]) {
+                                             const int64_t* __restrict__ blk, int64_t j, int64_t (&out)[8],
+                                             int* lds) {
     const int64_t b = j / kPerBlock;
-    for (int q = 0; q < 8; ++q) out[q] = blk[8 * b + q];
-    for (int64_t i = b * kPerBlock; i < j; ++i) {
+    int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = b * kPerBlock + threadIdx.x; i < j; i += kTB) {
         const TBCluster& k = cl[cluster_of(cl, nc, i)];
-        out[code_at(c, k.b + (i - k.j0), k)]++;
+        const int code = code_at(c, k.b + (i - k.j0), k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cnt[q] += code == q ? 1 : 0;
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int v = cnt[q];
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0) lds[q * (kTB / 64) + wave] = v;
+    }
+    __syncthreads();
+    for (int q = 0; q < 8; ++q) {
+        int64_t t = blk[8 * b + q];
+        for (int w = 0; w < kTB / 64; ++w) t += lds[q * (kTB / 64) + w];
+        out[q] = t;
+    }
+    __syncthreads();                                    // lds is reused by the next call
 }
 
-// One thread per split cluster: its children's ranges and code bases.
+// One work group per split cluster: its children's ranges and code bases.
 __global__ __launch_bounds__(kTB) void k_tb_split(const TBCluster* __restrict__ cl, int nc, TBCoords c,
                                                    const int64_t* __restrict__ blk, TBSplit* __restrict__ out) {
-    const int ci = blockIdx.x * kTB + threadIdx.x;
-    if (ci >= nc) return;
+    __shared__ int lds[8 * (kTB / 64)];
+    const int ci = blockIdx.x;
     const TBCluster k = cl[ci];
     int64_t lo[8], hi[8];
-    codes_before(cl, nc, c, blk, k.j0, lo);
-    codes_before(cl, nc, c, blk, k.j0 + (k.e - k.b), hi);
+    codes_before(cl, nc, c, blk, k.j0, lo, lds);
+    codes_before(cl, nc, c, blk, k.j0 + (k.e - k.b), hi, lds);
+    if (threadIdx.x != 0) return;
     TBSplit s;
     int64_t at = k.b;
     for (int q = 0; q < 8; ++q) {
@@ -250,14 +271,18 @@ __global__ __launch_bounds__(kTB) void k_tb_copy(const TBCluster* __restrict__ c
     to.idx[p] = from.idx[p];
 }
 
-// One workgroup per (split cluster, code): the child's box.
-__global__ __launch_bounds__(kTB) void k_tb_child_box(const TBSplit* __restrict__ sp, TBCoords c,
+// `subs` workgroups per (split cluster, code): the box of every subs-th
+// 256-particle stretch of the child, sub-box `sub` at boxes[6 (subs child +
+// sub)]; min and max are exact in any order, so the host takes those of the
+// sub-boxes.
+__global__ __launch_bounds__(kTB) void k_tb_child_box(const TBSplit* __restrict__ sp, TBCoords c, int subs,
                                                        double* __restrict__ boxes) {
     __shared__ double red[6][kTB];
-    const int ci = blockIdx.x >> 3, q = blockIdx.x & 7;
+    const int child = blockIdx.x / subs, sub = blockIdx.x % subs;
+    const int ci = child >> 3, q = child & 7;
     const int64_t s = sp[ci].start[q], n = sp[ci].cnt[q];
     double v[6] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, -HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
-    for (int64_t i = threadIdx.x; i < n; i += kTB) {
+    for (int64_t i = (int64_t)sub * kTB + threadIdx.x; i < n; i += (int64_t)subs * kTB) {
         const double p[3] = {c.x[s + i], c.y[s + i], c.z[s + i]};
         for (int d = 0; d < 3; ++d) {
             v[d] = fmin(v[d], p[d]);
@@ -386,13 +411,15 @@ void build_tree_device(int64_t n, const double* x, const double* y, const double
         upload(dcl, cl);
         dblk.reserve(sizeof(int64_t) * 8 * ((size_t)nblk + 1));
         dsplit.reserve(sizeof(TBSplit) * (size_t)nc);
-        dbox.reserve(sizeof(double) * 48 * (size_t)nc);
+        // enough workgroups for the few large children of the first levels
+        const int subs = (int)std::max<int64_t>(1, std::min<int64_t>(256, 2048 / (8 * (int64_t)nc)));
+        dbox.reserve(sizeof(double) * 48 * (size_t)nc * subs);
         const TBCluster* dc = dcl.as<TBCluster>();
         hipLaunchKernelGGL(k_tb_count, dim3(nblk), dim3(kTB), 0, st, dc, nc, total, A, dblk.as<int64_t>());
         TBCHK();
         hipLaunchKernelGGL(k_tb_scan, dim3(1), dim3(kTB), 0, st, dblk.as<int64_t>(), nblk);
         TBCHK();
-        hipLaunchKernelGGL(k_tb_split, dim3(grid_of(nc, kTB)), dim3(kTB), 0, st, dc, nc, A, dblk.as<int64_t>(),
+        hipLaunchKernelGGL(k_tb_split, dim3(nc), dim3(kTB), 0, st, dc, nc, A, dblk.as<int64_t>(),
                            dsplit.as<TBSplit>());
         TBCHK();
         hipLaunchKernelGGL(k_tb_scatter, dim3(nblk), dim3(kTB), 0, st, dc, nc, total, A, dblk.as<int64_t>(),
@@ -400,10 +427,11 @@ void build_tree_device(int64_t n, const double* x, const double* y, const double
         TBCHK();
         hipLaunchKernelGGL(k_tb_copy, dim3(grid_of(total, kTB)), dim3(kTB), 0, st, dc, nc, total, B, A);
         TBCHK();
-        hipLaunchKernelGGL(k_tb_child_box, dim3(8 * nc), dim3(kTB), 0, st, dsplit.as<TBSplit>(), A, dbox.as<double>());
+        hipLaunchKernelGGL(k_tb_child_box, dim3(8 * nc * subs), dim3(kTB), 0, st, dsplit.as<TBSplit>(), A, subs,
+                           dbox.as<double>());
         TBCHK();
         sp.resize(nc);
-        boxes.resize(48 * (size_t)nc);
+        boxes.resize(48 * (size_t)nc * subs);
         HIPCHK(hipMemcpyAsync(sp.data(), dsplit.p, sizeof(TBSplit) * nc, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(boxes.data(), dbox.p, sizeof(double) * boxes.size(), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -418,9 +446,14 @@ void build_tree_device(int64_t n, const double* x, const double* y, const double
             for (int q = 0; q < 8; ++q) {
                 if (!sp[ci].cnt[q]) continue;
                 BuildNode ch{};
+                const double* sb = boxes.data() + 6 * (size_t)subs * (8 * ci + q);
                 for (int d = 0; d < 3; ++d) {
-                    ch.lo[d] = boxes[48 * ci + 6 * q + d];
-                    ch.hi[d] = boxes[48 * ci + 6 * q + 3 + d];
+                    ch.lo[d] = sb[d];
+                    ch.hi[d] = sb[3 + d];
+                    for (int u = 1; u < subs; ++u) {
+                        ch.lo[d] = std::min(ch.lo[d], sb[6 * u + d]);
+                        ch.hi[d] = std::max(ch.hi[d], sb[6 * u + 3 + d]);
+                    }
                 }
                 ch.b = sp[ci].start[q];
                 ch.e = ch.b + sp[ci].cnt[q];
