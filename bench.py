@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -50,11 +51,16 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    """First 16 hex digits of the SHA-256 of the interaction kernels' sources."""
+    """First 16 hex digits of the SHA-256 of the interaction kernels' sources,
+    without their `//` comments and trailing blanks (a comment edit leaves the
+    code, and so the counter records, valid)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2012_06925_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2012_06925_amd", "csrc", name), encoding="utf-8") as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -18,8 +18,8 @@
 // address (broadcast).  In the one-sided passes each workgroup owns its
 // outputs.  A symmetric pass also produces sums for its sources, which other
 // workgroups' targets share: it writes them to slots of its own and the fold
-// adds them in a stored order (atomic adds only where a caller asks for them:
-// the batch kernel), so every compute gives the same bits.
+// adds them in a stored order (the batch kernel folds inside its tasks), so
+// every compute gives the same bits.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
