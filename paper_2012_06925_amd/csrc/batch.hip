@@ -178,12 +178,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const int c = a.kids[t - es];
             const int par = a.T.parent[c];
             wait2(a, a.dn + par, a.nq[par] + (a.T.parent[par] >= 0 ? 1 : 0), a.dn + c, a.nq[c]);
+            // the parent's potentials and the transfer matrices go to LDS while
+            // the cluster's symmetric CC slots are folded into its potentials
+            // (the same thread later adds the transfer to each output it folded)
+            down_transfer_stage<M>(c, a.T, a.tab, a.phihat, dl);
             if (a.n_c > 0 && a.cseg[c] >= 0) {
                 const FoldSeg sg = a.csegs[a.cseg[c]];
                 fold_body(sg, a.cparts, a.cslots, a.phihat + sg.off, 0, sg.n);
-                __syncthreads();              // the transfer reads what other threads folded
             }
-            down_transfer_body<M>(c, a.T, a.tab, a.phihat, dl);
+            __syncthreads();
+            down_transfer_apply<M>(c, a.phihat, dl);
             signal(a.dn + c);
         } else {
             const int i = t - e4;

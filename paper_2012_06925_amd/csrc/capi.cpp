@@ -422,7 +422,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         //     second stream and overlaps the degree choice and the packing of
         //     the rest.  It first waits for the work already on st (the
         //     previous compute still reads phi_tree).
-        //     Symmetric pairs go to their own pass (atomic adds), launched as
+        //     Symmetric pairs go to their own pass (slots, folded later), launched as
         //     soon as their items are packed; the remaining near-field pairs
         //     (few: those listed one way only) follow on the same stream.
         Lists& near_rest = pl->near_rest;

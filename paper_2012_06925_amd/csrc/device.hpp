@@ -511,53 +511,90 @@ __device__ __forceinline__ void up_transfer_body(int c, DevTree S, const double*
 // Outputs [k0, k1) of fold segment sg (fold.hpp; out points at the segment's
 // output 0): each adds the slots of its parts in their stored order, so the
 // sums do not depend on which item finished first.  The group's threads share
-// the outputs; the caller synchronises before other threads read them.  The
-// parts go eight at a time: eight independent loads (a part that does not
-// cover the output reads its own first slot, which exists, and is not added),
-// then the eight adds in order.
-__device__ __forceinline__ void fold_body(const FoldSeg& sg, const FoldPart* __restrict__ parts,
-                                          const double* __restrict__ slots, double* __restrict__ out, int k0, int k1) {
+// the outputs; the caller synchronises before other threads read them.
+// Latency, not bandwidth, bounds a fold (a few parts per output, slots
+// written by other CUs): a thread takes R outputs at once and the parts go
+// eight at a time, 8 R independent loads per batch; a part that does not
+// cover an output, or lies past the segment's end, reads a slot that exists
+// (its own first, or the segment's first part's) and is not added.
+template <int R>
+__device__ __forceinline__ void fold_pass(const FoldSeg& sg, const FoldPart* __restrict__ parts,
+                                          const double* __restrict__ slots, double* __restrict__ out, int k0,
+                                          int k1) {
     constexpr int U = 8;
-    for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) {
-        double v = 0.0;
-        int q = sg.pb;
-        for (; q + U <= sg.pe; q += U) {
-            double s[U];
-            bool in[U];
+    for (int kb = k0; kb < k1; kb += R * kBlock) {
+        int k[R];
+        double v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            k[r] = kb + r * kBlock + (int)threadIdx.x;
+            v[r] = 0.0;
+        }
+        for (int q = sg.pb; q < sg.pe; q += U) {
+            double s[U][R];
+            bool in[U][R];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const FoldPart pt = parts[q + u];
-                const unsigned r = (unsigned)(k - pt.lo);
-                in[u] = r < (unsigned)pt.len;
-                s[u] = slots[pt.slot + (in[u] ? r : 0u)];
+                const bool real = q + u < sg.pe;
+                const FoldPart pt = parts[real ? q + u : sg.pb];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const unsigned d = (unsigned)(k[r] - pt.lo);
+                    in[u][r] = real && d < (unsigned)pt.len;
+                    s[u][r] = slots[pt.slot + (in[u][r] ? d : 0u)];
+                }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) v = in[u] ? v + s[u] : v;
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = in[u][r] ? v[r] + s[u][r] : v[r];
         }
-        for (; q < sg.pe; ++q) {
-            const FoldPart pt = parts[q];
-            if (k >= pt.lo && k < pt.lo + pt.len) v += slots[pt.slot + (k - pt.lo)];
-        }
-        out[k] += v;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (k[r] < k1) out[k[r]] += v[r];
     }
+}
+
+__device__ __forceinline__ void fold_body(const FoldSeg& sg, const FoldPart* __restrict__ parts,
+                                          const double* __restrict__ slots, double* __restrict__ out, int k0, int k1) {
+    if (sg.pe == sg.pb) return;
+    if (k1 - k0 > kBlock) fold_pass<2>(sg, parts, slots, out, k0, k1);
+    else fold_pass<1>(sg, parts, slots, out, k0, k1);
 }
 
 template <int M>
 constexpr int down_transfer_lds_bytes() { return (int)sizeof(double) * (3 * M * M + 2 * M * M * M); }
 
+// The two halves of a transfer: the matrices and the parent's potentials into
+// LDS (stage), then, after a barrier, the contraction added to the child's
+// potentials (apply); work independent of both can go between them.
 template <int M>
-__device__ __forceinline__ void down_transfer_body(int c, DevTree T, const double* __restrict__ tab,
-                                                   double* __restrict__ phihat, double* lds) {
+__device__ __forceinline__ void down_transfer_stage(int c, DevTree T, const double* __restrict__ tab,
+                                                    const double* __restrict__ phihat, double* lds) {
     constexpr int P = M * M * M;
     double (*mat)[M][M] = reinterpret_cast<double (*)[M][M]>(lds);
     double* a = lds + 3 * M * M;
-    double* b = a + P;
     const int par = T.parent[c];
     build_mats<M>(mat, T.box + 6 * par, T.box + 6 * c, tab);
     for (int k = threadIdx.x; k < P; k += kBlock) a[k] = phihat[(int64_t)par * P + k];
-    __syncthreads();
+}
+
+template <int M>
+__device__ __forceinline__ void down_transfer_apply(int c, double* __restrict__ phihat, double* lds) {
+    constexpr int P = M * M * M;
+    const double (*mat)[M][M] = reinterpret_cast<const double (*)[M][M]>(lds);
+    double* a = lds + 3 * M * M;
+    double* b = a + P;
     apply3<M, true>(mat, a, b);
     for (int k = threadIdx.x; k < P; k += kBlock) phihat[(int64_t)c * P + k] += b[k];
+}
+
+template <int M>
+__device__ __forceinline__ void down_transfer_body(int c, DevTree T, const double* __restrict__ tab,
+                                                   double* __restrict__ phihat, double* lds) {
+    down_transfer_stage<M>(c, T, tab, phihat, lds);
+    __syncthreads();
+    down_transfer_apply<M>(c, phihat, lds);
 }
 
 // ---------------------------------------------------------------------------
