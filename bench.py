@@ -108,6 +108,22 @@ PMC_PASS_NAMES = {
 PMC_BATCH_PREFIX = "k_batch<"
 
 
+def summarize_markers(db: str) -> None:
+    """Markdown table of the library's host ranges (roctx) in a rocprofv3
+    --marker-trace database: calls and durations per range name."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select extdata, start, end from regions where category like '%MARKER%'").fetchall()
+    agg = collections.defaultdict(list)
+    for ext, t0, t1 in rows:
+        agg[json.loads(ext).get("message", "?")].append((t1 - t0) / 1e6)
+    print("| host range | calls | avg ms | min ms | max ms |")
+    print("|---|---:|---:|---:|---:|")
+    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| `{name}` | {len(v)} | {sum(v) / len(v):.3f} | {min(v):.3f} | {max(v):.3f} |")
+
+
 def summarize_pmc(prefix: str, mode: str) -> None:
     """Turn the four counter passes of `bench.py --mode MODE` (rocprofv3 output
     under PREFIX_A .. PREFIX_D, counters as PMC_PASSES) into the per-launch
@@ -665,6 +681,8 @@ def main() -> int:
                     help="all four interaction types vs PP + CC only (plain FP64, uniform and Gaussian)")
     ap.add_argument("--summarize-pmc", default=None, metavar="PREFIX",
                     help="write the profiles/ counter records from rocprofv3 passes PREFIX_A .. PREFIX_D of --mode")
+    ap.add_argument("--summarize-markers", default=None, metavar="DB",
+                    help="print the host ranges of a rocprofv3 --marker-trace database as a table")
     ap.add_argument("--treecodes", action="store_true",
                     help="Sec. 4.5: BLDTT vs BLTC vs CP-BLTC on unequal uniform sets (2E7/2E6 and 2E6/2E7)")
     ap.add_argument("--treecode-grid", default="0.7:8", help="comma list of theta:degree for --treecodes")
@@ -692,6 +710,9 @@ def main() -> int:
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
         return 2
+    if args.summarize_markers:
+        summarize_markers(args.summarize_markers)
+        return 0
 
     import torch
     from paper_2012_06925_amd import inputs

@@ -19,6 +19,7 @@
 
 #include "../../include/bldtt.h"
 #include "plan.hpp"
+#include "trace.hpp"
 #include "tune.hpp"
 
 using namespace bldtt;
@@ -574,6 +575,7 @@ int bldtt_batch_setup(bldtt_batch** out, int32_t count, const bldtt_particles* p
     }
     *out = nullptr;
     return guarded([&] {
+        HostRange range("bldtt_batch_setup");
         double t0 = now_ms();
         auto b = new_batch(count, problems, kernel, kernel_param, theta, degree, leaf_size, flags, false);
         KernelSpec ks{kernel, kernel_param};
@@ -675,7 +677,10 @@ int bldtt_batch_compute(bldtt_batch* b, double* const* potentials, void* hip_str
         set_error("device call on a host-only batch");
         return BLDTT_ESTATE;
     }
-    return guarded([&] { batch_compute(b, potentials, static_cast<hipStream_t>(hip_stream)); });
+    return guarded([&] {
+        HostRange range("bldtt_batch_compute");
+        batch_compute(b, potentials, static_cast<hipStream_t>(hip_stream));
+    });
 }
 
 int bldtt_batch_check(bldtt_batch* b, void* hip_stream) {

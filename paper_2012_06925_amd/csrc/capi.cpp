@@ -19,11 +19,13 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <optional>
 #include <string>
 #include <vector>
 
 #include "../../include/bldtt.h"
 #include "plan.hpp"
+#include "trace.hpp"
 #include "tune.hpp"
 
 namespace bldtt {
@@ -146,6 +148,7 @@ void fill_stats_tree(bldtt_plan* pl) {
 }
 
 void do_traverse(bldtt_plan* pl) {
+    HostRange range(pl->device_walk() ? "bldtt:traversal (GPU walk)" : "bldtt:traversal");
     double t0 = now_ms();
     const int scheme = scheme_of(pl->flags);
     if (pl->device_walk())
@@ -195,7 +198,8 @@ struct PhaseMark {
     bldtt_plan* pl;
     int ph;
     hipStream_t st;
-    PhaseMark(bldtt_plan* p, int phase, hipStream_t s) : pl(p), ph(phase), st(s) {
+    HostRange range;
+    PhaseMark(bldtt_plan* p, int phase, hipStream_t s) : pl(p), ph(phase), st(s), range(phase_range_name(phase)) {
         if (pl->flags & BLDTT_PROFILE) {
             HIPCHK(hipEventRecord(pl->prof_ev[pl->prof_cur][2 * ph], st));
             pl->prof_mask[pl->prof_cur] |= 1u << ph;
@@ -415,6 +419,8 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     do_traverse(pl);
     mark_host(1);
     double tp = now_ms();
+    std::optional<HostRange> pack_range;    // the list packing (and degree choice) after the traversal
+    pack_range.emplace("bldtt:packing");
     Lists& sep = pl->sep_lists;         // per-pair degree form: the typed separated pairs
     if (varied) {
         // 2a. The traversal deferred every separated pair, so the lists hold the
@@ -501,6 +507,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
         for (const Item& it : w.pitems)
             if (it.ee > it.eb) sep_items.push_back(it);
     pl->stats.traverse_ms += now_ms() - tp;
+    pack_range.reset();
     const double sym_w = symm ? pl->sym.pp_evaluations : 0.0, sym_c = symm ? scc.cc_evaluations : 0.0;
     const double self_w = symm ? pl->self_evaluations : 0.0;
     for (int k = 0; k < 4; ++k)
@@ -823,6 +830,7 @@ int bldtt_setup(bldtt_plan** out, const bldtt_particles* p, int32_t kernel, doub
     }
     *out = nullptr;
     return guarded([&] {
+        HostRange range("bldtt_setup");
         std::unique_ptr<bldtt_plan> pl(new_plan(p, kernel, kernel_param, theta, degree, leaf_size, flags));
         setup_device(pl.get(), p, static_cast<hipStream_t>(hip_stream));
         *out = pl.release();
@@ -871,7 +879,10 @@ int bldtt_compute(bldtt_plan* plan, double* potentials, void* hip_stream) {
         set_error("bldtt_compute on a host-only plan");
         return BLDTT_ESTATE;
     }
-    return guarded([&] { compute(plan, potentials, static_cast<hipStream_t>(hip_stream)); });
+    return guarded([&] {
+        HostRange range("bldtt_compute");
+        compute(plan, potentials, static_cast<hipStream_t>(hip_stream));
+    });
 }
 
 int bldtt_destroy(bldtt_plan* plan) {

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "trace.hpp"
 
 namespace bldtt {
 
@@ -95,6 +96,7 @@ void select_degrees_begin(bldtt_plan* pl, hipStream_t st) {
 }
 
 void select_degrees(bldtt_plan* pl, hipStream_t st) {
+    HostRange range("bldtt:degree choice");
     Lists& L = pl->lists;
     const Tree& T = pl->T();
     const Tree& S = pl->S;

@@ -229,6 +229,29 @@ def test_symmetric_batch_equals_one_sided_batch_and_replays():
     b.close()
 
 
+def test_symmetric_batch_of_tiny_problems_is_deterministic():
+    # many problems of one leaf (no symmetric items, nothing to fold) beside a
+    # few of several leaves: the folds skip the empty segments, every replay
+    # gives the same bits, and each problem equals its one-sided run
+    probs = [_dev_problem(p) for p in _problems(40, inputs.BASE_SEED + 59, lo=1.0, hi=3.3)]
+    kw = dict(theta=0.7, degree=5, leaf=200)
+    one = api.Batch(probs, flags=_lib.ONE_SIDED_PP, **kw)
+    ref = [o.cpu().numpy() for o in one.compute()]
+    one.check()
+    one.close()
+    b = api.Batch(probs, **kw)
+    first = [o.cpu().numpy() for o in b.compute()]
+    b.check()
+    assert sum(1 for p in probs if p[1][0].numel() <= 200) >= 10      # single-leaf problems present
+    assert max(_rel(f, r) for f, r in zip(first, ref)) <= 1e-13
+    for _ in range(2):
+        outs = b.compute()
+        b.check()
+        for f, o in zip(first, outs):
+            assert np.array_equal(f, o.cpu().numpy())
+    b.close()
+
+
 def test_batch_sync_flag_and_errors():
     probs = [_dev_problem(p) for p in _problems(3, inputs.BASE_SEED + 57)]
     b = api.Batch(probs, theta=0.7, degree=6, leaf=100, flags=_lib.SYNC)

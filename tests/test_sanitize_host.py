@@ -58,7 +58,7 @@ def test_host_engine_under_sanitizers(tmp_path):
     _run(cmds)
     exe = str(tmp_path / "host_engine_check")
     _run([[CLANG] + SAN + ["-o", exe, drv] + objs + [os.path.join(build_dir, d + ".o") for d in DEVICE_OBJECTS] +
-          ["-L/opt/rocm/lib", "-lamdhip64", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]])
+          ["-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]])
     r = subprocess.run([exe], capture_output=True, text=True, env=_env(), timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "0 failure(s)" in r.stdout
