@@ -11,16 +11,22 @@
 //              clusters listed as CC both ways, once for both; the sums go to
 //              the item's slots (fold.hpp); each item counts for its cluster
 //              and its partners
+//   [m item]   FP64 batches of targets = sources problems (Coulomb): a PC pair
+//              (leaf or cluster A, cluster B) listed with its mirror CP pair
+//              (B, A), once for both: A's particles against B's proxies (the
+//              same points as target and as source); A's sums go to the
+//              particle fold, B's to the proxy fold; each item counts for its
+//              problem (like an s item) and for every partner B
 //   [p item]   PP + PC sums into target particles (PC needs the upward pass)
 //   [s item]   FP64 batches of targets = sources problems (Coulomb): pairs of
 //              distinct leaves listed as PP both ways, once for both, into
 //              the item's slots
-//   [dn_xfer]  a cluster's symmetric CC slots folded into its proxy
+//   [dn_xfer]  a cluster's symmetric CC and CP slots folded into its proxy
 //              potentials in their stored order, then parent-to-child proxy
 //              potentials, shallowest level first (Sec. 2.7)
-//   [final]    a particle item's symmetric PP slots folded into its targets'
-//              sums, then leaf interpolation plus the PP/PC part, to the
-//              caller's buffers (after every symmetric item of its problem)
+//   [final]    a particle item's symmetric PP and PC slots folded into its
+//              targets' sums, then leaf interpolation plus the PP/PC part, to
+//              the caller's buffers (after every symmetric item of its problem)
 //
 // The one-way items each own their outputs (one proxy item per proxy at the
 // batch's one degree, one particle item per target) and write them; the
@@ -86,6 +92,15 @@ __device__ __forceinline__ void signal(int32_t* p) {
     if (threadIdx.x == 0) __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Same, counted in *first (if given) and in dn[entries[e].x] for e in [eb, ee).
+__device__ __forceinline__ void signal_partners(int32_t* first, int32_t* dn, const int2* entries, int eb, int ee) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0 && first) __hip_atomic_fetch_add(first, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int e = eb + (int)threadIdx.x; e < ee; e += kBlock)
+        __hip_atomic_fetch_add(dn + entries[e].x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Same, counted in dn[first] and in dn[entries[e].x] for e in [eb, ee).
 __device__ __forceinline__ void signal_clusters(int32_t* dn, int first, const int2* entries, int eb, int ee) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -109,8 +124,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     using V = typename Stage<F32>::V;
     V* vl = reinterpret_cast<V*>(pool);
 
-    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, eq = e1 + a.n_q, e2 = eq + a.n_c, e3 = e2 + a.n_p,
-              es = e3 + a.n_s, e4 = es + a.n_kids;
+    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, eq = e1 + a.n_q, e2 = eq + a.n_c, em = e2 + a.n_m,
+              e3 = em + a.n_p, es = e3 + a.n_s, e4 = es + a.n_kids;
     const int n_up = e1;
     bool up_seen = false;                     // this group has already acquired the finished upward pass
     for (;;) {
@@ -153,12 +168,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
                     up_seen = true;
                 }
-                sym_body<false, true>(it, a.centries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.cslots,
-                                      a.cbase[t - eq]);
+                const int64_t base = a.cbase[t - eq];
+                sym_body<false, true>(it, a.centries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.cslots, base,
+                                      a.cslots, base + it.tn);
                 signal_clusters(a.dn, it.cluster, a.centries, it.eb, it.ee);
             }
+        } else if (t < em) {
+            if constexpr (!F32 && KIND == K_COULOMB) {
+                const int i = t - e2;
+                const DevItem it = a.mitems[i];
+                if (!up_seen) {
+                    wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
+                    up_seen = true;
+                }
+                sym_body<false, false, 2, true>(it, a.mentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
+                                                a.mtbase[i], a.cslots, a.msbase[i]);
+                signal_partners(a.sdone + a.prob[it.cluster], a.dn, a.mentries, it.eb, it.ee);
+            }
         } else if (t < e3) {
-            const int i = t - e2;
+            const int i = t - em;
             const DevItem it = a.pitems[i];
             if (a.pneeds[i] && !up_seen) {
                 wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
@@ -170,8 +198,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         } else if (t < es) {
             if constexpr (!F32 && KIND == K_COULOMB) {
                 const DevItem it = a.sitems[t - e3];
-                sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
-                                       a.sbase[t - e3]);
+                const int64_t base = a.sbase[t - e3];
+                sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots, base,
+                                       a.sslots, base + it.tn);
                 signal(a.sdone + a.prob[it.cluster]);
             }
         } else if (t < e4) {
@@ -179,10 +208,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const int par = a.T.parent[c];
             wait2(a, a.dn + par, a.nq[par] + (a.T.parent[par] >= 0 ? 1 : 0), a.dn + c, a.nq[c]);
             // the parent's potentials and the transfer matrices go to LDS while
-            // the cluster's symmetric CC slots are folded into its potentials
-            // (the same thread later adds the transfer to each output it folded)
+            // the cluster's symmetric CC and CP slots are folded into its
+            // potentials (the same thread later adds the transfer to each
+            // output it folded)
             down_transfer_stage<M>(c, a.T, a.tab, a.phihat, dl);
-            if (a.n_c > 0 && a.cseg[c] >= 0) {
+            if (a.cslots && a.cseg[c] >= 0) {
                 const FoldSeg sg = a.csegs[a.cseg[c]];
                 fold_body(sg, a.cparts, a.cslots, a.phihat + sg.off, 0, sg.n);
             }
@@ -194,9 +224,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const DevItem it = a.pitems[i];
             const int c = it.cluster;
             const int prob = a.prob[c];
-            if (a.n_s > 0) wait2(a, a.sdone + prob, a.s_need[prob], nullptr, 0);
+            if (a.n_s + a.n_m > 0) wait2(a, a.sdone + prob, a.s_need[prob], nullptr, 0);
             wait2(a, a.pdone + i, 1, a.dn + c, a.nq[c] + (a.T.parent[c] >= 0 ? 1 : 0));
-            if (a.n_s > 0 && a.pseg[i] >= 0) {
+            if (a.sslots && a.pseg[i] >= 0) {
                 const FoldSeg sg = a.psegs[a.pseg[i]];
                 const int k0 = it.t0 - (int)sg.off;
                 fold_body(sg, a.pparts, a.sslots, a.phi_tree + sg.off, k0, k0 + it.tn);

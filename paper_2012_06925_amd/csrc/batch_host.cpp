@@ -41,7 +41,7 @@ struct bldtt_batch {
     Lists lists;
     Work work;
     Lists rest;                               // the lists without the symmetric PP pairs
-    SymWork sym;                              // symmetric PP items (FP64 targets = sources, Coulomb)
+    SymWork sym;                              // symmetric PP, CC and PC/CP items (FP64 targets = sources, Coulomb)
     bldtt_batch_stats stats{};
     bool symmetric() const {
         return aliased && kind == BLDTT_COULOMB && (flags & (BLDTT_FP32_EVAL | BLDTT_ONE_SIDED_PP)) == 0;
@@ -52,10 +52,10 @@ struct bldtt_batch {
     DevTreeBufs dS, dTt;
     const DevTreeBufs& dT() const { return aliased ? dS : dTt; }
     DevBuf leaves, parents, kids, qitems, qentries, qneeds, pitems, pentries, pneeds, has_far, nq, prob, caller0_d,
-        outs, counters, sitems, sentries, s_need, citems, centries;
+        outs, counters, sitems, sentries, s_need, citems, centries, mitems, mentries;
     // folds of the symmetric items: slots, slot bases, segments, parts, and the
     // segment of each particle item (PP) and of each target cluster (CC)
-    DevBuf sslots, sbase, psegs, pparts, pseg, cslots, cbase, csegs, cparts, cseg;
+    DevBuf sslots, sbase, mtbase, psegs, pparts, pseg, cslots, cbase, msbase, csegs, cparts, cseg;
     int n_leaves = 0, n_parents = 0, n_kids = 0;
     int64_t n_counters = 0;
     PinnedBuf outs_host;
@@ -238,16 +238,29 @@ void traverse_forest(bldtt_batch* b) {
     b->stats.traverse_ms = now_ms() - t0;
 }
 
-// The symmetric items' folds (fold.hpp) for the batch kernel: the PP
-// segments are the leaves, each folded by the final task of the particle item
-// that owns the targets; the CC segments are the clusters, each folded by the
+// The symmetric items' folds (fold.hpp) for the batch kernel.  The particle
+// fold (segments: the leaves) holds the PP items' slots and the PC/CP items'
+// target slots, each segment folded by the final task of the particle item
+// that owns the targets; the proxy fold (segments: the clusters) holds the CC
+// items' slots and the PC/CP items' source slots, each segment folded by the
 // downward task of the cluster before its parent's potentials are added.
 void upload_folds(bldtt_batch* b) {
     const Tree& T = b->T();
     const Work& w = b->work;
-    SymFold& pf = b->sym.pp_fold;
-    SymFold& cf = b->sym.cc_fold;
-    fold_parts(T, b->sym.pp_items, b->sym.pp_entries, false, pf);
+    SymWork& sw = b->sym;
+    SymFold& pf = sw.pp_fold;
+    SymFold& cf = sw.cc_fold;
+    const std::vector<FoldGroup> pg = {{&sw.pp_items, &sw.pp_entries, FoldGroup::kParticleBoth},
+                                       {&sw.pc_items, &sw.pc_entries, FoldGroup::kParticleTargets}};
+    const std::vector<FoldGroup> cg = {{&sw.cc_items, &sw.cc_entries, FoldGroup::kProxyBoth},
+                                       {&sw.pc_items, &sw.pc_entries, FoldGroup::kProxySources}};
+    std::vector<std::vector<int64_t>> pb, cb;
+    pf.clear();
+    cf.clear();
+    pf.nslots = fold_group_bases(pg, pb);
+    cf.nslots = fold_group_bases(cg, cb);
+    fold_group_parts(T, false, pg, pb, pf);
+    fold_group_parts(T, true, cg, cb, cf);
     // the PP segments are the leaves in cluster order
     std::vector<int32_t> leaf_seg(T.size(), -1);
     size_t k = 0;
@@ -273,12 +286,14 @@ void upload_folds(bldtt_batch* b) {
         cseg[c] = (int32_t)k;
     }
     b->sslots.alloc(sizeof(double) * std::max<int64_t>(1, pf.nslots));
-    upload(b->sbase, pf.ibase);
+    upload(b->sbase, pb[0]);
+    upload(b->mtbase, pb[1]);
     upload(b->psegs, pf.segs);
     upload(b->pparts, pf.parts);
     upload(b->pseg, pseg);
     b->cslots.alloc(sizeof(double) * std::max<int64_t>(1, cf.nslots));
-    upload(b->cbase, cf.ibase);
+    upload(b->cbase, cb[0]);
+    upload(b->msbase, cb[1]);
     upload(b->csegs, cf.segs);
     upload(b->cparts, cf.parts);
     upload(b->cseg, cseg);
@@ -290,7 +305,7 @@ void pack(bldtt_batch* b, int tpt) {
     Work& w = b->work;
     w.guard_near = (b->flags & BLDTT_FP32_EVAL) != 0;   // FP32 batches guard near particle ranges too
     if (b->symmetric()) {
-        split_symmetric(b->T(), b->lists, b->degree, true, true, b->rest, b->sym);
+        split_symmetric(b->T(), b->lists, b->degree, true, true, b->rest, b->sym, {}, false, true);
         const std::vector<uint32_t> extra = sym_cc_degrees(b->T(), b->sym);
         pack_work(b->T(), b->S, b->rest, b->degree, kThreads * tpt, kThreads * tpt, w, &extra);
     } else {
@@ -300,10 +315,13 @@ void pack(bldtt_batch* b, int tpt) {
     for (int k = 0; k < 4; ++k) b->stats.interactions[k] = w.interactions[k];
     b->stats.interactions[PP] += b->sym.pp_evaluations;
     b->stats.interactions[CC] += b->sym.cc_evaluations;
+    b->stats.interactions[PC] += 0.5 * b->sym.pc_evaluations;     // each value serves one PC and one CP term
+    b->stats.interactions[CP] += 0.5 * b->sym.pc_evaluations;
     b->packed_tpt = tpt;
     b->packed_tpt_valid = true;
     b->stats.n_tasks = (int64_t)b->n_leaves + b->n_parents + (int64_t)w.qitems.size() + 2 * (int64_t)w.pitems.size() +
-                       (int64_t)b->sym.pp_items.size() + (int64_t)b->sym.cc_items.size() + b->n_kids;
+                       (int64_t)b->sym.pp_items.size() + (int64_t)b->sym.cc_items.size() +
+                       (int64_t)b->sym.pc_items.size() + b->n_kids;
     if (b->host_only) return;
     auto needs = [](const std::vector<Item>& items, const std::vector<Entry>& entries) {
         std::vector<uint8_t> f(items.size(), 0);
@@ -316,13 +334,16 @@ void pack(bldtt_batch* b, int tpt) {
         return f;
     };
     // contributions each target cluster's proxy potentials wait for: its proxy
-    // items, and every symmetric CC item of it or with it as a partner
+    // items, every symmetric CC item of it or with it as a partner, and every
+    // symmetric PC/CP item with it as a partner
     std::vector<int32_t> nq(b->T().size(), 0);
     for (const Item& it : w.qitems) nq[it.cluster] += 1;
     for (const Item& it : b->sym.cc_items) {
         nq[it.cluster] += 1;
         for (int e = it.eb; e < it.ee; ++e) nq[b->sym.cc_entries[e].a] += 1;
     }
+    for (const Item& it : b->sym.pc_items)
+        for (int e = it.eb; e < it.ee; ++e) nq[b->sym.pc_entries[e].a] += 1;
     upload(b->qitems, w.qitems);
     upload(b->qentries, w.qentries);
     upload(b->qneeds, needs(w.qitems, w.qentries));
@@ -335,8 +356,12 @@ void pack(bldtt_batch* b, int tpt) {
     upload(b->sentries, b->sym.pp_entries);
     upload(b->citems, b->sym.cc_items);
     upload(b->centries, b->sym.cc_entries);
+    upload(b->mitems, b->sym.pc_items);
+    upload(b->mentries, b->sym.pc_entries);
+    // symmetric items each problem's final interpolations wait for (PP and PC/CP)
     std::vector<int32_t> s_need(b->count, 0);
     for (const Item& it : b->sym.pp_items) s_need[b->prob_of_cluster[it.cluster]] += 1;
+    for (const Item& it : b->sym.pc_items) s_need[b->prob_of_cluster[it.cluster]] += 1;
     upload(b->s_need, s_need);
     if (b->symmetric()) upload_folds(b);
     b->n_counters = kGlobalCounters + b->S.size() + b->T().size() + (int64_t)w.pitems.size() + b->count;
@@ -389,9 +414,14 @@ BatchDev device_args(const bldtt_batch* b) {
     a.citems = b->citems.as<DevItem>();
     a.centries = b->centries.as<int2>();
     a.n_c = (int)b->sym.cc_items.size();
+    a.mitems = b->mitems.as<DevItem>();
+    a.mentries = b->mentries.as<int2>();
+    a.n_m = (int)b->sym.pc_items.size();
     if (b->symmetric()) {
         a.sslots = b->sslots.as<double>();
         a.sbase = b->sbase.as<int64_t>();
+        a.mtbase = b->mtbase.as<int64_t>();
+        a.msbase = b->msbase.as<int64_t>();
         a.psegs = b->psegs.as<FoldSeg>();
         a.pparts = b->pparts.as<FoldPart>();
         a.pseg = b->pseg.as<int32_t>();
@@ -402,7 +432,7 @@ BatchDev device_args(const bldtt_batch* b) {
         a.cseg = b->cseg.as<int32_t>();
     }
     a.n_kids = b->n_kids;
-    a.n_tasks = a.n_leaves + a.n_parents + a.n_q + a.n_c + 2 * a.n_p + a.n_s + a.n_kids;
+    a.n_tasks = a.n_leaves + a.n_parents + a.n_q + a.n_c + a.n_m + 2 * a.n_p + a.n_s + a.n_kids;
     a.spin_limit = b->spin_limit;
     a.param = b->param;
     return a;

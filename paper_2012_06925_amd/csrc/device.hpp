@@ -935,13 +935,16 @@ constexpr int sym_lds_bytes() {
 // the move of its partial serve H pairs.  An item whose targets fill nslab = 1
 // or 2 waves runs 4 / nslab copies of those waves, each over its own 64 of the
 // 64 * copies sources staged per round.  The copies' target sums are added in
-// copy order in LDS and each target's total written to slots[base + r]; each
-// source's partial goes to its slot of the entry (after the targets, entry
-// by entry).
-template <bool F32, bool PROXY, int H = 2>
+// copy order in LDS and each target's total written to tslots[tbase + r]; the
+// partial of the item's g-th source (its entries' sources one after another)
+// goes to sslots[sbase + g].  PROXY: the targets are proxies (of degree
+// it.degree), else particles; SPROXY: the same for the sources (PP: neither,
+// CC: both, the PC/CP pairs of a particle tile with proxy grids: sources).
+template <bool F32, bool PROXY, int H = 2, bool SPROXY = PROXY>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, const double* __restrict__ tab, DegPtrs qhat, void* lds,
-                                         double* nfp64, double* __restrict__ slots, int64_t base) {
+                                         double* nfp64, double* __restrict__ tslots, int64_t tbase,
+                                         double* __restrict__ sslots, int64_t sbase) {
     using R = typename std::conditional<F32, float, double>::type;
     using V = typename std::conditional<F32, float4, double4>::type;
     // FP64: charges staged as q/2 for the folded Newton step (E64<K_COULOMB>)
@@ -960,7 +963,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                  cz = F32 ? 0.5 * (box[2] + box[5]) : 0.0;
     // proxies: degree of the item, grid size, per-degree tables and arrays
     const int m = it.degree + 1, P = m * m * m;
-    const double* qd = PROXY ? qhat.p[it.degree] : nullptr;
+    const double* qd = PROXY || SPROXY ? qhat.p[it.degree] : nullptr;
     R tx[H], ty[H], tz[H];
     double qi[H];               // FP32 form: the charge rounded to FP32, held in FP64
     int ti[H];
@@ -998,7 +1001,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     // entry boundaries, so only the last round has idle lanes.
     constexpr int kLow = (1 << 29) - 1;
     int G = 0;
-    for (int e = it.eb; e < it.ee; ++e) G += PROXY ? P : (entries[e].y & kLow);
+    for (int e = it.eb; e < it.ee; ++e) G += SPROXY ? P : (entries[e].y & kLow);
     int ec = it.eb, oc = 0;                                // entry and offset of the round's first source
     for (int r0 = 0; r0 < G; r0 += span) {
         // where the next round starts; the round guards r^2 == 0 if any entry
@@ -1008,8 +1011,8 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
         int e1 = ec, o1 = oc + span;
         while (e1 < it.ee) {
             const int2 en = entries[e1];
-            guard |= !PROXY && ((unsigned)en.y >> 29) == 1u;
-            const int bn = PROXY ? P : (en.y & kLow);
+            guard |= !PROXY && !SPROXY && ((unsigned)en.y >> 29) == 1u;
+            const int bn = SPROXY ? P : (en.y & kLow);
             if (o1 < bn) break;
             o1 -= bn;
             ++e1;
@@ -1022,14 +1025,14 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
             int2 en = make_int2(0, 0);
             while (e < it.ee) {
                 en = entries[e];
-                const int bn = PROXY ? P : (en.y & kLow);
+                const int bn = SPROXY ? P : (en.y & kLow);
                 if (o < bn) break;
                 o -= bn;
                 ++e;
             }
             if (e < it.ee) {
                 double x, y, z, q;
-                if constexpr (PROXY) {                     // proxy entries: en.x = cluster B
+                if constexpr (SPROXY) {                    // proxy entries: en.x = cluster B
                     proxy_point(T.box + 6 * en.x, m, tab + 32 * it.degree, o, x, y, z);
                     q = qd[(int64_t)en.x * P + o];
                 } else {
@@ -1065,7 +1068,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
                         r2 = dx * dx + r2;
                         if constexpr (F32) {
                             y[h] = (double)__builtin_amdgcn_rsqf(r2);
-                            if constexpr (!PROXY && decltype(guard)::value) {
+                            if constexpr (!PROXY && !SPROXY && decltype(guard)::value) {
                                 if (r2 <= thr32) {       // closer than FP32 resolves: FP64
                                     const int sj = sidx[64 * copy + ((lane + s) & 63)];
                                     y[h] = mine[h] && sj >= 0 ? g_fp64<K_COULOMB>(p, ti[h], p, sj, 0.0, nfp64) : 0.0;
@@ -1108,7 +1111,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
             double t = 0.0;
             for (int w = 0; w < nslab; ++w)
                 if (64 * H * w < it.tn) t += part_red[k * nslab + w][ms];
-            slots[base + it.tn + r0 + tid] = t;
+            sslots[sbase + r0 + tid] = t;
         }
         ec = e1;
         oc = o1;
@@ -1124,7 +1127,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     for (int r = tid; r < it.tn; r += kBlock) {
         double t = 0.0;
         for (int k = 0; k < copies; ++k) t += red[k * stride + r];
-        slots[base + r] = t;
+        tslots[tbase + r] = t;
     }
 }
 

@@ -219,20 +219,39 @@ void fold_bases(const std::vector<Item>& items, const std::vector<Entry>& entrie
 void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
                 SymFold& f);
 
+// A fold whose parts come from several item lists, taken in order (each
+// item's parts in order): symmetric PP items (their target tile and source
+// ranges, particle segments), symmetric CC items (target tile and source
+// proxies, proxy segments), and the two sides of the symmetric PC/CP items:
+// their target particles (particle segments, split at leaf boundaries) and
+// their source proxies (proxy segments).  fold_group_bases gives each item its
+// slot base (all groups' slots one after another) and returns the slot count.
+struct FoldGroup {
+    enum Kind { kParticleBoth, kProxyBoth, kParticleTargets, kProxySources };
+    const std::vector<Item>* items;
+    const std::vector<Entry>* entries;
+    Kind kind;
+};
+int64_t fold_group_bases(const std::vector<FoldGroup>& groups, std::vector<std::vector<int64_t>>& bases);
+void fold_group_parts(const Tree& T, bool proxies, const std::vector<FoldGroup>& groups,
+                      const std::vector<std::vector<int64_t>>& bases, SymFold& f);
+
 struct SymWork {
-    std::vector<Entry> pp_entries, cc_entries;
-    std::vector<Item> pp_items, cc_items;
+    std::vector<Entry> pp_entries, cc_entries, pc_entries;
+    std::vector<Item> pp_items, cc_items, pc_items;
     SymFold pp_fold, cc_fold;
     int64_t pp_plain = 0;
-    double pp_evaluations = 0.0, cc_evaluations = 0.0;
+    double pp_evaluations = 0.0, cc_evaluations = 0.0, pc_evaluations = 0.0;
     bool guard_near = false;                    // setting, as Work::guard_near
     void clear() {
         pp_entries.clear();
         cc_entries.clear();
+        pc_entries.clear();
         pp_items.clear();
         cc_items.clear();
+        pc_items.clear();
         pp_plain = 0;
-        pp_evaluations = cc_evaluations = 0.0;
+        pp_evaluations = cc_evaluations = pc_evaluations = 0.0;
         pp_fold.clear();
         cc_fold.clear();
     }
@@ -242,10 +261,16 @@ struct SymWork {
 // start early.  The PP fold's parts are left to the caller (fold_parts: the
 // fold runs after the pass, so they can be built while it runs); the CC
 // fold is built whole.
+// With pc, a PC pair (A, B) whose mirror CP pair (B, A) is listed at the same
+// degree is evaluated once for both too (A's particles against B's proxies,
+// which are the same points as target and as source): pc_items are tiles of
+// A's particles with the proxy entries of such partners B, grouped by degree;
+// their folds are left to the caller (fold_group_*).
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
-                     const std::function<void()>& pp_ready = {}, bool separate_guarded = false);
+                     const std::function<void()>& pp_ready = {}, bool separate_guarded = false, bool pc = false);
 
-// Per-cluster degree masks of the symmetric CC pairs (both clusters of each pair).
+// Per-cluster degree masks of the proxy potentials the symmetric passes add
+// to: both clusters of each CC pair, the proxy side of each PC/CP pair.
 std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw);
 
 }  // namespace bldtt

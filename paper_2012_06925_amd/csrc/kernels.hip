@@ -109,9 +109,9 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
     const DevItem it = items[blockIdx.x];
     const int64_t base = out.ibase[blockIdx.x];
     if (it.tn > 128)
-        sym_body<F32, PROXY, 4>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base);
+        sym_body<F32, PROXY, 4>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base, out.slots, base + it.tn);
     else
-        sym_body<F32, PROXY, 2>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base);
+        sym_body<F32, PROXY, 2>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base, out.slots, base + it.tn);
 }
 
 // ---------------------------------------------------------------------------

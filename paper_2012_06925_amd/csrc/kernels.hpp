@@ -168,14 +168,20 @@ struct BatchDev {
     const DevItem* citems;      // symmetric CC items (same batches), after the proxy items
     const int2* centries;
     int n_c;
-    // folds of the symmetric items (fold.hpp; set when n_s or n_c is nonzero)
-    double* sslots;             // symmetric PP items' slots, slot base per item, segments per leaf
-    const int64_t* sbase;
+    const DevItem* mitems;      // symmetric PC/CP items (same batches): particle tiles, proxy entries
+    const int2* mentries;
+    int n_m;
+    // folds of the symmetric items (fold.hpp; set for batches of targets =
+    // sources Coulomb problems in FP64, else null)
+    double* sslots;             // particle fold: the s items' slots, then the m items' target slots;
+    const int64_t* sbase;       // slot base per s item, segments per leaf
+    const int64_t* mtbase;      // per m item: the base of its target slots here
     const FoldSeg* psegs;
     const FoldPart* pparts;
     const int32_t* pseg;        // per particle item: the segment of its leaf
-    double* cslots;             // symmetric CC items' slots, slot base per item, segments per cluster
-    const int64_t* cbase;
+    double* cslots;             // proxy fold: the c items' slots, then the m items' source slots;
+    const int64_t* cbase;       // slot base per c item, segments per cluster
+    const int64_t* msbase;      // per m item: the base of its source slots here
     const FoldSeg* csegs;
     const FoldPart* cparts;
     const int32_t* cseg;        // per target cluster: its segment, or -1

@@ -585,20 +585,21 @@ std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw) {
     std::vector<uint32_t> m(T.size(), 0u);
     for (const Item& it : sw.cc_items) m[it.cluster] |= 1u << it.degree;
     for (const Entry& e : sw.cc_entries) m[e.a] |= 1u << (e.b & kCountMask);
+    for (const Entry& e : sw.pc_entries) m[e.a] |= 1u << (e.b & kCountMask);
     return m;
 }
 
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
-                     const std::function<void()>& pp_ready, bool separate_guarded) {
+                     const std::function<void()>& pp_ready, bool separate_guarded, bool pc) {
     sw.clear();
     const int64_t nc = T.size();
     constexpr int64_t kBlk = 256, kTile = 256;
     const int64_t nblk = (nc + kBlk - 1) / kBlk;
     // kept per calling thread, so a plan repacked every compute touches no fresh
     // pages; the workers reach the caller's copies through these references
-    static thread_local PairIndex tl_ipp, tl_icc;
+    static thread_local PairIndex tl_ipp, tl_icc, tl_ipc, tl_icp;
     static thread_local std::vector<uint8_t> tl_keep;
-    PairIndex &ipp = tl_ipp, &icc = tl_icc;
+    PairIndex &ipp = tl_ipp, &icc = tl_icc, &ipc = tl_ipc, &icp = tl_icp;
     std::vector<uint8_t>& keep = tl_keep;
     const std::vector<int8_t> no_degrees;        // PP pairs are matched without their degree
     if (pp)
@@ -609,6 +610,13 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         return pp && a != b && T.is_leaf(a) && T.is_leaf(b) && ipp.has(a, b, 0) && ipp.has(b, a, 0);
     };
     auto sym_cc = [&](int64_t a, int64_t b, int d) { return cc && a != b && icc.has(a, b, d) && icc.has(b, a, d); };
+    if (pc) {
+        auto all = [](int64_t, int64_t) { return true; };
+        ipc.build(nc, L.tc[PC], L.sc[PC], L.deg[PC], degree, all);        // particles of a <- proxies of b
+        icp.build(nc, L.tc[CP], L.sc[CP], L.deg[CP], degree, all);        // proxies of a <- particles of b
+    }
+    // PC (a, b) listed with its mirror CP (b, a) at degree d
+    auto sym_pc = [&](int64_t a, int64_t b, int d) { return pc && ipc.has(a, b, d) && icp.has(b, a, d); };
     if (pp) {
         // per leaf A: the partners B > A as merged particle ranges, tiles of A's particles
         std::vector<SymBlock> blks(nblk);
@@ -662,7 +670,7 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
     for (int k = 0; k < 4; ++k) {
         const bool typed = !L.deg[k].empty();
         const int64_t n = (int64_t)L.tc[k].size();
-        const bool filter = (k == PP && pp) || (k == CC && cc);
+        const bool filter = (k == PP && pp) || (k == CC && cc) || ((k == PC || k == CP) && pc);
         if (!filter) {
             rest.tc[k] = L.tc[k];
             rest.sc[k] = L.sc[k];
@@ -678,7 +686,8 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
             for (int64_t e = c * per; e < std::min(n, (c + 1) * per); ++e) {
                 const int64_t a = L.tc[k][e], b = L.sc[k][e];
                 const int d = typed ? (int)L.deg[k][e] : degree;
-                keep[e] = !((k == PP && sym_pp(a, b)) || (k == CC && sym_cc(a, b, d)));
+                keep[e] = !((k == PP && sym_pp(a, b)) || (k == CC && sym_cc(a, b, d)) || (k == PC && sym_pc(a, b, d)) ||
+                            (k == CP && sym_pc(b, a, d)));
                 m += keep[e];
             }
             kept[c + 1] = m;
@@ -732,6 +741,37 @@ void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc
         gather(blks, sw.cc_entries, sw.cc_items, sw.cc_evaluations);
         build_fold(T, sw.cc_items, sw.cc_entries, true, sw.cc_fold);
     }
+    if (pc) {
+        // per (cluster A, degree d): the partners B whose PC and CP pairs with A
+        // are both listed at d, as proxy entries; tiles of A's particles
+        std::vector<SymBlock> blks(nblk);
+        parallel_run(nblk, [&](int64_t bi) {
+            SymBlock& B = blks[bi];
+            for (int64_t a = bi * kBlk; a < std::min(nc, (bi + 1) * kBlk); ++a) {
+                uint32_t used = 0;
+                for (int64_t q = ipc.off[a]; q < ipc.off[a + 1]; ++q) used |= 1u << ipc.part[q].second;
+                for (int d = 0; d <= kMaxDegree; ++d) {
+                    if (!(used >> d & 1)) continue;
+                    const int64_t eb = (int64_t)B.entries.size();
+                    for (int64_t q = ipc.off[a]; q < ipc.off[a + 1]; ++q) {
+                        const int64_t b = ipc.part[q].first;
+                        if (ipc.part[q].second == d && icp.has(b, a, d))
+                            B.entries.push_back(Entry{(int32_t)b, (int32_t)((uint32_t)SRC_PROXY << 29 | (uint32_t)d)});
+                    }
+                    const int64_t ee = (int64_t)B.entries.size();
+                    if (ee == eb) continue;
+                    const double np = (double)cube(d) * (double)(ee - eb);
+                    B.evals += 2.0 * (double)T.count[a] * np;
+                    for (int64_t tb = T.begin[a]; tb < T.begin[a] + T.count[a]; tb += kTile) {
+                        const int64_t tn = std::min<int64_t>(kTile, T.begin[a] + T.count[a] - tb);
+                        B.items.push_back({np * (double)tn, Item{(int32_t)tb, (int32_t)tn, (int32_t)eb, (int32_t)ee,
+                                                                 (int32_t)a, (int32_t)d, (int32_t)tb}});
+                    }
+                }
+            }
+        });
+        gather(blks, sw.pc_entries, sw.pc_items, sw.pc_evaluations);
+    }
 }
 
 void build_fold(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
@@ -740,30 +780,40 @@ void build_fold(const Tree& T, const std::vector<Item>& items, const std::vector
     fold_parts(T, items, entries, proxies, f);
 }
 
-void fold_bases(const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies, SymFold& f) {
-    f.clear();
-    const int64_t ni = (int64_t)items.size();
-    // slot bases: per item its targets, then its sources in entry order
-    f.ibase.resize(ni);
-    int64_t slots = 0;
-    for (int64_t i = 0; i < ni; ++i) {
-        const Item& it = items[i];
-        f.ibase[i] = slots;
-        slots += it.tn;
-        if (proxies) {
-            slots += cube(it.degree) * (int64_t)(it.ee - it.eb);
-        } else {
-            for (int32_t e = it.eb; e < it.ee; ++e) slots += (int64_t)(entries[e].b & kCountMask);
-        }
-    }
-    f.nslots = slots;
+namespace {
+
+// Slots of one item of a fold group: its targets, its sources, or both.
+int64_t group_item_slots(const FoldGroup& g, const Item& it) {
+    int64_t n = 0;
+    if (g.kind != FoldGroup::kProxySources) n += it.tn;
+    if (g.kind == FoldGroup::kParticleTargets) return n;
+    if (g.kind == FoldGroup::kProxyBoth || g.kind == FoldGroup::kProxySources)
+        return n + cube(it.degree) * (int64_t)(it.ee - it.eb);
+    for (int32_t e = it.eb; e < it.ee; ++e) n += (int64_t)((*g.entries)[e].b & kCountMask);
+    return n;
 }
 
-void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
-                SymFold& f) {
+}  // namespace
+
+int64_t fold_group_bases(const std::vector<FoldGroup>& groups, std::vector<std::vector<int64_t>>& bases) {
+    bases.assign(groups.size(), {});
+    int64_t slots = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const std::vector<Item>& items = *groups[g].items;
+        bases[g].resize(items.size());
+        for (size_t i = 0; i < items.size(); ++i) {
+            bases[g][i] = slots;
+            slots += group_item_slots(groups[g], items[i]);
+        }
+    }
+    return slots;
+}
+
+void fold_group_parts(const Tree& T, bool proxies, const std::vector<FoldGroup>& groups,
+                      const std::vector<std::vector<int64_t>>& bases, SymFold& f) {
     f.segs.clear();
     f.parts.clear();
-    const int64_t ni = (int64_t)items.size(), nc = T.size();
+    const int64_t nc = T.size();
     constexpr int D = kMaxDegree + 1;
     // segments: every leaf in cluster order (particles), or every (cluster,
     // degree) an item or an entry names, by degree then cluster (proxies)
@@ -780,11 +830,11 @@ void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector
             }
     } else {
         std::vector<uint8_t> used(nc * D, 0);
-        for (int64_t i = 0; i < ni; ++i) {
-            const Item& it = items[i];
-            used[it.degree * nc + it.cluster] = 1;
-            for (int32_t e = it.eb; e < it.ee; ++e) used[it.degree * nc + entries[e].a] = 1;
-        }
+        for (const FoldGroup& g : groups)
+            for (const Item& it : *g.items) {
+                if (g.kind == FoldGroup::kProxyBoth) used[it.degree * nc + it.cluster] = 1;
+                for (int32_t e = it.eb; e < it.ee; ++e) used[it.degree * nc + (*g.entries)[e].a] = 1;
+            }
         seg_of.assign(nc * D, -1);
         for (int d = 0; d < D; ++d)
             for (int64_t c = 0; c < nc; ++c)
@@ -797,30 +847,49 @@ void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector
         const size_t k = (size_t)(std::upper_bound(leaf_begin.begin(), leaf_begin.end(), pos) - leaf_begin.begin()) - 1;
         return leaf_id[k];
     };
-    // one item's parts in order: its target tile, then its sources entry by
-    // entry (particle ranges split at leaf boundaries)
-    auto emit = [&](int64_t i, auto&& put) {
-        const Item& it = items[i];
-        int64_t o = f.ibase[i];
-        if (proxies) {
+    // parts of a particle range [a, a + len) whose slots start at o, split at leaf boundaries
+    auto range_parts = [&](int64_t a, int64_t len, int64_t o, auto&& put) {
+        for (int64_t pos = a; pos < a + len;) {
+            const int64_t L = leaf_at(pos);
+            const int64_t end = std::min(a + len, T.begin[L] + T.count[L]);
+            put(seg_of[L], FoldPart{o + (pos - a), (int32_t)(pos - T.begin[L]), (int32_t)(end - pos)});
+            pos = end;
+        }
+    };
+    // the items of all groups one after another; one item's parts in order:
+    // its target tile, then its sources entry by entry
+    std::vector<int64_t> first(groups.size() + 1, 0);
+    for (size_t g = 0; g < groups.size(); ++g) first[g + 1] = first[g] + (int64_t)groups[g].items->size();
+    const int64_t ni = first[groups.size()];
+    auto emit = [&](int64_t vi, auto&& put) {
+        const size_t g = (size_t)(std::upper_bound(first.begin(), first.end(), vi) - first.begin()) - 1;
+        const FoldGroup& G = groups[g];
+        const Item& it = (*G.items)[vi - first[g]];
+        const std::vector<Entry>& entries = *G.entries;
+        int64_t o = bases[g][vi - first[g]];
+        switch (G.kind) {
+        case FoldGroup::kProxyBoth:
+        case FoldGroup::kProxySources: {
             const int64_t P = cube(it.degree);
-            put(seg_of[it.degree * nc + it.cluster], FoldPart{o, it.t0, it.tn});
-            o += it.tn;
+            if (G.kind == FoldGroup::kProxyBoth) {
+                put(seg_of[it.degree * nc + it.cluster], FoldPart{o, it.t0, it.tn});
+                o += it.tn;
+            }
             for (int32_t e = it.eb; e < it.ee; ++e, o += P)
                 put(seg_of[it.degree * nc + entries[e].a], FoldPart{o, 0, (int32_t)P});
             return;
         }
-        put(seg_of[it.cluster], FoldPart{o, (int32_t)(it.t0 - T.begin[it.cluster]), it.tn});
-        o += it.tn;
-        for (int32_t e = it.eb; e < it.ee; ++e) {
-            const int64_t a = entries[e].a, len = entries[e].b & kCountMask;
-            for (int64_t pos = a; pos < a + len;) {
-                const int64_t L = leaf_at(pos);
-                const int64_t end = std::min(a + len, T.begin[L] + T.count[L]);
-                put(seg_of[L], FoldPart{o + (pos - a), (int32_t)(pos - T.begin[L]), (int32_t)(end - pos)});
-                pos = end;
+        case FoldGroup::kParticleTargets:
+            range_parts(it.t0, it.tn, o, put);
+            return;
+        default:
+            put(seg_of[it.cluster], FoldPart{o, (int32_t)(it.t0 - T.begin[it.cluster]), it.tn});
+            o += it.tn;
+            for (int32_t e = it.eb; e < it.ee; ++e) {
+                const int64_t len = entries[e].b & kCountMask;
+                range_parts(entries[e].a, len, o, put);
+                o += len;
             }
-            o += len;
         }
     };
     // parts grouped by segment, chunks of items in order (a parallel counting
@@ -849,6 +918,20 @@ void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector
         for (int64_t i = k * per; i < std::min(ni, (k + 1) * per); ++i)
             emit(i, [&](int32_t sg, const FoldPart& pt) { f.parts[fill[sg]++] = pt; });
     });
+}
+
+void fold_bases(const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies, SymFold& f) {
+    f.clear();
+    std::vector<std::vector<int64_t>> bases;
+    const FoldGroup g{&items, &entries, proxies ? FoldGroup::kProxyBoth : FoldGroup::kParticleBoth};
+    f.nslots = fold_group_bases({g}, bases);
+    f.ibase = std::move(bases[0]);
+}
+
+void fold_parts(const Tree& T, const std::vector<Item>& items, const std::vector<Entry>& entries, bool proxies,
+                SymFold& f) {
+    const FoldGroup g{&items, &entries, proxies ? FoldGroup::kProxyBoth : FoldGroup::kParticleBoth};
+    fold_group_parts(T, proxies, {g}, {f.ibase}, f);
 }
 
 }  // namespace bldtt
