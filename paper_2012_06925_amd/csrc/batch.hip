@@ -115,9 +115,13 @@ constexpr int cmax() { return A > B ? A : B; }
 
 template <int KIND, bool F32, int T, int M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchDev a) {
+    // the downward task folds beside the transfer's staged data, the final task
+    // before the interpolation
+    constexpr int kFoldLds = (int)sizeof(FoldPart) * kFoldLdsParts;
+    constexpr int kXferFold = (down_transfer_lds_bytes<M>() + 15) / 16 * 16;
     constexpr int kLds = cmax<cmax<cmax<interact_lds_bytes<F32>(), up_leaf_lds_bytes<M>()>(), sym_lds_bytes<F32>()>(),
-                              cmax<cmax<up_transfer_lds_bytes<M>(), down_transfer_lds_bytes<M>()>(),
-                                   down_leaf_lds_bytes<M>()>()>();
+                              cmax<cmax<up_transfer_lds_bytes<M>(), kXferFold + kFoldLds>(),
+                                   cmax<down_leaf_lds_bytes<M>(), kFoldLds>()>()>();
     __shared__ double4 pool[(kLds + 31) / 32];
     __shared__ int s_task;
     double* dl = reinterpret_cast<double*>(pool);
@@ -214,7 +218,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             down_transfer_stage<M>(c, a.T, a.tab, a.phihat, dl);
             if (a.cslots && a.cseg[c] >= 0) {
                 const FoldSeg sg = a.csegs[a.cseg[c]];
-                fold_body(sg, a.cparts, a.cslots, a.phihat + sg.off, 0, sg.n);
+                fold_body(sg, a.cparts, a.cslots, a.phihat + sg.off, 0, sg.n,
+                          reinterpret_cast<FoldPart*>(reinterpret_cast<char*>(pool) + kXferFold));
             }
             __syncthreads();
             down_transfer_apply<M>(c, a.phihat, dl);
@@ -229,7 +234,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (a.sslots && a.pseg[i] >= 0) {
                 const FoldSeg sg = a.psegs[a.pseg[i]];
                 const int k0 = it.t0 - (int)sg.off;
-                fold_body(sg, a.pparts, a.sslots, a.phi_tree + sg.off, k0, k0 + it.tn);
+                fold_body(sg, a.pparts, a.sslots, a.phi_tree + sg.off, k0, k0 + it.tn,
+                          reinterpret_cast<FoldPart*>(pool));
                 __syncthreads();              // the interpolation reads what other threads folded
             }
             down_leaf_body<M>(it, a.has_far[c] != 0, a.tgt, a.T, a.tab, a.phihat, a.phi_tree, a.perm,

@@ -512,16 +512,20 @@ __device__ __forceinline__ void up_transfer_body(int c, DevTree S, const double*
 // output 0): each adds the slots of its parts in their stored order, so the
 // sums do not depend on which item finished first.  The group's threads share
 // the outputs; the caller synchronises before other threads read them.
-// Latency, not bandwidth, bounds a fold (a few parts per output, slots
-// written by other CUs): a thread takes R outputs at once and the parts go
-// eight at a time, 8 R independent loads per batch; a part that does not
-// cover an output, or lies past the segment's end, reads a slot that exists
-// (its own first, or the segment's first part's) and is not added.
-template <int R>
+// Latency, not bandwidth, bounds a fold (tens of parts per output, slots
+// written by other CUs, caches cold after the dependency fences): the
+// segment's parts go to LDS (`lp`, room for kFoldLdsParts) in one coalesced
+// load per chunk, and a thread takes R outputs at once with U parts per
+// batch, R U independent slot loads; a part that does not cover an output,
+// or lies past the chunk's end, reads a slot that exists (its own first, or
+// the chunk's first part's) and is not added.  Every thread of the group
+// must call it (it synchronises).
+constexpr int kFoldLdsParts = 512;
+
+template <int R, int U>
 __device__ __forceinline__ void fold_pass(const FoldSeg& sg, const FoldPart* __restrict__ parts,
                                           const double* __restrict__ slots, double* __restrict__ out, int k0,
-                                          int k1) {
-    constexpr int U = 8;
+                                          int k1, FoldPart* lp) {
     for (int kb = k0; kb < k1; kb += R * kBlock) {
         int k[R];
         double v[R];
@@ -530,24 +534,30 @@ __device__ __forceinline__ void fold_pass(const FoldSeg& sg, const FoldPart* __r
             k[r] = kb + r * kBlock + (int)threadIdx.x;
             v[r] = 0.0;
         }
-        for (int q = sg.pb; q < sg.pe; q += U) {
-            double s[U][R];
-            bool in[U][R];
+        for (int c0 = sg.pb; c0 < sg.pe; c0 += kFoldLdsParts) {
+            const int cn = min(kFoldLdsParts, sg.pe - c0);
+            __syncthreads();                                   // the previous chunk's readers are done
+            for (int j = threadIdx.x; j < cn; j += kBlock) lp[j] = parts[c0 + j];
+            __syncthreads();
+            for (int q = 0; q < cn; q += U) {
+                double s[U][R];
+                bool in[U][R];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool real = q + u < sg.pe;
-                const FoldPart pt = parts[real ? q + u : sg.pb];
+                for (int u = 0; u < U; ++u) {
+                    const bool real = q + u < cn;
+                    const FoldPart pt = lp[real ? q + u : 0];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const unsigned d = (unsigned)(k[r] - pt.lo);
-                    in[u][r] = real && d < (unsigned)pt.len;
-                    s[u][r] = slots[pt.slot + (in[u][r] ? d : 0u)];
+                    for (int r = 0; r < R; ++r) {
+                        const unsigned d = (unsigned)(k[r] - pt.lo);
+                        in[u][r] = real && d < (unsigned)pt.len;
+                        s[u][r] = slots[pt.slot + (in[u][r] ? d : 0u)];
+                    }
                 }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[r] = in[u][r] ? v[r] + s[u][r] : v[r];
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = in[u][r] ? v[r] + s[u][r] : v[r];
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -556,10 +566,11 @@ __device__ __forceinline__ void fold_pass(const FoldSeg& sg, const FoldPart* __r
 }
 
 __device__ __forceinline__ void fold_body(const FoldSeg& sg, const FoldPart* __restrict__ parts,
-                                          const double* __restrict__ slots, double* __restrict__ out, int k0, int k1) {
+                                          const double* __restrict__ slots, double* __restrict__ out, int k0, int k1,
+                                          FoldPart* lp) {
     if (sg.pe == sg.pb) return;
-    if (k1 - k0 > kBlock) fold_pass<2>(sg, parts, slots, out, k0, k1);
-    else fold_pass<1>(sg, parts, slots, out, k0, k1);
+    if (k1 - k0 > kBlock) fold_pass<2, 8>(sg, parts, slots, out, k0, k1, lp);
+    else fold_pass<1, 16>(sg, parts, slots, out, k0, k1, lp);
 }
 
 template <int M>

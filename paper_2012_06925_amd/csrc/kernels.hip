@@ -122,8 +122,9 @@ __global__ __launch_bounds__(kBlock) void k_sym_fold(const FoldSeg* __restrict__
                                                      const FoldPart* __restrict__ parts,
                                                      const double* __restrict__ slots, double* __restrict__ phi,
                                                      DegOut phihat) {
+    __shared__ FoldPart lp[kFoldLdsParts];
     const FoldSeg sg = segs[blockIdx.x];
-    fold_body(sg, parts, slots, (sg.deg < 0 ? phi : phihat.p[sg.deg]) + sg.off, 0, sg.n);
+    fold_body(sg, parts, slots, (sg.deg < 0 ? phi : phihat.p[sg.deg]) + sg.off, 0, sg.n, lp);
 }
 
 // ---------------------------------------------------------------------------
