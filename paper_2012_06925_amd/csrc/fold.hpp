@@ -8,7 +8,11 @@
 // to every output, in a fixed order, the slot values that belong to it:
 // segment s covers outputs [0, n) at `off` of phi (deg < 0) or of the proxy
 // potentials of degree deg, and its parts pb .. pe-1 each give the values
-// slots[slot + k - lo] of its outputs k in [lo, lo + len).
+// slots[slot + k - lo] of its outputs k in [lo, lo + len).  (In a batch the
+// PC/CP items, whose targets are particles and whose sources are proxies,
+// write their target sums to the particle fold's slots and their source
+// partials to the proxy fold's; each fold then takes parts from two item
+// lists, FoldGroup in engine.hpp.)
 #pragma once
 
 #include <cstdint>
