@@ -708,7 +708,7 @@ def main() -> int:
     args.sweep_leaves = [int(x) for x in args.sweep_leaves.split(",")] if args.sweep_leaves else None
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
         return 2
     if args.summarize_markers:
         summarize_markers(args.summarize_markers)

@@ -37,7 +37,7 @@ typedef enum {
     BLDTT_ENOMEM = -2,        /* host or device allocation failed                     */
     BLDTT_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed           */
     BLDTT_ESTATE = -4,        /* call not valid in the plan's current state           */
-    BLDTT_EUNSUPPORTED = -5   /* valid request this build does not implement          */
+    BLDTT_EUNSUPPORTED = -5   /* valid request the library does not implement         */
 } bldtt_status;
 
 /* Interaction kernels G(x, y) (paper Sec. 4.6); r = |x - y|.
