@@ -489,7 +489,19 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     }
     Lists& rest = pl->rest_lists;       // the lists without their symmetric pairs
     if (symm && !varied) {
-        split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym, {}, sep_guard);
+        // the near-field symmetric pass (the longest) is enqueued as soon as its
+        // items are packed, and the rest is packed while it runs; it writes
+        // only its slots, so it may run before the passes that write phi_tree
+        // (its fold keeps its place after them)
+        split_symmetric(T, pl->lists, pl->degree, true, true, rest, pl->sym, [&] {
+            Upload us;
+            us.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
+            add_bases(us, pl->fold_pp, pl->sym.pp_fold);
+            us.run(pl->staging_near, pl->arena_near, pl->staging_near_free, st);
+            PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
+            sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, st);
+            mark_host(2);
+        }, sep_guard);
         fold_parts(T, pl->sym.pp_items, pl->sym.pp_entries, false, pl->sym.pp_fold);
         drop_self_pairs(rest);
     }
@@ -526,11 +538,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     up.add(pl->pitems, w.pitems).add(pl->pentries, w.pentries).add(pl->qitems, w.qitems)
         .add(pl->qentries, w.qentries).add(pl->has_far, w.leaf_has_far).add(pl->prolong, w.prolong);
     if (varied || symm) up.add(pl->sep_items, sep_items);
-    if (!varied && symm) {
-        up.add(pl->sym_items, pl->sym.pp_items).add(pl->sym_entries, pl->sym.pp_entries);
-        add_bases(up, pl->fold_pp, pl->sym.pp_fold);
-        add_parts(up, pl->fold_pp, pl->sym.pp_fold);
-    }
+    if (!varied && symm) add_parts(up, pl->fold_pp, pl->sym.pp_fold);
     if (symm) {
         up.add(pl->sym_cc_items, scc.cc_items).add(pl->sym_cc_entries, scc.cc_entries);
         add_bases(up, pl->fold_cc, scc.cc_fold);
@@ -551,7 +559,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     //    downward transfer from the root
     const int D = w.down_degree;
     {
-        if (!varied) mark_host(2);
+        if (!varied && !symm) mark_host(2);
         PhaseMark mark(pl, BLDTT_PH_CPCC, st);
         const uint32_t need = w.tgt_degrees | (1u << D);
         clear_proxies(need & ~prefill);
@@ -586,13 +594,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             if (symm) particle_pass(pl->sep_items, (int)sep_items.size(), pl->pentries, true, st);
             else particle_pass(pl->pitems, (int)w.pitems.size(), pl->pentries, false, st);
         }
-        if (symm) {
-            {
-                PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
-                sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, st);
-            }
-            sym_pp_fold(st);
-        }
+        if (symm) sym_pp_fold(st);          // its pass was enqueued after the traversal
     } else {
         // the symmetric near-field pairs' fold: its parts are built now, while
         // the passes run, and it follows the near-field passes (the side
