@@ -335,6 +335,11 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     double* nfp64 = pl->nfp64_ptr();
     // the FP32 matrix-core symmetric pass runs guarded ranges as items of their own
     const bool sep_guard = fp32 && pl->mfma_transfer();
+    // targets per symmetric item: the matrix-core pass takes 256 (64 rows per
+    // wave), the vector-ALU pass 1024 (four per lane, four slabs), which
+    // stages each partner's sources, and writes their partials, a quarter as
+    // often
+    const int sym_tile = fp32 && pl->mfma_transfer() ? 256 : 1024;
     auto particle_pass = [&](const DevBuf& items, int n, const DevBuf& entries, bool add, hipStream_t s) {
         if (mfma_pp)
             launch_pp_mfma(items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab,
@@ -456,7 +461,7 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
                 PhaseMark mark(pl, BLDTT_PH_PP_SYM, pl->side);
                 sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, pl->side);
                 mark_host(2);
-            }, sep_guard);
+            }, sep_guard, false, sym_tile);
             drop_self_pairs(near_rest);
         }
         pack_work(T, S, symm ? near_rest : pl->lists, pl->degree, tile, ptile, pl->work_near);
@@ -501,11 +506,11 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
             PhaseMark mark(pl, BLDTT_PH_PP_SYM, st);
             sym_pp_pass(pl->sym_items, pl->sym_entries, pl->sym, st);
             mark_host(2);
-        }, sep_guard);
+        }, sep_guard, false, sym_tile);
         fold_parts(T, pl->sym.pp_items, pl->sym.pp_entries, false, pl->sym.pp_fold);
         drop_self_pairs(rest);
     }
-    if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep, {}, sep_guard);
+    if (symm && varied) split_symmetric(T, sep, pl->degree, false, true, rest, pl->sym_sep, {}, sep_guard, false, sym_tile);
     const SymWork& scc = varied ? pl->sym_sep : pl->sym;          // symmetric CC pairs
     std::vector<uint32_t> scc_deg;
     if (symm) scc_deg = sym_cc_degrees(T, scc);

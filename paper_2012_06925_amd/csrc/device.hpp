@@ -943,9 +943,9 @@ constexpr int sym_lds_bytes() {
 
 // One symmetric work item; `lds` holds sym_lds_bytes<F32>() bytes.  Each lane
 // holds H targets (rows 64 h + lane of its wave's 64 H), so a staged source and
-// the move of its partial serve H pairs.  An item whose targets fill nslab = 1
-// or 2 waves runs 4 / nslab copies of those waves, each over its own 64 of the
-// 64 * copies sources staged per round.  The copies' target sums are added in
+// the move of its partial serve H pairs.  An item whose targets fill nslab = 1,
+// 2 or 4 waves (at most 256 H targets) runs 4 / nslab copies of those waves,
+// each over its own 64 of the 64 * copies sources staged per round.  The copies' target sums are added in
 // copy order in LDS and each target's total written to tslots[tbase + r]; the
 // partial of the item's g-th source (its entries' sources one after another)
 // goes to sslots[sbase + g].  PROXY: the targets are proxies (of degree
@@ -964,7 +964,7 @@ __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restric
     double (*part_red)[64] = reinterpret_cast<double (*)[64]>(src + 4 * 128);  // [4][64] wave partials
     int* sidx = reinterpret_cast<int*>(part_red + 4);            // [4 * 64] staged particle index, -1: none
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nslab = it.tn <= 64 * H ? 1 : 2;
+    const int nslab = it.tn <= 64 * H ? 1 : (it.tn <= 128 * H ? 2 : 4);
     const int copies = 4 / nslab, copy = wave / nslab, sw = wave % nslab;
     const int span = 64 * copies;                                // sources staged per round
     const V* mysrc = src + 128 * copy;

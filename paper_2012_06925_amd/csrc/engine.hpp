@@ -265,9 +265,11 @@ struct SymWork {
 // degree is evaluated once for both too (A's particles against B's proxies,
 // which are the same points as target and as source): pc_items are tiles of
 // A's particles with the proxy entries of such partners B, grouped by degree;
-// their folds are left to the caller (fold_group_*).
+// their folds are left to the caller (fold_group_*).  `tile`: targets per
+// item at most (the pass that runs the items must take that many).
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
-                     const std::function<void()>& pp_ready = {}, bool separate_guarded = false, bool pc = false);
+                     const std::function<void()>& pp_ready = {}, bool separate_guarded = false, bool pc = false,
+                     int tile = 256);
 
 // Per-cluster degree masks of the proxy potentials the symmetric passes add
 // to: both clusters of each CC pair, the proxy side of each PC/CP pair.

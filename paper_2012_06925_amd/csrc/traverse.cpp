@@ -590,10 +590,11 @@ std::vector<uint32_t> sym_cc_degrees(const Tree& T, const SymWork& sw) {
 }
 
 void split_symmetric(const Tree& T, const Lists& L, int degree, bool pp, bool cc, Lists& rest, SymWork& sw,
-                     const std::function<void()>& pp_ready, bool separate_guarded, bool pc) {
+                     const std::function<void()>& pp_ready, bool separate_guarded, bool pc, int tile) {
     sw.clear();
     const int64_t nc = T.size();
-    constexpr int64_t kBlk = 256, kTile = 256;
+    constexpr int64_t kBlk = 256;
+    const int64_t kTile = tile;
     const int64_t nblk = (nc + kBlk - 1) / kBlk;
     // kept per calling thread, so a plan repacked every compute touches no fresh
     // pages; the workers reach the caller's copies through these references
