@@ -336,10 +336,24 @@ void compute(bldtt_plan* pl, double* out, hipStream_t st) {
     // the FP32 matrix-core symmetric pass runs guarded ranges as items of their own
     const bool sep_guard = fp32 && pl->mfma_transfer();
     // targets per symmetric item: the matrix-core pass takes 256 (64 rows per
-    // wave), the vector-ALU pass 1024 (four per lane, four slabs), which
+    // wave); the vector-ALU pass up to 1024 (four per lane, four slabs), which
     // stages each partner's sources, and writes their partials, a quarter as
-    // often
-    const int sym_tile = fp32 && pl->mfma_transfer() ? 256 : 1024;
+    // often, but only while the leaves still give at least 8 items per
+    // resident work group (4 per CU): fewer, larger items leave the GPU
+    // unbalanced on small problems
+    int sym_tile = 256;
+    if (!(fp32 && pl->mfma_transfer())) {
+        const int64_t want = 8 * 4 * (int64_t)std::max(1, pl->cus);
+        for (int t : {1024, 512}) {
+            int64_t items = 0;
+            for (int64_t c = 0; c < T.size(); ++c)
+                if (T.is_leaf(c)) items += (T.count[c] + t - 1) / t;
+            if (items >= want) {
+                sym_tile = t;
+                break;
+            }
+        }
+    }
     auto particle_pass = [&](const DevBuf& items, int n, const DevBuf& entries, bool add, hipStream_t s) {
         if (mfma_pp)
             launch_pp_mfma(items.as<DevItem>(), n, entries.as<int2>(), pl->dtgt(), dT, pl->dsrc(), dS, tab,
@@ -672,6 +686,11 @@ void setup_host_tree(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
 void setup_device(bldtt_plan* pl, const bldtt_particles* p, hipStream_t st) {
     double t0 = now_ms();
     HIPCHK(hipStreamSynchronize(st));
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     const int64_t M = p->M, N = p->N;
     if (pl->flags & BLDTT_DEVICE_TREE) {
         // trees built on the GPU (treebuild.hip): the particles never leave the device

@@ -297,6 +297,7 @@ struct bldtt_plan {
     }
 
     int tpt = 2, tpt_proxy = 2;              // targets per thread in the interaction kernels
+    int cus = 256;                           // compute units of the plan's device (set at setup)
     uint32_t up_degrees_last = 0;            // source degrees of the last per-pair degree compute
     int P() const { return (degree + 1) * (degree + 1) * (degree + 1); }
     DevParticles dsrc() const { return DevParticles{sx.as<double>(), sy.as<double>(), sz.as<double>(), sq.as<double>()}; }
