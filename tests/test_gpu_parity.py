@@ -479,6 +479,23 @@ def test_cube1e7_bench_config_sampled():
     _sampled_parity(p, p, True, "coulomb", 0.8, 7, 2000, seed=3)
 
 
+def test_cube1e7_fp32_vector_alu_large_tiles():
+    # at 1E7 the vector-ALU symmetric passes take items of up to 1024 targets
+    # (four slabs of 256): the FP32 form on the vector ALUs gives the same bits
+    # on a recompute and stays within the FP32 bound of the FP64 form
+    p = inputs.particles(10_000_000, "uniform", seed=inputs.workload_seed("cube1e7"))
+    kw = dict(theta=0.8, degree=7, leaf=2000)
+    plan, phi64, _ = gpu_plan(p, p, True, **kw)
+    plan.close()
+    plan, phi32, _ = gpu_plan(p, p, True, flags=1 | VALU_PASSES, **kw)
+    again = plan.compute().cpu().numpy()
+    plan.close()
+    assert np.array_equal(again, phi32)
+    err = core.rel_l2(phi32, phi64)
+    print(f"\n  1E7 FP32 vector-ALU passes vs FP64: {err:.2e}")
+    assert err < FP32_BOUND_CUBE, err
+
+
 def test_cube1e7_tuned_form_meets_error_target():
     # the timed tuned form (FP32 evaluation, learned degree, the workload's theta,
     # tau and fallback degree) on the same particles: relative l2 error against
