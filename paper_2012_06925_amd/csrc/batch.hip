@@ -6,6 +6,10 @@
 //
 //   [up_leaf]  proxy charges of each source leaf (Sec. 2.5)
 //   [up_xfer]  proxy charges of each source parent, deepest level first
+//   [s item]   FP64 batches of targets = sources problems (Coulomb): pairs of
+//              distinct leaves listed as PP both ways, once for both, into
+//              the item's slots (they need nothing before them, and keep the
+//              SIMDs busy while the upward pass completes)
 //   [q item]   CP + CC sums into target proxies (needs the upward pass)
 //   [c item]   FP64 batches of targets = sources problems (Coulomb): pairs of
 //              clusters listed as CC both ways, once for both; the sums go to
@@ -18,9 +22,6 @@
 //              particle fold, B's to the proxy fold; each item counts for its
 //              problem (like an s item) and for every partner B
 //   [p item]   PP + PC sums into target particles (PC needs the upward pass)
-//   [s item]   FP64 batches of targets = sources problems (Coulomb): pairs of
-//              distinct leaves listed as PP both ways, once for both, into
-//              the item's slots
 //   [dn_xfer]  a cluster's symmetric CC and CP slots folded into its proxy
 //              potentials in their stored order, then parent-to-child proxy
 //              potentials, shallowest level first (Sec. 2.7)
@@ -128,8 +129,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     using V = typename Stage<F32>::V;
     V* vl = reinterpret_cast<V*>(pool);
 
-    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, eq = e1 + a.n_q, e2 = eq + a.n_c, em = e2 + a.n_m,
-              e3 = em + a.n_p, es = e3 + a.n_s, e4 = es + a.n_kids;
+    // the symmetric PP items right after the upward pass: they need nothing
+    // before them, and keep the SIMDs busy while the upward pass completes
+    const int e0 = a.n_leaves, e1 = e0 + a.n_parents, ev = e1 + a.n_s, eq = ev + a.n_q, e2 = eq + a.n_c,
+              em = e2 + a.n_m, e3 = em + a.n_p, e4 = e3 + a.n_kids;
     const int n_up = e1;
     bool up_seen = false;                     // this group has already acquired the finished upward pass
     for (;;) {
@@ -155,8 +158,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             signal(par >= 0 ? a.up_cnt + par : a.ctr + C_UP_DONE);
             if (par >= 0 && threadIdx.x == 0)
                 __hip_atomic_fetch_add(a.ctr + C_UP_DONE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (t < ev) {
+            if constexpr (!F32 && KIND == K_COULOMB) {
+                const DevItem it = a.sitems[t - e1];
+                const int64_t base = a.sbase[t - e1];
+                sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots, base,
+                                       a.sslots, base + it.tn);
+                signal(a.sdone + a.prob[it.cluster]);
+            }
         } else if (t < eq) {
-            const int i = t - e1;
+            const int i = t - ev;
             const DevItem it = a.qitems[i];
             if (a.qneeds[i] && !up_seen) {
                 wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
@@ -199,16 +210,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             interact_body<KIND, F32, T, false>(it, a.pentries, a.tgt, a.T, a.src, a.S, a.tab_all, a.qp, a.param,
                                                a.phi_tree, a.po, vl, OUT_WRITE);
             signal(a.pdone + i);
-        } else if (t < es) {
-            if constexpr (!F32 && KIND == K_COULOMB) {
-                const DevItem it = a.sitems[t - e3];
-                const int64_t base = a.sbase[t - e3];
-                sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots, base,
-                                       a.sslots, base + it.tn);
-                signal(a.sdone + a.prob[it.cluster]);
-            }
         } else if (t < e4) {
-            const int c = a.kids[t - es];
+            const int c = a.kids[t - e3];
             const int par = a.T.parent[c];
             wait2(a, a.dn + par, a.nq[par] + (a.T.parent[par] >= 0 ? 1 : 0), a.dn + c, a.nq[c]);
             // the parent's potentials and the transfer matrices go to LDS while
