@@ -162,8 +162,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if constexpr (!F32 && KIND == K_COULOMB) {
                 const DevItem it = a.sitems[t - e1];
                 const int64_t base = a.sbase[t - e1];
-                sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots, base,
-                                       a.sslots, base + it.tn);
+                // the tails of leaves (at most 64 targets): one per lane
+                if (it.tn <= 64)
+                    sym_body<false, false, 1>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
+                                              base, a.sslots, base + it.tn);
+                else
+                    sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots, base,
+                                           a.sslots, base + it.tn);
                 signal(a.sdone + a.prob[it.cluster]);
             }
         } else if (t < eq) {
@@ -196,8 +201,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     wait2(a, a.ctr + C_UP_DONE, n_up, nullptr, 0);
                     up_seen = true;
                 }
-                sym_body<false, false, 2, true>(it, a.mentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
-                                                a.mtbase[i], a.cslots, a.msbase[i]);
+                if (it.tn <= 64)
+                    sym_body<false, false, 1, true>(it, a.mentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr,
+                                                    a.sslots, a.mtbase[i], a.cslots, a.msbase[i]);
+                else
+                    sym_body<false, false, 2, true>(it, a.mentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr,
+                                                    a.sslots, a.mtbase[i], a.cslots, a.msbase[i]);
                 signal_partners(a.sdone + a.prob[it.cluster], a.dn, a.mentries, it.eb, it.ee);
             }
         } else if (t < e3) {
