@@ -162,9 +162,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if constexpr (!F32 && KIND == K_COULOMB) {
                 const DevItem it = a.sitems[t - e1];
                 const int64_t base = a.sbase[t - e1];
-                // the tails of leaves (at most 64 targets): one per lane
+                // the tails of leaves: one target per lane for at most 64,
+                // three for 129..192
                 if (it.tn <= 64)
                     sym_body<false, false, 1>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
+                                              base, a.sslots, base + it.tn);
+                else if (it.tn > 128 && it.tn <= 192)
+                    sym_body<false, false, 3>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots,
                                               base, a.sslots, base + it.tn);
                 else
                     sym_body<false, false>(it, a.sentries, a.src, a.S, a.tab_all, a.qp, pool, nullptr, a.sslots, base,

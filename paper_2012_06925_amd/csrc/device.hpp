@@ -953,7 +953,8 @@ constexpr int sym_lds_bytes() {
 // CC: both, the PC/CP pairs of a particle tile with proxy grids: sources).
 // A tile of at most 64 targets gets one slab and four copies with H = 1 or 2,
 // and the same bits (a lane's second row is padding with charge 0), so the
-// particle passes give such tiles H = 1 and no lane slot idles.
+// particle passes give such tiles H = 1 and no lane slot idles; tiles of 129
+// to 192 particles take H = 3 (192 lane slots in place of 256).
 template <bool F32, bool PROXY, int H = 2, bool SPROXY = PROXY>
 __device__ __forceinline__ void sym_body(const DevItem it, const int2* __restrict__ entries, DevParticles p,
                                          DevTree T, const double* __restrict__ tab, DegPtrs qhat, void* lds,

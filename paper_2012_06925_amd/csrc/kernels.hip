@@ -105,13 +105,15 @@ __global__ __launch_bounds__(kBlock) void k_sym(const DevItem* __restrict__ item
                                                 DevParticles p, DevTree T, const double* __restrict__ tab,
                                                 DegPtrs qhat, double* __restrict__ nfp64, SymSlots out) {
     __shared__ double4 pool[(sym_lds_bytes<F32>() + 31) / 32];
-    // tiles of more than 128 targets: four per lane (one wave per copy); tiles
-    // of at most 64 particles (the tails of leaves): one per lane, so no lane
-    // slot idles.  The proxy passes keep two (their register count doubles
-    // with the one-per-lane body, and proxy tiles are never that small).
+    // tiles of more than 128 targets: four per lane (one wave per copy); the
+    // tails of leaves take fewer, so that fewer lane slots idle: three for
+    // 129..192 particles, one for at most 64.  The proxy passes keep two and
+    // four (their register count doubles with the one-per-lane body).
     const DevItem it = items[blockIdx.x];
     const int64_t base = out.ibase[blockIdx.x];
-    if (it.tn > 128)
+    if (!PROXY && it.tn > 128 && it.tn <= 192)
+        sym_body<F32, PROXY, 3>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base, out.slots, base + it.tn);
+    else if (it.tn > 128)
         sym_body<F32, PROXY, 4>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base, out.slots, base + it.tn);
     else if (PROXY || it.tn > 64)
         sym_body<F32, PROXY, 2>(it, entries, p, T, tab, qhat, pool, nfp64, out.slots, base, out.slots, base + it.tn);
