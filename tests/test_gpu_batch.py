@@ -229,6 +229,26 @@ def test_symmetric_batch_equals_one_sided_batch_and_replays():
     b.close()
 
 
+def test_symmetric_batch_tail_bodies_match_oracle():
+    # the batch's symmetric particle tasks pick one, two or three targets per
+    # lane by tile size: a Plummer problem with leaves of every such size
+    # (tiles of 256) against the oracle, the same bits on a replay
+    p = inputs.particles(30_000, "plummer", seed=61)
+    kw = dict(theta=0.7, degree=5, leaf=300)
+    b = api.Batch([_dev_problem(p)], **kw)
+    got = b.compute()[0].cpu().numpy()
+    again = b.compute()[0].cpu().numpy()
+    b.check()
+    b.close()
+    t = core.build_tree(p, 300)
+    ns = t["count"][t["nchild"] == 0]
+    for lo, hi in ((1, 64), (65, 128), (129, 192), (193, 256)):
+        assert np.count_nonzero((ns >= lo) & (ns <= hi)) >= 10, (lo, hi)
+    assert np.array_equal(got, again)
+    ref = core.Run(p, p, **kw).run_all()
+    assert core.rel_l2(got, ref) <= 1e-12 and core.max_rel(got, ref) <= 1e-12
+
+
 def test_symmetric_batch_of_tiny_problems_is_deterministic():
     # many problems of one leaf (no symmetric items, nothing to fold) beside a
     # few of several leaves: the folds skip the empty segments, every replay

@@ -215,6 +215,43 @@ def test_plummer_distribution_parity():
     assert e < FP32_BOUND_CUBE
 
 
+def _leaf_counts(plan):
+    t = plan.tree(0)
+    return t["count"][t["nchild"] == 0]
+
+
+# target counts of the symmetric items' per-lane bodies: one, two, three and
+# four targets per lane (tiles of up to 256 particles below 8192 items)
+TAIL_BODIES = ((1, 64), (65, 128), (129, 192), (193, 256))
+
+
+def test_symmetric_tail_bodies_parity():
+    # Plummer set with leaves of 300: leaf sizes (the symmetric items' tiles)
+    # in every range of the per-lane bodies; the FP64 passes against the
+    # oracle, and the FP32 vector-ALU passes bit-identical on recompute and
+    # within the FP32 bound of the FP64 result
+    p = inputs.particles(30_000, "plummer", seed=61)
+    kw = dict(theta=0.7, degree=5, leaf=300)
+    full_parity(p, p, True, **kw)
+    api = _api()
+    s = [dev(a) for a in (p.x, p.y, p.z, p.q)]
+    p64 = api.Plan(None, s, **kw)
+    ns = _leaf_counts(p64)
+    for lo, hi in TAIL_BODIES:
+        assert np.count_nonzero((ns >= lo) & (ns <= hi)) >= 10, (lo, hi)
+    phi64 = p64.compute().cpu().numpy()
+    assert p64.stats()["pass_interactions"][2] > 0       # the symmetric PP pass ran
+    p64.close()
+    p32 = api.Plan(None, s, flags=1 | VALU_PASSES, **kw)
+    a = p32.compute().cpu().numpy()
+    b = p32.compute().cpu().numpy()
+    p32.close()
+    assert np.array_equal(a, b)
+    e = core.rel_l2(a, phi64)
+    print(f"\n  FP32 vector-ALU vs FP64: {e:.2e}")
+    assert e < FP32_BOUND_CUBE
+
+
 @pytest.mark.parametrize("dist", ["slab", "rod"])
 def test_non_cubic_domains_parity(dist):
     # Sec. 4.4's non-cubic domains: slab 1 x 10 x 10 (the tree splits two
